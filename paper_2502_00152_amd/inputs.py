@@ -1,0 +1,141 @@
+"""Seeded synthetic inputs shared by the HIP path, the oracle and the tests.
+
+This module only draws random numbers and lays them out; it holds none of the
+method's arithmetic (no staggered phases, no boundary signs, no stencil, no
+solver).  Both sides of every parity check read the fields produced here.
+
+Gauge fields
+    Each link is a random SU(3) matrix W = exp(i*eps*H) with H a traceless
+    Hermitian 3x3 matrix, H = sum_a h_a * lambda_a / 2 over the eight
+    Gell-Mann matrices, h_a ~ N(0, 1) i.i.d.  The exponential is evaluated from
+    the eigendecomposition of H, H = Q diag(theta) Q^H, as
+    W = Q diag(exp(i*eps*theta)) Q^H.  Fat and long (Naik) links are two
+    independent draws from this distribution, with their own seeds.  The paper
+    measures on MILC HISQ ensembles (Table 1), which are not available; these
+    fields stand in for them at the paper's shapes.
+
+Layouts (canonical, lexicographic with x fastest)
+    dims = (X, Y, Z, T)
+    links   complex128 [4][T][Z][Y][X][3][3]   (mu = x, y, z, t; row-major a,b)
+    spinors complex128 [nrhs][T][Z][Y][X][3]
+
+Random streams
+    numpy PCG64.  Links are drawn direction by direction and time slice by time
+    slice, in that order, from one generator per field; a source is one
+    generator per right-hand side.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "GELL_MANN",
+    "random_su3_field",
+    "random_su3_matrices",
+    "gaussian_source",
+    "gaussian_even_vectors",
+    "random_gauge_transform",
+    "unit_links",
+    "config",
+    "CONFIGS",
+]
+
+
+def _gell_mann() -> np.ndarray:
+    lam = np.zeros((8, 3, 3), dtype=np.complex128)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1] = -1j
+    lam[1][1, 0] = 1j
+    lam[2][0, 0] = 1
+    lam[2][1, 1] = -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2] = -1j
+    lam[4][2, 0] = 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2] = -1j
+    lam[6][2, 1] = 1j
+    lam[7][0, 0] = lam[7][1, 1] = 1 / np.sqrt(3)
+    lam[7][2, 2] = -2 / np.sqrt(3)
+    return lam
+
+
+GELL_MANN = _gell_mann()
+
+
+def random_su3_matrices(rng: np.random.Generator, shape, eps: float) -> np.ndarray:
+    """Draw exp(i*eps*H) for a batch of Gaussian traceless Hermitian H."""
+    n = int(np.prod(shape))
+    h = rng.standard_normal((n, 8))
+    H = np.einsum("na,aij->nij", h, GELL_MANN) * 0.5
+    theta, Q = np.linalg.eigh(H)
+    ph = np.exp(1j * eps * theta)
+    W = np.einsum("nij,nj,nkj->nik", Q, ph, Q.conj())
+    return W.reshape(tuple(shape) + (3, 3))
+
+
+def random_su3_field(dims, eps: float, seed: int) -> np.ndarray:
+    """Links complex128 [4][T][Z][Y][X][3][3], one PCG64 stream per field."""
+    X, Y, Z, T = (int(d) for d in dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((4, T, Z, Y, X, 3, 3), dtype=np.complex128)
+    for mu in range(4):
+        for t in range(T):
+            out[mu, t] = random_su3_matrices(rng, (Z, Y, X), eps)
+    return out
+
+
+def unit_links(dims) -> np.ndarray:
+    """Free field: every link the 3x3 identity."""
+    X, Y, Z, T = (int(d) for d in dims)
+    out = np.zeros((4, T, Z, Y, X, 3, 3), dtype=np.complex128)
+    for a in range(3):
+        out[..., a, a] = 1.0
+    return out
+
+
+def gaussian_source(dims, seed: int) -> np.ndarray:
+    """Full-lattice source complex128 [T][Z][Y][X][3], Re and Im ~ N(0,1)."""
+    X, Y, Z, T = (int(d) for d in dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    re = rng.standard_normal((T, Z, Y, X, 3))
+    im = rng.standard_normal((T, Z, Y, X, 3))
+    return re + 1j * im
+
+
+def gaussian_even_vectors(n: int, n_cplx: int, seed: int) -> np.ndarray:
+    """n generic complex vectors of length n_cplx (no lattice structure)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((n, n_cplx)) + 1j * rng.standard_normal((n, n_cplx))
+
+
+def random_gauge_transform(dims, seed: int, eps: float = 3.0) -> np.ndarray:
+    """Site-local SU(3) matrices Omega(x), complex128 [T][Z][Y][X][3][3]."""
+    X, Y, Z, T = (int(d) for d in dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return random_su3_matrices(rng, (T, Z, Y, X), eps)
+
+
+# Synthetic workloads at the paper's shapes.  Seeds: fat 10000c+1,
+# long 10000c+2, source j 10000c+100+j, eigensolver start 10000c+7.
+CONFIGS = {
+    0: dict(name="plain-cg-8^4", dims=(8, 8, 8, 8), eps=0.3, two_m=0.1, nrhs=1,
+            n_ev=0, tol=1e-10),
+    1: dict(name="deflated-cg-16^3x32", dims=(16, 16, 16, 32), eps=0.5, two_m=0.01,
+            nrhs=12, n_ev=64, tol=1e-10),
+    2: dict(name="mixed-precision-32^3x64", dims=(32, 32, 32, 64), eps=0.5,
+            two_m=0.005, nrhs=24, n_ev=256, tol=1e-10),
+}
+C_FAT = 1.0
+C_LONG = -1.0 / 24.0
+
+
+def config(c: int) -> dict:
+    """Recipe of workload c, with its seeds."""
+    d = dict(CONFIGS[c])
+    d["seed_fat"] = 10000 * c + 1
+    d["seed_long"] = 10000 * c + 2
+    d["seed_src"] = [10000 * c + 100 + j for j in range(d["nrhs"])]
+    d["seed_eig"] = 10000 * c + 7
+    d["c_fat"] = C_FAT
+    d["c_long"] = C_LONG
+    return d
