@@ -1,0 +1,274 @@
+/*
+ * hisq.h - C ABI of libhisq: the even-odd preconditioned HISQ solve on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the one stated in arXiv:2502.00152, section 2: propagators
+ * psi solve M psi = eta with M = D + 2m, D the anti-Hermitian HISQ matrix; the
+ * normal equation M^H M psi = M^H eta (Eq. (1)) is solved by even-odd (Schur)
+ * preconditioned conjugate gradient on the even sites,
+ *
+ *     A psi_e = y_e,   A = (2m)^2 - D_eo D_oe,   y_e = 2m eta_e - D_eo eta_o,
+ *
+ * the odd half follows as psi_o = (eta_o - D_oe psi_e) / (2m), and the CG can
+ * start from the low-mode deflation guess x0 = sum_i v_i v_i^H b / lambda_i
+ * (Eq. (4)) built from eigenpairs of A computed by thick-restart Lanczos
+ * (section 2, the eigensolver paragraph).  The stencil is
+ *
+ *   (D psi)(x) = sum_mu [ F_mu(x) psi(x+mu) - F_mu(x-mu)^H psi(x-mu)
+ *                       + L_mu(x) psi(x+3mu) - L_mu(x-3mu)^H psi(x-3mu) ]
+ *
+ * with F the fat links and L the long (Naik) links, coordinates periodic,
+ * and no factor 1/2.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - dims = {X, Y, Z, T}; every extent even and >= 2.  Lexicographic site
+ *    index lex = ((t*Z + z)*Y + y)*X + x; parity = (x+y+z+t) mod 2;
+ *    checkerboard index cb = lex >> 1, 0 <= cb < Vh = X*Y*Z*T/2.
+ *  - A "parity vector" (even or odd) is complex double, SoA layout
+ *    [nrhs][3 colours][Vh], each complex stored as (re, im) doubles: element
+ *    (r, c, cb) sits at byte offset 16*((r*3 + c)*Vh + cb).
+ *  - A "full vector" is complex double [nrhs][T][Z][Y][X][3] (canonical).
+ *  - Every pointer argument named *_dev is device memory (hipMalloc'd or a
+ *    torch CUDA tensor), 16-byte aligned, owned by the caller, and not retained
+ *    after the call returns.  Host arrays are named *_host.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it.  Calls that return host values
+ *    (cg_solve, eigensolve, stats) synchronise that stream before returning.
+ *  - Calls on one gauge handle must not overlap (the handle owns scratch
+ *    buffers); different handles are independent.
+ *  - Every call returns a hisq_status and never throws.  On a non-OK status,
+ *    hisq_last_error() returns a message for the calling thread.
+ */
+#ifndef HISQ_H
+#define HISQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hisq_status {
+    HISQ_OK = 0,
+    HISQ_ERR_INVALID_ARG = 1,  /* bad extent, size, pointer, parity or parameter */
+    HISQ_ERR_HIP = 2,          /* a HIP runtime call failed */
+    HISQ_ERR_OOM = 3,          /* device allocation failed */
+    HISQ_ERR_NOT_CONVERGED = 4,/* iteration limit reached; best iterate returned */
+    HISQ_ERR_NAN = 5,          /* NaN or Inf met in a residual or a reduction */
+    HISQ_ERR_BREAKDOWN = 6,    /* <p, A p> <= 0 in CG, or an invariant Krylov space
+                                  smaller than requested in the eigensolver */
+    HISQ_ERR_UNSUPPORTED = 7   /* valid request that this build does not implement */
+} hisq_status;
+
+typedef enum hisq_prec { HISQ_FP64 = 0, HISQ_FP32 = 1, HISQ_BF16 = 2 } hisq_prec;
+
+/* hisq_gauge_create flags */
+enum {
+    HISQ_GAUGE_FOLD_PHASES = 1u,     /* multiply link mu at x by the staggered phase
+                                        eta_mu(x): 1, (-1)^x, (-1)^(x+y), (-1)^(x+y+z) */
+    HISQ_GAUGE_ANTIPERIODIC_T = 2u   /* multiply a time link of hop h at t by
+                                        (-1)^floor((t+h)/T) (antiperiodic fermions) */
+};
+
+typedef struct hisq_gauge_s *hisq_gauge;
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *hisq_last_error(void);
+
+/* ABI revision of this header; bumped on any incompatible change. */
+int hisq_abi_version(void);
+#define HISQ_ABI_VERSION 1
+
+/* ------------------------------------------------------------------ gauge */
+
+/*
+ * Build a gauge handle from fat links F and long links L (section 2: the HISQ
+ * matrix; the stencil is written out at the top of this file).
+ *   dims        {X, Y, Z, T}, even, >= 2, with X*Y*Z*T/2 < 2^31.
+ *   fat_dev,    complex double [4][T][Z][Y][X][3][3] (row-major colour matrix,
+ *   long_dev    mu = x, y, z, t); device memory, read only during the call.
+ *   c_fat,      scalar factors applied to the fat and long links.
+ *   c_long
+ *   flags       HISQ_GAUGE_* bits: fold staggered phases and the antiperiodic
+ *               time sign into the stored links.  Pass 0 (and 1.0, 1.0) for
+ *               links that already carry everything.
+ * The links are copied into the handle in the layout the kernels use; the
+ * caller's buffers may be freed afterwards.  Errors: INVALID_ARG for bad
+ * dims/pointers, OOM, HIP.
+ */
+hisq_status hisq_gauge_create(hisq_gauge *out, const int dims[4], const void *fat_dev,
+                              const void *long_dev, double c_fat, double c_long,
+                              unsigned flags, void *stream);
+
+/* Release the handle and every buffer it owns (synchronises the device). */
+hisq_status hisq_gauge_destroy(hisq_gauge g);
+
+/* Vh = X*Y*Z*T/2 of the handle (0 for a NULL handle). */
+int64_t hisq_gauge_half_volume(hisq_gauge g);
+
+/* ---------------------------------------------------------------- layouts */
+
+/*
+ * Split full vectors [nrhs][T][Z][Y][X][3] into even and odd parity vectors
+ * (layout above).  Either output may be NULL to skip it.
+ */
+hisq_status hisq_spinor_split(hisq_gauge g, const void *full_dev, void *even_dev,
+                              void *odd_dev, int nrhs, void *stream);
+
+/* Inverse of hisq_spinor_split.  A NULL input parity writes zeros there. */
+hisq_status hisq_spinor_merge(hisq_gauge g, const void *even_dev, const void *odd_dev,
+                              void *full_dev, int nrhs, void *stream);
+
+/* ------------------------------------------------------------- operators */
+
+/*
+ * Half stencil: out = D_{p,1-p} in for output parity p = out_parity
+ * (0 = even: D_eo, odd -> even; 1 = odd: D_oe, even -> odd).  `in` is a parity
+ * vector of parity 1-p, `out` of parity p; they must not overlap.
+ * Section 2 (the HISQ matrix D; even-odd split).  prec: HISQ_FP64 only in
+ * this build (others return UNSUPPORTED).
+ */
+hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
+                           void *out_dev, int nrhs, hisq_prec prec, void *stream);
+
+/*
+ * Even-site normal operator: out_e = ((2m)^2 - D_eo D_oe) in_e, the even-even
+ * block of M^H M (Eq. (1) after even-odd preconditioning).  two_m = 2m >= 0.
+ * in_e and out_e must not overlap.  Uses an odd-parity scratch vector owned by
+ * the handle.
+ */
+hisq_status hisq_mdagm(hisq_gauge g, double two_m, const void *in_e_dev, void *out_e_dev,
+                       int nrhs, hisq_prec prec, void *stream);
+
+/*
+ * Even-site source of the preconditioned system: y_e = 2m eta_e - D_eo eta_o,
+ * the even half of M^H eta (section 2, the Schur step before the CG).
+ */
+hisq_status hisq_prepare_source(hisq_gauge g, double two_m, const void *eta_e_dev,
+                                const void *eta_o_dev, void *y_e_dev, int nrhs,
+                                void *stream);
+
+/*
+ * Odd half of the solution from the odd rows of M psi = eta:
+ * psi_o = (eta_o - D_oe psi_e) / (2m).  two_m > 0.  (Section 2 prints this
+ * step garbled; this is the form under which M psi = eta holds exactly.)
+ */
+hisq_status hisq_reconstruct_odd(hisq_gauge g, double two_m, const void *psi_e_dev,
+                                 const void *eta_o_dev, void *psi_o_dev, int nrhs,
+                                 void *stream);
+
+/* ------------------------------------------------------------------- CG */
+
+typedef struct hisq_cg_params {
+    double tol;            /* stop when ||b - A x|| / ||b|| <= tol (true residual, FP64) */
+    int max_iter;          /* iteration limit per right-hand side */
+    int check_interval;    /* iterations between host polls of the convergence state
+                              (0 = default 16).  It does not change the iterates. */
+    hisq_prec sloppy_prec; /* HISQ_FP64: plain FP64 CG (the only value in this build) */
+    int reserved[8];       /* must be zero */
+} hisq_cg_params;
+
+typedef struct hisq_cg_stats {
+    int iterations;        /* operator applications inside the loop */
+    int true_residual_checks; /* recomputations of b - A x (after the initial one) */
+    int converged;         /* 1 if the true residual met tol */
+    int reserved0;
+    double true_residual;  /* final ||b - A x|| / ||b||, FP64 */
+    double b_norm;         /* ||b|| */
+} hisq_cg_stats;
+
+/*
+ * Solve A x = b on even sites, A = (2m)^2 - D_eo D_oe, for nrhs right-hand
+ * sides at once (section 2: the even-odd preconditioned CG, the paper's
+ * baseline; Eq. (1)).  x_e_dev holds the initial guess on entry (zeros, or a
+ * deflation guess from hisq_deflate) and the solution on return.  Each
+ * right-hand side follows its own CG recurrence with FP64 global reductions
+ * in a fixed order, so results are bitwise reproducible run to run.  A
+ * right-hand side stops when its iterated residual crosses tol and the
+ * recomputed true residual confirms it; if the true residual does not, CG
+ * continues from it with the search direction kept.  b = 0 gives x = 0.
+ *   stats_host: array of nrhs structs, filled on return (may be NULL).
+ * Returns NOT_CONVERGED if any right-hand side hit max_iter (x holds its last
+ * iterate), NAN, BREAKDOWN, or INVALID_ARG (two_m <= 0, tol <= 0, ...).
+ * Synchronises `stream`.
+ */
+hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e_dev, void *x_e_dev,
+                          int nrhs, const hisq_cg_params *params,
+                          hisq_cg_stats *stats_host, void *stream);
+
+/* ------------------------------------------------------------ deflation */
+
+/*
+ * Deflation guess x0 = V diag(1 / (eps_i + (2m)^2)) V^H b (Eq. (4)), where the
+ * columns of V are orthonormal even-site eigenvectors of the massless
+ * operator -D_eo D_oe with eigenvalues eps_i (Eq. (3): the massive eigenvalue
+ * is eps_i + (2m)^2 and the vectors do not depend on m).
+ *   evecs_dev       n_ev even parity vectors [n_ev][3][Vh] (complex double).
+ *   evals_host      eps_i, n_ev doubles (host); eps_i + (2m)^2 must be > 0.
+ *   b_e_dev, x0_e_dev  parity vectors with nrhs right-hand sides; must not overlap.
+ * The two contractions run on the FP64 matrix cores.
+ */
+hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_dev,
+                         const double *evals_host, double two_m, const void *b_e_dev,
+                         void *x0_e_dev, int nrhs, void *stream);
+
+/* --------------------------------------------------------- eigensolver */
+
+typedef struct hisq_eig_params {
+    int n_kr;              /* Krylov basis size (0 = auto: max(2*n_ev, n_ev + 32)) */
+    int cheb_degree;       /* Chebyshev filter degree (0 = auto) */
+    double cheb_a;         /* filter interval [a, b] of A to suppress (0 = auto) */
+    double cheb_b;
+    double tol;            /* accept when ||A v - lambda v|| <= tol * lambda_max(A) */
+    int max_restarts;      /* 0 = default 200 */
+    int reserved0;
+    uint64_t seed;         /* seed of the counter-based start vector */
+    int reserved[8];       /* must be zero */
+} hisq_eig_params;
+
+typedef struct hisq_eig_stats {
+    int restarts;
+    int matvecs;           /* applications of A (each = two half stencils) */
+    int converged;         /* number of accepted pairs (n_ev on success) */
+    int cheb_degree;
+    double cheb_a, cheb_b;
+    double lambda_max;     /* estimated largest eigenvalue of A */
+    double max_residual;   /* max_i ||A v_i - lambda_i v_i|| after Rayleigh-Ritz */
+    double seconds;
+} hisq_eig_stats;
+
+/*
+ * Lowest n_ev eigenpairs of A = (2m)^2 - D_eo D_oe on even sites by
+ * thick-restart Lanczos on a Chebyshev-filtered A, ending with a Rayleigh-Ritz
+ * step on A itself (section 2: eigenvectors of the squared operator from
+ * thick-restart Lanczos, used for deflation; the vectors are single parity,
+ * section 3).
+ *   evecs_dev   caller-allocated [n_ev][3][Vh] complex double (orthonormal on exit)
+ *   evals_host  n_ev doubles, ascending: eigenvalues of A at this two_m
+ *   stats_host  may be NULL.
+ * Returns NOT_CONVERGED if max_restarts passes without n_ev accepted pairs
+ * (the best Ritz pairs are still written), BREAKDOWN, INVALID_ARG
+ * (n_ev < 1, n_kr <= n_ev, n_kr >= 3*Vh), OOM.  Synchronises `stream`.
+ */
+hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
+                            const hisq_eig_params *params, void *evecs_dev,
+                            double *evals_host, hisq_eig_stats *stats_host, void *stream);
+
+/* ------------------------------------------------------ instrumentation */
+
+/*
+ * Per-kernel timing with HIP events recorded on the launch stream around
+ * every launch of the named kernel class ("dslash", "blas", "gemm"); off by
+ * default.  hisq_profile_read returns the number of timed launches and their
+ * total milliseconds (synchronises the device), and clears the record.
+ */
+hisq_status hisq_profile_enable(int on);
+hisq_status hisq_profile_read(const char *kernel_class, int64_t *launches,
+                              double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISQ_H */

@@ -1,0 +1,295 @@
+// Vector updates and FP64 global reductions of the CG iteration
+// (arXiv:2502.00152, section 2: conjugate gradient on the even-odd
+// preconditioned normal equation, stopped on the true residual).
+//
+// Each right-hand side r runs its own recurrence
+//   alpha = rho / Re<p, Ap>;  x += alpha p;  r -= alpha Ap;
+//   rho' = <r, r>;  beta = rho' / rho;  p = r + beta p
+// The scalars live in device memory.  A reduction is finished inside the
+// kernel that produces it: every block stores its partial sums, and the last
+// block to arrive adds them up in block order, so the sum does not depend on
+// which block finished last and results are bitwise reproducible.
+#include "device_util.h"
+#include "hisq_internal.h"
+
+namespace hisq {
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+namespace {
+
+constexpr int kBS = 256;
+
+// Grid: x = blocks per RHS (grid-stride over n complex entries), y = RHS.
+struct BlasGrid {
+    int nbx;
+    int64_t n;
+};
+
+BlasGrid make_grid(int64_t n) {
+    BlasGrid g;
+    g.n = n;
+    int64_t nb = (n + 4 * kBS - 1) / (4 * kBS);
+    if (nb < 1) nb = 1;
+    if (nb > 1024) nb = 1024;
+    g.nbx = (int)nb;
+    return g;
+}
+
+__device__ __forceinline__ double norm2(dvec2 v) { return fma(v.x, v.x, v.y * v.y); }
+
+// r = b - Ax; p = r; partials: ||b||^2 and ||r||^2 per RHS.
+__global__ __launch_bounds__(kBS) void k_cg_init(int64_t n, int nrhs, const dvec2 *__restrict__ b,
+                                                 const dvec2 *__restrict__ Ax,
+                                                 dvec2 *__restrict__ r, dvec2 *__restrict__ p,
+                                                 double tol, CgDev cg, Reduce red) {
+    const int rhs = blockIdx.y;
+    const int64_t off = rhs * n;
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+        const dvec2 bb = b[off + i];
+        const dvec2 rr = bb - Ax[off + i];
+        r[off + i] = rr;
+        p[off + i] = rr;
+        v[0] += norm2(bb);
+        v[1] += norm2(rr);
+    }
+    __shared__ double lds[2 * (kBS / kWave)];
+    block_sum<2, kBS>(v, lds);
+    const int nbx = gridDim.x;
+    if (threadIdx.x == 0) {
+        red.partials[(int64_t)rhs * nbx + blockIdx.x] = v[0];
+        red.partials[(int64_t)(nrhs + rhs) * nbx + blockIdx.x] = v[1];
+    }
+    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
+        __shared__ double w[kBS / kWave];
+        for (int q = 0; q < nrhs; ++q) {
+            const double bn = sum_partials<kBS>(red.partials + (int64_t)q * nbx, nbx, w);
+            const double rn = sum_partials<kBS>(red.partials + (int64_t)(nrhs + q) * nbx, nbx, w);
+            if (threadIdx.x == 0) {
+                cg.bnorm2[q] = bn;
+                cg.tol2b[q] = tol * tol * bn;
+                cg.rho[q] = rn;
+                cg.true_res2[q] = rn;
+                cg.iters[q] = 0;
+                cg.checks[q] = 0;
+                cg.alpha[q] = 0.0;
+                cg.beta[q] = 0.0;
+                if (!isfinite(bn) || !isfinite(rn))
+                    cg.status[q] = CG_NAN;
+                else if (bn == 0.0 || rn <= tol * tol * bn)
+                    cg.status[q] = CG_CONVERGED;
+                else
+                    cg.status[q] = CG_ACTIVE;
+            }
+        }
+        last_block_done(red.counter);
+    }
+}
+
+// x += alpha p; r -= alpha Ap; partial ||r||^2 (active RHS only).
+__global__ __launch_bounds__(kBS) void k_cg_update(int64_t n, int nrhs, dvec2 *__restrict__ x,
+                                                   dvec2 *__restrict__ r,
+                                                   const dvec2 *__restrict__ p,
+                                                   const dvec2 *__restrict__ Ap, CgDev cg,
+                                                   Reduce red) {
+    const int rhs = blockIdx.y;
+    const int64_t off = rhs * n;
+    double v[1] = {0.0};
+    if (cg.status[rhs] == CG_ACTIVE) {
+        const double al = cg.alpha[rhs];
+        for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * kBS) {
+            const dvec2 pp = p[off + i];
+            const dvec2 qq = Ap[off + i];
+            dvec2 xx = x[off + i];
+            dvec2 rr = r[off + i];
+            xx.x = fma(al, pp.x, xx.x);
+            xx.y = fma(al, pp.y, xx.y);
+            rr.x = fma(-al, qq.x, rr.x);
+            rr.y = fma(-al, qq.y, rr.y);
+            x[off + i] = xx;
+            r[off + i] = rr;
+            v[0] += norm2(rr);
+        }
+    }
+    __shared__ double lds[kBS / kWave];
+    block_sum<1, kBS>(v, lds);
+    const int nbx = gridDim.x;
+    if (threadIdx.x == 0) red.partials[(int64_t)rhs * nbx + blockIdx.x] = v[0];
+    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
+        __shared__ double w[kBS / kWave];
+        for (int q = 0; q < nrhs; ++q) {
+            const double rn = sum_partials<kBS>(red.partials + (int64_t)q * nbx, nbx, w);
+            if (threadIdx.x == 0 && cg.status[q] == CG_ACTIVE) {
+                cg.iters[q] += 1;
+                if (!isfinite(rn)) {
+                    cg.status[q] = CG_NAN;
+                } else if (rn <= cg.tol2b[q]) {
+                    cg.rho_pend[q] = rn;
+                    cg.status[q] = CG_PENDING;
+                } else {
+                    cg.beta[q] = rn / cg.rho[q];
+                    cg.rho[q] = rn;
+                    if (cg.iters[q] >= cg.max_iter) cg.status[q] = CG_MAXITER;
+                }
+            }
+        }
+        last_block_done(red.counter);
+    }
+}
+
+// p = r + beta p for active RHS (or for RHS in `want` state).
+__global__ __launch_bounds__(kBS) void k_cg_update_p(int64_t n, const dvec2 *__restrict__ r,
+                                                     dvec2 *__restrict__ p, CgDev cg) {
+    const int rhs = blockIdx.y;
+    if (cg.status[rhs] != CG_ACTIVE) return;
+    const int64_t off = rhs * n;
+    const double be = cg.beta[rhs];
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+        const dvec2 rr = r[off + i];
+        dvec2 pp = p[off + i];
+        pp.x = fma(be, pp.x, rr.x);
+        pp.y = fma(be, pp.y, rr.y);
+        p[off + i] = pp;
+    }
+}
+
+// For pending RHS (or all, with final_only): r = b - Ax and ||r||^2; then
+// decide convergence of each pending RHS.
+__global__ __launch_bounds__(kBS) void k_cg_true_residual(int64_t n, int nrhs,
+                                                          const dvec2 *__restrict__ b,
+                                                          const dvec2 *__restrict__ Ax,
+                                                          dvec2 *__restrict__ r, CgDev cg,
+                                                          Reduce red, int final_only) {
+    const int rhs = blockIdx.y;
+    const int64_t off = rhs * n;
+    double v[1] = {0.0};
+    const int st = cg.status[rhs];
+    if (final_only || st == CG_PENDING) {
+        for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * kBS) {
+            const dvec2 rr = b[off + i] - Ax[off + i];
+            if (!final_only) r[off + i] = rr;
+            v[0] += norm2(rr);
+        }
+    }
+    __shared__ double lds[kBS / kWave];
+    block_sum<1, kBS>(v, lds);
+    const int nbx = gridDim.x;
+    if (threadIdx.x == 0) red.partials[(int64_t)rhs * nbx + blockIdx.x] = v[0];
+    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
+        __shared__ double w[kBS / kWave];
+        for (int q = 0; q < nrhs; ++q) {
+            const double tr = sum_partials<kBS>(red.partials + (int64_t)q * nbx, nbx, w);
+            if (threadIdx.x == 0) {
+                if (final_only) {
+                    cg.true_res2[q] = tr;
+                } else if (cg.status[q] == CG_PENDING) {
+                    cg.checks[q] += 1;
+                    cg.true_res2[q] = tr;
+                    if (!isfinite(tr)) {
+                        cg.status[q] = CG_NAN;
+                    } else if (tr <= cg.tol2b[q]) {
+                        cg.status[q] = CG_CONVERGED;
+                    } else if (cg.iters[q] >= cg.max_iter) {
+                        cg.status[q] = CG_MAXITER;
+                    } else {
+                        cg.beta[q] = tr / cg.rho[q];
+                        cg.rho[q] = tr;
+                        cg.status[q] = CG_RESTART;
+                    }
+                }
+            }
+        }
+        last_block_done(red.counter);
+    }
+}
+
+// p = r + beta p for RHS restarting from a true residual; then mark them active.
+__global__ __launch_bounds__(kBS) void k_cg_restart_p(int64_t n, int nrhs,
+                                                      const dvec2 *__restrict__ r,
+                                                      dvec2 *__restrict__ p, CgDev cg,
+                                                      Reduce red) {
+    const int rhs = blockIdx.y;
+    if (cg.status[rhs] == CG_RESTART) {
+        const int64_t off = rhs * n;
+        const double be = cg.beta[rhs];
+        for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * kBS) {
+            const dvec2 rr = r[off + i];
+            dvec2 pp = p[off + i];
+            pp.x = fma(be, pp.x, rr.x);
+            pp.y = fma(be, pp.y, rr.y);
+            p[off + i] = pp;
+        }
+    }
+    __syncthreads();
+    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
+        if (threadIdx.x == 0)
+            for (int q = 0; q < nrhs; ++q)
+                if (cg.status[q] == CG_RESTART) cg.status[q] = CG_ACTIVE;
+        last_block_done(red.counter);
+    }
+}
+
+}  // namespace
+
+int blas_reduce_blocks(int64_t n) { return make_grid(n).nbx; }
+
+#define AS_V(p) reinterpret_cast<dvec2 *>(p)
+#define AS_CV(p) reinterpret_cast<const dvec2 *>(p)
+
+hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, double2 *r,
+                    double2 *p, double tol, const CgDev &cg, const Reduce &red,
+                    hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_init, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs, AS_CV(b),
+                       AS_CV(Ax), AS_V(r), AS_V(p), tol, cg, red);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status cg_update(int64_t n, int nrhs, double2 *x, double2 *r, const double2 *p,
+                      const double2 *Ap, const CgDev &cg, const Reduce &red, hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_update, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs, AS_V(x),
+                       AS_V(r), AS_CV(p), AS_CV(Ap), cg, red);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status cg_update_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
+                        hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_update_p, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_CV(r),
+                       AS_V(p), cg);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status cg_true_residual(int64_t n, int nrhs, const double2 *b, const double2 *Ax,
+                             double2 *r, const CgDev &cg, const Reduce &red, bool final_only,
+                             hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_true_residual, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs,
+                       AS_CV(b), AS_CV(Ax), AS_V(r), cg, red, final_only ? 1 : 0);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status cg_restart_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
+                         const Reduce &red, hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_restart_p, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs,
+                       AS_CV(r), AS_V(p), cg, red);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+}  // namespace hisq

@@ -1,0 +1,112 @@
+// Device helpers: complex arithmetic on double2, fixed-order block reductions,
+// the last-block arrival used to finish a global reduction inside a kernel,
+// and the XCD-aware block order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hisq {
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, 32 CUs each
+
+// ------------------------------------------------------------ complex math
+__device__ __forceinline__ void cmac(double2 &acc, double2 a, double2 b) {
+    // acc += a * b
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+
+__device__ __forceinline__ void cmac_conj(double2 &acc, double2 a, double2 b) {
+    // acc += conj(a) * b
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+}
+
+__device__ __forceinline__ double redot(double2 a, double2 b) {
+    // Re(conj(a) * b)
+    return fma(a.x, b.x, a.y * b.y);
+}
+
+// ------------------------------------------------------------- block order
+// Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
+// b % 8).  Renumber them so that each XCD receives one contiguous range of
+// logical blocks: neighbouring sites then share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+    const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
+    const int x = b % kNumXcd, j = b / kNumXcd;
+    return x * q + (x < r ? x : r) + j;
+}
+
+// ---------------------------------------------------------- reductions
+// Sum over the 64 lanes of a wave, in a fixed order; result in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Block-wide sum of NV values per thread.  The result is returned in thread 0
+// (other threads get unspecified values).  `lds` holds NV * (BS/64) doubles.
+template <int NV, int BS>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+    constexpr int NW = BS / kWave;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) lds[j * NW + w] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < NW; ++k) s += lds[j * NW + k];
+            v[j] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Every block calls this once after thread 0 has stored its partial sums.
+// Returns true in exactly one block - the last to arrive - after making the
+// other blocks' stores visible to it.  The counter is reset by that block
+// through last_block_done().
+__device__ __forceinline__ bool last_block_arrive(unsigned *counter, unsigned total) {
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == total - 1u);
+    }
+    __syncthreads();
+    const bool last = is_last != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+__device__ __forceinline__ void last_block_done(unsigned *counter) {
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+}
+
+// Fixed-order sum of partials[0..nb) by one block (all threads call it).
+template <int BS>
+__device__ __forceinline__ double sum_partials(const double *partials, int nb, double *lds) {
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < nb; i += BS) v[0] += partials[i];
+    block_sum<1, BS>(v, lds);
+    __shared__ double result;
+    if (threadIdx.x == 0) result = v[0];
+    __syncthreads();
+    const double r = result;
+    __syncthreads();
+    return r;
+}
+
+}  // namespace hisq

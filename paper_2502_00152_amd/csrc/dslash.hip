@@ -1,0 +1,309 @@
+// HISQ half stencil D_{p,1-p} on gfx950, FP64.
+//
+//   out(x) = ca * aux(x) + cd * sum_mu [ F_mu(x) in(x+mu) - F_mu(x-mu)^H in(x-mu)
+//                                      + L_mu(x) in(x+3mu) - L_mu(x-3mu)^H in(x-3mu) ]
+//
+// for every site x of parity p (arXiv:2502.00152, section 2: the HISQ matrix
+// D of M = D + 2m; the even-odd split makes D map one parity to the other).
+//
+// One thread owns one output site and NR right-hand sides.  Forward links are
+// read at the thread's own checkerboard index (coalesced); backward links are
+// read at the neighbour's index in the other parity's array, which is
+// coalesced too for y, z, t hops (constant offset) and nearly so for x hops.
+// Links are streamed with non-temporal loads: each is used once per launch,
+// so they should not evict the input field, which every site reads 16 times.
+// The HBM traffic per output site is 16 links * 144 B + (in + out) * 48 B * NR,
+// so the kernel is bound by HBM bandwidth.
+#include "device_util.h"
+#include "hisq_internal.h"
+
+namespace hisq {
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+namespace {
+
+constexpr int kBS = 256;
+
+struct DslashArgs {
+    const dvec2 *fat_out;  // links on output-parity sites  [4][9][Vh]
+    const dvec2 *fat_in;   // links on input-parity sites   [4][9][Vh]
+    const dvec2 *lng_out;
+    const dvec2 *lng_in;
+    const dvec2 *in;       // [nrhs][3][Vh], parity 1-p
+    dvec2 *out;            // [nrhs][3][Vh], parity p
+    const dvec2 *aux;      // [nrhs][3][Vh], parity p (optional)
+    double ca, cd;
+    Geom geom;
+    int out_parity;
+    int nrhs;
+    int ngroups;           // ceil(nrhs / NR)
+    int nsb;               // site blocks
+    // fused reduction (FIN_CG_ALPHA)
+    double *partials;      // [nrhs][nsb]
+    unsigned *counter;
+    CgDev cg;
+};
+
+__device__ __forceinline__ int wrap(int c, int L) {
+    c = c < 0 ? c + L : c;
+    c = c < 0 ? c + L : c;
+    c = c >= L ? c - L : c;
+    c = c >= L ? c - L : c;
+    return c;
+}
+
+__device__ __forceinline__ dvec2 ldnt(const dvec2 *p) { return __builtin_nontemporal_load(p); }
+
+template <int NR>
+__device__ __forceinline__ void hop_forward(const dvec2 *__restrict__ U, int vh, int cbU,
+                                            const dvec2 *__restrict__ in, int64_t rstride,
+                                            int cbN, int nr, dvec2 (&acc)[NR][3]) {
+    dvec2 u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = ldnt(U + (int64_t)k * vh + cbU);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+            const dvec2 *v = in + r * rstride + cbN;
+            const dvec2 v0 = v[0], v1 = v[vh], v2 = v[2 * (int64_t)vh];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dvec2 s = acc[r][a];
+                s.x = fma(u[3 * a].x, v0.x, s.x);  s.x = fma(-u[3 * a].y, v0.y, s.x);
+                s.y = fma(u[3 * a].x, v0.y, s.y);  s.y = fma(u[3 * a].y, v0.x, s.y);
+                s.x = fma(u[3 * a + 1].x, v1.x, s.x);  s.x = fma(-u[3 * a + 1].y, v1.y, s.x);
+                s.y = fma(u[3 * a + 1].x, v1.y, s.y);  s.y = fma(u[3 * a + 1].y, v1.x, s.y);
+                s.x = fma(u[3 * a + 2].x, v2.x, s.x);  s.x = fma(-u[3 * a + 2].y, v2.y, s.x);
+                s.y = fma(u[3 * a + 2].x, v2.y, s.y);  s.y = fma(u[3 * a + 2].y, v2.x, s.y);
+                acc[r][a] = s;
+            }
+        }
+    }
+}
+
+// acc -= U^H v, with U read at the neighbour's index.
+template <int NR>
+__device__ __forceinline__ void hop_backward(const dvec2 *__restrict__ U, int vh, int cbN,
+                                             const dvec2 *__restrict__ in, int64_t rstride,
+                                             int nr, dvec2 (&acc)[NR][3]) {
+    dvec2 u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = ldnt(U + (int64_t)k * vh + cbN);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+            const dvec2 *v = in + r * rstride + cbN;
+            const dvec2 v0 = v[0], v1 = v[vh], v2 = v[2 * (int64_t)vh];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                // (U^H)_{ab} = conj(U_{ba})
+                dvec2 s = acc[r][a];
+                s.x = fma(-u[a].x, v0.x, s.x);  s.x = fma(-u[a].y, v0.y, s.x);
+                s.y = fma(-u[a].x, v0.y, s.y);  s.y = fma(u[a].y, v0.x, s.y);
+                s.x = fma(-u[3 + a].x, v1.x, s.x);  s.x = fma(-u[3 + a].y, v1.y, s.x);
+                s.y = fma(-u[3 + a].x, v1.y, s.y);  s.y = fma(u[3 + a].y, v1.x, s.y);
+                s.x = fma(-u[6 + a].x, v2.x, s.x);  s.x = fma(-u[6 + a].y, v2.y, s.x);
+                s.y = fma(-u[6 + a].x, v2.y, s.y);  s.y = fma(u[6 + a].y, v2.x, s.y);
+                acc[r][a] = s;
+            }
+        }
+    }
+}
+
+template <int NR, bool AUX, bool DOT>
+__global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
+    const Geom g = a.geom;
+    const int vh = g.vh;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int sb = lb / a.ngroups, grp = lb - sb * a.ngroups;
+    const int cb = sb * kBS + threadIdx.x;
+    const int r0 = grp * NR;
+    const int nr = min(NR, a.nrhs - r0);
+    const int64_t rstride = 3 * (int64_t)vh;
+
+    double dotv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dotv[r] = 0.0;
+
+    if (cb < vh) {
+        // coordinates of the output site
+        int t = cb / g.Xh;
+        const int xh = cb - t * g.Xh;
+        const int y = t % g.Y;
+        t /= g.Y;
+        const int z = t % g.Z;
+        t /= g.Z;
+        const int x = 2 * xh + ((a.out_parity + y + z + t) & 1);
+        const int rowYZT = (t * g.Z + z) * g.Y + y;  // lex = rowYZT * X + x
+
+        dvec2 acc[NR][3];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[r][c] = dvec2{0.0, 0.0};
+
+        const dvec2 *in = a.in + r0 * rstride;
+        const int64_t lstride = 9 * (int64_t)vh;
+
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int hop = h == 0 ? 1 : 3;
+            const dvec2 *Uo = h == 0 ? a.fat_out : a.lng_out;
+            const dvec2 *Ui = h == 0 ? a.fat_in : a.lng_in;
+            // mu = 0 (x)
+            {
+                const int f = (rowYZT * g.X + wrap(x + hop, g.X)) >> 1;
+                const int b = (rowYZT * g.X + wrap(x - hop, g.X)) >> 1;
+                hop_forward<NR>(Uo, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR>(Ui, vh, b, in, rstride, nr, acc);
+            }
+            // mu = 1 (y)
+            {
+                const int f = ((((t * g.Z + z) * g.Y + wrap(y + hop, g.Y)) * g.X) + x) >> 1;
+                const int b = ((((t * g.Z + z) * g.Y + wrap(y - hop, g.Y)) * g.X) + x) >> 1;
+                hop_forward<NR>(Uo + lstride, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR>(Ui + lstride, vh, b, in, rstride, nr, acc);
+            }
+            // mu = 2 (z)
+            {
+                const int f = ((((t * g.Z + wrap(z + hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
+                const int b = ((((t * g.Z + wrap(z - hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
+                hop_forward<NR>(Uo + 2 * lstride, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR>(Ui + 2 * lstride, vh, b, in, rstride, nr, acc);
+            }
+            // mu = 3 (t)
+            {
+                const int f = ((((wrap(t + hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
+                const int b = ((((wrap(t - hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
+                hop_forward<NR>(Uo + 3 * lstride, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR>(Ui + 3 * lstride, vh, b, in, rstride, nr, acc);
+            }
+        }
+
+        // epilogue
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r < nr) {
+                const int64_t base = (r0 + r) * rstride + cb;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dvec2 o = acc[r][c] * a.cd;
+                    if (AUX) {
+                        const dvec2 ax = a.aux[base + c * (int64_t)vh];
+                        o.x = fma(a.ca, ax.x, o.x);
+                        o.y = fma(a.ca, ax.y, o.y);
+                        if (DOT) dotv[r] = fma(ax.x, o.x, fma(ax.y, o.y, dotv[r]));
+                    }
+                    a.out[base + c * (int64_t)vh] = o;
+                }
+            }
+        }
+    }
+
+    if (DOT) {
+        __shared__ double lds[NR * (kBS / kWave)];
+        block_sum<NR, kBS>(dotv, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr) a.partials[(int64_t)(r0 + r) * a.nsb + sb] = dotv[r];
+        }
+        if (last_block_arrive(a.counter, gridDim.x)) {
+            __shared__ double red[kBS / kWave];
+            for (int r = 0; r < a.nrhs; ++r) {
+                const double pap = sum_partials<kBS>(a.partials + (int64_t)r * a.nsb, a.nsb, red);
+                if (threadIdx.x == 0 && a.cg.status[r] == CG_ACTIVE) {
+                    if (!isfinite(pap)) {
+                        a.cg.status[r] = CG_NAN;
+                        a.cg.alpha[r] = 0.0;
+                    } else if (!(pap > 0.0)) {
+                        a.cg.status[r] = CG_BREAKDOWN;
+                        a.cg.alpha[r] = 0.0;
+                    } else {
+                        a.cg.alpha[r] = a.cg.rho[r] / pap;
+                    }
+                }
+            }
+            last_block_done(a.counter);
+        }
+    }
+}
+
+template <int NR>
+hisq_status launch_nr(const DslashArgs &args, int nblocks, bool aux, bool dot, hipStream_t s) {
+    if (dot)
+        hipLaunchKernelGGL((k_dslash<NR, true, true>), dim3(nblocks), dim3(kBS), 0, s, args);
+    else if (aux)
+        hipLaunchKernelGGL((k_dslash<NR, true, false>), dim3(nblocks), dim3(kBS), 0, s, args);
+    else
+        hipLaunchKernelGGL((k_dslash<NR, false, false>), dim3(nblocks), dim3(kBS), 0, s, args);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+// Right-hand sides per thread.
+int pick_nr(int nrhs) {
+    if (nrhs <= 4) return nrhs;
+    // smallest group count with at most 4 per thread, balanced
+    const int groups = (nrhs + 3) / 4;
+    return (nrhs + groups - 1) / groups;
+}
+
+}  // namespace
+
+int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs) {
+    (void)nrhs;
+    return (g->geom.vh + kBS - 1) / kBS;
+}
+
+hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
+                          double2 *out, int nrhs, const double2 *aux, double ca, double cd,
+                          DslashFinal fin, const CgDev *cg, const Reduce *red,
+                          hipStream_t s) {
+    DslashArgs a{};
+    const int p = out_parity;
+    a.fat_out = reinterpret_cast<const dvec2 *>(g->fat[p]);
+    a.fat_in = reinterpret_cast<const dvec2 *>(g->fat[1 - p]);
+    a.lng_out = reinterpret_cast<const dvec2 *>(g->lng[p]);
+    a.lng_in = reinterpret_cast<const dvec2 *>(g->lng[1 - p]);
+    a.in = reinterpret_cast<const dvec2 *>(in);
+    a.out = reinterpret_cast<dvec2 *>(out);
+    a.aux = reinterpret_cast<const dvec2 *>(aux);
+    a.ca = ca;
+    a.cd = cd;
+    a.geom = g->geom;
+    a.out_parity = p;
+    a.nrhs = nrhs;
+    const int nr = pick_nr(nrhs);
+    a.ngroups = (nrhs + nr - 1) / nr;
+    a.nsb = (g->geom.vh + kBS - 1) / kBS;
+    const bool dot = fin == FIN_CG_ALPHA;
+    if (dot) {
+        a.partials = red->partials;
+        a.counter = red->counter;
+        a.cg = *cg;
+    }
+    const int nblocks = a.nsb * a.ngroups;
+    ProfileScope prof("dslash", s);
+    switch (nr) {
+        case 1: return launch_nr<1>(a, nblocks, aux != nullptr, dot, s);
+        case 2: return launch_nr<2>(a, nblocks, aux != nullptr, dot, s);
+        case 3: return launch_nr<3>(a, nblocks, aux != nullptr, dot, s);
+        case 4: return launch_nr<4>(a, nblocks, aux != nullptr, dot, s);
+        default: return fail(HISQ_ERR_INVALID_ARG, "dslash: bad RHS grouping");
+    }
+}
+
+hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,
+                        int nrhs, hipStream_t s) {
+    void *tmp = nullptr;
+    HISQ_TRY(g->ws.get("mdagm_tmp", sizeof(double2) * 3 * (size_t)g->geom.vh * nrhs, &tmp));
+    double2 *t = static_cast<double2 *>(tmp);
+    HISQ_TRY(launch_dslash(g, 1, in, t, nrhs, nullptr, 0.0, 1.0, FIN_NONE, nullptr, nullptr, s));
+    HISQ_TRY(launch_dslash(g, 0, t, out, nrhs, in, two_m * two_m, -1.0, FIN_NONE, nullptr,
+                           nullptr, s));
+    return HISQ_OK;
+}
+
+}  // namespace hisq

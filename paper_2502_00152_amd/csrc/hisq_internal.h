@@ -1,0 +1,166 @@
+// Internal declarations shared by the libhisq translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hisq.h"
+
+namespace hisq {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    hisq_status status;
+    std::string msg;
+};
+
+void set_error(const std::string &msg);
+hisq_status fail(hisq_status st, const std::string &msg);
+
+#define HISQ_HIP(call)                                                             \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return ::hisq::fail(e_ == hipErrorOutOfMemory ? HISQ_ERR_OOM : HISQ_ERR_HIP, \
+                                std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define HISQ_TRY(expr)                        \
+    do {                                      \
+        hisq_status s_ = (expr);              \
+        if (s_ != HISQ_OK) return s_;         \
+    } while (0)
+
+// --------------------------------------------------------------- geometry
+// Lattice extents and derived sizes, passed by value to kernels.
+struct Geom {
+    int X, Y, Z, T;
+    int Xh;        // X / 2
+    int vh;        // X*Y*Z*T / 2
+};
+
+// ------------------------------------------------------------- workspace
+// Device scratch buffers owned by a gauge handle, grown on demand and kept
+// until the handle is destroyed.
+class Workspace {
+public:
+    ~Workspace();
+    hisq_status get(const char *name, size_t bytes, void **ptr);
+    void release();
+
+private:
+    struct Buf {
+        void *ptr = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Buf> bufs_;
+};
+
+}  // namespace hisq
+
+// The gauge handle: links in kernel layout plus scratch.
+//   fat[p], lng[p]: links living on sites of parity p, complex double SoA
+//   [4 mu][9 = 3x3 row-major][Vh]; the entry (mu, k, cb) is at (mu*9 + k)*Vh + cb.
+struct hisq_gauge_s {
+    hisq::Geom geom;
+    int device = 0;
+    double2 *fat[2] = {nullptr, nullptr};
+    double2 *lng[2] = {nullptr, nullptr};
+    hisq::Workspace ws;
+};
+
+namespace hisq {
+
+// ------------------------------------------------------------ profiling
+// Event-timed launches, per kernel class.
+class ProfileScope {
+public:
+    ProfileScope(const char *cls, hipStream_t s);
+    ~ProfileScope();
+
+private:
+    int slot_ = -1;
+    hipStream_t s_;
+    const char *cls_;
+};
+
+// ------------------------------------------------- CG per-RHS device state
+enum CgStatus : int {
+    CG_ACTIVE = 0,
+    CG_PENDING = 1,     // iterated residual passed: waits for a true-residual check
+    CG_CONVERGED = 2,
+    CG_RESTART = 3,     // true residual failed: p must be rebuilt from the true r
+    CG_MAXITER = 4,
+    CG_BREAKDOWN = 5,
+    CG_NAN = 6,
+};
+
+// Arrays of nrhs entries each, in device memory.
+struct CgDev {
+    double *rho;       // <r, r> of the current residual
+    double *rho_pend;  // iterated <r, r> that triggered a pending check
+    double *alpha;
+    double *beta;
+    double *bnorm2;
+    double *tol2b;     // tol^2 ||b||^2
+    double *true_res2; // last true ||b - A x||^2
+    int *status;
+    int *iters;
+    int *checks;
+    int max_iter;
+};
+
+// Reduction bookkeeping for kernels that end with a fixed-order global sum.
+struct Reduce {
+    double *partials;   // [nvals][nblocks]
+    unsigned *counter;  // arrival counter, zero between launches
+};
+
+// ------------------------------------------------------- kernel launchers
+enum DslashFinal : int {
+    FIN_NONE = 0,
+    FIN_CG_ALPHA = 1,   // alpha = rho / Re<aux, out> per active RHS
+};
+
+// out = ca * aux + cd * D_{p,1-p} in  (aux may be null: then ca is ignored).
+// With fin == FIN_CG_ALPHA, also reduces Re<aux, out> per RHS and sets cg.alpha.
+hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
+                          double2 *out, int nrhs, const double2 *aux, double ca, double cd,
+                          DslashFinal fin, const CgDev *cg, const Reduce *red,
+                          hipStream_t s);
+
+// Number of reduction blocks the dslash launch for (g, nrhs) uses.
+int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs);
+
+// BLAS for CG on parity vectors of n = 3*Vh complex entries per RHS.
+int blas_reduce_blocks(int64_t n);
+hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, double2 *r,
+                    double2 *p, double tol, const CgDev &cg, const Reduce &red,
+                    hipStream_t s);
+hisq_status cg_update(int64_t n, int nrhs, double2 *x, double2 *r, const double2 *p,
+                      const double2 *Ap, const CgDev &cg, const Reduce &red, hipStream_t s);
+hisq_status cg_update_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
+                        hipStream_t s);
+hisq_status cg_true_residual(int64_t n, int nrhs, const double2 *b, const double2 *Ax,
+                             double2 *r, const CgDev &cg, const Reduce &red, bool final_only,
+                             hipStream_t s);
+hisq_status cg_restart_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
+                         const Reduce &red, hipStream_t s);
+
+// Layout conversion.
+hisq_status launch_split(const hisq_gauge_s *g, const double2 *full, double2 *even,
+                         double2 *odd, int nrhs, hipStream_t s);
+hisq_status launch_merge(const hisq_gauge_s *g, const double2 *even, const double2 *odd,
+                         double2 *full, int nrhs, hipStream_t s);
+hisq_status launch_pack_links(const hisq_gauge_s *g, const double2 *canon, double2 *soa[2],
+                              double coef, unsigned flags, bool is_long, hipStream_t s);
+
+// Operators built from dslash.
+hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,
+                        int nrhs, hipStream_t s);
+
+}  // namespace hisq

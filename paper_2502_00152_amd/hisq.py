@@ -1,0 +1,339 @@
+"""Python binding of libhisq (ctypes).  Argument marshalling only.
+
+Every function here has the name of the C entry point it calls (include/hisq.h)
+and takes torch tensors for device buffers; torch supplies memory and the
+current stream, the library does all the work.  There is no CPU fallback: if
+libhisq.so is missing or no GPU is present, calls raise.
+
+Layouts (see include/hisq.h):
+    links          complex128 [4, T, Z, Y, X, 3, 3]  (device)
+    full vectors   complex128 [nrhs, T, Z, Y, X, 3]
+    parity vectors complex128 [nrhs, 3, Vh]          (Vh = X*Y*Z*T/2)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhisq.so")
+
+HISQ_OK = 0
+HISQ_ERR_INVALID_ARG = 1
+HISQ_ERR_HIP = 2
+HISQ_ERR_OOM = 3
+HISQ_ERR_NOT_CONVERGED = 4
+HISQ_ERR_NAN = 5
+HISQ_ERR_BREAKDOWN = 6
+HISQ_ERR_UNSUPPORTED = 7
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED", 5: "NAN",
+                6: "BREAKDOWN", 7: "UNSUPPORTED"}
+
+HISQ_FP64, HISQ_FP32, HISQ_BF16 = 0, 1, 2
+HISQ_GAUGE_FOLD_PHASES = 1
+HISQ_GAUGE_ANTIPERIODIC_T = 2
+ABI_VERSION = 1
+
+# Entry points declared in include/hisq.h (the tests check the library exports them all).
+EXPORTS = (
+    "hisq_last_error", "hisq_abi_version", "hisq_gauge_create", "hisq_gauge_destroy",
+    "hisq_gauge_half_volume", "hisq_spinor_split", "hisq_spinor_merge", "hisq_dslash_eo",
+    "hisq_mdagm", "hisq_prepare_source", "hisq_reconstruct_odd", "hisq_cg_solve",
+    "hisq_deflate", "hisq_eigensolve", "hisq_profile_enable", "hisq_profile_read",
+)
+
+
+class HisqError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CgParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("check_interval", ctypes.c_int), ("sloppy_prec", ctypes.c_int),
+                ("reserved", ctypes.c_int * 8)]
+
+
+class CgStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("true_residual_checks", ctypes.c_int),
+                ("converged", ctypes.c_int), ("reserved0", ctypes.c_int),
+                ("true_residual", ctypes.c_double), ("b_norm", ctypes.c_double)]
+
+
+class EigParams(ctypes.Structure):
+    _fields_ = [("n_kr", ctypes.c_int), ("cheb_degree", ctypes.c_int),
+                ("cheb_a", ctypes.c_double), ("cheb_b", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
+                ("reserved0", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("reserved", ctypes.c_int * 8)]
+
+
+class EigStats(ctypes.Structure):
+    _fields_ = [("restarts", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("converged", ctypes.c_int), ("cheb_degree", ctypes.c_int),
+                ("cheb_a", ctypes.c_double), ("cheb_b", ctypes.c_double),
+                ("lambda_max", ctypes.c_double), ("max_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhisq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2502_00152_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
+    sigs = {
+        "hisq_last_error": ([], ctypes.c_char_p),
+        "hisq_abi_version": ([], I),
+        "hisq_gauge_create": ([ctypes.POINTER(P), ctypes.POINTER(I), P, P, D, D, U, P], I),
+        "hisq_gauge_destroy": ([P], I),
+        "hisq_gauge_half_volume": ([P], ctypes.c_int64),
+        "hisq_spinor_split": ([P, P, P, P, I, P], I),
+        "hisq_spinor_merge": ([P, P, P, P, I, P], I),
+        "hisq_dslash_eo": ([P, I, P, P, I, I, P], I),
+        "hisq_mdagm": ([P, D, P, P, I, I, P], I),
+        "hisq_prepare_source": ([P, D, P, P, P, I, P], I),
+        "hisq_reconstruct_odd": ([P, D, P, P, P, I, P], I),
+        "hisq_cg_solve": ([P, D, P, P, I, ctypes.POINTER(CgParams), ctypes.POINTER(CgStats),
+                           P], I),
+        "hisq_deflate": ([P, I, P, ctypes.POINTER(D), D, P, P, I, P], I),
+        "hisq_eigensolve": ([P, D, I, ctypes.POINTER(EigParams), P, ctypes.POINTER(D),
+                             ctypes.POINTER(EigStats), P], I),
+        "hisq_profile_enable": ([I], I),
+        "hisq_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(D)], I),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name, None)
+        if fn is None:
+            continue
+        fn.argtypes = args
+        fn.restype = res
+    if L.hisq_abi_version() != ABI_VERSION:
+        raise RuntimeError("libhisq ABI version mismatch: rebuild the library")
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str, ok=(HISQ_OK,)):
+    if status not in ok:
+        raise HisqError(status, where, lib().hisq_last_error().decode())
+    return status
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, name, dtype_ok=("complex128",)):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if str(t.dtype).replace("torch.", "") not in dtype_ok:
+        raise TypeError(f"{name} must have dtype {dtype_ok}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ sizes
+def vector_bytes(dims, n_vectors: int, single_parity: bool = True, prec: int = HISQ_FP64) -> int:
+    """Bytes of n colour-vector fields: 3 complex per site, 8/4/2 bytes per real."""
+    V = int(np.prod([int(d) for d in dims]))
+    sites = V // 2 if single_parity else V
+    real = {HISQ_FP64: 8, HISQ_FP32: 4, HISQ_BF16: 2}[prec]
+    return sites * n_vectors * 3 * 2 * real
+
+
+# ------------------------------------------------------------------ gauge
+class Gauge:
+    """Owns a hisq_gauge handle."""
+
+    def __init__(self, dims, fat, lng, c_fat=1.0, c_long=1.0,
+                 flags=HISQ_GAUGE_FOLD_PHASES | HISQ_GAUGE_ANTIPERIODIC_T, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.handle = hisq_gauge_create(self.dims, fat, lng, c_fat, c_long, flags, stream)
+        self.vh = int(lib().hisq_gauge_half_volume(self.handle))
+
+    def close(self):
+        if self.handle:
+            hisq_gauge_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _h(g):
+    return g.handle if isinstance(g, Gauge) else g
+
+
+def _nrhs(t, vh, name):
+    if t.dim() != 3 or t.shape[1] != 3 or t.shape[2] != vh:
+        raise ValueError(f"{name} must have shape [nrhs, 3, {vh}], got {tuple(t.shape)}")
+    return int(t.shape[0])
+
+
+def hisq_gauge_create(dims, fat, lng, c_fat, c_long, flags, stream=None):
+    X, Y, Z, T = (int(d) for d in dims)
+    for t, nm in ((fat, "fat"), (lng, "long")):
+        if tuple(t.shape) != (4, T, Z, Y, X, 3, 3):
+            raise ValueError(f"{nm} links must have shape [4,T,Z,Y,X,3,3]")
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int * 4)(X, Y, Z, T)
+    _check(lib().hisq_gauge_create(ctypes.byref(h), d, _ptr(fat, "fat"), _ptr(lng, "long"),
+                                   float(c_fat), float(c_long), int(flags), _stream(stream)),
+           "hisq_gauge_create")
+    return h
+
+
+def hisq_gauge_destroy(handle):
+    _check(lib().hisq_gauge_destroy(handle), "hisq_gauge_destroy")
+
+
+def hisq_spinor_split(g, full, even, odd, stream=None):
+    nrhs = int(full.shape[0])
+    _check(lib().hisq_spinor_split(_h(g), _ptr(full, "full"),
+                                   None if even is None else _ptr(even, "even"),
+                                   None if odd is None else _ptr(odd, "odd"), nrhs,
+                                   _stream(stream)), "hisq_spinor_split")
+
+
+def hisq_spinor_merge(g, even, odd, full, stream=None):
+    nrhs = int(full.shape[0])
+    _check(lib().hisq_spinor_merge(_h(g), None if even is None else _ptr(even, "even"),
+                                   None if odd is None else _ptr(odd, "odd"),
+                                   _ptr(full, "full"), nrhs, _stream(stream)),
+           "hisq_spinor_merge")
+
+
+def hisq_dslash_eo(g, out_parity, inp, out, prec=HISQ_FP64, stream=None):
+    nrhs = _nrhs(inp, g.vh, "in")
+    if _nrhs(out, g.vh, "out") != nrhs:
+        raise ValueError("in and out must have the same nrhs")
+    _check(lib().hisq_dslash_eo(_h(g), int(out_parity), _ptr(inp, "in"), _ptr(out, "out"),
+                                nrhs, int(prec), _stream(stream)), "hisq_dslash_eo")
+
+
+def hisq_mdagm(g, two_m, inp, out, prec=HISQ_FP64, stream=None):
+    nrhs = _nrhs(inp, g.vh, "in")
+    if _nrhs(out, g.vh, "out") != nrhs:
+        raise ValueError("in and out must have the same nrhs")
+    _check(lib().hisq_mdagm(_h(g), float(two_m), _ptr(inp, "in"), _ptr(out, "out"), nrhs,
+                            int(prec), _stream(stream)), "hisq_mdagm")
+
+
+def hisq_prepare_source(g, two_m, eta_e, eta_o, y_e, stream=None):
+    nrhs = _nrhs(eta_e, g.vh, "eta_e")
+    for t, nm in ((eta_o, "eta_o"), (y_e, "y_e")):
+        if _nrhs(t, g.vh, nm) != nrhs:
+            raise ValueError("all vectors must have the same nrhs")
+    _check(lib().hisq_prepare_source(_h(g), float(two_m), _ptr(eta_e, "eta_e"),
+                                     _ptr(eta_o, "eta_o"), _ptr(y_e, "y_e"), nrhs,
+                                     _stream(stream)), "hisq_prepare_source")
+
+
+def hisq_reconstruct_odd(g, two_m, psi_e, eta_o, psi_o, stream=None):
+    nrhs = _nrhs(psi_e, g.vh, "psi_e")
+    for t, nm in ((eta_o, "eta_o"), (psi_o, "psi_o")):
+        if _nrhs(t, g.vh, nm) != nrhs:
+            raise ValueError("all vectors must have the same nrhs")
+    _check(lib().hisq_reconstruct_odd(_h(g), float(two_m), _ptr(psi_e, "psi_e"),
+                                      _ptr(eta_o, "eta_o"), _ptr(psi_o, "psi_o"), nrhs,
+                                      _stream(stream)), "hisq_reconstruct_odd")
+
+
+@dataclass
+class CgResult:
+    status: int
+    iterations: list
+    true_residual: list
+    converged: list
+    checks: list
+    b_norm: list
+
+
+def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
+                  sloppy_prec=HISQ_FP64, stream=None, raise_on_fail=True) -> CgResult:
+    nrhs = _nrhs(b, g.vh, "b")
+    if _nrhs(x, g.vh, "x") != nrhs:
+        raise ValueError("b and x must have the same nrhs")
+    p = CgParams(tol=float(tol), max_iter=int(max_iter), check_interval=int(check_interval),
+                 sloppy_prec=int(sloppy_prec))
+    stats = (CgStats * nrhs)()
+    st = lib().hisq_cg_solve(_h(g), float(two_m), _ptr(b, "b"), _ptr(x, "x"), nrhs,
+                             ctypes.byref(p), stats, _stream(stream))
+    if raise_on_fail:
+        _check(st, "hisq_cg_solve")
+    elif st not in (HISQ_OK, HISQ_ERR_NOT_CONVERGED, HISQ_ERR_NAN, HISQ_ERR_BREAKDOWN):
+        _check(st, "hisq_cg_solve")
+    return CgResult(st, [s.iterations for s in stats], [s.true_residual for s in stats],
+                    [bool(s.converged) for s in stats], [s.true_residual_checks for s in stats],
+                    [s.b_norm for s in stats])
+
+
+def hisq_deflate(g, evecs, evals, two_m, b, x0, stream=None):
+    n_ev = _nrhs(evecs, g.vh, "evecs")
+    nrhs = _nrhs(b, g.vh, "b")
+    if _nrhs(x0, g.vh, "x0") != nrhs:
+        raise ValueError("b and x0 must have the same nrhs")
+    ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+    if ev.shape != (n_ev,):
+        raise ValueError("evals must have one entry per eigenvector")
+    _check(lib().hisq_deflate(_h(g), n_ev, _ptr(evecs, "evecs"),
+                              ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(two_m),
+                              _ptr(b, "b"), _ptr(x0, "x0"), nrhs, _stream(stream)),
+           "hisq_deflate")
+
+
+def hisq_eigensolve(g, two_m, n_ev, evecs, n_kr=0, cheb_degree=0, cheb_a=0.0, cheb_b=0.0,
+                    tol=1e-10, max_restarts=0, seed=0, stream=None, raise_on_fail=True):
+    if _nrhs(evecs, g.vh, "evecs") != n_ev:
+        raise ValueError("evecs must hold n_ev vectors")
+    p = EigParams(n_kr=int(n_kr), cheb_degree=int(cheb_degree), cheb_a=float(cheb_a),
+                  cheb_b=float(cheb_b), tol=float(tol), max_restarts=int(max_restarts),
+                  seed=int(seed))
+    evals = np.zeros(n_ev, dtype=np.float64)
+    stats = EigStats()
+    st = lib().hisq_eigensolve(_h(g), float(two_m), int(n_ev), ctypes.byref(p),
+                               _ptr(evecs, "evecs"),
+                               evals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(stats), _stream(stream))
+    if raise_on_fail:
+        _check(st, "hisq_eigensolve")
+    return st, evals, stats
+
+
+def hisq_profile_enable(on: bool):
+    _check(lib().hisq_profile_enable(1 if on else 0), "hisq_profile_enable")
+
+
+def hisq_profile_read(kernel_class: str):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib().hisq_profile_read(kernel_class.encode(), ctypes.byref(n), ctypes.byref(ms)),
+           "hisq_profile_read")
+    return int(n.value), float(ms.value)

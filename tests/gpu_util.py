@@ -1,0 +1,96 @@
+"""Helpers of the GPU parity tests: independent layout conversion (numpy) and
+building the same synthetic problem for the GPU library and the oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import hisq_oracle as O
+from paper_2502_00152_amd import inputs as I
+
+FLAGS = 3  # fold staggered phases + antiperiodic time
+
+
+def parity_lex(dims, p):
+    X, Y, Z, T = dims
+    lex = np.arange(X * Y * Z * T)
+    x = lex % X
+    y = (lex // X) % Y
+    z = (lex // (X * Y)) % Z
+    t = lex // (X * Y * Z)
+    return lex[((x + y + z + t) % 2) == p]
+
+
+def to_parity(full, dims, p):
+    """full [nrhs][T][Z][Y][X][3] (or without nrhs) -> [nrhs][3][Vh] of parity p."""
+    f = np.asarray(full)
+    if f.ndim == 5:
+        f = f[None]
+    n = f.shape[0]
+    V = int(np.prod(dims))
+    flat = f.reshape(n, V, 3)
+    lex = parity_lex(dims, p)
+    out = np.zeros((n, 3, V // 2), dtype=np.complex128)
+    out[:, :, lex >> 1] = flat[:, lex, :].transpose(0, 2, 1)
+    return out
+
+
+def from_parity(soa, dims, p):
+    """[nrhs][3][Vh] of parity p -> full [nrhs][T][Z][Y][X][3], zero elsewhere."""
+    s = np.asarray(soa)
+    n = s.shape[0]
+    X, Y, Z, T = dims
+    V = X * Y * Z * T
+    lex = parity_lex(dims, p)
+    flat = np.zeros((n, V, 3), dtype=np.complex128)
+    flat[:, lex, :] = s[:, :, lex >> 1].transpose(0, 2, 1)
+    return flat.reshape(n, T, Z, Y, X, 3)
+
+
+class Problem:
+    """Seeded links for both sides: raw SU(3) draws for the GPU (which folds the
+    phases itself) and oracle-folded links for the oracle."""
+
+    def __init__(self, dims, eps, seed_fat, seed_long, c_fat=I.C_FAT, c_long=I.C_LONG,
+                 free=False):
+        self.dims = tuple(dims)
+        if free:
+            self.W = I.unit_links(dims)
+            self.N = I.unit_links(dims)
+        else:
+            self.W = I.random_su3_field(dims, eps, seed_fat)
+            self.N = I.random_su3_field(dims, eps, seed_long)
+        self.c_fat, self.c_long = c_fat, c_long
+        self.F, self.L = O.fold_links(self.W, self.N, c_fat, c_long)
+
+    @classmethod
+    def from_config(cls, c):
+        cfg = I.config(c)
+        return cls(cfg["dims"], cfg["eps"], cfg["seed_fat"], cfg["seed_long"])
+
+    def gauge(self):
+        import torch
+        from paper_2502_00152_amd import hisq
+        W = torch.from_numpy(self.W).cuda()
+        N = torch.from_numpy(self.N).cuda()
+        g = hisq.Gauge(self.dims, W, N, self.c_fat, self.c_long, FLAGS)
+        torch.cuda.synchronize()
+        del W, N
+        return g
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_per_rhs(got, ref):
+    got = np.asarray(got).reshape(got.shape[0], -1)
+    ref = np.asarray(ref).reshape(ref.shape[0], -1)
+    return [np.linalg.norm(got[i] - ref[i]) / max(np.linalg.norm(ref[i]), 1e-300)
+            for i in range(ref.shape[0])]

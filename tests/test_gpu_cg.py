@@ -1,0 +1,145 @@
+"""GPU parity of hisq_cg_solve against the oracle CG (section 2: even-odd CG on
+the normal equation, true-residual stopping test).
+
+Bar: the oracle-evaluated FP64 true residual of the GPU solution meets tol;
+the solution matches the oracle's (solved to 1e-13) to 1e-9 relative when the
+GPU solve is tightened to 1e-9/kappa; iteration counts agree with the oracle's
+to max(2, 1%).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import hisq_oracle as O
+from paper_2502_00152_amd import inputs as I
+from tests.gpu_util import Problem, dev, from_parity, host, rel_per_rhs, to_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_true_residual(pr, two_m, x_soa, b_soa):
+    out = []
+    for j in range(b_soa.shape[0]):
+        x = from_parity(x_soa[j:j + 1], pr.dims, 0)[0]
+        b = from_parity(b_soa[j:j + 1], pr.dims, 0)[0]
+        out.append(O.norm(b - O.apply_A(pr.F, pr.L, two_m, x)) / O.norm(b))
+    return out
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    cfg = I.config(0)
+    pr = Problem.from_config(0)
+    pr.g = pr.gauge()
+    eta = I.gaussian_source(cfg["dims"], cfg["seed_src"][0])
+    pr.two_m = cfg["two_m"]
+    pr.y = O.source_even(pr.F, pr.L, pr.two_m, eta)
+    yield pr
+    pr.g.close()
+
+
+def test_cg_config0_iterations_and_residual(cfg0):
+    """8^4, eps 0.3, 2m = 0.1, one Gaussian source, tol 1e-10."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = cfg0
+    b = dev(to_parity(pr.y, pr.dims, 0))
+    x = torch.zeros_like(b)
+    res = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=1e-10)
+    assert res.converged == [True]
+    _, it_oracle, _ = O.solve_even(pr.F, pr.L, pr.two_m, pr.y, tol=1e-10)
+    assert abs(res.iterations[0] - it_oracle) <= max(2, 0.01 * it_oracle)
+    tr = oracle_true_residual(pr, pr.two_m, host(x), host(b))
+    assert tr[0] <= 1e-10
+    assert abs(res.true_residual[0] - tr[0]) <= 1e-3 * tr[0] + 1e-16
+
+
+def test_cg_config0_solution_matches_oracle(cfg0):
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = cfg0
+    b = dev(to_parity(pr.y, pr.dims, 0))
+    x = torch.zeros_like(b)
+    hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=1e-12)
+    ref, _, res = O.solve_even(pr.F, pr.L, pr.two_m, pr.y, tol=1e-13)
+    assert res <= 1e-13
+    assert rel_per_rhs(host(x), to_parity(ref, pr.dims, 0))[0] <= 1e-9
+
+
+def test_cg_batched_equals_single_and_is_reproducible():
+    """Each RHS follows its own recurrence with fixed-order reductions, so a
+    batched solve is bitwise identical to solving the RHS one at a time, and
+    to itself run again.  One RHS is zero (x = 0, no iterations)."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (4, 6, 8, 10)
+    pr = Problem(dims, 0.5, 2001, 2002)
+    g = pr.gauge()
+    two_m = 0.05
+    etas = [I.gaussian_source(dims, 300 + j) for j in range(5)]
+    y = np.concatenate([to_parity(O.source_even(pr.F, pr.L, two_m, e), dims, 0) for e in etas])
+    y[2] = 0
+    b = dev(y)
+    x = torch.zeros_like(b)
+    x[2] = 1.0  # b = 0 must give x = 0 whatever the guess
+    res = hisq.hisq_cg_solve(g, two_m, b, x, tol=1e-10)
+    assert all(res.converged)
+    assert res.iterations[2] == 0
+    xb = host(x)
+    assert not xb[2].any()
+    x2 = torch.zeros_like(b)
+    x2[2] = 1.0
+    hisq.hisq_cg_solve(g, two_m, b, x2, tol=1e-10)
+    assert np.array_equal(host(x2), xb)
+    for j in (0, 3, 4):
+        xs = torch.zeros((1, 3, g.vh), dtype=torch.complex128, device="cuda")
+        r1 = hisq.hisq_cg_solve(g, two_m, b[j:j + 1].clone(), xs, tol=1e-10)
+        assert r1.iterations[0] == res.iterations[j]
+        assert np.array_equal(host(xs)[0], xb[j])
+    tr = oracle_true_residual(pr, two_m, xb[[0, 1, 3, 4]], y[[0, 1, 3, 4]])
+    assert max(tr) <= 1e-10
+    g.close()
+
+
+def test_cg_exact_guess_and_iteration_limit():
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (4, 4, 4, 4)
+    pr = Problem(dims, 0.4, 2101, 2102)
+    g = pr.gauge()
+    two_m = 0.2
+    y = to_parity(I.gaussian_source(dims, 3), dims, 0)
+    A = O.dense_A(pr.F, pr.L, two_m)
+    # compact order of the oracle -> parity layout
+    xc = np.linalg.solve(A, O.to_compact(from_parity(y, dims, 0)[0], dims))
+    x_exact = to_parity(O.from_compact(xc, dims), dims, 0)
+    b = dev(y)
+    x = dev(x_exact)
+    res = hisq.hisq_cg_solve(g, two_m, b, x, tol=1e-10)
+    assert res.iterations == [0] and res.converged == [True]
+    x = torch.zeros_like(b)
+    res = hisq.hisq_cg_solve(g, two_m, b, x, tol=1e-14, max_iter=3, raise_on_fail=False)
+    assert res.status == hisq.HISQ_ERR_NOT_CONVERGED
+    assert res.iterations == [3] and res.converged == [False]
+    _, it, tr = O.solve_even(pr.F, pr.L, two_m, from_parity(y, dims, 0)[0], tol=1e-14, max_iter=3)
+    assert abs(res.true_residual[0] - tr) <= 1e-10 * tr
+    g.close()
+
+
+@pytest.mark.parametrize("interval", [1, 5, 64])
+def test_cg_check_interval_does_not_change_iterates(interval):
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (4, 4, 6, 8)
+    pr = Problem(dims, 0.5, 2201, 2202)
+    g = pr.gauge()
+    y = np.concatenate([to_parity(I.gaussian_source(dims, 40 + j), dims, 0) for j in range(3)])
+    b = dev(y)
+    x = torch.zeros_like(b)
+    ref = torch.zeros_like(b)
+    r0 = hisq.hisq_cg_solve(g, 0.05, b, ref, tol=1e-10, check_interval=16)
+    r1 = hisq.hisq_cg_solve(g, 0.05, b, x, tol=1e-10, check_interval=interval)
+    assert r0.iterations == r1.iterations
+    assert np.array_equal(host(x), host(ref))
+    g.close()
