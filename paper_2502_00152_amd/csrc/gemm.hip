@@ -1,0 +1,300 @@
+// Complex tall-skinny contractions on the FP64 matrix cores (gfx950
+// v_mfma_f64_16x16x4f64), used by the deflation projection (Eq. (4) of
+// arXiv:2502.00152: coefficients V^H b, then x0 = V c) and by the
+// eigensolver's Gram-Schmidt, Rayleigh-Ritz and basis rotation blocks.
+//
+// Vectors are columns of length N = 3*Vh complex, stored one after another
+// (column j at offset j*N complex); each complex is (re, im) doubles, so a
+// column is 2N reals.
+//
+//   gemm_tn:  C[j][i] = sum_s conj(V[i][s]) B[j][s]          (k x n, reduction over N)
+//   gemm_nn:  X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i] (N x n, k summed)
+//
+// Real forms.  With v = V[i][s], b = B[j][s]:
+//   Re conj(v) b = vr br + vi bi,   Im conj(v) b = vr bi - vi br
+// so over the interleaved reals of the columns, Re C = V~^T B~ and
+// Im C = V~^T B~' where B~' is B~ with each (re, im) pair mapped to (im, -re).
+// gemm_tn therefore multiplies a k x 2N real matrix by a 2N x 2n one, the 2n
+// columns being the n right-hand sides read twice.  The matrix core's K
+// dimension (4 per instruction) runs over the 2N reals; each lane loads 4
+// consecutive reals of one column and the instruction's K slots are assigned
+// so that A and B use the same permutation of the reduction index.
+//
+// Output layout of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l,
+// accumulator register r holds C[4r + l/16][l%16]; lane l supplies
+// A[l%16][l/16] and B[l/16][l%16].
+#include "device_util.h"
+#include "hisq_internal.h"
+
+namespace hisq {
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kBS = 256;        // 4 waves
+constexpr int kStep = 16;       // reals of the reduction index per wave step
+
+__device__ __forceinline__ dvec4 mfma(double a, double b, dvec4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------- tn
+// Grid: x = reduction chunks, y = 64-column tiles of V (i), z = 32-column
+// tiles of the real right-hand-side columns (2n).
+// partials: [gridDim.x][kpad][ncpad] doubles.
+struct TnArgs {
+    const double *V;   // k columns of 2N reals
+    const double *B;   // n columns of 2N reals
+    double *partials;
+    int64_t twoN;      // reals per column
+    int k, n;
+    int kpad, ncpad;   // multiples of 16
+    int64_t steps;     // twoN / kStep
+};
+
+template <int MT, int NT>
+__global__ __launch_bounds__(kBS) void k_gemm_tn(TnArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, q = lane >> 4;
+    const int i0 = blockIdx.y * (16 * MT);
+    const int j0 = blockIdx.z * (16 * NT);
+    dvec4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = dvec4{0, 0, 0, 0};
+
+    // column pointers of this lane (null when past the end: contributes 0)
+    const double *vcol[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int i = i0 + 16 * m + lr;
+        vcol[m] = i < a.k ? a.V + (int64_t)i * a.twoN : nullptr;
+    }
+    const double *bcol[NT];
+    bool imag_part[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int j = j0 + 16 * t + lr;  // real column index in [0, 2n)
+        imag_part[t] = j >= a.n;
+        const int jj = imag_part[t] ? j - a.n : j;
+        bcol[t] = j < 2 * a.n ? a.B + (int64_t)jj * a.twoN : nullptr;
+    }
+
+    // the block owns steps [s0, s1), its waves interleave
+    const int64_t per = (a.steps + gridDim.x - 1) / gridDim.x;
+    const int64_t s0 = blockIdx.x * per;
+    const int64_t s1 = min(a.steps, s0 + per);
+    for (int64_t s = s0 + wave; s < s1; s += 4) {
+        const int64_t off = s * kStep + 4 * q;
+        double av[MT][4], bv[NT][4];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (vcol[m]) {
+                const dvec2 x0 = *reinterpret_cast<const dvec2 *>(vcol[m] + off);
+                const dvec2 x1 = *reinterpret_cast<const dvec2 *>(vcol[m] + off + 2);
+                av[m][0] = x0.x; av[m][1] = x0.y; av[m][2] = x1.x; av[m][3] = x1.y;
+            } else {
+                av[m][0] = av[m][1] = av[m][2] = av[m][3] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (bcol[t]) {
+                const dvec2 y0 = *reinterpret_cast<const dvec2 *>(bcol[t] + off);
+                const dvec2 y1 = *reinterpret_cast<const dvec2 *>(bcol[t] + off + 2);
+                if (imag_part[t]) {
+                    // (re, im) -> (im, -re)
+                    bv[t][0] = y0.y; bv[t][1] = -y0.x; bv[t][2] = y1.y; bv[t][3] = -y1.x;
+                } else {
+                    bv[t][0] = y0.x; bv[t][1] = y0.y; bv[t][2] = y1.x; bv[t][3] = y1.y;
+                }
+            } else {
+                bv[t][0] = bv[t][1] = bv[t][2] = bv[t][3] = 0.0;
+            }
+        }
+        // K slot q of sub-step u <-> real index off_q + u: the same map for A and B
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[m][t] = mfma(av[m][u], bv[t][u], acc[m][t]);
+    }
+
+    // sum the four waves in a fixed order through LDS, then store the partial tile
+    __shared__ double lds[4][MT * NT * 4][64];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds[wave][(m * NT + t) * 4 + r][lane] = acc[m][t][r];
+    __syncthreads();
+    double *P = a.partials + (int64_t)blockIdx.x * a.kpad * a.ncpad;
+    for (int e = threadIdx.x; e < MT * NT * 4 * 64; e += kBS) {
+        const int slot = e / 64, ln = e % 64;
+        const double v = ((lds[0][slot][ln] + lds[1][slot][ln]) + lds[2][slot][ln]) + lds[3][slot][ln];
+        const int mt = slot / (NT * 4), t = (slot / 4) % NT, r = slot % 4;
+        const int i = i0 + 16 * mt + 4 * r + (ln >> 4);
+        const int j = j0 + 16 * t + (ln & 15);
+        if (i < a.kpad && j < a.ncpad) P[(int64_t)i * a.ncpad + j] = v;
+    }
+}
+
+// C[j][i] (complex, [n][k] row-major) = scale_i * sum_b partials[b][i][j or n+j]
+// in block order; C is written as C = out_scale * C (+ previous when accumulate).
+__global__ __launch_bounds__(kBS) void k_tn_reduce(const double *__restrict__ partials, int nb,
+                                                   int k, int n, int kpad, int ncpad,
+                                                   const double *__restrict__ row_scale,
+                                                   double out_scale, dvec2 *__restrict__ C) {
+    const int e = blockIdx.x * kBS + threadIdx.x;
+    if (e >= k * n) return;
+    const int j = e / k, i = e % k;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double *P = partials + (int64_t)b * kpad * ncpad + (int64_t)i * ncpad;
+        re += P[j];
+        im += P[n + j];
+    }
+    double s = out_scale;
+    if (row_scale) s *= row_scale[i];
+    C[(int64_t)j * k + i] = dvec2{re * s, im * s};
+}
+
+// ------------------------------------------------------------------- nn
+// X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i].  Transposed real form:
+// X~^T (n x 2N) = C_big^T (n x 2k) * V_big^T (2k x 2N) with
+// V_big[2s+c][2i+d] = (c,d) = (0,0): vr, (0,1): -vi, (1,0): vi, (1,1): vr and
+// C_big[2i][j] = Re C[j][i], C_big[2i+1][j] = Im C[j][i].
+// Output rows are right-hand sides (16 per tile), output columns 16 reals of
+// X (8 sites): each store instruction writes 128 contiguous bytes per RHS.
+// Grid: x = column tiles (grid-stride), y = groups of 16*MT right-hand sides.
+struct NnArgs {
+    const double *V;      // k columns of 2N reals
+    const dvec2 *C;       // [n][k] complex coefficients
+    double *X;            // n columns of 2N reals
+    int64_t twoN;
+    int k, n;
+    double beta;
+    int64_t tiles;        // twoN / 16
+};
+
+template <int MT>
+__global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, q = lane >> 4;
+    const int jbase = blockIdx.y * (16 * MT);
+    const int c = lr & 1;   // 0: real row, 1: imaginary row of this lane's output column
+    const int dsel = q & 1; // K slot parity: 0 -> Re part of C / (vr | vi), 1 -> Im part
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < a.tiles;
+         tile += (int64_t)gridDim.x * 4) {
+        const int64_t col = tile * 16 + lr;     // real index in a column of X
+        const int64_t site = col >> 1;          // complex index
+        dvec4 acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = dvec4{0, 0, 0, 0};
+        // each MFMA consumes two eigenvectors: slot q <-> (i0 + (q >> 1), d = q & 1)
+        for (int i0 = 0; i0 < a.k; i0 += 2) {
+            const int i = i0 + (q >> 1);
+            double bval = 0.0;
+            if (i < a.k) {
+                const dvec2 v = *reinterpret_cast<const dvec2 *>(a.V + (int64_t)i * a.twoN + 2 * site);
+                // V_big[2s+c][2i+d]
+                bval = c == 0 ? (dsel == 0 ? v.x : -v.y) : (dsel == 0 ? v.y : v.x);
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int j = jbase + 16 * m + lr;  // A operand row = right-hand side
+                double aval = 0.0;
+                if (j < a.n && i < a.k) {
+                    const dvec2 cc = a.C[(int64_t)j * a.k + i];
+                    aval = dsel == 0 ? cc.x : cc.y;
+                }
+                acc[m] = mfma(aval, bval, acc[m]);
+            }
+        }
+        // acc[m][r] = X~^T[jbase + 16m + 4r + q][tile*16 + lr]
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jbase + 16 * m + 4 * r + q;
+                if (j < a.n) {
+                    double *dst = a.X + (int64_t)j * a.twoN + tile * 16 + lr;
+                    double v = acc[m][r];
+                    if (a.beta != 0.0) v = fma(a.beta, *dst, v);
+                    *dst = v;
+                }
+            }
+    }
+}
+
+int round16(int v) { return (v + 15) / 16 * 16; }
+
+}  // namespace
+
+// C = out_scale * diag(row_scale) * V^H B   (C complex [n][k] on the device)
+hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, int n,
+                    int64_t N, const double *row_scale_dev, double out_scale, double2 *C,
+                    hipStream_t s) {
+    TnArgs a{};
+    a.V = reinterpret_cast<const double *>(V);
+    a.B = reinterpret_cast<const double *>(B);
+    a.twoN = 2 * N;
+    a.k = k;
+    a.n = n;
+    a.kpad = round16(k);
+    a.ncpad = round16(2 * n);
+    if (a.twoN % kStep) return fail(HISQ_ERR_INVALID_ARG, "gemm_tn: 2N must be a multiple of 16");
+    a.steps = a.twoN / kStep;
+    // MT = 4 (64 rows of C per block), NT = 2 (32 real columns)
+    const int mtiles = (a.kpad + 63) / 64, ntiles = (a.ncpad + 31) / 32;
+    int64_t nbx = (a.steps + 63) / 64;  // about 16 steps per wave
+    nbx = std::max<int64_t>(1, std::min<int64_t>(nbx, 1024));
+    void *p = nullptr;
+    HISQ_TRY(g->ws.get("gemm_partials", sizeof(double) * nbx * a.kpad * a.ncpad, &p));
+    a.partials = static_cast<double *>(p);
+    {
+        ProfileScope prof("gemm", s);
+        hipLaunchKernelGGL((k_gemm_tn<4, 2>), dim3((unsigned)nbx, mtiles, ntiles), dim3(kBS), 0, s,
+                           a);
+        HISQ_HIP(hipGetLastError());
+    }
+    const int tot = k * n;
+    hipLaunchKernelGGL(k_tn_reduce, dim3((tot + kBS - 1) / kBS), dim3(kBS), 0, s, a.partials,
+                       (int)nbx, k, n, a.kpad, a.ncpad, row_scale_dev, out_scale,
+                       reinterpret_cast<dvec2 *>(C));
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+// X = beta X + V C   (C complex [n][k] on the device)
+hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N, double beta,
+                    double2 *X, hipStream_t s) {
+    NnArgs a{};
+    a.V = reinterpret_cast<const double *>(V);
+    a.C = reinterpret_cast<const dvec2 *>(C);
+    a.X = reinterpret_cast<double *>(X);
+    a.twoN = 2 * N;
+    a.k = k;
+    a.n = n;
+    a.beta = beta;
+    if (a.twoN % 16) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: 2N must be a multiple of 16");
+    a.tiles = a.twoN / 16;
+    int64_t nbx = (a.tiles + 3) / 4;
+    nbx = std::max<int64_t>(1, std::min<int64_t>(nbx, 2048));
+    ProfileScope prof("gemm", s);
+    if (n <= 16) {
+        hipLaunchKernelGGL((k_gemm_nn<1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
+    } else {
+        const int groups = (n + 63) / 64;
+        hipLaunchKernelGGL((k_gemm_nn<4>), dim3((unsigned)nbx, groups), dim3(kBS), 0, s, a);
+    }
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+}  // namespace hisq

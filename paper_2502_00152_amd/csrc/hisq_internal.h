@@ -159,6 +159,15 @@ hisq_status launch_merge(const hisq_gauge_s *g, const double2 *even, const doubl
 hisq_status launch_pack_links(const hisq_gauge_s *g, const double2 *canon, double2 *soa[2],
                               double coef, unsigned flags, bool is_long, hipStream_t s);
 
+// Complex tall-skinny contractions on the FP64 matrix cores (columns of N complex).
+// C[j][i] = out_scale * row_scale[i] * sum_s conj(V[i][s]) B[j][s]   (C: [n][k] complex)
+hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, int n,
+                    int64_t N, const double *row_scale_dev, double out_scale, double2 *C,
+                    hipStream_t s);
+// X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i]
+hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N, double beta,
+                    double2 *X, hipStream_t s);
+
 // Operators built from dslash.
 hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,
                         int nrhs, hipStream_t s);
