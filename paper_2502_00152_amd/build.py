@@ -2,7 +2,7 @@
 
     python -m paper_2502_00152_amd.build [-v]
 
-Every .hip file under csrc/ is compiled to an object in _build/ and linked into
+Every .hip (device + host) and .cpp (host-only) file under csrc/ is compiled to an object in _build/ and linked into
 paper_2502_00152_amd/libhisq.so.  Always rebuilds.
 """
 from __future__ import annotations
@@ -42,7 +42,11 @@ COMMON = [
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + COMMON + ["-c", src, "-o", obj]
+    if src.endswith(".cpp"):  # host-only C++
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC,
+               "-c", src, "-o", obj]
+    else:
+        cmd = [hipcc()] + COMMON + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,7 +61,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
     tmp = LIB + ".tmp"

@@ -152,7 +152,7 @@ hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev, voi
     HISQ_TRY(check_vec(out_dev, "out_dev"));
     if (in_dev == out_dev) return fail(HISQ_ERR_INVALID_ARG, "in and out must not overlap");
     return launch_dslash(g, out_parity, static_cast<const double2 *>(in_dev),
-                         static_cast<double2 *>(out_dev), nrhs, nullptr, 0.0, 1.0, FIN_NONE,
+                         static_cast<double2 *>(out_dev), nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
                          nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
@@ -181,7 +181,7 @@ hisq_status hisq_prepare_source(hisq_gauge g, double two_m, const void *eta_e_de
     // y_e = 2m eta_e - D_eo eta_o
     return launch_dslash(g, 0, static_cast<const double2 *>(eta_o_dev),
                          static_cast<double2 *>(y_e_dev), nrhs,
-                         static_cast<const double2 *>(eta_e_dev), two_m, -1.0, FIN_NONE, nullptr,
+                         static_cast<const double2 *>(eta_e_dev), two_m, nullptr, 0.0, -1.0, FIN_NONE, nullptr,
                          nullptr, static_cast<hipStream_t>(stream));
 }
 
@@ -199,7 +199,7 @@ hisq_status hisq_reconstruct_odd(hisq_gauge g, double two_m, const void *psi_e_d
     const double inv = 1.0 / two_m;
     return launch_dslash(g, 1, static_cast<const double2 *>(psi_e_dev),
                          static_cast<double2 *>(psi_o_dev), nrhs,
-                         static_cast<const double2 *>(eta_o_dev), inv, -inv, FIN_NONE, nullptr,
+                         static_cast<const double2 *>(eta_o_dev), inv, nullptr, 0.0, -inv, FIN_NONE, nullptr,
                          nullptr, static_cast<hipStream_t>(stream));
 }
 

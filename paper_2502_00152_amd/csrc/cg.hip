@@ -146,9 +146,9 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     const double m2 = two_m * two_m;
 
     auto iterate = [&]() -> hisq_status {
-        HISQ_TRY(launch_dslash(g, 1, B.p, t, nrhs, nullptr, 0.0, 1.0, FIN_NONE, nullptr,
+        HISQ_TRY(launch_dslash(g, 1, B.p, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE, nullptr,
                                nullptr, s));
-        HISQ_TRY(launch_dslash(g, 0, t, B.Ap, nrhs, B.p, m2, -1.0, FIN_CG_ALPHA, &B.dev,
+        HISQ_TRY(launch_dslash(g, 0, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA, &B.dev,
                                &B.red, s));
         HISQ_TRY(cg_update(n, nrhs, x, B.r, B.p, B.Ap, B.dev, B.red, s));
         HISQ_TRY(cg_update_p(n, nrhs, B.r, B.p, B.dev, s));

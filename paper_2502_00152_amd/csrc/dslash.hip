@@ -1,6 +1,6 @@
 // HISQ half stencil D_{p,1-p} on gfx950, FP64.
 //
-//   out(x) = ca * aux(x) + cd * sum_mu [ F_mu(x) in(x+mu) - F_mu(x-mu)^H in(x-mu)
+//   out(x) = ca * aux(x) + cb * aux2(x) + cd * sum_mu [ F_mu(x) in(x+mu) - F_mu(x-mu)^H in(x-mu)
 //                                      + L_mu(x) in(x+3mu) - L_mu(x-3mu)^H in(x-3mu) ]
 //
 // for every site x of parity p (arXiv:2502.00152, section 2: the HISQ matrix
@@ -33,7 +33,8 @@ struct DslashArgs {
     const dvec2 *in;       // [nrhs][3][Vh], parity 1-p
     dvec2 *out;            // [nrhs][3][Vh], parity p
     const dvec2 *aux;      // [nrhs][3][Vh], parity p (optional)
-    double ca, cd;
+    const dvec2 *aux2;     // [nrhs][3][Vh], parity p (optional; may alias out)
+    double ca, cb, cd;
     Geom geom;
     int out_parity;
     int nrhs;
@@ -111,7 +112,7 @@ __device__ __forceinline__ void hop_backward(const dvec2 *__restrict__ U, int vh
     }
 }
 
-template <int NR, bool AUX, bool DOT>
+template <int NR, bool AUX, bool AUX2, bool DOT>
 __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
     const Geom g = a.geom;
     const int vh = g.vh;
@@ -193,6 +194,11 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
                         const dvec2 ax = a.aux[base + c * (int64_t)vh];
                         o.x = fma(a.ca, ax.x, o.x);
                         o.y = fma(a.ca, ax.y, o.y);
+                        if (AUX2) {
+                            const dvec2 a2 = a.aux2[base + c * (int64_t)vh];
+                            o.x = fma(a.cb, a2.x, o.x);
+                            o.y = fma(a.cb, a2.y, o.y);
+                        }
                         if (DOT) dotv[r] = fma(ax.x, o.x, fma(ax.y, o.y, dotv[r]));
                     }
                     a.out[base + c * (int64_t)vh] = o;
@@ -231,13 +237,16 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
 }
 
 template <int NR>
-hisq_status launch_nr(const DslashArgs &args, int nblocks, bool aux, bool dot, hipStream_t s) {
+hisq_status launch_nr(const DslashArgs &args, int nblocks, bool aux, bool aux2, bool dot,
+                      hipStream_t s) {
     if (dot)
-        hipLaunchKernelGGL((k_dslash<NR, true, true>), dim3(nblocks), dim3(kBS), 0, s, args);
+        hipLaunchKernelGGL((k_dslash<NR, true, false, true>), dim3(nblocks), dim3(kBS), 0, s, args);
+    else if (aux2)
+        hipLaunchKernelGGL((k_dslash<NR, true, true, false>), dim3(nblocks), dim3(kBS), 0, s, args);
     else if (aux)
-        hipLaunchKernelGGL((k_dslash<NR, true, false>), dim3(nblocks), dim3(kBS), 0, s, args);
+        hipLaunchKernelGGL((k_dslash<NR, true, false, false>), dim3(nblocks), dim3(kBS), 0, s, args);
     else
-        hipLaunchKernelGGL((k_dslash<NR, false, false>), dim3(nblocks), dim3(kBS), 0, s, args);
+        hipLaunchKernelGGL((k_dslash<NR, false, false, false>), dim3(nblocks), dim3(kBS), 0, s, args);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
@@ -258,9 +267,10 @@ int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs) {
 }
 
 hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
-                          double2 *out, int nrhs, const double2 *aux, double ca, double cd,
-                          DslashFinal fin, const CgDev *cg, const Reduce *red,
-                          hipStream_t s) {
+                          double2 *out, int nrhs, const double2 *aux, double ca,
+                          const double2 *aux2, double cb, double cd, DslashFinal fin,
+                          const CgDev *cg, const Reduce *red, hipStream_t s) {
+    if (aux2 && !aux) return fail(HISQ_ERR_INVALID_ARG, "dslash: aux2 needs aux");
     DslashArgs a{};
     const int p = out_parity;
     a.fat_out = reinterpret_cast<const dvec2 *>(g->fat[p]);
@@ -270,7 +280,9 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
     a.in = reinterpret_cast<const dvec2 *>(in);
     a.out = reinterpret_cast<dvec2 *>(out);
     a.aux = reinterpret_cast<const dvec2 *>(aux);
+    a.aux2 = reinterpret_cast<const dvec2 *>(aux2);
     a.ca = ca;
+    a.cb = cb;
     a.cd = cd;
     a.geom = g->geom;
     a.out_parity = p;
@@ -287,10 +299,10 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
     const int nblocks = a.nsb * a.ngroups;
     ProfileScope prof("dslash", s);
     switch (nr) {
-        case 1: return launch_nr<1>(a, nblocks, aux != nullptr, dot, s);
-        case 2: return launch_nr<2>(a, nblocks, aux != nullptr, dot, s);
-        case 3: return launch_nr<3>(a, nblocks, aux != nullptr, dot, s);
-        case 4: return launch_nr<4>(a, nblocks, aux != nullptr, dot, s);
+        case 1: return launch_nr<1>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
+        case 2: return launch_nr<2>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
+        case 3: return launch_nr<3>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
+        case 4: return launch_nr<4>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
         default: return fail(HISQ_ERR_INVALID_ARG, "dslash: bad RHS grouping");
     }
 }
@@ -300,9 +312,10 @@ hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double
     void *tmp = nullptr;
     HISQ_TRY(g->ws.get("mdagm_tmp", sizeof(double2) * 3 * (size_t)g->geom.vh * nrhs, &tmp));
     double2 *t = static_cast<double2 *>(tmp);
-    HISQ_TRY(launch_dslash(g, 1, in, t, nrhs, nullptr, 0.0, 1.0, FIN_NONE, nullptr, nullptr, s));
-    HISQ_TRY(launch_dslash(g, 0, t, out, nrhs, in, two_m * two_m, -1.0, FIN_NONE, nullptr,
-                           nullptr, s));
+    HISQ_TRY(launch_dslash(g, 1, in, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
+                           nullptr, nullptr, s));
+    HISQ_TRY(launch_dslash(g, 0, t, out, nrhs, in, two_m * two_m, nullptr, 0.0, -1.0, FIN_NONE,
+                           nullptr, nullptr, s));
     return HISQ_OK;
 }
 

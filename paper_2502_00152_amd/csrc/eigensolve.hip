@@ -1,13 +1,475 @@
-// hisq_eigensolve: thick-restart Lanczos with a Chebyshev filter (in progress).
+// hisq_eigensolve: lowest eigenpairs of A = (2m)^2 - D_eo D_oe on even sites by
+// thick-restart Lanczos on a Chebyshev-filtered A, closed by a Rayleigh-Ritz
+// step on A itself (arXiv:2502.00152, section 2: eigenvectors of the squared
+// operator from thick-restart Lanczos, used for deflation; section 3:
+// single-parity vectors).
+//
+// Outline
+//   1. Pilot: plain Lanczos on A (full re-orthogonalisation, n_kr steps) gives
+//      an upper bound b of the spectrum and a cut a above the wanted part.  By
+//      Cauchy interlacing the (n_ev+1)-th smallest Ritz value is at least the
+//      (n_ev+1)-th eigenvalue, so at least n_ev eigenvalues lie below a.
+//   2. Filter p(A) = T_d(l(A)), l(x) = (a + b - 2x) / (b - a): eigenvalues in
+//      [a, b] map into [-1, 1], those below a above 1, monotonically, so the
+//      largest eigenvalues of p(A) belong to the smallest of A.
+//   3. Thick-restart Lanczos on p(A) with classical Gram-Schmidt applied twice
+//      against the whole basis; after each cycle the small arrowhead +
+//      tridiagonal matrix is diagonalised on the host, the Ritz vectors of
+//      the kept part become the new leading basis and the residual vector the
+//      next one.
+//   4. When the n_ev wanted Ritz values have residuals below tol (relative to
+//      each Ritz value), form the Ritz vectors, apply A to them, diagonalise
+//      the Gram matrix U^H A U on the host, rotate, and accept when every
+//      ||A v - lambda v|| <= tol * lambda_max; otherwise tighten and go on.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <vector>
+
 #include "hisq_internal.h"
 
+namespace hisq {
+hisq_status check_gauge(hisq_gauge g);
+hisq_status check_vec(const void *p, const char *name);
+hisq_status check_mass(double two_m, bool positive);
+int heev_jacobi(int n, std::complex<double> *A, double *w, std::complex<double> *Z, int max_sweeps);
+hisq_status vec_random(double2 *x, int64_t n, uint64_t seed, hipStream_t s);
+hisq_status vec_dot(hisq_gauge_s *g, const double2 *x, const double2 *y, int64_t n, double *out,
+                    hipStream_t s);
+hisq_status vec_axpby2(double2 *y, double a, const double2 *x1, double b1, const double2 *x2,
+                       double b2, int64_t n, hipStream_t s);
+hisq_status vec_col_residuals(hisq_gauge_s *g, const double2 *W, const double2 *U,
+                              const double *lam_dev, int64_t n, int k, double *out_dev,
+                              hipStream_t s);
+}  // namespace hisq
+
 using namespace hisq;
+using cd = std::complex<double>;
+
+namespace {
+
+struct Pinned {
+    void *ptr = nullptr;
+    ~Pinned() {
+        if (ptr) (void)hipHostFree(ptr);
+    }
+};
+
+class Solver {
+public:
+    Solver(hisq_gauge_s *g, double two_m, hipStream_t s)
+        : g_(g), two_m_(two_m), s_(s), N_(3 * (int64_t)g->geom.vh) {}
+
+    hisq_gauge_s *g_;
+    double two_m_;
+    hipStream_t s_;
+    int64_t N_;
+    double2 *V_ = nullptr, *Vt_ = nullptr, *w_ = nullptr, *y1_ = nullptr, *y2_ = nullptr;
+    double2 *coef_ = nullptr;  // device complex coefficients (GEMM operands)
+    double *dscal_ = nullptr;  // device scalars
+    double *hscal_ = nullptr;  // pinned host mirror
+    Pinned pin_;
+    int matvecs_ = 0;
+    int nkr_ = 0;
+    size_t coef_cap_ = 0;
+
+    double2 *col(double2 *base, int i) const { return base + (size_t)i * N_; }
+
+    hisq_status alloc(int nkr, int n_ev) {
+        nkr_ = nkr;
+        void *p = nullptr;
+        const size_t vb = sizeof(double2) * (size_t)N_;
+        HISQ_TRY(g_->ws.get("eig_V", vb * (nkr + 1), &p));
+        V_ = static_cast<double2 *>(p);
+        HISQ_TRY(g_->ws.get("eig_Vt", vb * std::max(nkr + 1, 3 * n_ev), &p));
+        Vt_ = static_cast<double2 *>(p);
+        HISQ_TRY(g_->ws.get("eig_w", vb, &p));
+        w_ = static_cast<double2 *>(p);
+        HISQ_TRY(g_->ws.get("eig_y1", vb, &p));
+        y1_ = static_cast<double2 *>(p);
+        HISQ_TRY(g_->ws.get("eig_y2", vb, &p));
+        y2_ = static_cast<double2 *>(p);
+        coef_cap_ = (size_t)(nkr + 1) * std::max(nkr + 1, n_ev) + 64;
+        HISQ_TRY(g_->ws.get("eig_coef", sizeof(double2) * coef_cap_, &p));
+        coef_ = static_cast<double2 *>(p);
+        HISQ_TRY(g_->ws.get("eig_scal", sizeof(double) * (4 + 2 * (size_t)n_ev), &p));
+        dscal_ = static_cast<double *>(p);
+        HISQ_HIP(hipHostMalloc(&pin_.ptr, sizeof(double) * (4 + 2 * (size_t)n_ev),
+                               hipHostMallocDefault));
+        hscal_ = static_cast<double *>(pin_.ptr);
+        return HISQ_OK;
+    }
+
+    hisq_status applyA(const double2 *in, double2 *out, int nrhs = 1) {
+        matvecs_ += nrhs;
+        return apply_mdagm(g_, two_m_, in, out, nrhs, s_);
+    }
+
+    hisq_status dot(const double2 *x, const double2 *y, cd *out) {
+        HISQ_TRY(vec_dot(g_, x, y, N_, dscal_, s_));
+        HISQ_HIP(hipMemcpyAsync(hscal_, dscal_, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
+        HISQ_HIP(hipStreamSynchronize(s_));
+        *out = cd(hscal_[0], hscal_[1]);
+        return HISQ_OK;
+    }
+
+    hisq_status norm(const double2 *x, double *out) {
+        cd d;
+        HISQ_TRY(dot(x, x, &d));
+        *out = std::sqrt(std::max(d.real(), 0.0));
+        return HISQ_OK;
+    }
+
+    // w -= Q[0..j) (Q[0..j)^H w), twice (Q = the Lanczos basis by default)
+    hisq_status orthogonalise(double2 *w, int j, const double2 *Q = nullptr) {
+        if (j <= 0) return HISQ_OK;
+        if (!Q) Q = V_;
+        for (int pass = 0; pass < 2; ++pass) {
+            HISQ_TRY(gemm_tn(g_, Q, j, w, 1, N_, nullptr, -1.0, coef_, s_));
+            HISQ_TRY(gemm_nn(Q, j, coef_, 1, N_, 1.0, w, s_));
+        }
+        return HISQ_OK;
+    }
+
+    // p(x) = T_d(l(x)) for a scalar x
+    static double cheb_value(double x, int d, double a, double b) {
+        const double l = (a + b - 2.0 * x) / (b - a);
+        if (std::fabs(l) <= 1.0) return std::cos(d * std::acos(l));
+        const double v = std::cosh(d * std::acosh(std::fabs(l)));
+        return (l < 0.0 && (d & 1)) ? -v : v;
+    }
+
+    // out = X Y, Y host complex [k][n] row-major (columns = new vectors): X has k columns
+    hisq_status rotate(const double2 *X, int k, const std::vector<cd> &Y, int ldY, int n,
+                       double2 *out) {
+        // device coefficients C[j][i] = Y[i][j]
+        std::vector<cd> C((size_t)n * k);
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < k; ++i) C[(size_t)j * k + i] = Y[(size_t)i * ldY + j];
+        if (C.size() > coef_cap_) return fail(HISQ_ERR_INVALID_ARG, "eigensolve: coefficient buffer");
+        HISQ_HIP(hipMemcpyAsync(coef_, C.data(), sizeof(double2) * C.size(), hipMemcpyHostToDevice,
+                                s_));
+        HISQ_TRY(gemm_nn(X, k, coef_, n, N_, 0.0, out, s_));
+        return HISQ_OK;
+    }
+
+    // w = T_d(l(A)) v with l(x) = (a + b - 2x) / (b - a)
+    hisq_status chebyshev(const double2 *v, double2 *w, int d, double a, double b) {
+        const double s1 = (a + b) / (b - a), s2 = -2.0 / (b - a);
+        const double m2 = two_m_ * two_m_;
+        void *tp = nullptr;
+        HISQ_TRY(g_->ws.get("mdagm_tmp", sizeof(double2) * (size_t)N_, &tp));
+        double2 *t = static_cast<double2 *>(tp);
+        // y1 = l(A) v = (s1 + s2 m2) v - s2 D_eo D_oe v
+        double2 *prev = nullptr, *cur = nullptr;
+        {
+            double2 *dst = d == 1 ? w : y1_;
+            HISQ_TRY(launch_dslash(g_, 1, v, t, 1, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
+                                   nullptr, nullptr, s_));
+            HISQ_TRY(launch_dslash(g_, 0, t, dst, 1, v, s1 + s2 * m2, nullptr, 0.0, -s2, FIN_NONE,
+                                   nullptr, nullptr, s_));
+            ++matvecs_;
+            prev = const_cast<double2 *>(v);
+            cur = dst;
+        }
+        // y_{i+1} = 2 l(A) y_i - y_{i-1}
+        for (int i = 1; i < d; ++i) {
+            double2 *dst = (i == d - 1) ? w : (prev == v ? y2_ : prev);
+            HISQ_TRY(launch_dslash(g_, 1, cur, t, 1, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
+                                   nullptr, nullptr, s_));
+            HISQ_TRY(launch_dslash(g_, 0, t, dst, 1, cur, 2.0 * (s1 + s2 * m2), prev, -1.0,
+                                   -2.0 * s2, FIN_NONE, nullptr, nullptr, s_));
+            ++matvecs_;
+            prev = cur;
+            cur = dst;
+        }
+        return HISQ_OK;
+    }
+
+    // After w has been orthogonalised against V[0..j]: beta = ||w||, V[j+1] = w / beta.
+    // On breakdown (beta tiny) a fresh random vector orthogonal to the basis is used
+    // and beta is set to 0, decoupling the new Krylov block.
+    hisq_status next_vector(int j, double scale, uint64_t seed, double *beta) {
+        double b = 0.0;
+        HISQ_TRY(norm(w_, &b));
+        if (!std::isfinite(b)) return fail(HISQ_ERR_NAN, "eigensolve: NaN in the Lanczos vector");
+        if (b <= 1e-12 * scale) {
+            HISQ_TRY(vec_random(w_, N_, seed, s_));
+            HISQ_TRY(orthogonalise(w_, j + 1));
+            double nb = 0.0;
+            HISQ_TRY(norm(w_, &nb));
+            if (!(nb > 0.0)) return fail(HISQ_ERR_BREAKDOWN, "eigensolve: basis exhausted");
+            HISQ_TRY(vec_axpby2(col(V_, j + 1), 0.0, w_, 1.0 / nb, nullptr, 0.0, N_, s_));
+            *beta = 0.0;
+            return HISQ_OK;
+        }
+        HISQ_TRY(vec_axpby2(col(V_, j + 1), 0.0, w_, 1.0 / b, nullptr, 0.0, N_, s_));
+        *beta = b;
+        return HISQ_OK;
+    }
+};
+
+// eigen-decomposition of a real symmetric matrix held as complex (row-major)
+int small_heev(int n, std::vector<cd> &A, std::vector<double> &w, std::vector<cd> &Z) {
+    w.assign(n, 0.0);
+    Z.assign((size_t)n * n, 0.0);
+    return heev_jacobi(n, A.data(), w.data(), Z.data(), 100);
+}
+
+}  // namespace
 
 extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
                                        const hisq_eig_params *params, void *evecs_dev,
                                        double *evals_host, hisq_eig_stats *stats_host,
                                        void *stream) {
-    (void)g; (void)two_m; (void)n_ev; (void)params; (void)evecs_dev; (void)evals_host;
-    (void)stats_host; (void)stream;
-    return fail(HISQ_ERR_UNSUPPORTED, "hisq_eigensolve is not implemented yet");
+    const auto t_start = std::chrono::steady_clock::now();
+    HISQ_TRY(check_gauge(g));
+    HISQ_TRY(check_mass(two_m, false));
+    HISQ_TRY(check_vec(evecs_dev, "evecs_dev"));
+    if (!evals_host) return fail(HISQ_ERR_INVALID_ARG, "evals_host is null");
+    if (!params) return fail(HISQ_ERR_INVALID_ARG, "params is null");
+    for (int k = 0; k < 8; ++k)
+        if (params->reserved[k]) return fail(HISQ_ERR_INVALID_ARG, "reserved fields must be 0");
+    const int64_t N = 3 * (int64_t)g->geom.vh;
+    if (n_ev < 1 || n_ev >= N) return fail(HISQ_ERR_INVALID_ARG, "n_ev must be in [1, 3*Vh)");
+    int nkr = params->n_kr > 0 ? params->n_kr : std::max(2 * n_ev, n_ev + 32);
+    if (params->n_kr <= 0) nkr = (int)std::min<int64_t>(nkr, N - 1);
+    if (nkr <= n_ev || nkr >= N)
+        return fail(HISQ_ERR_INVALID_ARG, "need n_ev < n_kr < 3*Vh");
+    const double tol = params->tol > 0.0 ? params->tol : 1e-10;
+    const int max_restarts = params->max_restarts > 0 ? params->max_restarts : 200;
+    if (params->cheb_a < 0.0 || params->cheb_b < 0.0 || params->cheb_degree < 0)
+        return fail(HISQ_ERR_INVALID_ARG, "Chebyshev parameters must be >= 0");
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Solver S(g, two_m, s);
+    HISQ_TRY(S.alloc(nkr, n_ev));
+    const uint64_t seed = params->seed;
+
+    // ---------------------------------------------------------------- pilot
+    HISQ_TRY(vec_random(S.col(S.V_, 0), N, seed, s));
+    {
+        double nv = 0.0;
+        HISQ_TRY(S.norm(S.col(S.V_, 0), &nv));
+        HISQ_TRY(vec_axpby2(S.col(S.V_, 0), 1.0 / nv, nullptr, 0.0, nullptr, 0.0, N, s));
+    }
+    const int m = nkr;
+    std::vector<double> al(m, 0.0), be(m, 0.0);
+    double scale = 0.0;
+    for (int j = 0; j < m; ++j) {
+        HISQ_TRY(S.applyA(S.col(S.V_, j), S.w_));
+        cd a;
+        HISQ_TRY(S.dot(S.col(S.V_, j), S.w_, &a));
+        al[j] = a.real();
+        scale = std::max(scale, std::abs(al[j]));
+        HISQ_TRY(vec_axpby2(S.w_, 1.0, S.col(S.V_, j), -al[j], j > 0 ? S.col(S.V_, j - 1) : nullptr,
+                            j > 0 ? -be[j - 1] : 0.0, N, s));
+        HISQ_TRY(S.orthogonalise(S.w_, j + 1));
+        HISQ_TRY(S.next_vector(j, scale, seed + 1000 + j, &be[j]));
+    }
+    double lam_max = 0.0, cut = 0.0;
+    std::vector<cd> Vstart_coef;
+    {
+        std::vector<cd> T((size_t)m * m, 0.0), Z;
+        std::vector<double> th;
+        for (int j = 0; j < m; ++j) {
+            T[(size_t)j * m + j] = al[j];
+            if (j + 1 < m) T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] = be[j];
+        }
+        if (small_heev(m, T, th, Z) < 0)
+            return fail(HISQ_ERR_BREAKDOWN, "eigensolve: pilot eigenproblem did not converge");
+        const double rtop = std::abs(be[m - 1] * Z[(size_t)(m - 1) * m + (m - 1)].real()) +
+                            std::abs(be[m - 1] * Z[(size_t)(m - 1) * m + (m - 1)].imag());
+        lam_max = th[m - 1] + rtop;
+        cut = th[std::min(n_ev, m - 1)];
+        // start the filtered iteration from the sum of the lowest pilot Ritz vectors
+        Vstart_coef.assign(m, 0.0);
+        for (int i = 0; i < n_ev; ++i)
+            for (int r = 0; r < m; ++r) Vstart_coef[r] += Z[(size_t)r * m + i];
+    }
+    const double b = params->cheb_b > 0.0 ? params->cheb_b : 1.02 * lam_max;
+    const double a = params->cheb_a > 0.0 ? params->cheb_a : cut;
+    if (!(a < b)) return fail(HISQ_ERR_INVALID_ARG, "Chebyshev interval needs a < b");
+    int deg = params->cheb_degree;
+    if (deg <= 0) {
+        const double l0 = (a + b - 2.0 * two_m * two_m) / (b - a);
+        const double ac = std::acosh(std::max(l0, 1.0 + 1e-12));
+        deg = (int)std::ceil(14.0 / ac);
+        deg = std::max(8, std::min(deg, 120));
+    }
+
+    // ------------------------------------------------- filtered thick restart
+    HISQ_TRY(S.rotate(S.V_, m, Vstart_coef, 1, 1, S.w_));
+    {
+        double nv = 0.0;
+        HISQ_TRY(S.norm(S.w_, &nv));
+        HISQ_TRY(vec_axpby2(S.col(S.V_, 0), 0.0, S.w_, 1.0 / nv, nullptr, 0.0, N, s));
+    }
+    std::vector<double> alpha(nkr, 0.0), beta(nkr, 0.0), theta, sigma;
+    int k0 = 0, restarts = 0;
+    double tol_l = tol, max_res = INFINITY;
+    bool accepted = false;
+    std::vector<double> lam_out(n_ev, 0.0);
+    hisq_status final_status = HISQ_ERR_NOT_CONVERGED;
+    double fscale = 0.0;
+    for (; restarts <= max_restarts; ++restarts) {
+        for (int j = k0; j < nkr; ++j) {
+            HISQ_TRY(S.chebyshev(S.col(S.V_, j), S.w_, deg, a, b));
+            if (j == k0 && k0 > 0) {
+                // w -= sum_i sigma_i v_i
+                std::vector<cd> c(k0);
+                for (int i = 0; i < k0; ++i) c[i] = -sigma[i];
+                HISQ_HIP(hipMemcpyAsync(S.coef_, c.data(), sizeof(double2) * k0,
+                                        hipMemcpyHostToDevice, s));
+                HISQ_TRY(gemm_nn(S.V_, k0, S.coef_, 1, N, 1.0, S.w_, s));
+            } else if (j > k0) {
+                HISQ_TRY(vec_axpby2(S.w_, 1.0, S.col(S.V_, j - 1), -beta[j - 1], nullptr, 0.0, N, s));
+            }
+            cd aj;
+            HISQ_TRY(S.dot(S.col(S.V_, j), S.w_, &aj));
+            alpha[j] = aj.real();
+            fscale = std::max(fscale, std::abs(alpha[j]));
+            HISQ_TRY(vec_axpby2(S.w_, 1.0, S.col(S.V_, j), -alpha[j], nullptr, 0.0, N, s));
+            HISQ_TRY(S.orthogonalise(S.w_, j + 1));
+            HISQ_TRY(S.next_vector(j, fscale, seed + 7777 + 131 * restarts + j, &beta[j]));
+        }
+        // projected matrix: arrowhead (kept Ritz values + couplings) + tridiagonal
+        std::vector<cd> T((size_t)nkr * nkr, 0.0), Z;
+        std::vector<double> th;
+        for (int i = 0; i < k0; ++i) {
+            T[(size_t)i * nkr + i] = theta[i];
+            T[(size_t)i * nkr + k0] = T[(size_t)k0 * nkr + i] = sigma[i];
+        }
+        for (int j = k0; j < nkr; ++j) {
+            T[(size_t)j * nkr + j] = alpha[j];
+            if (j + 1 < nkr) T[(size_t)j * nkr + j + 1] = T[(size_t)(j + 1) * nkr + j] = beta[j];
+        }
+        if (small_heev(nkr, T, th, Z) < 0)
+            return fail(HISQ_ERR_BREAKDOWN, "eigensolve: projected eigenproblem did not converge");
+        // descending order: the largest filtered values belong to the smallest of A
+        std::vector<double> Th(nkr);
+        std::vector<cd> Y((size_t)nkr * nkr);
+        for (int c2 = 0; c2 < nkr; ++c2) {
+            Th[c2] = th[nkr - 1 - c2];
+            for (int r = 0; r < nkr; ++r) Y[(size_t)r * nkr + c2] = Z[(size_t)r * nkr + (nkr - 1 - c2)];
+        }
+        const double bl = beta[nkr - 1];
+        bool conv = true;
+        for (int i = 0; i < n_ev; ++i) {
+            const double rho = std::abs(bl * Y[(size_t)(nkr - 1) * nkr + i]);
+            if (!(rho <= tol_l * std::abs(Th[i]))) conv = false;
+        }
+        if (conv || restarts == max_restarts) {
+            // Ritz vectors U -> Vt[0..n_ev), A U -> Vt[n_ev..2 n_ev)
+            double2 *U = S.Vt_, *W = S.col(S.Vt_, n_ev);
+            HISQ_TRY(S.rotate(S.V_, nkr, Y, nkr, n_ev, U));
+            HISQ_TRY(S.applyA(U, W, n_ev));
+            // G = U^H A U: C[j][i] = <U_i, W_j> = G[i][j]
+            HISQ_TRY(gemm_tn(g, U, n_ev, W, n_ev, N, nullptr, 1.0, S.coef_, s));
+            std::vector<cd> C((size_t)n_ev * n_ev), G((size_t)n_ev * n_ev), Zg;
+            HISQ_HIP(hipMemcpyAsync(C.data(), S.coef_, sizeof(double2) * C.size(),
+                                    hipMemcpyDeviceToHost, s));
+            HISQ_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i < n_ev; ++i)
+                for (int j = 0; j < n_ev; ++j) {
+                    // Hermitian part (rounding makes G slightly non-Hermitian)
+                    const cd gij = C[(size_t)j * n_ev + i], gji = C[(size_t)i * n_ev + j];
+                    G[(size_t)i * n_ev + j] = 0.5 * (gij + std::conj(gji));
+                }
+            std::vector<double> lam;
+            if (small_heev(n_ev, G, lam, Zg) < 0)
+                return fail(HISQ_ERR_BREAKDOWN, "eigensolve: Rayleigh-Ritz did not converge");
+            // rotated vectors and their images: evecs = U Z, A evecs = W Z
+            double2 *E = static_cast<double2 *>(evecs_dev);
+            double2 *AE = S.col(S.Vt_, 2 * n_ev);
+            HISQ_TRY(S.rotate(U, n_ev, Zg, n_ev, n_ev, E));
+            HISQ_TRY(S.rotate(W, n_ev, Zg, n_ev, n_ev, AE));
+            HISQ_HIP(hipMemcpyAsync(S.dscal_, lam.data(), sizeof(double) * n_ev,
+                                    hipMemcpyHostToDevice, s));
+            HISQ_TRY(vec_col_residuals(g, AE, E, S.dscal_, N, n_ev, S.dscal_ + n_ev, s));
+            std::vector<double> r2(n_ev);
+            HISQ_HIP(hipMemcpyAsync(r2.data(), S.dscal_ + n_ev, sizeof(double) * n_ev,
+                                    hipMemcpyDeviceToHost, s));
+            HISQ_HIP(hipStreamSynchronize(s));
+            max_res = 0.0;
+            for (int i = 0; i < n_ev; ++i) max_res = std::max(max_res, std::sqrt(r2[i]));
+            lam_out = lam;
+            if (max_res <= tol * lam_max) {
+                // Completeness: residuals cannot reveal a copy of a degenerate
+                // eigenvalue that never entered the Krylov space.  Filter a random
+                // vector orthogonal to the accepted ones; if its Rayleigh quotient
+                // falls below the last accepted eigenvalue, it joins the basis.
+                double2 *u = S.w_;
+                HISQ_TRY(vec_random(u, N, seed + 424242 + restarts, s));
+                double un = 0.0;
+                for (int it = 0; it < 4; ++it) {
+                    if (it > 0) {
+                        HISQ_TRY(S.chebyshev(u, S.col(S.Vt_, 0), deg, a, b));
+                        HISQ_HIP(hipMemcpyAsync(u, S.col(S.Vt_, 0), sizeof(double2) * (size_t)N,
+                                                hipMemcpyDeviceToDevice, s));
+                    }
+                    HISQ_TRY(S.orthogonalise(u, n_ev, E));
+                    HISQ_TRY(S.norm(u, &un));
+                    if (!(un > 0.0)) break;
+                    HISQ_TRY(vec_axpby2(u, 1.0 / un, nullptr, 0.0, nullptr, 0.0, N, s));
+                }
+                double lam_u = INFINITY;
+                if (un > 0.0) {
+                    double2 *Au = S.col(S.Vt_, 0);
+                    HISQ_TRY(S.applyA(u, Au));
+                    cd q;
+                    HISQ_TRY(S.dot(u, Au, &q));
+                    lam_u = q.real();
+                }
+                if (!(lam_u < lam[n_ev - 1] - 1e-8 * lam_max)) {
+                    accepted = true;
+                    final_status = HISQ_OK;
+                    break;
+                }
+                if (restarts == max_restarts) break;
+                // restart from [accepted vectors, u]: p(A) e_i = p(lambda_i) e_i up to
+                // the accepted residual, so the kept block carries no coupling
+                HISQ_HIP(hipMemcpyAsync(S.V_, E, sizeof(double2) * (size_t)N * n_ev,
+                                        hipMemcpyDeviceToDevice, s));
+                HISQ_HIP(hipMemcpyAsync(S.col(S.V_, n_ev), u, sizeof(double2) * (size_t)N,
+                                        hipMemcpyDeviceToDevice, s));
+                theta.assign(n_ev, 0.0);
+                sigma.assign(n_ev, 0.0);
+                for (int i = 0; i < n_ev; ++i) theta[i] = Solver::cheb_value(lam[i], deg, a, b);
+                k0 = n_ev;
+                continue;
+            }
+            if (restarts == max_restarts) break;
+            // not yet: ask the Lanczos cycle for more and continue restarting
+            tol_l *= 0.1;
+        }
+        // thick restart: keep k0n Ritz vectors and the residual direction
+        const int k0n = std::min(n_ev + (nkr - n_ev) / 2, nkr - 1);
+        HISQ_TRY(S.rotate(S.V_, nkr, Y, nkr, k0n, S.Vt_));
+        HISQ_HIP(hipMemcpyAsync(S.col(S.Vt_, k0n), S.col(S.V_, nkr), sizeof(double2) * (size_t)N,
+                                hipMemcpyDeviceToDevice, s));
+        std::swap(S.V_, S.Vt_);
+        theta.assign(Th.begin(), Th.begin() + k0n);
+        sigma.resize(k0n);
+        for (int i = 0; i < k0n; ++i) sigma[i] = bl * Y[(size_t)(nkr - 1) * nkr + i].real();
+        k0 = k0n;
+    }
+    HISQ_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n_ev; ++i) evals_host[i] = lam_out[i];
+    if (stats_host) {
+        stats_host->restarts = restarts;
+        stats_host->matvecs = S.matvecs_;
+        stats_host->converged = accepted ? n_ev : 0;
+        stats_host->cheb_degree = deg;
+        stats_host->cheb_a = a;
+        stats_host->cheb_b = b;
+        stats_host->lambda_max = lam_max;
+        stats_host->max_residual = max_res;
+        stats_host->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (final_status != HISQ_OK)
+        return fail(final_status, "eigensolve: residual target not met within max_restarts");
+    return HISQ_OK;
 }

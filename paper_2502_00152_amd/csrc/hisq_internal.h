@@ -23,16 +23,16 @@ hisq_status fail(hisq_status st, const std::string &msg);
 
 #define HISQ_HIP(call)                                                             \
     do {                                                                           \
-        hipError_t e_ = (call);                                                    \
-        if (e_ != hipSuccess)                                                      \
-            return ::hisq::fail(e_ == hipErrorOutOfMemory ? HISQ_ERR_OOM : HISQ_ERR_HIP, \
-                                std::string(#call) + ": " + hipGetErrorString(e_)); \
+        hipError_t hisq_he_ = (call);                                              \
+        if (hisq_he_ != hipSuccess)                                                \
+            return ::hisq::fail(hisq_he_ == hipErrorOutOfMemory ? HISQ_ERR_OOM : HISQ_ERR_HIP, \
+                                std::string(#call) + ": " + hipGetErrorString(hisq_he_)); \
     } while (0)
 
 #define HISQ_TRY(expr)                        \
     do {                                      \
-        hisq_status s_ = (expr);              \
-        if (s_ != HISQ_OK) return s_;         \
+        hisq_status hisq_st_ = (expr);        \
+        if (hisq_st_ != HISQ_OK) return hisq_st_; \
     } while (0)
 
 // --------------------------------------------------------------- geometry
@@ -126,12 +126,13 @@ enum DslashFinal : int {
     FIN_CG_ALPHA = 1,   // alpha = rho / Re<aux, out> per active RHS
 };
 
-// out = ca * aux + cd * D_{p,1-p} in  (aux may be null: then ca is ignored).
+// out = ca * aux + cb * aux2 + cd * D_{p,1-p} in.  aux/aux2 may be null (their
+// coefficient is then ignored; aux2 needs aux); aux and aux2 may alias out.
 // With fin == FIN_CG_ALPHA, also reduces Re<aux, out> per RHS and sets cg.alpha.
 hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
-                          double2 *out, int nrhs, const double2 *aux, double ca, double cd,
-                          DslashFinal fin, const CgDev *cg, const Reduce *red,
-                          hipStream_t s);
+                          double2 *out, int nrhs, const double2 *aux, double ca,
+                          const double2 *aux2, double cb, double cd, DslashFinal fin,
+                          const CgDev *cg, const Reduce *red, hipStream_t s);
 
 // Number of reduction blocks the dslash launch for (g, nrhs) uses.
 int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs);

@@ -1,0 +1,71 @@
+"""Host logic of the library tested on the CPU: the dense Hermitian Jacobi
+eigensolver used for the small projected matrices of the eigensolver."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def heev(tmp_path_factory):
+    out = tmp_path_factory.mktemp("hostlib") / "libhost_eig_test.so"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", str(out),
+                    os.path.join(ROOT, "paper_2502_00152_amd", "csrc", "dense_eig.cpp"),
+                    os.path.join(ROOT, "tests", "host_eig_shim.cpp")], check=True)
+    L = ctypes.CDLL(str(out))
+    L.test_heev.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_int]
+    L.test_heev.restype = ctypes.c_int
+
+    def run(A):
+        n = A.shape[0]
+        a = np.ascontiguousarray(A, dtype=np.complex128).copy()
+        w = np.zeros(n)
+        Z = np.zeros((n, n), dtype=np.complex128)
+        sweeps = L.test_heev(n, a.ctypes.data, w.ctypes.data, Z.ctypes.data, 60)
+        return sweeps, w, Z
+    return run
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 33, 96])
+def test_jacobi_hermitian(heev, n):
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = M + M.conj().T
+    sweeps, w, Z = heev(A)
+    assert sweeps >= 0
+    ref = np.linalg.eigvalsh(A)
+    assert np.abs(w - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(Z.conj().T @ Z - np.eye(n)).max() <= 1e-12
+    assert np.abs(A @ Z - Z * w).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_jacobi_graded_arrowhead(heev):
+    """The filtered Lanczos matrices span many orders of magnitude."""
+    n = 60
+    rng = np.random.default_rng(1)
+    d = np.concatenate([10.0 ** rng.uniform(0, 12, 20), rng.uniform(-1, 1, 40)])
+    A = np.diag(d).astype(np.complex128)
+    A[:20, 20] = A[20, :20] = rng.standard_normal(20) * 1e-3
+    for j in range(20, n - 1):
+        A[j, j + 1] = A[j + 1, j] = rng.uniform(0.1, 1)
+    sweeps, w, Z = heev(A)
+    ref = np.linalg.eigvalsh(A)
+    # backward stable: errors of order eps * ||A|| (both solvers)
+    assert np.abs(w - ref).max() <= 1e-14 * np.abs(ref).max()
+    assert np.abs(A @ Z - Z * w).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(Z.conj().T @ Z - np.eye(n)).max() <= 1e-12
+
+
+def test_jacobi_degenerate_and_zero(heev):
+    A = np.diag([2.0, 2.0, 2.0, -1.0]).astype(np.complex128)
+    sweeps, w, Z = heev(A)
+    assert np.allclose(w, [-1, 2, 2, 2])
+    sweeps, w, Z = heev(np.zeros((3, 3), dtype=np.complex128))
+    assert np.all(w == 0)
