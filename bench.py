@@ -1,0 +1,336 @@
+"""Benchmark of the HISQ deflated even-odd CG path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-dslash-scan] [--pmc-probe]
+
+Workload (the deflated-CG configuration, synthetic): 16^3 x 32 lattice, random
+SU(3) fat and long links (eps 0.5, long links scaled by -1/24, staggered phases
+and antiperiodic time folded in), 2m = 0.01, 12 Gaussian sources, 64 lowest
+eigenpairs, true-residual target 1e-10, FP64 throughout.
+
+One step solves the 12 sources end to end on the GPU, inputs already resident
+in HBM: source preparation y_e = 2m eta_e - D_eo eta_o, deflation guess
+x0 = V diag(1/lambda) V^H y_e, batched CG to ||y - A x|| <= 1e-10 ||y||, odd
+reconstruction psi_o = (eta_o - D_oe psi_e) / (2m).  Setup (gauge packing) and
+the eigensolve are outside the timed region, as in the paper, which amortises
+the eigensolve over the solves of one gauge field; both are timed and
+reported.  value = solves per second = 12 * K / (time of K steps).
+
+Also reported: plain FP64 even-odd CG (no deflation, one source at a time) on
+the same GPU, the half-stencil bandwidth at 32^3 x 64 (beyond the 256 MB
+last-level cache), the half-stencil roofline measured live with HIP events
+inside the timed region, and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s at 1e-10 true residual (learned+mixed+batched vs plain CG); Dslash GB/s"
+HBM_PEAK_GBS = 8000.0
+LINK_BYTES = 16 * 18 * 8      # 16 links of 18 doubles per output site
+SPINOR_BYTES = 6 * 8          # one colour vector per site
+
+
+def dslash_alg_bytes(vh, nrhs, aux_fields):
+    """Algorithmic HBM bytes of one half-stencil launch: links once, the input
+    field once, the output once and each epilogue field once, per RHS."""
+    return vh * (LINK_BYTES + nrhs * SPINOR_BYTES * (2 + aux_fields))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dslash.hip", "device_util.h"):
+        with open(os.path.join(ROOT, "paper_2502_00152_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM traffic per half-stencil launch from the committed counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "dslash_traffic_16x16x16x32.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_problem(cfg):
+    import torch
+    from paper_2502_00152_amd import hisq, inputs as I
+    dims = cfg["dims"]
+    W = torch.from_numpy(I.random_su3_field(dims, cfg["eps"], cfg["seed_fat"])).cuda()
+    N = torch.from_numpy(I.random_su3_field(dims, cfg["eps"], cfg["seed_long"])).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = hisq.Gauge(dims, W, N, cfg["c_fat"], cfg["c_long"])
+    t_pack = time.perf_counter() - t0
+    del W, N
+    eta = np.stack([I.gaussian_source(dims, sd) for sd in cfg["seed_src"]])
+    full = torch.from_numpy(eta).cuda()
+    nrhs = len(cfg["seed_src"])
+    ee = torch.empty((nrhs, 3, g.vh), dtype=torch.complex128, device="cuda")
+    eo = torch.empty_like(ee)
+    hisq.hisq_spinor_split(g, full, ee, eo)
+    torch.cuda.synchronize()
+    return g, ee, eo, t_pack
+
+
+def pmc_probe(cfg):
+    """Light run for hardware-counter passes: the half-stencil launches of one
+    CG iteration at the timed configuration, and a plain 1 GiB copy whose
+    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    g, ee, eo, _ = build_problem(cfg)
+    t = torch.empty_like(eo)
+    out = torch.empty_like(ee)
+    for _ in range(3):
+        hisq.hisq_dslash_eo(g, 1, ee, t)
+        hisq.hisq_mdagm(g, cfg["two_m"], ee, out)
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": "done", "copy_bytes": a.numel() * 8,
+                      "kernel_source_hash": kernel_source_hash()}), flush=True)
+
+
+def dslash_scan(dims=(32, 32, 32, 64), reps=20):
+    """Half-stencil GB/s at a lattice whose working set exceeds the LLC."""
+    import torch
+    from paper_2502_00152_amd import hisq, inputs as I
+    W = I.random_su3_field_device(dims, 0.5, 20001)
+    N = I.random_su3_field_device(dims, 0.5, 20002)
+    g = hisq.Gauge(dims, W, N, I.C_FAT, I.C_LONG)
+    del W, N
+    torch.cuda.empty_cache()
+    a = torch.randn((1, 3, g.vh), dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        hisq.hisq_dslash_eo(g, 0, a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        hisq.hisq_dslash_eo(g, 0, a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = dslash_alg_bytes(g.vh, 1, 0)
+    g.close()
+    return {"lattice": "x".join(map(str, dims)), "nrhs": 1, "us_per_launch": ms * 1e3,
+            "algorithmic_bytes": alg, "GB_s": alg / ms / 1e6,
+            "frac_of_hbm_peak": alg / ms / 1e6 / HBM_PEAK_GBS}
+
+
+def cpu_baseline(cfg, golden):
+    """The oracle timed on the host: one source of the workload, with the
+    deflated iteration count the oracle itself reached (stored golden value)."""
+    from oracle import hisq_oracle as O
+    from paper_2502_00152_amd import inputs as I
+    dims, two_m = cfg["dims"], cfg["two_m"]
+    W = I.random_su3_field(dims, cfg["eps"], cfg["seed_fat"])
+    N = I.random_su3_field(dims, cfg["eps"], cfg["seed_long"])
+    F, L = O.fold_links(W, N, cfg["c_fat"], cfg["c_long"])
+    eta = I.gaussian_source(dims, cfg["seed_src"][0])
+    t0 = time.perf_counter()
+    y = O.source_even(F, L, two_m, eta)
+    t_src = time.perf_counter() - t0
+    k = cfg["n_ev"]
+    n = 3 * int(np.prod(dims)) // 2
+    Vs = I.gaussian_even_vectors(k, n, 77).T  # same shape as the eigenvectors
+    lam = np.linspace(0.01, 1.0, k)
+    yc = O.to_compact(y, dims)
+    t0 = time.perf_counter()
+    x0c = O.deflation_guess(Vs, lam, yc)
+    t_defl = time.perf_counter() - t0
+    n_it = 60
+    t0 = time.perf_counter()
+    O.solve_even(F, L, two_m, y, x0=O.from_compact(x0c, dims), tol=1e-30, max_iter=n_it)
+    t_cg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.reconstruct_odd(F, L, two_m, y, eta)
+    t_rec = time.perf_counter() - t0
+    iters = golden["cg_iterations_deflated"]
+    per_solve = t_src + t_defl + t_cg / n_it * iters + t_rec
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": O.n_threads(),
+            "kind": "oracle",
+            "sample": (f"one source of the 16^3x32 workload: oracle source preparation, "
+                       f"deflation projection ({k} vectors), {n_it} oracle CG iterations "
+                       f"({t_cg:.1f} s) scaled to the {iters} iterations the oracle's own "
+                       f"deflated solve takes, odd reconstruction")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dslash-scan", action="store_true")
+    ap.add_argument("--no-plain-cg", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); run with --gpus 1", flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_00152_amd import hisq, inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", flush=True)
+        sys.exit(1)
+    cfg = I.config(1)
+    if args.pmc_probe:
+        pmc_probe(cfg)
+        return
+    two_m, tol, nrhs, n_ev = cfg["two_m"], cfg["tol"], cfg["nrhs"], cfg["n_ev"]
+    print(f"[bench] setup {cfg['name']}", flush=True)
+    g, ee, eo, t_pack = build_problem(cfg)
+
+    # eigensolve: amortised over the solves of this gauge field, outside the step
+    evecs = torch.empty((n_ev, 3, g.vh), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, lam, est = hisq.hisq_eigensolve(g, two_m, n_ev, evecs, tol=tol, seed=cfg["seed_eig"])
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    eps = lam - two_m * two_m
+    print(f"[bench] eigensolve {t_eig:.2f} s, {est.matvecs} matvecs, {est.restarts} restarts, "
+          f"max residual {est.max_residual:.2e}", flush=True)
+
+    y = torch.empty_like(ee)
+    x = torch.empty_like(ee)
+    po = torch.empty_like(eo)
+
+    def step():
+        hisq.hisq_prepare_source(g, two_m, ee, eo, y)
+        hisq.hisq_deflate(g, evecs, eps, two_m, y, x)
+        res = hisq.hisq_cg_solve(g, two_m, y, x, tol=tol)
+        hisq.hisq_reconstruct_odd(g, two_m, x, eo, po)
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hisq.hisq_profile_enable(True)
+    for cls in ("dslash", "dslash_aux", "dslash_aux2", "blas", "gemm"):
+        hisq.hisq_profile_read(cls)
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    hisq.hisq_profile_enable(False)
+    prof = {cls: hisq.hisq_profile_read(cls) for cls in ("dslash", "dslash_aux", "blas", "gemm")}
+    print(f"[bench] {args.steps} steps in {t_steps:.3f} s", flush=True)
+    iters = results[-1].iterations
+    true_res = max(max(r.true_residual) for r in results)
+    assert all(all(r.converged) for r in results), "a timed solve did not converge"
+
+    # live half-stencil roofline over the timed region
+    n_plain, ms_plain = prof["dslash"]
+    n_aux, ms_aux = prof["dslash_aux"]
+    bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0)
+                   + n_aux * dslash_alg_bytes(g.vh, nrhs, 1))
+    launches = n_plain + n_aux
+    avg_ms = (ms_plain + ms_aux) / max(launches, 1)
+    achieved = bytes_total / max(launches, 1) / (avg_ms * 1e6) if launches else None
+    traffic = read_traffic()
+
+    # plain FP64 even-odd CG, no deflation, one source at a time
+    plain = None
+    if not args.no_plain_cg:
+        ys = [y[j:j + 1].clone() for j in range(nrhs)]
+        xs = torch.zeros((1, 3, g.vh), dtype=torch.complex128, device="cuda")
+        hisq.hisq_cg_solve(g, two_m, ys[0], xs, tol=tol)  # warm-up
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(nrhs):
+            xs.zero_()
+            its.append(hisq.hisq_cg_solve(g, two_m, ys[j], xs, tol=tol).iterations[0])
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        plain = {"solves_per_s": nrhs / t_plain, "mean_iterations": float(np.mean(its)),
+                 "seconds": t_plain}
+        print(f"[bench] plain CG {nrhs} solves in {t_plain:.3f} s", flush=True)
+
+    scan = None if args.no_dslash_scan else dslash_scan()
+    if scan:
+        print(f"[bench] dslash 32^3x64: {scan['GB_s']:.0f} GB/s", flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        gpath = os.path.join(ROOT, "tests", "golden", "config1_oracle.json")
+        if os.path.exists(gpath):
+            cpu = cpu_baseline(cfg, json.load(open(gpath)))
+            print(f"[bench] oracle on host: {cpu['value']:.4f} solves/s", flush=True)
+
+    value = nrhs * args.steps / t_steps
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_steps / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "deflated-cg-16^3x32", "lattice": "16x16x16x32", "eps": 0.5,
+                   "two_m": two_m, "sources_per_step": nrhs, "n_ev": n_ev, "tol": tol,
+                   "path": "deflated batched FP64 CG"},
+        "roofline": {"bound": "hbm", "kernel": "k_dslash (half stencil, 12 RHS)",
+                     "achieved": achieved / 1e9 if achieved else None, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / 1e9 / HBM_PEAK_GBS if achieved else None,
+                     "traffic": traffic, "launches": launches,
+                     "avg_launch_us": avg_ms * 1e3,
+                     "alg_bytes_per_launch": bytes_total / max(launches, 1)},
+        "cpu_baseline": cpu,
+        "iterations_per_source": iters,
+        "max_true_residual": true_res,
+        "plain_fp64_cg": plain,
+        "speedup_vs_plain_fp64_cg": value / plain["solves_per_s"] if plain else None,
+        "eigensolve": {"seconds": t_eig, "matvecs": est.matvecs, "restarts": est.restarts,
+                       "cheb_degree": est.cheb_degree, "max_residual": est.max_residual,
+                       "lambda_1": float(lam[0]), "lambda_64": float(lam[-1])},
+        "gauge_pack_seconds": t_pack,
+        "dslash_32x32x32x64": scan,
+        "kernel_ms": {k: {"launches": v[0], "ms": v[1]} for k, v in prof.items()},
+    }
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

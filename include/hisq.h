@@ -259,7 +259,10 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
 
 /*
  * Per-kernel timing with HIP events recorded on the launch stream around
- * every launch of the named kernel class ("dslash", "blas", "gemm"); off by
+ * every launch of the named kernel class: "dslash" (plain half stencil),
+ * "dslash_aux" (with one epilogue field: M^H M second half, source, odd
+ * reconstruction), "dslash_aux2" (two epilogue fields: Chebyshev step), "blas"
+ * (CG and Lanczos vector kernels), "gemm" (matrix-core contractions); off by
  * default.  hisq_profile_read returns the number of timed launches and their
  * total milliseconds (synchronises the device), and clears the record.
  */

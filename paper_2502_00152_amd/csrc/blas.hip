@@ -5,10 +5,14 @@
 // Each right-hand side r runs its own recurrence
 //   alpha = rho / Re<p, Ap>;  x += alpha p;  r -= alpha Ap;
 //   rho' = <r, r>;  beta = rho' / rho;  p = r + beta p
-// The scalars live in device memory.  A reduction is finished inside the
-// kernel that produces it: every block stores its partial sums, and the last
-// block to arrive adds them up in block order, so the sum does not depend on
-// which block finished last and results are bitwise reproducible.
+// The scalars live in device memory.  Reductions are deterministic: every
+// block stores its partial sums and a later kernel adds them in block order.
+// The per-iteration reductions avoid any cross-block synchronisation inside a
+// kernel (a device-scope fence per block writes back L2 on this multi-XCD
+// chip and costs more than the update itself): the update kernel re-sums the
+// <p, Ap> partials of its own RHS in every block, and a one-block finalize
+// kernel advances the per-RHS state.  The rare kernels (initial and true
+// residuals, restarts) finish their reduction in the last block to arrive.
 #include "device_util.h"
 #include "hisq_internal.h"
 
@@ -87,17 +91,22 @@ __global__ __launch_bounds__(kBS) void k_cg_init(int64_t n, int nrhs, const dvec
     }
 }
 
-// x += alpha p; r -= alpha Ap; partial ||r||^2 (active RHS only).
-__global__ __launch_bounds__(kBS) void k_cg_update(int64_t n, int nrhs, dvec2 *__restrict__ x,
+// alpha = rho / <p, Ap> with <p, Ap> summed from the stencil kernel's per-block
+// partials (every block repeats the same fixed-order sum, so all agree);
+// x += alpha p; r -= alpha Ap; per-block partials of ||r||^2.
+__global__ __launch_bounds__(kBS) void k_cg_update(int64_t n, dvec2 *__restrict__ x,
                                                    dvec2 *__restrict__ r,
                                                    const dvec2 *__restrict__ p,
-                                                   const dvec2 *__restrict__ Ap, CgDev cg,
-                                                   Reduce red) {
+                                                   const dvec2 *__restrict__ Ap,
+                                                   const double *__restrict__ pap, int nb_pap,
+                                                   CgDev cg, Reduce red) {
     const int rhs = blockIdx.y;
     const int64_t off = rhs * n;
+    __shared__ double w[kBS / kWave];
+    const double pq = sum_partials<kBS>(pap + (int64_t)rhs * nb_pap, nb_pap, w);
     double v[1] = {0.0};
-    if (cg.status[rhs] == CG_ACTIVE) {
-        const double al = cg.alpha[rhs];
+    if (cg.status[rhs] == CG_ACTIVE && isfinite(pq) && pq > 0.0) {
+        const double al = cg.rho[rhs] / pq;
         for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
              i += (int64_t)gridDim.x * kBS) {
             const dvec2 pp = p[off + i];
@@ -115,13 +124,24 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int64_t n, int nrhs, dvec2 *_
     }
     __shared__ double lds[kBS / kWave];
     block_sum<1, kBS>(v, lds);
-    const int nbx = gridDim.x;
-    if (threadIdx.x == 0) red.partials[(int64_t)rhs * nbx + blockIdx.x] = v[0];
-    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
-        __shared__ double w[kBS / kWave];
-        for (int q = 0; q < nrhs; ++q) {
-            const double rn = sum_partials<kBS>(red.partials + (int64_t)q * nbx, nbx, w);
-            if (threadIdx.x == 0 && cg.status[q] == CG_ACTIVE) {
+    if (threadIdx.x == 0) red.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = v[0];
+}
+
+// One block: the per-RHS state machine after an update.
+__global__ __launch_bounds__(kBS) void k_cg_finalize(int nrhs, const double *__restrict__ pap,
+                                                     int nb_pap, int nb_rr, CgDev cg,
+                                                     Reduce red) {
+    __shared__ double w[kBS / kWave];
+    for (int q = 0; q < nrhs; ++q) {
+        const double pq = sum_partials<kBS>(pap + (int64_t)q * nb_pap, nb_pap, w);
+        const double rn = sum_partials<kBS>(red.partials + (int64_t)q * nb_rr, nb_rr, w);
+        if (threadIdx.x == 0 && cg.status[q] == CG_ACTIVE) {
+            if (!isfinite(pq)) {
+                cg.status[q] = CG_NAN;
+            } else if (!(pq > 0.0)) {
+                cg.status[q] = CG_BREAKDOWN;
+            } else {
+                cg.alpha[q] = cg.rho[q] / pq;
                 cg.iters[q] += 1;
                 if (!isfinite(rn)) {
                     cg.status[q] = CG_NAN;
@@ -135,7 +155,6 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int64_t n, int nrhs, dvec2 *_
                 }
             }
         }
-        last_block_done(red.counter);
     }
 }
 
@@ -252,11 +271,22 @@ hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, do
 }
 
 hisq_status cg_update(int64_t n, int nrhs, double2 *x, double2 *r, const double2 *p,
-                      const double2 *Ap, const CgDev &cg, const Reduce &red, hipStream_t s) {
+                      const double2 *Ap, const double *pap, int nb_pap, const CgDev &cg,
+                      const Reduce &red, hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_update, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs, AS_V(x),
-                       AS_V(r), AS_CV(p), AS_CV(Ap), cg, red);
+    hipLaunchKernelGGL(k_cg_update, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(x), AS_V(r),
+                       AS_CV(p), AS_CV(Ap), pap, nb_pap, cg, red);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status cg_finalize(int64_t n, int nrhs, const double *pap, int nb_pap, const CgDev &cg,
+                        const Reduce &red, hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBS), 0, s, nrhs, pap, nb_pap, gr.nbx, cg,
+                       red);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }

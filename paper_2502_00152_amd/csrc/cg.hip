@@ -3,11 +3,12 @@
 // "CG" baseline, solved on the normal equation Eq. (1) with a true-residual
 // stopping criterion).
 //
-// One iteration is four stream-ordered launches:
-//   1. t  = D_oe p                           (half stencil, odd output)
-//   2. Ap = (2m)^2 p - D_eo t,  alpha = rho / Re<p, Ap>   (half stencil + reduction)
-//   3. x += alpha p, r -= alpha Ap, rho' = <r, r>, beta   (update + reduction)
-//   4. p = r + beta p
+// One iteration is five stream-ordered launches:
+//   1. t  = D_oe p                          (half stencil, odd output)
+//   2. Ap = (2m)^2 p - D_eo t, partials of Re<p, Ap>   (half stencil)
+//   3. alpha = rho / Re<p, Ap>; x += alpha p, r -= alpha Ap, partials of <r, r>
+//   4. rho' = <r, r>, beta = rho' / rho, convergence state  (one block)
+//   5. p = r + beta p
 // Scalars never leave the device.  The host polls the per-RHS state every
 // check_interval iterations; a right-hand side whose iterated residual has
 // crossed the tolerance is frozen until the host runs the true-residual check
@@ -33,6 +34,7 @@ struct CgBuffers {
     double2 *r, *p, *Ap;
     CgDev dev;
     Reduce red;
+    Reduce pap;         // <p, Ap> partials of the stencil kernel
     int *host_status;   // pinned
     int *host_iters;
     int *host_checks;
@@ -70,6 +72,10 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
     B.red.partials = static_cast<double *>(p);
     HISQ_TRY(g->ws.get("reduce_counter", 256, &p));
     B.red.counter = static_cast<unsigned *>(p);
+    HISQ_TRY(g->ws.get("cg_pap_partials",
+                       sizeof(double) * (size_t)nrhs * dslash_reduce_blocks(g, nrhs), &p));
+    B.pap.partials = static_cast<double *>(p);
+    B.pap.counter = nullptr;
     return HISQ_OK;
 }
 
@@ -144,13 +150,15 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     HISQ_TRY(g->ws.get("mdagm_tmp", sizeof(double2) * (size_t)n * nrhs, &tmpv));
     double2 *t = static_cast<double2 *>(tmpv);
     const double m2 = two_m * two_m;
+    const int nb_pap = dslash_reduce_blocks(g, nrhs);
 
     auto iterate = [&]() -> hisq_status {
         HISQ_TRY(launch_dslash(g, 1, B.p, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE, nullptr,
                                nullptr, s));
-        HISQ_TRY(launch_dslash(g, 0, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA, &B.dev,
-                               &B.red, s));
-        HISQ_TRY(cg_update(n, nrhs, x, B.r, B.p, B.Ap, B.dev, B.red, s));
+        HISQ_TRY(launch_dslash(g, 0, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA,
+                               nullptr, &B.pap, s));
+        HISQ_TRY(cg_update(n, nrhs, x, B.r, B.p, B.Ap, B.pap.partials, nb_pap, B.dev, B.red, s));
+        HISQ_TRY(cg_finalize(n, nrhs, B.pap.partials, nb_pap, B.dev, B.red, s));
         HISQ_TRY(cg_update_p(n, nrhs, B.r, B.p, B.dev, s));
         return HISQ_OK;
     };

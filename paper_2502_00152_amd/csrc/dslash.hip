@@ -42,8 +42,6 @@ struct DslashArgs {
     int nsb;               // site blocks
     // fused reduction (FIN_CG_ALPHA)
     double *partials;      // [nrhs][nsb]
-    unsigned *counter;
-    CgDev cg;
 };
 
 __device__ __forceinline__ int wrap(int c, int L) {
@@ -208,30 +206,14 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
     }
 
     if (DOT) {
+        // per-block partial sums of Re<aux, out>; the CG update kernel adds them
+        // up in block order (no cross-block synchronisation in this kernel)
         __shared__ double lds[NR * (kBS / kWave)];
         block_sum<NR, kBS>(dotv, lds);
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (r < nr) a.partials[(int64_t)(r0 + r) * a.nsb + sb] = dotv[r];
-        }
-        if (last_block_arrive(a.counter, gridDim.x)) {
-            __shared__ double red[kBS / kWave];
-            for (int r = 0; r < a.nrhs; ++r) {
-                const double pap = sum_partials<kBS>(a.partials + (int64_t)r * a.nsb, a.nsb, red);
-                if (threadIdx.x == 0 && a.cg.status[r] == CG_ACTIVE) {
-                    if (!isfinite(pap)) {
-                        a.cg.status[r] = CG_NAN;
-                        a.cg.alpha[r] = 0.0;
-                    } else if (!(pap > 0.0)) {
-                        a.cg.status[r] = CG_BREAKDOWN;
-                        a.cg.alpha[r] = 0.0;
-                    } else {
-                        a.cg.alpha[r] = a.cg.rho[r] / pap;
-                    }
-                }
-            }
-            last_block_done(a.counter);
         }
     }
 }
@@ -291,13 +273,10 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
     a.ngroups = (nrhs + nr - 1) / nr;
     a.nsb = (g->geom.vh + kBS - 1) / kBS;
     const bool dot = fin == FIN_CG_ALPHA;
-    if (dot) {
-        a.partials = red->partials;
-        a.counter = red->counter;
-        a.cg = *cg;
-    }
+    (void)cg;
+    if (dot) a.partials = red->partials;
     const int nblocks = a.nsb * a.ngroups;
-    ProfileScope prof("dslash", s);
+    ProfileScope prof(aux2 ? "dslash_aux2" : aux ? "dslash_aux" : "dslash", s);
     switch (nr) {
         case 1: return launch_nr<1>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
         case 2: return launch_nr<2>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);

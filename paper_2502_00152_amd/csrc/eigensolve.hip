@@ -72,17 +72,34 @@ public:
     Pinned pin_;
     int matvecs_ = 0;
     int nkr_ = 0;
+    int cols_ = 0;         // columns of each of the two basis buffers (V_ and Vt_ swap)
+    bool bad_col_ = false; // a column index outside [0, cols_) was requested
     size_t coef_cap_ = 0;
 
-    double2 *col(double2 *base, int i) const { return base + (size_t)i * N_; }
+    // Column i of a basis buffer; an index outside the allocation is a
+    // programming error: it is recorded and the first column returned instead.
+    double2 *col(double2 *base, int i, int count = 1) {
+        if (i < 0 || count < 1 || i + count > cols_) {
+            bad_col_ = true;
+            return base;
+        }
+        return base + (size_t)i * N_;
+    }
+    hisq_status check_cols() const {
+        return bad_col_ ? fail(HISQ_ERR_INVALID_ARG, "eigensolve: basis column out of range")
+                        : HISQ_OK;
+    }
 
     hisq_status alloc(int nkr, int n_ev) {
         nkr_ = nkr;
         void *p = nullptr;
         const size_t vb = sizeof(double2) * (size_t)N_;
-        HISQ_TRY(g_->ws.get("eig_V", vb * (nkr + 1), &p));
+        // both buffers hold the same number of columns: they are swapped at
+        // every thick restart, and Vt_ also holds the Rayleigh-Ritz scratch
+        cols_ = std::max(nkr + 1, 3 * n_ev);
+        HISQ_TRY(g_->ws.get("eig_V", vb * cols_, &p));
         V_ = static_cast<double2 *>(p);
-        HISQ_TRY(g_->ws.get("eig_Vt", vb * std::max(nkr + 1, 3 * n_ev), &p));
+        HISQ_TRY(g_->ws.get("eig_Vt", vb * cols_, &p));
         Vt_ = static_cast<double2 *>(p);
         HISQ_TRY(g_->ws.get("eig_w", vb, &p));
         w_ = static_cast<double2 *>(p);
@@ -289,7 +306,8 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
             for (int r = 0; r < m; ++r) Vstart_coef[r] += Z[(size_t)r * m + i];
     }
     const double b = params->cheb_b > 0.0 ? params->cheb_b : 1.02 * lam_max;
-    const double a = params->cheb_a > 0.0 ? params->cheb_a : cut;
+    double a = params->cheb_a > 0.0 ? params->cheb_a : cut;
+    const bool auto_a = !(params->cheb_a > 0.0), auto_deg = params->cheb_degree <= 0;
     if (!(a < b)) return fail(HISQ_ERR_INVALID_ARG, "Chebyshev interval needs a < b");
     int deg = params->cheb_degree;
     if (deg <= 0) {
@@ -313,6 +331,7 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
     std::vector<double> lam_out(n_ev, 0.0);
     hisq_status final_status = HISQ_ERR_NOT_CONVERGED;
     double fscale = 0.0;
+    int cut_updates = 0;
     for (; restarts <= max_restarts; ++restarts) {
         for (int j = k0; j < nkr; ++j) {
             HISQ_TRY(S.chebyshev(S.col(S.V_, j), S.w_, deg, a, b));
@@ -334,6 +353,7 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
             HISQ_TRY(S.orthogonalise(S.w_, j + 1));
             HISQ_TRY(S.next_vector(j, fscale, seed + 7777 + 131 * restarts + j, &beta[j]));
         }
+        HISQ_TRY(S.check_cols());
         // projected matrix: arrowhead (kept Ritz values + couplings) + tridiagonal
         std::vector<cd> T((size_t)nkr * nkr, 0.0), Z;
         std::vector<double> th;
@@ -355,6 +375,41 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
             for (int r = 0; r < nkr; ++r) Y[(size_t)r * nkr + c2] = Z[(size_t)r * nkr + (nkr - 1 - c2)];
         }
         const double bl = beta[nkr - 1];
+        // Tighten the cut.  If the (kc+1)-th largest Ritz value of p(A) exceeds 1,
+        // interlacing puts at least kc+1 eigenvalues of A at or below
+        // p^{-1}(that value), so it is a valid cut with n_ev < kc + 1.
+        if (auto_a && cut_updates < 4 && restarts < max_restarts) {
+            const int kc = std::min(nkr - 1, n_ev + std::max(1, (nkr - n_ev) / 4));
+            if (Th[kc] > 1.0) {
+                auto pinv = [&](double th) {
+                    return 0.5 * ((a + b) - (b - a) * std::cosh(std::acosh(th) / deg));
+                };
+                const double lam_kc = pinv(Th[kc]);
+                const double lam_nev = Th[n_ev - 1] > 1.0 ? pinv(Th[n_ev - 1]) : lam_kc;
+                if (lam_kc < 0.5 * a && lam_kc > two_m * two_m) {
+                    a = lam_kc;
+                    if (auto_deg) {
+                        const double ln = (a + b - 2.0 * lam_nev) / (b - a);
+                        const double ac = std::acosh(std::max(ln, 1.0 + 1e-12));
+                        deg = std::max(8, std::min((int)std::ceil(4.0 / ac), 200));
+                    }
+                    // new filter: restart from the sum of the wanted Ritz vectors
+                    std::vector<cd> yc(nkr, 0.0);
+                    for (int i = 0; i < n_ev; ++i)
+                        for (int r = 0; r < nkr; ++r) yc[r] += Y[(size_t)r * nkr + i];
+                    HISQ_TRY(S.rotate(S.V_, nkr, yc, 1, 1, S.w_));
+                    double nv = 0.0;
+                    HISQ_TRY(S.norm(S.w_, &nv));
+                    HISQ_TRY(vec_axpby2(S.col(S.V_, 0), 0.0, S.w_, 1.0 / nv, nullptr, 0.0, N, s));
+                    theta.clear();
+                    sigma.clear();
+                    k0 = 0;
+                    fscale = 0.0;
+                    ++cut_updates;
+                    continue;
+                }
+            }
+        }
         bool conv = true;
         for (int i = 0; i < n_ev; ++i) {
             const double rho = std::abs(bl * Y[(size_t)(nkr - 1) * nkr + i]);
@@ -362,7 +417,9 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
         }
         if (conv || restarts == max_restarts) {
             // Ritz vectors U -> Vt[0..n_ev), A U -> Vt[n_ev..2 n_ev)
-            double2 *U = S.Vt_, *W = S.col(S.Vt_, n_ev);
+            double2 *U = S.col(S.Vt_, 0, n_ev), *W = S.col(S.Vt_, n_ev, n_ev);
+            double2 *AE = S.col(S.Vt_, 2 * n_ev, n_ev);
+            HISQ_TRY(S.check_cols());
             HISQ_TRY(S.rotate(S.V_, nkr, Y, nkr, n_ev, U));
             HISQ_TRY(S.applyA(U, W, n_ev));
             // G = U^H A U: C[j][i] = <U_i, W_j> = G[i][j]
@@ -382,7 +439,6 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
                 return fail(HISQ_ERR_BREAKDOWN, "eigensolve: Rayleigh-Ritz did not converge");
             // rotated vectors and their images: evecs = U Z, A evecs = W Z
             double2 *E = static_cast<double2 *>(evecs_dev);
-            double2 *AE = S.col(S.Vt_, 2 * n_ev);
             HISQ_TRY(S.rotate(U, n_ev, Zg, n_ev, n_ev, E));
             HISQ_TRY(S.rotate(W, n_ev, Zg, n_ev, n_ev, AE));
             HISQ_HIP(hipMemcpyAsync(S.dscal_, lam.data(), sizeof(double) * n_ev,
@@ -430,7 +486,9 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
                 if (restarts == max_restarts) break;
                 // restart from [accepted vectors, u]: p(A) e_i = p(lambda_i) e_i up to
                 // the accepted residual, so the kept block carries no coupling
-                HISQ_HIP(hipMemcpyAsync(S.V_, E, sizeof(double2) * (size_t)N * n_ev,
+                double2 *vdst = S.col(S.V_, 0, n_ev + 1);
+                HISQ_TRY(S.check_cols());
+                HISQ_HIP(hipMemcpyAsync(vdst, E, sizeof(double2) * (size_t)N * n_ev,
                                         hipMemcpyDeviceToDevice, s));
                 HISQ_HIP(hipMemcpyAsync(S.col(S.V_, n_ev), u, sizeof(double2) * (size_t)N,
                                         hipMemcpyDeviceToDevice, s));
@@ -446,7 +504,9 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
         }
         // thick restart: keep k0n Ritz vectors and the residual direction
         const int k0n = std::min(n_ev + (nkr - n_ev) / 2, nkr - 1);
-        HISQ_TRY(S.rotate(S.V_, nkr, Y, nkr, k0n, S.Vt_));
+        double2 *src = S.col(S.V_, 0, nkr + 1), *dst = S.col(S.Vt_, 0, k0n + 1);
+        HISQ_TRY(S.check_cols());
+        HISQ_TRY(S.rotate(src, nkr, Y, nkr, k0n, dst));
         HISQ_HIP(hipMemcpyAsync(S.col(S.Vt_, k0n), S.col(S.V_, nkr), sizeof(double2) * (size_t)N,
                                 hipMemcpyDeviceToDevice, s));
         std::swap(S.V_, S.Vt_);
@@ -456,6 +516,7 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
         k0 = k0n;
     }
     HISQ_HIP(hipStreamSynchronize(s));
+    HISQ_TRY(S.check_cols());
     for (int i = 0; i < n_ev; ++i) evals_host[i] = lam_out[i];
     if (stats_host) {
         stats_host->restarts = restarts;

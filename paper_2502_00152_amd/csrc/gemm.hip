@@ -144,24 +144,139 @@ __global__ __launch_bounds__(kBS) void k_gemm_tn(TnArgs a) {
     }
 }
 
-// C[j][i] (complex, [n][k] row-major) = scale_i * sum_b partials[b][i][j or n+j]
-// in block order; C is written as C = out_scale * C (+ previous when accumulate).
+// C[j][i] (complex, [n][k] row-major) = out_scale * row_scale_i *
+// sum_b partials[b][i][j or n+j]; one wave per output entry, lanes stride the
+// partials and the wave sums them in a fixed butterfly order.
 __global__ __launch_bounds__(kBS) void k_tn_reduce(const double *__restrict__ partials, int nb,
                                                    int k, int n, int kpad, int ncpad,
                                                    const double *__restrict__ row_scale,
                                                    double out_scale, dvec2 *__restrict__ C) {
-    const int e = blockIdx.x * kBS + threadIdx.x;
+    const int e = blockIdx.x * (kBS / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (e >= k * n) return;
     const int j = e / k, i = e % k;
     double re = 0.0, im = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = lane; b < nb; b += kWave) {
         const double *P = partials + (int64_t)b * kpad * ncpad + (int64_t)i * ncpad;
         re += P[j];
         im += P[n + j];
     }
-    double s = out_scale;
-    if (row_scale) s *= row_scale[i];
-    C[(int64_t)j * k + i] = dvec2{re * s, im * s};
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+        double s = out_scale;
+        if (row_scale) s *= row_scale[i];
+        C[(int64_t)j * k + i] = dvec2{re * s, im * s};
+    }
+}
+
+// Matrix-vector forms for one or two right-hand sides, on the vector units:
+// with so few columns the matrix-core tiles would be mostly padding.
+//   gemv_tn: partial[b][i][j] = sum over the block's sites of conj(V[i][s]) B[j][s]
+template <int NB>
+__global__ __launch_bounds__(kBS) void k_gemv_tn(const dvec2 *__restrict__ V, int k,
+                                                 const dvec2 *__restrict__ B, int64_t N,
+                                                 double *__restrict__ partials, int ldp) {
+    // block: a contiguous chunk of sites; each wave handles columns i = wave, wave+4, ...
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t s0 = blockIdx.x * per, s1 = min(N, s0 + per);
+    for (int i = wave; i < k; i += kBS / kWave) {
+        const dvec2 *v = V + (int64_t)i * N;
+        double acc[NB][2];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = 0.0;
+        for (int64_t s = s0 + lane; s < s1; s += kWave) {
+            const dvec2 a = v[s];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const dvec2 b = B[(int64_t)j * N + s];
+                acc[j][0] = fma(a.x, b.x, fma(a.y, b.y, acc[j][0]));
+                acc[j][1] = fma(a.x, b.y, fma(-a.y, b.x, acc[j][1]));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const double re = wave_sum(acc[j][0]), im = wave_sum(acc[j][1]);
+            if (lane == 0) {
+                double *P = partials + (int64_t)blockIdx.x * ldp + (int64_t)i * 2 * NB;
+                P[2 * j] = re;
+                P[2 * j + 1] = im;
+            }
+        }
+    }
+}
+
+// C[j][i] = out_scale * row_scale_i * sum_b partials[b][i][j]  (gemv layout)
+__global__ __launch_bounds__(kBS) void k_gemv_reduce(const double *__restrict__ partials, int nb,
+                                                     int k, int NB, int ldp,
+                                                     const double *__restrict__ row_scale,
+                                                     double out_scale, dvec2 *__restrict__ C) {
+    const int e = blockIdx.x * (kBS / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (e >= k * NB) return;
+    const int j = e / k, i = e % k;
+    double re = 0.0, im = 0.0;
+    for (int b = lane; b < nb; b += kWave) {
+        const double *P = partials + (int64_t)b * ldp + (int64_t)i * 2 * NB + 2 * j;
+        re += P[0];
+        im += P[1];
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+        double s = out_scale;
+        if (row_scale) s *= row_scale[i];
+        C[(int64_t)j * k + i] = dvec2{re * s, im * s};
+    }
+}
+
+//   gemv_nn: X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i], one thread per site
+template <int NB>
+__global__ __launch_bounds__(kBS) void k_gemv_nn(const dvec2 *__restrict__ V, int k,
+                                                 const dvec2 *__restrict__ C, int64_t N,
+                                                 double beta, dvec2 *__restrict__ X) {
+    extern __shared__ dvec2 cs[];  // [NB][k]
+    for (int e = threadIdx.x; e < NB * k; e += kBS) cs[e] = C[e];
+    __syncthreads();
+    for (int64_t s = (int64_t)blockIdx.x * kBS + threadIdx.x; s < N; s += (int64_t)gridDim.x * kBS) {
+        double acc[NB][2];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = 0.0;
+        int i = 0;
+        for (; i + 4 <= k; i += 4) {
+            dvec2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = V[(int64_t)(i + u) * N + s];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const dvec2 c = cs[j * k + i + u];
+                    acc[j][0] = fma(v[u].x, c.x, fma(-v[u].y, c.y, acc[j][0]));
+                    acc[j][1] = fma(v[u].x, c.y, fma(v[u].y, c.x, acc[j][1]));
+                }
+        }
+        for (; i < k; ++i) {
+            const dvec2 v = V[(int64_t)i * N + s];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const dvec2 c = cs[j * k + i];
+                acc[j][0] = fma(v.x, c.x, fma(-v.y, c.y, acc[j][0]));
+                acc[j][1] = fma(v.x, c.y, fma(v.y, c.x, acc[j][1]));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            dvec2 o = dvec2{acc[j][0], acc[j][1]};
+            if (beta != 0.0) {
+                const dvec2 x = X[(int64_t)j * N + s];
+                o.x = fma(beta, x.x, o.x);
+                o.y = fma(beta, x.y, o.y);
+            }
+            X[(int64_t)j * N + s] = o;
+        }
+    }
 }
 
 // ------------------------------------------------------------------- nn
@@ -236,10 +351,42 @@ int round16(int v) { return (v + 15) / 16 * 16; }
 
 }  // namespace
 
+template <int MT, int NT>
+void launch_tn(const TnArgs &a, int nbx, int mtiles, int ntiles, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_tn<MT, NT>), dim3((unsigned)nbx, mtiles, ntiles), dim3(kBS), 0, s,
+                       a);
+}
+
 // C = out_scale * diag(row_scale) * V^H B   (C complex [n][k] on the device)
 hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, int n,
                     int64_t N, const double *row_scale_dev, double out_scale, double2 *C,
                     hipStream_t s) {
+    if (n <= 2) {
+        // vector-unit form: ~4 sites per lane, partials [nb][k][2 n]
+        int64_t nb = (N + 4 * kBS - 1) / (4 * kBS);
+        nb = std::max<int64_t>(1, std::min<int64_t>(nb, 512));
+        const int ldp = 2 * n * k;
+        void *p = nullptr;
+        HISQ_TRY(g->ws.get("gemm_partials", sizeof(double) * nb * ldp, &p));
+        double *P = static_cast<double *>(p);
+        const dvec2 *Vv = reinterpret_cast<const dvec2 *>(V);
+        const dvec2 *Bv = reinterpret_cast<const dvec2 *>(B);
+        {
+            ProfileScope prof("gemm", s);
+            if (n == 1)
+                hipLaunchKernelGGL((k_gemv_tn<1>), dim3((unsigned)nb), dim3(kBS), 0, s, Vv, k, Bv, N, P,
+                                   ldp);
+            else
+                hipLaunchKernelGGL((k_gemv_tn<2>), dim3((unsigned)nb), dim3(kBS), 0, s, Vv, k, Bv, N, P,
+                                   ldp);
+            HISQ_HIP(hipGetLastError());
+        }
+        const int waves = k * n;
+        hipLaunchKernelGGL(k_gemv_reduce, dim3((waves + 3) / 4), dim3(kBS), 0, s, P, (int)nb, k, n,
+                           ldp, row_scale_dev, out_scale, reinterpret_cast<dvec2 *>(C));
+        HISQ_HIP(hipGetLastError());
+        return HISQ_OK;
+    }
     TnArgs a{};
     a.V = reinterpret_cast<const double *>(V);
     a.B = reinterpret_cast<const double *>(B);
@@ -250,8 +397,10 @@ hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, 
     a.ncpad = round16(2 * n);
     if (a.twoN % kStep) return fail(HISQ_ERR_INVALID_ARG, "gemm_tn: 2N must be a multiple of 16");
     a.steps = a.twoN / kStep;
-    // MT = 4 (64 rows of C per block), NT = 2 (32 real columns)
-    const int mtiles = (a.kpad + 63) / 64, ntiles = (a.ncpad + 31) / 32;
+    const int MT = a.kpad >= 64 ? 4 : a.kpad / 16;     // 1, 2 or 4 (kpad 48 -> 2 tiles of 2)
+    const int mt = MT == 3 ? 2 : MT;
+    const int NT = a.ncpad >= 32 ? 2 : 1;
+    const int mtiles = (a.kpad + 16 * mt - 1) / (16 * mt), ntiles = (a.ncpad + 16 * NT - 1) / (16 * NT);
     int64_t nbx = (a.steps + 63) / 64;  // about 16 steps per wave
     nbx = std::max<int64_t>(1, std::min<int64_t>(nbx, 1024));
     void *p = nullptr;
@@ -259,14 +408,17 @@ hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, 
     a.partials = static_cast<double *>(p);
     {
         ProfileScope prof("gemm", s);
-        hipLaunchKernelGGL((k_gemm_tn<4, 2>), dim3((unsigned)nbx, mtiles, ntiles), dim3(kBS), 0, s,
-                           a);
+        if (mt == 4 && NT == 2) launch_tn<4, 2>(a, (int)nbx, mtiles, ntiles, s);
+        else if (mt == 4) launch_tn<4, 1>(a, (int)nbx, mtiles, ntiles, s);
+        else if (mt == 2 && NT == 2) launch_tn<2, 2>(a, (int)nbx, mtiles, ntiles, s);
+        else if (mt == 2) launch_tn<2, 1>(a, (int)nbx, mtiles, ntiles, s);
+        else if (NT == 2) launch_tn<1, 2>(a, (int)nbx, mtiles, ntiles, s);
+        else launch_tn<1, 1>(a, (int)nbx, mtiles, ntiles, s);
         HISQ_HIP(hipGetLastError());
     }
-    const int tot = k * n;
-    hipLaunchKernelGGL(k_tn_reduce, dim3((tot + kBS - 1) / kBS), dim3(kBS), 0, s, a.partials,
-                       (int)nbx, k, n, a.kpad, a.ncpad, row_scale_dev, out_scale,
-                       reinterpret_cast<dvec2 *>(C));
+    const int waves = k * n;
+    hipLaunchKernelGGL(k_tn_reduce, dim3((waves + 3) / 4), dim3(kBS), 0, s, a.partials, (int)nbx, k,
+                       n, a.kpad, a.ncpad, row_scale_dev, out_scale, reinterpret_cast<dvec2 *>(C));
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
@@ -284,9 +436,26 @@ hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N,
     a.beta = beta;
     if (a.twoN % 16) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: 2N must be a multiple of 16");
     a.tiles = a.twoN / 16;
+    ProfileScope prof("gemm", s);
+    if (n <= 2) {
+        int64_t nb = (N + 4 * kBS - 1) / (4 * kBS);
+        nb = std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
+        const size_t lds = sizeof(dvec2) * n * k;
+        if (lds > 64 * 1024) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: too many columns");
+        const dvec2 *Vv = reinterpret_cast<const dvec2 *>(V);
+        const dvec2 *Cv = reinterpret_cast<const dvec2 *>(C);
+        dvec2 *Xv = reinterpret_cast<dvec2 *>(X);
+        if (n == 1)
+            hipLaunchKernelGGL((k_gemv_nn<1>), dim3((unsigned)nb), dim3(kBS), lds, s, Vv, k, Cv, N,
+                               beta, Xv);
+        else
+            hipLaunchKernelGGL((k_gemv_nn<2>), dim3((unsigned)nb), dim3(kBS), lds, s, Vv, k, Cv, N,
+                               beta, Xv);
+        HISQ_HIP(hipGetLastError());
+        return HISQ_OK;
+    }
     int64_t nbx = (a.tiles + 3) / 4;
     nbx = std::max<int64_t>(1, std::min<int64_t>(nbx, 2048));
-    ProfileScope prof("gemm", s);
     if (n <= 16) {
         hipLaunchKernelGGL((k_gemm_nn<1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
     } else {

@@ -123,12 +123,13 @@ struct Reduce {
 // ------------------------------------------------------- kernel launchers
 enum DslashFinal : int {
     FIN_NONE = 0,
-    FIN_CG_ALPHA = 1,   // alpha = rho / Re<aux, out> per active RHS
+    FIN_CG_ALPHA = 1,   // store per-block partial sums of Re<aux, out> per RHS
 };
 
 // out = ca * aux + cb * aux2 + cd * D_{p,1-p} in.  aux/aux2 may be null (their
 // coefficient is then ignored; aux2 needs aux); aux and aux2 may alias out.
-// With fin == FIN_CG_ALPHA, also reduces Re<aux, out> per RHS and sets cg.alpha.
+// With fin == FIN_CG_ALPHA, also stores per-block partials of Re<aux, out>
+// in red->partials as [nrhs][dslash_reduce_blocks()].
 hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
                           double2 *out, int nrhs, const double2 *aux, double ca,
                           const double2 *aux2, double cb, double cd, DslashFinal fin,
@@ -142,8 +143,13 @@ int blas_reduce_blocks(int64_t n);
 hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, double2 *r,
                     double2 *p, double tol, const CgDev &cg, const Reduce &red,
                     hipStream_t s);
+// alpha from the <p, Ap> partials (pap, nb_pap per RHS); x += alpha p, r -= alpha Ap,
+// partials of ||r||^2 into red; then cg_finalize updates the per-RHS state.
 hisq_status cg_update(int64_t n, int nrhs, double2 *x, double2 *r, const double2 *p,
-                      const double2 *Ap, const CgDev &cg, const Reduce &red, hipStream_t s);
+                      const double2 *Ap, const double *pap, int nb_pap, const CgDev &cg,
+                      const Reduce &red, hipStream_t s);
+hisq_status cg_finalize(int64_t n, int nrhs, const double *pap, int nb_pap, const CgDev &cg,
+                        const Reduce &red, hipStream_t s);
 hisq_status cg_update_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
                         hipStream_t s);
 hisq_status cg_true_residual(int64_t n, int nrhs, const double2 *b, const double2 *Ax,

@@ -38,6 +38,7 @@ __all__ = [
     "unit_links",
     "config",
     "CONFIGS",
+    "random_su3_field_device",
 ]
 
 
@@ -139,3 +140,34 @@ def config(c: int) -> dict:
     d["c_fat"] = C_FAT
     d["c_long"] = C_LONG
     return d
+
+
+def random_su3_field_device(dims, eps: float, seed: int, device="cuda"):
+    """Same distribution as random_su3_field, drawn with torch on the device.
+
+    For timing-only runs on lattices too large to draw on the host quickly; the
+    random stream differs from random_su3_field, so parity tests use that one.
+    exp(i eps H) is evaluated by scaling and squaring of its Taylor series
+    (||i eps H / 16|| < 0.4 for the eps used here, 14 terms: error < 1e-16).
+    """
+    import torch
+
+    X, Y, Z, T = (int(d) for d in dims)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    lam = torch.from_numpy(np.ascontiguousarray(GELL_MANN.reshape(8, 9))).to(device)
+    out = torch.empty((4, T, Z, Y, X, 3, 3), dtype=torch.complex128, device=device)
+    eye = torch.eye(3, dtype=torch.complex128, device=device)
+    for mu in range(4):
+        h = torch.randn((T, Z, Y, X, 8), dtype=torch.float64, generator=gen, device=device)
+        H = (torch.matmul(h.to(torch.complex128), lam) * 0.5).reshape(T, Z, Y, X, 3, 3)
+        B = (1j * eps / 16.0) * H
+        E = eye.expand_as(B).clone()
+        term = eye.expand_as(B).clone()
+        for k in range(1, 15):
+            term = torch.matmul(term, B) / k
+            E = E + term
+        for _ in range(4):
+            E = torch.matmul(E, E)
+        out[mu] = E
+    return out
