@@ -204,7 +204,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", flush=True)
         sys.exit(1)
-    cfg = I.config(1)
+    cfg = I.workload(1)
     if args.pmc_probe:
         pmc_probe(cfg)
         return
@@ -289,7 +289,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        gpath = os.path.join(ROOT, "tests", "golden", "config1_oracle.json")
+        gpath = os.path.join(ROOT, "tests", "golden", "oracle_16x16x16x32.json")
         if os.path.exists(gpath):
             cpu = cpu_baseline(cfg, json.load(open(gpath)))
             print(f"[bench] oracle on host: {cpu['value']:.4f} solves/s", flush=True)

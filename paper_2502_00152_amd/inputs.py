@@ -36,8 +36,8 @@ __all__ = [
     "gaussian_even_vectors",
     "random_gauge_transform",
     "unit_links",
-    "config",
-    "CONFIGS",
+    "workload",
+    "WORKLOADS",
     "random_su3_field_device",
 ]
 
@@ -118,7 +118,7 @@ def random_gauge_transform(dims, seed: int, eps: float = 3.0) -> np.ndarray:
 
 # Synthetic workloads at the paper's shapes.  Seeds: fat 10000c+1,
 # long 10000c+2, source j 10000c+100+j, eigensolver start 10000c+7.
-CONFIGS = {
+WORKLOADS = {
     0: dict(name="plain-cg-8^4", dims=(8, 8, 8, 8), eps=0.3, two_m=0.1, nrhs=1,
             n_ev=0, tol=1e-10),
     1: dict(name="deflated-cg-16^3x32", dims=(16, 16, 16, 32), eps=0.5, two_m=0.01,
@@ -130,9 +130,9 @@ C_FAT = 1.0
 C_LONG = -1.0 / 24.0
 
 
-def config(c: int) -> dict:
+def workload(c: int) -> dict:
     """Recipe of workload c, with its seeds."""
-    d = dict(CONFIGS[c])
+    d = dict(WORKLOADS[c])
     d["seed_fat"] = 10000 * c + 1
     d["seed_long"] = 10000 * c + 2
     d["seed_src"] = [10000 * c + 100 + j for j in range(d["nrhs"])]

@@ -1,4 +1,4 @@
-"""Write tests/golden/config1_oracle.json: oracle-only reference values for the
+"""Write tests/golden/oracle_16x16x16x32.json: oracle-only reference values for the
 16^3 x 32 deflated-CG workload (eps 0.5, 2m = 0.01, Gaussian source 0).
 
 Calls only the oracle and the seeded input generators:
@@ -6,7 +6,7 @@ Calls only the oracle and the seeded input generators:
     plus the 65th to report the gap at the cut;
   * the oracle CG iteration counts for source 0 to a true residual of 1e-10,
     undeflated and deflated with the oracle's own eigenvectors (Eq. (4)).
-Run:  python tests/golden/make_config1_golden.py   (several minutes on 8 cores)
+Run:  python tests/golden/make_workload_16x16x16x32_golden.py   (several minutes on 8 cores)
 """
 from __future__ import annotations
 
@@ -25,7 +25,7 @@ from paper_2502_00152_amd import inputs as I  # noqa: E402
 
 
 def main():
-    cfg = I.config(1)
+    cfg = I.workload(1)
     dims, two_m = cfg["dims"], cfg["two_m"]
     W = I.random_su3_field(dims, cfg["eps"], cfg["seed_fat"])
     N = I.random_su3_field(dims, cfg["eps"], cfg["seed_long"])
@@ -55,7 +55,7 @@ def main():
           flush=True)
     out = {
         "workload": "16x16x16x32 eps=0.5 2m=0.01, Gaussian source 0, tol 1e-10",
-        "generator": "tests/golden/make_config1_golden.py (oracle + seeded inputs only)",
+        "generator": "tests/golden/make_workload_16x16x16x32_golden.py (oracle + seeded inputs only)",
         "two_m": two_m,
         "eigenvalues": [float(v) for v in w[:k]],
         "eigenvalue_next": float(w[k]),
@@ -66,7 +66,7 @@ def main():
         "oracle_seconds": {"cg_undeflated": t_plain, "eigsh": t_eig, "cg_deflated": t_defl},
         "oracle_threads": O.n_threads(),
     }
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "config1_oracle.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_16x16x16x32.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

@@ -63,8 +63,8 @@ class Problem:
         self.F, self.L = O.fold_links(self.W, self.N, c_fat, c_long)
 
     @classmethod
-    def from_config(cls, c):
-        cfg = I.config(c)
+    def from_workload(cls, c):
+        cfg = I.workload(c)
         return cls(cfg["dims"], cfg["eps"], cfg["seed_fat"], cfg["seed_long"])
 
     def gauge(self):

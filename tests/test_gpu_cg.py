@@ -28,9 +28,9 @@ def oracle_true_residual(pr, two_m, x_soa, b_soa):
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    cfg = I.config(0)
-    pr = Problem.from_config(0)
+def w8():
+    cfg = I.workload(0)
+    pr = Problem.from_workload(0)
     pr.g = pr.gauge()
     eta = I.gaussian_source(cfg["dims"], cfg["seed_src"][0])
     pr.two_m = cfg["two_m"]
@@ -39,11 +39,11 @@ def cfg0():
     pr.g.close()
 
 
-def test_cg_config0_iterations_and_residual(cfg0):
+def test_cg_8to4_iterations_and_residual(w8):
     """8^4, eps 0.3, 2m = 0.1, one Gaussian source, tol 1e-10."""
     import torch
     from paper_2502_00152_amd import hisq
-    pr = cfg0
+    pr = w8
     b = dev(to_parity(pr.y, pr.dims, 0))
     x = torch.zeros_like(b)
     res = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=1e-10)
@@ -55,10 +55,10 @@ def test_cg_config0_iterations_and_residual(cfg0):
     assert abs(res.true_residual[0] - tr[0]) <= 1e-3 * tr[0] + 1e-16
 
 
-def test_cg_config0_solution_matches_oracle(cfg0):
+def test_cg_8to4_solution_matches_oracle(w8):
     import torch
     from paper_2502_00152_amd import hisq
-    pr = cfg0
+    pr = w8
     b = dev(to_parity(pr.y, pr.dims, 0))
     x = torch.zeros_like(b)
     hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=1e-12)

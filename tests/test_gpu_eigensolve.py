@@ -70,8 +70,8 @@ def test_eigensolve_small_vs_dense(dims, n_ev, two_m):
 
 def test_eigensolve_8to4_vs_arpack():
     """The 8^4 workload (eps 0.3), 32 lowest pairs, against ARPACK."""
-    cfg = I.config(0)
-    pr = Problem.from_config(0)
+    cfg = I.workload(0)
+    pr = Problem.from_workload(0)
     two_m = cfg["two_m"]
     lam, V, stats = gpu_eigs(pr, two_m, 32)
     w, _ = O.lowest_eigenpairs(pr.F, pr.L, two_m, 32, method="arpack",

@@ -1,7 +1,7 @@
 """GPU parity at the full size of the benchmarked workload (16^3 x 32, eps 0.5,
 2m = 0.01, 12 Gaussian sources, 64 eigenpairs, tol 1e-10), in the launch
 configuration bench.py times, against values the oracle computes here or
-stored by tests/golden/make_config1_golden.py (oracle only)."""
+stored by tests/golden/make_workload_16x16x16x32_golden.py (oracle only)."""
 from __future__ import annotations
 
 import json
@@ -16,15 +16,15 @@ from tests.gpu_util import Problem, dev, from_parity, host, to_parity
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config1_oracle.json")))
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_16x16x16x32.json")))
 
 
 @pytest.fixture(scope="module")
-def c1():
+def wl():
     import torch
     from paper_2502_00152_amd import hisq
-    cfg = I.config(1)
-    pr = Problem.from_config(1)
+    cfg = I.workload(1)
+    pr = Problem.from_workload(1)
     pr.cfg = cfg
     pr.g = pr.gauge()
     pr.eta = np.stack([I.gaussian_source(cfg["dims"], sd) for sd in cfg["seed_src"]])
@@ -34,32 +34,32 @@ def c1():
     hisq.hisq_spinor_split(pr.g, full, pr.ee, pr.eo)
     pr.y = torch.empty_like(pr.ee)
     hisq.hisq_prepare_source(pr.g, cfg["two_m"], pr.ee, pr.eo, pr.y)
-    print("[config1] setup done", flush=True)
+    print("[16x16x16x32] setup done", flush=True)
     yield pr
     pr.g.close()
 
 
 @pytest.fixture(scope="module")
-def eig(c1):
+def eig(wl):
     import torch
     from paper_2502_00152_amd import hisq
-    cfg = c1.cfg
-    ev = torch.empty((64, 3, c1.g.vh), dtype=torch.complex128, device="cuda")
-    st, lam, stats = hisq.hisq_eigensolve(c1.g, cfg["two_m"], 64, ev, tol=1e-10,
+    cfg = wl.cfg
+    ev = torch.empty((64, 3, wl.g.vh), dtype=torch.complex128, device="cuda")
+    st, lam, stats = hisq.hisq_eigensolve(wl.g, cfg["two_m"], 64, ev, tol=1e-10,
                                           seed=cfg["seed_eig"])
-    print(f"[config1] eigensolve {stats.seconds:.2f}s restarts={stats.restarts} "
+    print(f"[16x16x16x32] eigensolve {stats.seconds:.2f}s restarts={stats.restarts} "
           f"matvecs={stats.matvecs} deg={stats.cheb_degree} a={stats.cheb_a:.4g} "
           f"maxres={stats.max_residual:.3g}", flush=True)
     return ev, lam, stats
 
 
-def test_dslash_sampled_sites(c1):
+def test_dslash_sampled_sites(wl):
     """12-RHS half stencil (the CG's launch configuration) at 300 random sites."""
     import torch
     from paper_2502_00152_amd import hisq
-    dims = c1.dims
-    out = torch.empty_like(c1.ee)
-    hisq.hisq_dslash_eo(c1.g, 0, c1.eo, out)
+    dims = wl.dims
+    out = torch.empty_like(wl.ee)
+    hisq.hisq_dslash_eo(wl.g, 0, wl.eo, out)
     got = host(out)
     rng = np.random.default_rng(5)
     lex_even = np.nonzero(O.even_mask(dims).ravel())[0]
@@ -68,13 +68,13 @@ def test_dslash_sampled_sites(c1):
     for lex in rng.choice(lex_even, 300, replace=False):
         x, y, z, t = lex % X, (lex // X) % Y, (lex // (X * Y)) % Z, lex // (X * Y * Z)
         for r in (0, 5, 11):
-            ref = O.dslash_site(c1.F, c1.L, np.ascontiguousarray(c1.eta[r]), (x, y, z, t))
+            ref = O.dslash_site(wl.F, wl.L, np.ascontiguousarray(wl.eta[r]), (x, y, z, t))
             g = got[r, :, lex >> 1]
             worst = max(worst, np.abs(g - ref).max() / np.abs(ref).max())
     assert worst <= 1e-13
 
 
-def test_eigenpairs_match_oracle(c1, eig):
+def test_eigenpairs_match_oracle(wl, eig):
     ev, lam, stats = eig
     ref = np.array(GOLDEN["eigenvalues"])
     lmax = stats.lambda_max
@@ -82,45 +82,45 @@ def test_eigenpairs_match_oracle(c1, eig):
     V = host(ev)
     G = V.reshape(64, -1).conj() @ V.reshape(64, -1).T
     assert np.abs(G - np.eye(64)).max() <= 1e-12
-    two_m = c1.cfg["two_m"]
+    two_m = wl.cfg["two_m"]
     res = []
     for i in range(0, 64, 7):
-        v = from_parity(V[i:i + 1], c1.dims, 0)[0]
-        res.append(O.norm(O.apply_A(c1.F, c1.L, two_m, v) - lam[i] * v))
+        v = from_parity(V[i:i + 1], wl.dims, 0)[0]
+        res.append(O.norm(O.apply_A(wl.F, wl.L, two_m, v) - lam[i] * v))
     assert max(res) <= 1e-10 * lmax
 
 
-def test_deflated_batched_cg(c1, eig):
+def test_deflated_batched_cg(wl, eig):
     """The benchmarked step: deflate, batched CG on 12 sources, reconstruct."""
     import torch
     from paper_2502_00152_amd import hisq
     ev, lam, stats = eig
-    cfg = c1.cfg
+    cfg = wl.cfg
     two_m = cfg["two_m"]
-    x = torch.empty_like(c1.y)
-    hisq.hisq_deflate(c1.g, ev, lam - two_m ** 2, two_m, c1.y, x)
-    res = hisq.hisq_cg_solve(c1.g, two_m, c1.y, x, tol=1e-10)
+    x = torch.empty_like(wl.y)
+    hisq.hisq_deflate(wl.g, ev, lam - two_m ** 2, two_m, wl.y, x)
+    res = hisq.hisq_cg_solve(wl.g, two_m, wl.y, x, tol=1e-10)
     assert all(res.converged)
     it0 = GOLDEN["cg_iterations_deflated"]
     assert abs(res.iterations[0] - it0) <= max(2, 0.01 * it0)
-    xs, ys = host(x), host(c1.y)
+    xs, ys = host(x), host(wl.y)
     for r in range(12):
-        xe = from_parity(xs[r:r + 1], c1.dims, 0)[0]
-        ye = from_parity(ys[r:r + 1], c1.dims, 0)[0]
-        tr = O.norm(ye - O.apply_A(c1.F, c1.L, two_m, xe)) / O.norm(ye)
+        xe = from_parity(xs[r:r + 1], wl.dims, 0)[0]
+        ye = from_parity(ys[r:r + 1], wl.dims, 0)[0]
+        tr = O.norm(ye - O.apply_A(wl.F, wl.L, two_m, xe)) / O.norm(ye)
         assert tr <= 1e-10, (r, tr)
     # full-lattice solution: M psi = eta up to (even residual)/(2m)
-    po = torch.empty_like(c1.eo)
-    hisq.hisq_reconstruct_odd(c1.g, two_m, x, c1.eo, po)
-    psi = from_parity(xs[:1], c1.dims, 0)[0] + from_parity(host(po)[:1], c1.dims, 1)[0]
-    r = O.apply_M(c1.F, c1.L, two_m, psi) - c1.eta[0]
+    po = torch.empty_like(wl.eo)
+    hisq.hisq_reconstruct_odd(wl.g, two_m, x, wl.eo, po)
+    psi = from_parity(xs[:1], wl.dims, 0)[0] + from_parity(host(po)[:1], wl.dims, 1)[0]
+    r = O.apply_M(wl.F, wl.L, two_m, psi) - wl.eta[0]
     assert O.norm(r) <= 1e-10 * O.norm(ys[0]) / two_m * 1.01
 
 
-def test_plain_cg_iterations(c1):
+def test_plain_cg_iterations(wl):
     import torch
     from paper_2502_00152_amd import hisq
-    x = torch.zeros((1, 3, c1.g.vh), dtype=torch.complex128, device="cuda")
-    res = hisq.hisq_cg_solve(c1.g, c1.cfg["two_m"], c1.y[:1].clone(), x, tol=1e-10)
+    x = torch.zeros((1, 3, wl.g.vh), dtype=torch.complex128, device="cuda")
+    res = hisq.hisq_cg_solve(wl.g, wl.cfg["two_m"], wl.y[:1].clone(), x, tol=1e-10)
     it0 = GOLDEN["cg_iterations_undeflated"]
     assert abs(res.iterations[0] - it0) <= max(2, 0.01 * it0)
