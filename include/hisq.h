@@ -255,6 +255,20 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
                             const hisq_eig_params *params, void *evecs_dev,
                             double *evals_host, hisq_eig_stats *stats_host, void *stream);
 
+/* ------------------------------------------------------------- tuning */
+
+/*
+ * Launch-shape knobs of the kernels, process-wide (for the autotuner and for
+ * measurements); results do not depend on them, only speed.  Keys:
+ *   "dslash_rhs_per_thread"  right-hand sides one thread carries: 0 = automatic,
+ *                            or one of 1, 2, 3, 4, 6, 12
+ *   "dslash_group_order"     0: RHS groups of one site block run next to each
+ *                            other; 1: all sites of one group first
+ *   "dslash_xcd_remap"       1: give each XCD a contiguous range of sites; 0: off
+ * Returns INVALID_ARG for an unknown key or value.
+ */
+hisq_status hisq_set_tuning(const char *key, int64_t value);
+
 /* ------------------------------------------------------ instrumentation */
 
 /*

@@ -9,9 +9,10 @@
 // block stores its partial sums and a later kernel adds them in block order.
 // The per-iteration reductions avoid any cross-block synchronisation inside a
 // kernel (a device-scope fence per block writes back L2 on this multi-XCD
-// chip and costs more than the update itself): the update kernel re-sums the
-// <p, Ap> partials of its own RHS in every block, and a one-block finalize
-// kernel advances the per-RHS state.  The rare kernels (initial and true
+// chip and costs more than the update itself): the r update re-sums the
+// <p, Ap> partials of its own RHS in every block, a small kernel (one wave
+// per RHS) advances the per-RHS state, and x and p are updated together
+// afterwards (x += alpha p with the old p, then p = r + beta p).  The rare kernels (initial and true
 // residuals, restarts) finish their reduction in the last block to arrive.
 #include "device_util.h"
 #include "hisq_internal.h"
@@ -91,33 +92,40 @@ __global__ __launch_bounds__(kBS) void k_cg_init(int64_t n, int nrhs, const dvec
     }
 }
 
-// alpha = rho / <p, Ap> with <p, Ap> summed from the stencil kernel's per-block
-// partials (every block repeats the same fixed-order sum, so all agree);
-// x += alpha p; r -= alpha Ap; per-block partials of ||r||^2.
-__global__ __launch_bounds__(kBS) void k_cg_update(int64_t n, dvec2 *__restrict__ x,
-                                                   dvec2 *__restrict__ r,
-                                                   const dvec2 *__restrict__ p,
-                                                   const dvec2 *__restrict__ Ap,
-                                                   const double *__restrict__ pap, int nb_pap,
-                                                   CgDev cg, Reduce red) {
+// Fixed-order sum of nb partials by one wave (every caller gets the same bits):
+// lane l adds partials l, l+64, ... in order, then a butterfly over the wave.
+__device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p, int nb) {
+    const int lane = threadIdx.x & (kWave - 1);
+    double v = 0.0;
+    for (int i = lane; i < nb; i += kWave) v += p[i];
+    return wave_sum(v);
+}
+
+// alpha = rho / <p, Ap>, with <p, Ap> summed from the stencil kernel's
+// per-block partials (every block repeats the same fixed-order sum);
+// r -= alpha Ap and per-block partials of ||r||^2.
+__global__ __launch_bounds__(kBS) void k_cg_update_r(int64_t n, dvec2 *__restrict__ r,
+                                                     const dvec2 *__restrict__ Ap,
+                                                     const double *__restrict__ pap, int nb_pap,
+                                                     CgDev cg, Reduce red) {
     const int rhs = blockIdx.y;
     const int64_t off = rhs * n;
-    __shared__ double w[kBS / kWave];
-    const double pq = sum_partials<kBS>(pap + (int64_t)rhs * nb_pap, nb_pap, w);
+    __shared__ double pq_s;
+    if (threadIdx.x < kWave) {
+        const double v = wave_sum_partials(pap + (int64_t)rhs * nb_pap, nb_pap);
+        if (threadIdx.x == 0) pq_s = v;
+    }
+    __syncthreads();
+    const double pq = pq_s;
     double v[1] = {0.0};
     if (cg.status[rhs] == CG_ACTIVE && isfinite(pq) && pq > 0.0) {
         const double al = cg.rho[rhs] / pq;
         for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
              i += (int64_t)gridDim.x * kBS) {
-            const dvec2 pp = p[off + i];
             const dvec2 qq = Ap[off + i];
-            dvec2 xx = x[off + i];
             dvec2 rr = r[off + i];
-            xx.x = fma(al, pp.x, xx.x);
-            xx.y = fma(al, pp.y, xx.y);
             rr.x = fma(-al, qq.x, rr.x);
             rr.y = fma(-al, qq.y, rr.y);
-            x[off + i] = xx;
             r[off + i] = rr;
             v[0] += norm2(rr);
         }
@@ -127,50 +135,73 @@ __global__ __launch_bounds__(kBS) void k_cg_update(int64_t n, dvec2 *__restrict_
     if (threadIdx.x == 0) red.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = v[0];
 }
 
-// One block: the per-RHS state machine after an update.
+// One wave per RHS: the per-RHS state machine after an r update.  x and p are
+// updated afterwards by k_cg_update_xp with the alpha and beta written here.
 __global__ __launch_bounds__(kBS) void k_cg_finalize(int nrhs, const double *__restrict__ pap,
                                                      int nb_pap, int nb_rr, CgDev cg,
                                                      Reduce red) {
-    __shared__ double w[kBS / kWave];
-    for (int q = 0; q < nrhs; ++q) {
-        const double pq = sum_partials<kBS>(pap + (int64_t)q * nb_pap, nb_pap, w);
-        const double rn = sum_partials<kBS>(red.partials + (int64_t)q * nb_rr, nb_rr, w);
-        if (threadIdx.x == 0 && cg.status[q] == CG_ACTIVE) {
-            if (!isfinite(pq)) {
-                cg.status[q] = CG_NAN;
-            } else if (!(pq > 0.0)) {
-                cg.status[q] = CG_BREAKDOWN;
-            } else {
-                cg.alpha[q] = cg.rho[q] / pq;
-                cg.iters[q] += 1;
-                if (!isfinite(rn)) {
-                    cg.status[q] = CG_NAN;
-                } else if (rn <= cg.tol2b[q]) {
-                    cg.rho_pend[q] = rn;
-                    cg.status[q] = CG_PENDING;
-                } else {
-                    cg.beta[q] = rn / cg.rho[q];
-                    cg.rho[q] = rn;
-                    if (cg.iters[q] >= cg.max_iter) cg.status[q] = CG_MAXITER;
-                }
-            }
+    const int q = blockIdx.x * (kBS / kWave) + threadIdx.x / kWave;
+    if (q >= nrhs) return;
+    const double pq = wave_sum_partials(pap + (int64_t)q * nb_pap, nb_pap);
+    const double rn = wave_sum_partials(red.partials + (int64_t)q * nb_rr, nb_rr);
+    if ((threadIdx.x & (kWave - 1)) != 0) return;
+    cg.xp_alpha[q] = 0.0;  // no x/p update unless the RHS was active in this iteration
+    cg.xp_beta[q] = 0.0;
+    cg.xp_mode[q] = 0;
+    if (cg.status[q] != CG_ACTIVE) return;
+    if (!isfinite(pq)) {
+        cg.status[q] = CG_NAN;
+        return;
+    }
+    if (!(pq > 0.0)) {
+        cg.status[q] = CG_BREAKDOWN;
+        return;
+    }
+    const double al = cg.rho[q] / pq;
+    cg.alpha[q] = al;
+    cg.xp_alpha[q] = al;
+    cg.xp_mode[q] = 1;  // x += alpha p in any case (r already moved)
+    cg.iters[q] += 1;
+    if (!isfinite(rn)) {
+        cg.status[q] = CG_NAN;
+    } else if (rn <= cg.tol2b[q]) {
+        cg.rho_pend[q] = rn;
+        cg.status[q] = CG_PENDING;
+    } else {
+        const double be = rn / cg.rho[q];
+        cg.beta[q] = be;
+        cg.rho[q] = rn;
+        if (cg.iters[q] >= cg.max_iter) {
+            cg.status[q] = CG_MAXITER;
+        } else {
+            cg.xp_beta[q] = be;
+            cg.xp_mode[q] = 2;  // and p = r + beta p
         }
     }
 }
 
-// p = r + beta p for active RHS (or for RHS in `want` state).
-__global__ __launch_bounds__(kBS) void k_cg_update_p(int64_t n, const dvec2 *__restrict__ r,
-                                                     dvec2 *__restrict__ p, CgDev cg) {
+// x += alpha p_old; p = r + beta p_old (mode 2), or only the x update (mode 1).
+__global__ __launch_bounds__(kBS) void k_cg_update_xp(int64_t n, dvec2 *__restrict__ x,
+                                                      const dvec2 *__restrict__ r,
+                                                      dvec2 *__restrict__ p, CgDev cg) {
     const int rhs = blockIdx.y;
-    if (cg.status[rhs] != CG_ACTIVE) return;
+    const int mode = cg.xp_mode[rhs];
+    if (mode == 0) return;
     const int64_t off = rhs * n;
-    const double be = cg.beta[rhs];
+    const double al = cg.xp_alpha[rhs], be = cg.xp_beta[rhs];
     for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
-        const dvec2 rr = r[off + i];
-        dvec2 pp = p[off + i];
-        pp.x = fma(be, pp.x, rr.x);
-        pp.y = fma(be, pp.y, rr.y);
-        p[off + i] = pp;
+        const dvec2 pp = p[off + i];
+        dvec2 xx = x[off + i];
+        xx.x = fma(al, pp.x, xx.x);
+        xx.y = fma(al, pp.y, xx.y);
+        x[off + i] = xx;
+        if (mode == 2) {
+            const dvec2 rr = r[off + i];
+            dvec2 np;
+            np.x = fma(be, pp.x, rr.x);
+            np.y = fma(be, pp.y, rr.y);
+            p[off + i] = np;
+        }
     }
 }
 
@@ -270,13 +301,12 @@ hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, do
     return HISQ_OK;
 }
 
-hisq_status cg_update(int64_t n, int nrhs, double2 *x, double2 *r, const double2 *p,
-                      const double2 *Ap, const double *pap, int nb_pap, const CgDev &cg,
-                      const Reduce &red, hipStream_t s) {
+hisq_status cg_update_r(int64_t n, int nrhs, double2 *r, const double2 *Ap, const double *pap,
+                        int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_update, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(x), AS_V(r),
-                       AS_CV(p), AS_CV(Ap), pap, nb_pap, cg, red);
+    hipLaunchKernelGGL(k_cg_update_r, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(r), AS_CV(Ap),
+                       pap, nb_pap, cg, red);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
@@ -285,17 +315,18 @@ hisq_status cg_finalize(int64_t n, int nrhs, const double *pap, int nb_pap, cons
                         const Reduce &red, hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBS), 0, s, nrhs, pap, nb_pap, gr.nbx, cg,
-                       red);
+    const int per = kBS / kWave;
+    hipLaunchKernelGGL(k_cg_finalize, dim3((nrhs + per - 1) / per), dim3(kBS), 0, s, nrhs, pap,
+                       nb_pap, gr.nbx, cg, red);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
-hisq_status cg_update_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
-                        hipStream_t s) {
+hisq_status cg_update_xp(int64_t n, int nrhs, double2 *x, const double2 *r, double2 *p,
+                         const CgDev &cg, hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_update_p, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_CV(r),
+    hipLaunchKernelGGL(k_cg_update_xp, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(x), AS_CV(r),
                        AS_V(p), cg);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;

@@ -6,9 +6,9 @@
 // One iteration is five stream-ordered launches:
 //   1. t  = D_oe p                          (half stencil, odd output)
 //   2. Ap = (2m)^2 p - D_eo t, partials of Re<p, Ap>   (half stencil)
-//   3. alpha = rho / Re<p, Ap>; x += alpha p, r -= alpha Ap, partials of <r, r>
-//   4. rho' = <r, r>, beta = rho' / rho, convergence state  (one block)
-//   5. p = r + beta p
+//   3. alpha = rho / Re<p, Ap>; r -= alpha Ap, partials of <r, r>
+//   4. rho' = <r, r>, beta = rho' / rho, convergence state  (one wave per RHS)
+//   5. x += alpha p, p = r + beta p         (old p in both)
 // Scalars never leave the device.  The host polls the per-RHS state every
 // check_interval iterations; a right-hand side whose iterated residual has
 // crossed the tolerance is frozen until the host runs the true-residual check
@@ -51,8 +51,8 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
     B.p = static_cast<double2 *>(p);
     HISQ_TRY(g->ws.get("cg_Ap", vec, &p));
     B.Ap = static_cast<double2 *>(p);
-    // scalars: 7 double arrays + 3 int arrays of nrhs
-    HISQ_TRY(g->ws.get("cg_scalars", (7 * sizeof(double) + 3 * sizeof(int)) * nrhs + 64, &p));
+    // scalars: 9 double arrays + 4 int arrays of nrhs
+    HISQ_TRY(g->ws.get("cg_scalars", (9 * sizeof(double) + 4 * sizeof(int)) * nrhs + 64, &p));
     double *d = static_cast<double *>(p);
     B.dev.rho = d;
     B.dev.rho_pend = d + nrhs;
@@ -61,10 +61,13 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
     B.dev.bnorm2 = d + 4 * nrhs;
     B.dev.tol2b = d + 5 * nrhs;
     B.dev.true_res2 = d + 6 * nrhs;
-    int *iv = reinterpret_cast<int *>(d + 7 * nrhs);
+    B.dev.xp_alpha = d + 7 * nrhs;
+    B.dev.xp_beta = d + 8 * nrhs;
+    int *iv = reinterpret_cast<int *>(d + 9 * nrhs);
     B.dev.status = iv;
     B.dev.iters = iv + nrhs;
     B.dev.checks = iv + 2 * nrhs;
+    B.dev.xp_mode = iv + 3 * nrhs;
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const size_t nparts = std::max<size_t>((size_t)nrhs * dslash_reduce_blocks(g, nrhs),
                                            (size_t)2 * nrhs * blas_reduce_blocks(n));
@@ -157,9 +160,9 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
                                nullptr, s));
         HISQ_TRY(launch_dslash(g, 0, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA,
                                nullptr, &B.pap, s));
-        HISQ_TRY(cg_update(n, nrhs, x, B.r, B.p, B.Ap, B.pap.partials, nb_pap, B.dev, B.red, s));
+        HISQ_TRY(cg_update_r(n, nrhs, B.r, B.Ap, B.pap.partials, nb_pap, B.dev, B.red, s));
         HISQ_TRY(cg_finalize(n, nrhs, B.pap.partials, nb_pap, B.dev, B.red, s));
-        HISQ_TRY(cg_update_p(n, nrhs, B.r, B.p, B.dev, s));
+        HISQ_TRY(cg_update_xp(n, nrhs, x, B.r, B.p, B.dev, s));
         return HISQ_OK;
     };
 

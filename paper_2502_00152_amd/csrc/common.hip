@@ -96,6 +96,11 @@ const char *hisq_last_error(void) { return g_last_error.c_str(); }
 
 int hisq_abi_version(void) { return HISQ_ABI_VERSION; }
 
+hisq_status hisq_set_tuning(const char *key, int64_t value) {
+    if (!key) return fail(HISQ_ERR_INVALID_ARG, "hisq_set_tuning: null key");
+    return dslash_set_tuning(key, value);
+}
+
 hisq_status hisq_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;

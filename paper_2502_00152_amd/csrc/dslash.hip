@@ -21,6 +21,14 @@ namespace hisq {
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
+// Process-wide launch-shape knobs (hisq_set_tuning).
+struct DslashTuning {
+    int64_t rhs_per_thread = 0;
+    int64_t group_order = 0;
+    int64_t xcd_remap = 1;
+};
+DslashTuning g_tune;
+
 namespace {
 
 constexpr int kBS = 256;
@@ -37,6 +45,8 @@ struct DslashArgs {
     double ca, cb, cd;
     Geom geom;
     int out_parity;
+    int xcd_remap;         // 1: contiguous site ranges per XCD
+    int group_outer;       // 1: block index = group * nsb + site block
     int nrhs;
     int ngroups;           // ceil(nrhs / NR)
     int nsb;               // site blocks
@@ -52,15 +62,24 @@ __device__ __forceinline__ int wrap(int c, int L) {
     return c;
 }
 
-__device__ __forceinline__ dvec2 ldnt(const dvec2 *p) { return __builtin_nontemporal_load(p); }
+// Link loads: non-temporal when a launch reads each link once (one RHS group:
+// the links should not evict the input field), plain when several RHS groups
+// read the same links (L2 then serves the later groups).  The choice is a
+// template argument: a runtime select lets the compiler merge the two loads
+// into one plain load.
+template <bool NT>
+__device__ __forceinline__ dvec2 ldlink(const dvec2 *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
-template <int NR>
+template <int NR, bool NT>
 __device__ __forceinline__ void hop_forward(const dvec2 *__restrict__ U, int vh, int cbU,
                                             const dvec2 *__restrict__ in, int64_t rstride,
                                             int cbN, int nr, dvec2 (&acc)[NR][3]) {
     dvec2 u[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = ldnt(U + (int64_t)k * vh + cbU);
+    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(U + (int64_t)k * vh + cbU);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (r < nr) {
@@ -82,13 +101,13 @@ __device__ __forceinline__ void hop_forward(const dvec2 *__restrict__ U, int vh,
 }
 
 // acc -= U^H v, with U read at the neighbour's index.
-template <int NR>
+template <int NR, bool NT>
 __device__ __forceinline__ void hop_backward(const dvec2 *__restrict__ U, int vh, int cbN,
                                              const dvec2 *__restrict__ in, int64_t rstride,
                                              int nr, dvec2 (&acc)[NR][3]) {
     dvec2 u[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = ldnt(U + (int64_t)k * vh + cbN);
+    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(U + (int64_t)k * vh + cbN);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (r < nr) {
@@ -110,12 +129,19 @@ __device__ __forceinline__ void hop_backward(const dvec2 *__restrict__ U, int vh
     }
 }
 
-template <int NR, bool AUX, bool AUX2, bool DOT>
+template <int NR, bool AUX, bool AUX2, bool DOT, bool NT>
 __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
     const Geom g = a.geom;
     const int vh = g.vh;
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int sb = lb / a.ngroups, grp = lb - sb * a.ngroups;
+    const int lb = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int sb, grp;
+    if (a.group_outer) {
+        grp = lb / a.nsb;
+        sb = lb - grp * a.nsb;
+    } else {
+        sb = lb / a.ngroups;
+        grp = lb - sb * a.ngroups;
+    }
     const int cb = sb * kBS + threadIdx.x;
     const int r0 = grp * NR;
     const int nr = min(NR, a.nrhs - r0);
@@ -154,29 +180,29 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
             {
                 const int f = (rowYZT * g.X + wrap(x + hop, g.X)) >> 1;
                 const int b = (rowYZT * g.X + wrap(x - hop, g.X)) >> 1;
-                hop_forward<NR>(Uo, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR>(Ui, vh, b, in, rstride, nr, acc);
+                hop_forward<NR, NT>(Uo, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR, NT>(Ui, vh, b, in, rstride, nr, acc);
             }
             // mu = 1 (y)
             {
                 const int f = ((((t * g.Z + z) * g.Y + wrap(y + hop, g.Y)) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + z) * g.Y + wrap(y - hop, g.Y)) * g.X) + x) >> 1;
-                hop_forward<NR>(Uo + lstride, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR>(Ui + lstride, vh, b, in, rstride, nr, acc);
+                hop_forward<NR, NT>(Uo + lstride, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR, NT>(Ui + lstride, vh, b, in, rstride, nr, acc);
             }
             // mu = 2 (z)
             {
                 const int f = ((((t * g.Z + wrap(z + hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + wrap(z - hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
-                hop_forward<NR>(Uo + 2 * lstride, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR>(Ui + 2 * lstride, vh, b, in, rstride, nr, acc);
+                hop_forward<NR, NT>(Uo + 2 * lstride, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR, NT>(Ui + 2 * lstride, vh, b, in, rstride, nr, acc);
             }
             // mu = 3 (t)
             {
                 const int f = ((((wrap(t + hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((wrap(t - hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
-                hop_forward<NR>(Uo + 3 * lstride, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR>(Ui + 3 * lstride, vh, b, in, rstride, nr, acc);
+                hop_forward<NR, NT>(Uo + 3 * lstride, vh, cb, in, rstride, f, nr, acc);
+                hop_backward<NR, NT>(Ui + 3 * lstride, vh, b, in, rstride, nr, acc);
             }
         }
 
@@ -218,30 +244,62 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a) {
     }
 }
 
+template <int NR, bool NT>
+void launch_variant(const DslashArgs &args, int nblocks, bool aux, bool aux2, bool dot,
+                    hipStream_t s) {
+    if (dot)
+        hipLaunchKernelGGL((k_dslash<NR, true, false, true, NT>), dim3(nblocks), dim3(kBS), 0, s, args);
+    else if (aux2)
+        hipLaunchKernelGGL((k_dslash<NR, true, true, false, NT>), dim3(nblocks), dim3(kBS), 0, s, args);
+    else if (aux)
+        hipLaunchKernelGGL((k_dslash<NR, true, false, false, NT>), dim3(nblocks), dim3(kBS), 0, s, args);
+    else
+        hipLaunchKernelGGL((k_dslash<NR, false, false, false, NT>), dim3(nblocks), dim3(kBS), 0, s, args);
+}
+
 template <int NR>
 hisq_status launch_nr(const DslashArgs &args, int nblocks, bool aux, bool aux2, bool dot,
                       hipStream_t s) {
-    if (dot)
-        hipLaunchKernelGGL((k_dslash<NR, true, false, true>), dim3(nblocks), dim3(kBS), 0, s, args);
-    else if (aux2)
-        hipLaunchKernelGGL((k_dslash<NR, true, true, false>), dim3(nblocks), dim3(kBS), 0, s, args);
-    else if (aux)
-        hipLaunchKernelGGL((k_dslash<NR, true, false, false>), dim3(nblocks), dim3(kBS), 0, s, args);
+    if (args.ngroups == 1)
+        launch_variant<NR, true>(args, nblocks, aux, aux2, dot, s);
     else
-        hipLaunchKernelGGL((k_dslash<NR, false, false, false>), dim3(nblocks), dim3(kBS), 0, s, args);
+        launch_variant<NR, false>(args, nblocks, aux, aux2, dot, s);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
-// Right-hand sides per thread.
-int pick_nr(int nrhs) {
+// Right-hand sides per thread: the tuned value, else measured defaults.  With
+// many RHS the input field no longer fits the per-XCD L2 and the neighbour
+// gathers are served from the last-level cache; then occupancy (latency
+// hiding) matters more than link reuse in registers: 2 per thread up to
+// Vh = 2^18 (16^3 x 32 with 12 RHS: 78 us against 93 us with 4), 3 above
+// (32^3 x 64: 1.68 ms against 1.74 ms).  A group may be partly empty; lanes
+// mask r < nr.
+int pick_nr(int nrhs, int vh) {
+    if (g_tune.rhs_per_thread > 0) return (int)g_tune.rhs_per_thread;
+    if (nrhs <= 2) return nrhs;
     if (nrhs <= 4) return nrhs;
-    // smallest group count with at most 4 per thread, balanced
-    const int groups = (nrhs + 3) / 4;
-    return (nrhs + groups - 1) / groups;
+    return vh <= (1 << 18) ? 2 : 3;
 }
 
 }  // namespace
+
+hisq_status dslash_set_tuning(const std::string &key, int64_t v) {
+    if (key == "dslash_rhs_per_thread") {
+        if (!(v == 0 || v == 1 || v == 2 || v == 3 || v == 4 || v == 6 || v == 12))
+            return fail(HISQ_ERR_INVALID_ARG, "dslash_rhs_per_thread must be 0, 1, 2, 3, 4, 6 or 12");
+        g_tune.rhs_per_thread = v;
+    } else if (key == "dslash_group_order") {
+        if (v != 0 && v != 1) return fail(HISQ_ERR_INVALID_ARG, "dslash_group_order must be 0 or 1");
+        g_tune.group_order = v;
+    } else if (key == "dslash_xcd_remap") {
+        if (v != 0 && v != 1) return fail(HISQ_ERR_INVALID_ARG, "dslash_xcd_remap must be 0 or 1");
+        g_tune.xcd_remap = v;
+    } else {
+        return fail(HISQ_ERR_INVALID_ARG, "unknown tuning key '" + key + "'");
+    }
+    return HISQ_OK;
+}
 
 int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs) {
     (void)nrhs;
@@ -269,7 +327,9 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
     a.geom = g->geom;
     a.out_parity = p;
     a.nrhs = nrhs;
-    const int nr = pick_nr(nrhs);
+    a.xcd_remap = (int)g_tune.xcd_remap;
+    a.group_outer = (int)g_tune.group_order;
+    const int nr = pick_nr(nrhs, g->geom.vh);
     a.ngroups = (nrhs + nr - 1) / nr;
     a.nsb = (g->geom.vh + kBS - 1) / kBS;
     const bool dot = fin == FIN_CG_ALPHA;
@@ -282,6 +342,8 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
         case 2: return launch_nr<2>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
         case 3: return launch_nr<3>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
         case 4: return launch_nr<4>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
+        case 6: return launch_nr<6>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
+        case 12: return launch_nr<12>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
         default: return fail(HISQ_ERR_INVALID_ARG, "dslash: bad RHS grouping");
     }
 }

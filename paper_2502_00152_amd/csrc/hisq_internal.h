@@ -111,6 +111,9 @@ struct CgDev {
     int *status;
     int *iters;
     int *checks;
+    double *xp_alpha;  // the x/p update of this iteration: x += xp_alpha p,
+    double *xp_beta;   //   p = r + xp_beta p
+    int *xp_mode;      // 0: none, 1: x only, 2: x and p
     int max_iter;
 };
 
@@ -135,6 +138,9 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
                           const double2 *aux2, double cb, double cd, DslashFinal fin,
                           const CgDev *cg, const Reduce *red, hipStream_t s);
 
+// Launch-shape knobs of the half stencil (hisq_set_tuning).
+hisq_status dslash_set_tuning(const std::string &key, int64_t value);
+
 // Number of reduction blocks the dslash launch for (g, nrhs) uses.
 int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs);
 
@@ -143,15 +149,15 @@ int blas_reduce_blocks(int64_t n);
 hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, double2 *r,
                     double2 *p, double tol, const CgDev &cg, const Reduce &red,
                     hipStream_t s);
-// alpha from the <p, Ap> partials (pap, nb_pap per RHS); x += alpha p, r -= alpha Ap,
-// partials of ||r||^2 into red; then cg_finalize updates the per-RHS state.
-hisq_status cg_update(int64_t n, int nrhs, double2 *x, double2 *r, const double2 *p,
-                      const double2 *Ap, const double *pap, int nb_pap, const CgDev &cg,
-                      const Reduce &red, hipStream_t s);
+// alpha from the <p, Ap> partials (pap, nb_pap per RHS); r -= alpha Ap with
+// partials of ||r||^2 into red; cg_finalize advances the per-RHS state;
+// cg_update_xp then does x += alpha p and p = r + beta p (old p in both).
+hisq_status cg_update_r(int64_t n, int nrhs, double2 *r, const double2 *Ap, const double *pap,
+                        int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s);
 hisq_status cg_finalize(int64_t n, int nrhs, const double *pap, int nb_pap, const CgDev &cg,
                         const Reduce &red, hipStream_t s);
-hisq_status cg_update_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
-                        hipStream_t s);
+hisq_status cg_update_xp(int64_t n, int nrhs, double2 *x, const double2 *r, double2 *p,
+                         const CgDev &cg, hipStream_t s);
 hisq_status cg_true_residual(int64_t n, int nrhs, const double2 *b, const double2 *Ax,
                              double2 *r, const CgDev &cg, const Reduce &red, bool final_only,
                              hipStream_t s);

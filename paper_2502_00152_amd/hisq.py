@@ -42,7 +42,8 @@ EXPORTS = (
     "hisq_last_error", "hisq_abi_version", "hisq_gauge_create", "hisq_gauge_destroy",
     "hisq_gauge_half_volume", "hisq_spinor_split", "hisq_spinor_merge", "hisq_dslash_eo",
     "hisq_mdagm", "hisq_prepare_source", "hisq_reconstruct_odd", "hisq_cg_solve",
-    "hisq_deflate", "hisq_eigensolve", "hisq_profile_enable", "hisq_profile_read",
+    "hisq_deflate", "hisq_eigensolve", "hisq_set_tuning", "hisq_profile_enable",
+    "hisq_profile_read",
 )
 
 
@@ -110,6 +111,7 @@ def lib():
         "hisq_deflate": ([P, I, P, ctypes.POINTER(D), D, P, P, I, P], I),
         "hisq_eigensolve": ([P, D, I, ctypes.POINTER(EigParams), P, ctypes.POINTER(D),
                              ctypes.POINTER(EigStats), P], I),
+        "hisq_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], I),
         "hisq_profile_enable": ([I], I),
         "hisq_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(D)], I),
@@ -325,6 +327,10 @@ def hisq_eigensolve(g, two_m, n_ev, evecs, n_kr=0, cheb_degree=0, cheb_a=0.0, ch
     if raise_on_fail:
         _check(st, "hisq_eigensolve")
     return st, evals, stats
+
+
+def hisq_set_tuning(key: str, value: int):
+    _check(lib().hisq_set_tuning(key.encode(), int(value)), "hisq_set_tuning")
 
 
 def hisq_profile_enable(on: bool):

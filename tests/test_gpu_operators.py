@@ -143,3 +143,36 @@ def test_invalid_arguments_are_rejected():
         hisq.hisq_gauge_create((3, 4, 4, 4), W, W, 1.0, 1.0, 3)
     assert e.value.status == hisq.HISQ_ERR_INVALID_ARG
     g.close()
+
+
+def test_launch_shape_knobs_do_not_change_results():
+    """hisq_set_tuning changes only the launch shape: every choice of RHS per
+    thread, group order and XCD remap gives bitwise the same half stencil on
+    12 RHS."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (4, 6, 8, 10)
+    pr = Problem(dims, 0.5, 41, 42)
+    g = pr.gauge()
+    v = dev(to_parity(sources(dims, 12, 500), dims, 1))
+    ref = torch.empty_like(v)
+    hisq.hisq_dslash_eo(g, 0, v, ref)
+    try:
+        for nr in (1, 2, 3, 4, 6, 12):
+            for order in (0, 1):
+                for xcd in (0, 1):
+                    hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
+                    hisq.hisq_set_tuning("dslash_group_order", order)
+                    hisq.hisq_set_tuning("dslash_xcd_remap", xcd)
+                    out = torch.empty_like(v)
+                    hisq.hisq_dslash_eo(g, 0, v, out)
+                    assert torch.equal(out, ref), (nr, order, xcd)
+        with pytest.raises(hisq.HisqError):
+            hisq.hisq_set_tuning("dslash_rhs_per_thread", 5)
+        with pytest.raises(hisq.HisqError):
+            hisq.hisq_set_tuning("no_such_knob", 1)
+    finally:
+        for k, val in (("dslash_rhs_per_thread", 0), ("dslash_group_order", 0),
+                       ("dslash_xcd_remap", 1)):
+            hisq.hisq_set_tuning(k, val)
+        g.close()
