@@ -1,24 +1,31 @@
 """Benchmark of the HISQ deflated even-odd CG path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--no-dslash-scan] [--pmc-probe]
+                    [--no-dslash-scan] [--no-plain-cg] [--pmc-probe]
 
 Workload (the deflated-CG configuration, synthetic): 16^3 x 32 lattice, random
 SU(3) fat and long links (eps 0.5, long links scaled by -1/24, staggered phases
 and antiperiodic time folded in), 2m = 0.01, 12 Gaussian sources, 64 lowest
-eigenpairs, true-residual target 1e-10, FP64 throughout.
+eigenpairs, true-residual target 1e-10 (FP64 residual b - A x).
 
 One step solves the 12 sources end to end on the GPU, inputs already resident
-in HBM: source preparation y_e = 2m eta_e - D_eo eta_o, deflation guess
-x0 = V diag(1/lambda) V^H y_e, batched CG to ||y - A x|| <= 1e-10 ||y||, odd
-reconstruction psi_o = (eta_o - D_oe psi_e) / (2m).  Setup (gauge packing) and
-the eigensolve are outside the timed region, as in the paper, which amortises
-the eigensolve over the solves of one gauge field; both are timed and
-reported.  value = solves per second = 12 * K / (time of K steps).
+in HBM, with the paper's production method (sections 2 and 3): source
+preparation y_e = 2m eta_e - D_eo eta_o (FP64); deflation guess
+x0 = V diag(1/lambda) V^H y_e with single-precision eigenvectors; batched
+mixed-precision CG (FP32 stencil and vectors, FP64 dot products, FP64
+reliable updates at delta_rd = 0.1) with re-deflation whenever the true
+residual has fallen by delta_tr = 1e-3 since the last deflation, to
+||y - A x|| <= 1e-10 ||y||; odd reconstruction psi_o = (eta_o - D_oe psi_e) / (2m)
+(FP64).  Setup (gauge packing) and the eigensolve (FP64) are outside the
+timed region, as in the paper, which amortises the eigensolve over the solves
+of one gauge field; both are timed and reported.
+value = solves per second = 12 * K / (time of K steps).
 
-Also reported: plain FP64 even-odd CG (no deflation, one source at a time) on
-the same GPU, the half-stencil bandwidth at 32^3 x 64 (beyond the 256 MB
-last-level cache), the half-stencil roofline measured live with HIP events
+Also reported: the same step in FP64 throughout (FP64 eigenvectors, single
+deflation, FP64 CG), plain FP64 even-odd CG (no deflation, one source at a
+time), the relative difference of the mixed solutions from the FP64 ones, the
+half-stencil bandwidth at 32^3 x 64 (beyond the 256 MB last-level cache) in
+both precisions, the FP32 half-stencil roofline measured live with HIP events
 inside the timed region, and the oracle timed on the host cores.
 """
 from __future__ import annotations
@@ -37,28 +44,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/s at 1e-10 true residual (learned+mixed+batched vs plain CG); Dslash GB/s"
 HBM_PEAK_GBS = 8000.0
-LINK_BYTES = 16 * 18 * 8      # 16 links of 18 doubles per output site
-SPINOR_BYTES = 6 * 8          # one colour vector per site
 
 
-def dslash_alg_bytes(vh, nrhs, aux_fields):
-    """Algorithmic HBM bytes of one half-stencil launch: links once, the input
-    field once, the output once and each epilogue field once, per RHS."""
-    return vh * (LINK_BYTES + nrhs * SPINOR_BYTES * (2 + aux_fields))
+def dslash_alg_bytes(vh, nrhs, aux_fields, real_bytes=8):
+    """Algorithmic HBM bytes of one half-stencil launch: 16 links of 18 reals
+    per output site once, the input field once, the output once and each
+    epilogue field once, per RHS (one colour vector = 6 reals per site)."""
+    return vh * (16 * 18 * real_bytes + nrhs * 6 * real_bytes * (2 + aux_fields))
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dslash.hip", "device_util.h"):
+    for f in ("dslash_kernel.h", "dslash.hip", "dslash_f32.hip", "device_util.h"):
         with open(os.path.join(ROOT, "paper_2502_00152_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(name="dslash_f32_traffic_16x16x16x32.md"):
     """HBM traffic per half-stencil launch from the committed counter summary,
     if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "dslash_traffic_16x16x16x32.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -97,16 +103,17 @@ def build_problem(cfg):
 
 def pmc_probe(cfg):
     """Light run for hardware-counter passes: the half-stencil launches of one
-    CG iteration at the timed configuration, and a plain 1 GiB copy whose
-    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    CG iteration at the timed configuration (FP32, then FP64), and a plain
+    1 GiB copy whose counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2502_00152_amd import hisq
     g, ee, eo, _ = build_problem(cfg)
-    t = torch.empty_like(eo)
-    out = torch.empty_like(ee)
-    for _ in range(3):
-        hisq.hisq_dslash_eo(g, 1, ee, t)
-        hisq.hisq_mdagm(g, cfg["two_m"], ee, out)
+    for a in (ee.to(torch.complex64), ee):
+        t = torch.empty_like(a)
+        out = torch.empty_like(a)
+        for _ in range(3):
+            hisq.hisq_dslash_eo(g, 1, a, t)
+            hisq.hisq_mdagm(g, cfg["two_m"], a, out)
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
     a.fill_(1.0)
     b = torch.empty_like(a)
@@ -118,7 +125,8 @@ def pmc_probe(cfg):
 
 
 def dslash_scan(dims=(32, 32, 32, 64), reps=20):
-    """Half-stencil GB/s at a lattice whose working set exceeds the LLC."""
+    """Half-stencil GB/s at a lattice whose working set exceeds the LLC, one
+    RHS, FP64 and FP32."""
     import torch
     from paper_2502_00152_amd import hisq, inputs as I
     W = I.random_su3_field_device(dims, 0.5, 20001)
@@ -126,23 +134,25 @@ def dslash_scan(dims=(32, 32, 32, 64), reps=20):
     g = hisq.Gauge(dims, W, N, I.C_FAT, I.C_LONG)
     del W, N
     torch.cuda.empty_cache()
-    a = torch.randn((1, 3, g.vh), dtype=torch.complex128, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        hisq.hisq_dslash_eo(g, 0, a, b)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        hisq.hisq_dslash_eo(g, 0, a, b)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    alg = dslash_alg_bytes(g.vh, 1, 0)
+    out = {"lattice": "x".join(map(str, dims)), "nrhs": 1}
+    for name, dt, rb in (("f64", torch.complex128, 8), ("f32", torch.complex64, 4)):
+        a = torch.randn((1, 3, g.vh), dtype=dt, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            hisq.hisq_dslash_eo(g, 0, a, b)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            hisq.hisq_dslash_eo(g, 0, a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg = dslash_alg_bytes(g.vh, 1, 0, rb)
+        out[name] = {"us_per_launch": ms * 1e3, "algorithmic_bytes": alg, "GB_s": alg / ms / 1e6,
+                     "frac_of_hbm_peak": alg / ms / 1e6 / HBM_PEAK_GBS}
     g.close()
-    return {"lattice": "x".join(map(str, dims)), "nrhs": 1, "us_per_launch": ms * 1e3,
-            "algorithmic_bytes": alg, "GB_s": alg / ms / 1e6,
-            "frac_of_hbm_peak": alg / ms / 1e6 / HBM_PEAK_GBS}
+    return out
 
 
 def cpu_baseline(cfg, golden):
@@ -223,22 +233,34 @@ def main():
     print(f"[bench] eigensolve {t_eig:.2f} s, {est.matvecs} matvecs, {est.restarts} restarts, "
           f"max residual {est.max_residual:.2e}", flush=True)
 
+    ev32 = evecs.to(torch.complex64)  # single-precision eigenvectors (section 3)
     y = torch.empty_like(ee)
     x = torch.empty_like(ee)
     po = torch.empty_like(eo)
+    F32 = hisq.HISQ_FP32
 
     def step():
         hisq.hisq_prepare_source(g, two_m, ee, eo, y)
-        hisq.hisq_deflate(g, evecs, eps, two_m, y, x)
-        res = hisq.hisq_cg_solve(g, two_m, y, x, tol=tol)
+        hisq.hisq_deflate(g, ev32, eps, two_m, y, x)
+        res = hisq.hisq_cg_solve(g, two_m, y, x, tol=tol, sloppy_prec=F32, reliable_delta=0.1,
+                                 evecs=ev32, evals=eps, tol_restart=1e-3)
         hisq.hisq_reconstruct_odd(g, two_m, x, eo, po)
         return res
 
+    def step_fp64(xo):
+        hisq.hisq_prepare_source(g, two_m, ee, eo, y)
+        hisq.hisq_deflate(g, evecs, eps, two_m, y, xo)
+        res = hisq.hisq_cg_solve(g, two_m, y, xo, tol=tol)
+        hisq.hisq_reconstruct_odd(g, two_m, xo, eo, po)
+        return res
+
+    classes = ("dslash", "dslash_aux", "dslash_aux2", "dslash_f32", "dslash_f32_aux",
+               "dslash_f32_aux2", "blas", "gemm")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     hisq.hisq_profile_enable(True)
-    for cls in ("dslash", "dslash_aux", "dslash_aux2", "blas", "gemm"):
+    for cls in classes:
         hisq.hisq_profile_read(cls)
     results = []
     torch.cuda.synchronize()
@@ -248,22 +270,38 @@ def main():
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
     hisq.hisq_profile_enable(False)
-    prof = {cls: hisq.hisq_profile_read(cls) for cls in ("dslash", "dslash_aux", "blas", "gemm")}
+    prof = {cls: hisq.hisq_profile_read(cls) for cls in classes}
     print(f"[bench] {args.steps} steps in {t_steps:.3f} s", flush=True)
-    iters = results[-1].iterations
+    last = results[-1]
     true_res = max(max(r.true_residual) for r in results)
     assert all(all(r.converged) for r in results), "a timed solve did not converge"
 
-    # live half-stencil roofline over the timed region
-    n_plain, ms_plain = prof["dslash"]
-    n_aux, ms_aux = prof["dslash_aux"]
-    bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0)
-                   + n_aux * dslash_alg_bytes(g.vh, nrhs, 1))
+    # live FP32 half-stencil roofline over the timed region (the CG's stencil)
+    n_plain, ms_plain = prof["dslash_f32"]
+    n_aux, ms_aux = prof["dslash_f32_aux"]
+    bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0, 4)
+                   + n_aux * dslash_alg_bytes(g.vh, nrhs, 1, 4))
     launches = n_plain + n_aux
     avg_ms = (ms_plain + ms_aux) / max(launches, 1)
     # GB/s = (bytes per launch) / (ms per launch * 1e-3) / 1e9
     achieved = bytes_total / max(launches, 1) / avg_ms / 1e6 if launches else None
     traffic = read_traffic()
+
+    # the same step in FP64 throughout, and the mixed solutions against it
+    x64 = torch.empty_like(ee)
+    step_fp64(x64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r64 = step_fp64(x64)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    diff = ((x - x64).abs().pow(2).sum(dim=(1, 2)).sqrt()
+            / x64.abs().pow(2).sum(dim=(1, 2)).sqrt()).max().item()
+    fp64 = {"solves_per_s": nrhs * args.steps / t_fp64, "iterations_per_source": r64.iterations,
+            "max_true_residual": max(r64.true_residual),
+            "path": "FP64 eigenvectors, single deflation, FP64 CG"}
+    print(f"[bench] FP64 deflated: {fp64['solves_per_s']:.1f} solves/s", flush=True)
 
     # plain FP64 even-odd CG, no deflation, one source at a time
     plain = None
@@ -285,7 +323,8 @@ def main():
 
     scan = None if args.no_dslash_scan else dslash_scan()
     if scan:
-        print(f"[bench] dslash 32^3x64: {scan['GB_s']:.0f} GB/s", flush=True)
+        print(f"[bench] dslash 32^3x64: {scan['f64']['GB_s']:.0f} GB/s (f64), "
+              f"{scan['f32']['GB_s']:.0f} GB/s (f32)", flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -306,20 +345,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "deflated-cg-16^3x32", "lattice": "16x16x16x32", "eps": 0.5,
                    "two_m": two_m, "sources_per_step": nrhs, "n_ev": n_ev, "tol": tol,
-                   "path": "deflated batched FP64 CG"},
-        "roofline": {"bound": "hbm", "kernel": "k_dslash (half stencil, 12 RHS)",
+                   "path": ("FP32 eigenvectors, batched mixed-precision CG (FP32 stencil and "
+                            "vectors, FP64 reductions and reliable updates, delta_rd 0.1), "
+                            "re-deflation at delta_tr 1e-3")},
+        "roofline": {"bound": "hbm", "kernel": "k_dslash<float> (FP32 half stencil, 12 RHS)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic, "launches": launches,
                      "avg_launch_us": avg_ms * 1e3,
                      "alg_bytes_per_launch": bytes_total / max(launches, 1)},
         "cpu_baseline": cpu,
-        "iterations_per_source": iters,
+        "iterations_per_source": last.iterations,
+        "reliable_updates_per_source": last.reliable_updates,
+        "redeflations_per_source": last.redeflations,
         "max_true_residual": true_res,
+        "max_rel_diff_vs_fp64_solution": diff,
+        "deflated_fp64_cg": fp64,
         "plain_fp64_cg": plain,
         "speedup_vs_plain_fp64_cg": value / plain["solves_per_s"] if plain else None,
         "eigensolve": {"seconds": t_eig, "matvecs": est.matvecs, "restarts": est.restarts,

@@ -78,7 +78,7 @@ const char *hisq_last_error(void);
 
 /* ABI revision of this header; bumped on any incompatible change. */
 int hisq_abi_version(void);
-#define HISQ_ABI_VERSION 1
+#define HISQ_ABI_VERSION 2
 
 /* ------------------------------------------------------------------ gauge */
 
@@ -126,8 +126,10 @@ hisq_status hisq_spinor_merge(hisq_gauge g, const void *even_dev, const void *od
  * Half stencil: out = D_{p,1-p} in for output parity p = out_parity
  * (0 = even: D_eo, odd -> even; 1 = odd: D_oe, even -> odd).  `in` is a parity
  * vector of parity 1-p, `out` of parity p; they must not overlap.
- * Section 2 (the HISQ matrix D; even-odd split).  prec: HISQ_FP64 only in
- * this build (others return UNSUPPORTED).
+ * Section 2 (the HISQ matrix D; even-odd split).  prec: HISQ_FP64 (vectors
+ * of complex double) or HISQ_FP32 (vectors of complex float, same layout,
+ * 8 bytes per complex; FP32 links and FP32 arithmetic, the FP32 links made
+ * from the FP64 ones on first use).  HISQ_BF16 returns UNSUPPORTED.
  */
 hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
                            void *out_dev, int nrhs, hisq_prec prec, void *stream);
@@ -136,7 +138,7 @@ hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
  * Even-site normal operator: out_e = ((2m)^2 - D_eo D_oe) in_e, the even-even
  * block of M^H M (Eq. (1) after even-odd preconditioning).  two_m = 2m >= 0.
  * in_e and out_e must not overlap.  Uses an odd-parity scratch vector owned by
- * the handle.
+ * the handle.  prec as for hisq_dslash_eo.
  */
 hisq_status hisq_mdagm(hisq_gauge g, double two_m, const void *in_e_dev, void *out_e_dev,
                        int nrhs, hisq_prec prec, void *stream);
@@ -164,8 +166,24 @@ typedef struct hisq_cg_params {
     double tol;            /* stop when ||b - A x|| / ||b|| <= tol (true residual, FP64) */
     int max_iter;          /* iteration limit per right-hand side */
     int check_interval;    /* iterations between host polls of the convergence state
-                              (0 = default 16).  It does not change the iterates. */
-    hisq_prec sloppy_prec; /* HISQ_FP64: plain FP64 CG (the only value in this build) */
+                              (0 = default 16).  It does not change the iterates of the
+                              FP64 solve. */
+    hisq_prec sloppy_prec; /* HISQ_FP64: plain FP64 CG.  HISQ_FP32: mixed precision,
+                              the iteration in FP32 with FP64 reliable updates */
+    int reliable_interval; /* FP32 only: also a reliable update after this many
+                              iterations since the last one (0 = only the delta
+                              trigger, as in the paper) */
+    double reliable_delta; /* FP32 only: reliable update when the iterated residual
+                              falls below reliable_delta times the true residual of
+                              the last update (0 = default 0.1, the paper's delta_rd) */
+    /* multi-deflation (section 3): re-deflate the residual during the solve */
+    int n_ev;              /* 0: no re-deflation */
+    hisq_prec evec_prec;   /* HISQ_FP64 or HISQ_FP32 eigenvectors */
+    const void *evecs_dev; /* n_ev even parity vectors (layout of hisq_deflate) */
+    const double *evals_host; /* eps_i of the massless operator, n_ev doubles */
+    double tol_restart;    /* re-deflate at a reliable update when the true residual has
+                              fallen by this factor since the last deflation
+                              (the paper's delta_tr, e.g. 1e-3; 0 = never) */
     int reserved[8];       /* must be zero */
 } hisq_cg_params;
 
@@ -173,6 +191,8 @@ typedef struct hisq_cg_stats {
     int iterations;        /* operator applications inside the loop */
     int true_residual_checks; /* recomputations of b - A x (after the initial one) */
     int converged;         /* 1 if the true residual met tol */
+    int reliable_updates;  /* FP64 true-residual replacements of the sloppy residual */
+    int redeflations;      /* deflations of the residual during the solve */
     int reserved0;
     double true_residual;  /* final ||b - A x|| / ||b||, FP64 */
     double b_norm;         /* ||b|| */
@@ -189,6 +209,16 @@ typedef struct hisq_cg_stats {
  * recomputed true residual confirms it; if the true residual does not, CG
  * continues from it with the search direction kept.  b = 0 gives x = 0.
  *   stats_host: array of nrhs structs, filled on return (may be NULL).
+ * With sloppy_prec = HISQ_FP32 (section 2: the conventional solve is
+ * mixed-precision CG; reliable updates as in section 3) the recurrence runs
+ * on FP32 vectors with the FP32 operator and FP64-accumulated dot products;
+ * the solution accumulates in FP64, and a reliable update (x += x_sloppy,
+ * r = b - A x in FP64) follows whenever the iterated residual has fallen by
+ * reliable_delta since the last one (and, if set, every reliable_interval
+ * iterations), and before any convergence decision.  With n_ev > 0 and tol_restart > 0 the residual is
+ * re-deflated, x += V diag(1/(eps + (2m)^2)) V^H r, when the true residual has
+ * fallen by tol_restart since the last deflation, and the recurrence restarts
+ * (section 3: multi-deflation with single-precision eigenvectors).
  * Returns NOT_CONVERGED if any right-hand side hit max_iter (x holds its last
  * iterate), NAN, BREAKDOWN, or INVALID_ARG (two_m <= 0, tol <= 0, ...).
  * Synchronises `stream`.
@@ -204,12 +234,16 @@ hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e_dev, void 
  * columns of V are orthonormal even-site eigenvectors of the massless
  * operator -D_eo D_oe with eigenvalues eps_i (Eq. (3): the massive eigenvalue
  * is eps_i + (2m)^2 and the vectors do not depend on m).
- *   evecs_dev       n_ev even parity vectors [n_ev][3][Vh] (complex double).
+ *   evecs_dev       n_ev even parity vectors [n_ev][3][Vh], complex double
+ *                   (evec_prec = HISQ_FP64) or complex float (HISQ_FP32: the
+ *                   single-precision eigenvectors of section 3).
  *   evals_host      eps_i, n_ev doubles (host); eps_i + (2m)^2 must be > 0.
- *   b_e_dev, x0_e_dev  parity vectors with nrhs right-hand sides; must not overlap.
- * The two contractions run on the FP64 matrix cores.
+ *   b_e_dev, x0_e_dev  complex double parity vectors with nrhs right-hand sides;
+ *                   must not overlap.
+ * The two contractions run on the FP64 matrix cores (FP32 eigenvectors are
+ * widened on load; coefficients are FP64).
  */
-hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_dev,
+hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_dev, hisq_prec evec_prec,
                          const double *evals_host, double two_m, const void *b_e_dev,
                          void *x0_e_dev, int nrhs, void *stream);
 
@@ -275,7 +309,8 @@ hisq_status hisq_set_tuning(const char *key, int64_t value);
  * Per-kernel timing with HIP events recorded on the launch stream around
  * every launch of the named kernel class: "dslash" (plain half stencil),
  * "dslash_aux" (with one epilogue field: M^H M second half, source, odd
- * reconstruction), "dslash_aux2" (two epilogue fields: Chebyshev step), "blas"
+ * reconstruction), "dslash_aux2" (two epilogue fields: Chebyshev step),
+ * "dslash_f32", "dslash_f32_aux", "dslash_f32_aux2" (the same in FP32), "blas"
  * (CG and Lanczos vector kernels), "gemm" (matrix-core contractions); off by
  * default.  hisq_profile_read returns the number of timed launches and their
  * total milliseconds (synchronises the device), and clears the record.

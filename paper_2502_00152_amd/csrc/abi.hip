@@ -29,9 +29,8 @@ hisq_status check_nrhs(int nrhs) {
 }
 
 hisq_status check_prec(hisq_prec p) {
-    if (p == HISQ_FP64) return HISQ_OK;
-    if (p == HISQ_FP32 || p == HISQ_BF16)
-        return fail(HISQ_ERR_UNSUPPORTED, "only HISQ_FP64 is implemented for this call");
+    if (p == HISQ_FP64 || p == HISQ_FP32) return HISQ_OK;
+    if (p == HISQ_BF16) return fail(HISQ_ERR_UNSUPPORTED, "BF16 is not implemented for this call");
     return fail(HISQ_ERR_INVALID_ARG, "unknown precision");
 }
 
@@ -109,6 +108,8 @@ hisq_status hisq_gauge_destroy(hisq_gauge g) {
     for (int p = 0; p < 2; ++p) {
         if (g->fat[p]) (void)hipFree(g->fat[p]);
         if (g->lng[p]) (void)hipFree(g->lng[p]);
+        if (g->fat32[p]) (void)hipFree(g->fat32[p]);
+        if (g->lng32[p]) (void)hipFree(g->lng32[p]);
     }
     g->ws.release();
     delete g;
@@ -151,6 +152,10 @@ hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev, voi
     HISQ_TRY(check_vec(in_dev, "in_dev"));
     HISQ_TRY(check_vec(out_dev, "out_dev"));
     if (in_dev == out_dev) return fail(HISQ_ERR_INVALID_ARG, "in and out must not overlap");
+    if (prec == HISQ_FP32)
+        return launch_dslash_f32(g, out_parity, static_cast<const float2 *>(in_dev),
+                                 static_cast<float2 *>(out_dev), nrhs, nullptr, 0.0, nullptr, 0.0,
+                                 1.0, nullptr, static_cast<hipStream_t>(stream));
     return launch_dslash(g, out_parity, static_cast<const double2 *>(in_dev),
                          static_cast<double2 *>(out_dev), nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
                          nullptr, nullptr, static_cast<hipStream_t>(stream));
@@ -165,6 +170,10 @@ hisq_status hisq_mdagm(hisq_gauge g, double two_m, const void *in_e_dev, void *o
     HISQ_TRY(check_vec(in_e_dev, "in_e_dev"));
     HISQ_TRY(check_vec(out_e_dev, "out_e_dev"));
     if (in_e_dev == out_e_dev) return fail(HISQ_ERR_INVALID_ARG, "in and out must not overlap");
+    if (prec == HISQ_FP32)
+        return apply_mdagm_f32(g, two_m, static_cast<const float2 *>(in_e_dev),
+                               static_cast<float2 *>(out_e_dev), nrhs, nullptr,
+                               static_cast<hipStream_t>(stream));
     return apply_mdagm(g, two_m, static_cast<const double2 *>(in_e_dev),
                        static_cast<double2 *>(out_e_dev), nrhs, static_cast<hipStream_t>(stream));
 }

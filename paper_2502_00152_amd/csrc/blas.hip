@@ -20,6 +20,7 @@
 namespace hisq {
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -104,10 +105,12 @@ __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p
 // alpha = rho / <p, Ap>, with <p, Ap> summed from the stencil kernel's
 // per-block partials (every block repeats the same fixed-order sum);
 // r -= alpha Ap and per-block partials of ||r||^2.
-__global__ __launch_bounds__(kBS) void k_cg_update_r(int64_t n, dvec2 *__restrict__ r,
-                                                     const dvec2 *__restrict__ Ap,
+template <typename V>
+__global__ __launch_bounds__(kBS) void k_cg_update_r(int64_t n, V *__restrict__ r,
+                                                     const V *__restrict__ Ap,
                                                      const double *__restrict__ pap, int nb_pap,
                                                      CgDev cg, Reduce red) {
+    using R = decltype(V{}.x);
     const int rhs = blockIdx.y;
     const int64_t off = rhs * n;
     __shared__ double pq_s;
@@ -119,15 +122,15 @@ __global__ __launch_bounds__(kBS) void k_cg_update_r(int64_t n, dvec2 *__restric
     const double pq = pq_s;
     double v[1] = {0.0};
     if (cg.status[rhs] == CG_ACTIVE && isfinite(pq) && pq > 0.0) {
-        const double al = cg.rho[rhs] / pq;
+        const R al = (R)(cg.rho[rhs] / pq);
         for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
              i += (int64_t)gridDim.x * kBS) {
-            const dvec2 qq = Ap[off + i];
-            dvec2 rr = r[off + i];
+            const V qq = Ap[off + i];
+            V rr = r[off + i];
             rr.x = fma(-al, qq.x, rr.x);
             rr.y = fma(-al, qq.y, rr.y);
             r[off + i] = rr;
-            v[0] += norm2(rr);
+            v[0] += norm2(dvec2{(double)rr.x, (double)rr.y});
         }
     }
     __shared__ double lds[kBS / kWave];
@@ -171,6 +174,10 @@ __global__ __launch_bounds__(kBS) void k_cg_finalize(int nrhs, const double *__r
         const double be = rn / cg.rho[q];
         cg.beta[q] = be;
         cg.rho[q] = rn;
+        // mixed precision: the iterated residual fell by delta since the last
+        // reliable update; the host runs it at its next poll (the recurrence
+        // goes on meanwhile)
+        if (cg.delta2 > 0.0 && rn <= cg.delta2 * cg.rho_ru[q]) cg.ru_flag[q] = 1;
         if (cg.iters[q] >= cg.max_iter) {
             cg.status[q] = CG_MAXITER;
         } else {
@@ -181,23 +188,25 @@ __global__ __launch_bounds__(kBS) void k_cg_finalize(int nrhs, const double *__r
 }
 
 // x += alpha p_old; p = r + beta p_old (mode 2), or only the x update (mode 1).
-__global__ __launch_bounds__(kBS) void k_cg_update_xp(int64_t n, dvec2 *__restrict__ x,
-                                                      const dvec2 *__restrict__ r,
-                                                      dvec2 *__restrict__ p, CgDev cg) {
+template <typename V>
+__global__ __launch_bounds__(kBS) void k_cg_update_xp(int64_t n, V *__restrict__ x,
+                                                      const V *__restrict__ r,
+                                                      V *__restrict__ p, CgDev cg) {
+    using R = decltype(V{}.x);
     const int rhs = blockIdx.y;
     const int mode = cg.xp_mode[rhs];
     if (mode == 0) return;
     const int64_t off = rhs * n;
-    const double al = cg.xp_alpha[rhs], be = cg.xp_beta[rhs];
+    const R al = (R)cg.xp_alpha[rhs], be = (R)cg.xp_beta[rhs];
     for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
-        const dvec2 pp = p[off + i];
-        dvec2 xx = x[off + i];
+        const V pp = p[off + i];
+        V xx = x[off + i];
         xx.x = fma(al, pp.x, xx.x);
         xx.y = fma(al, pp.y, xx.y);
         x[off + i] = xx;
         if (mode == 2) {
-            const dvec2 rr = r[off + i];
-            dvec2 np;
+            const V rr = r[off + i];
+            V np;
             np.x = fma(be, pp.x, rr.x);
             np.y = fma(be, pp.y, rr.y);
             p[off + i] = np;
@@ -305,8 +314,8 @@ hisq_status cg_update_r(int64_t n, int nrhs, double2 *r, const double2 *Ap, cons
                         int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_update_r, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(r), AS_CV(Ap),
-                       pap, nb_pap, cg, red);
+    hipLaunchKernelGGL(k_cg_update_r<dvec2>, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(r),
+                       AS_CV(Ap), pap, nb_pap, cg, red);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
@@ -326,8 +335,31 @@ hisq_status cg_update_xp(int64_t n, int nrhs, double2 *x, const double2 *r, doub
                          const CgDev &cg, hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_update_xp, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(x), AS_CV(r),
-                       AS_V(p), cg);
+    hipLaunchKernelGGL(k_cg_update_xp<dvec2>, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(x),
+                       AS_CV(r), AS_V(p), cg);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+#define AS_F(p) reinterpret_cast<fvec2 *>(p)
+#define AS_CF(p) reinterpret_cast<const fvec2 *>(p)
+
+hisq_status cg_update_r(int64_t n, int nrhs, float2 *r, const float2 *Ap, const double *pap,
+                        int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_update_r<fvec2>, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_F(r),
+                       AS_CF(Ap), pap, nb_pap, cg, red);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status cg_update_xp(int64_t n, int nrhs, float2 *x, const float2 *r, float2 *p,
+                         const CgDev &cg, hipStream_t s) {
+    const BlasGrid gr = make_grid(n);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_cg_update_xp<fvec2>, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_F(x),
+                       AS_CF(r), AS_F(p), cg);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }

@@ -51,8 +51,8 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
     B.p = static_cast<double2 *>(p);
     HISQ_TRY(g->ws.get("cg_Ap", vec, &p));
     B.Ap = static_cast<double2 *>(p);
-    // scalars: 9 double arrays + 4 int arrays of nrhs
-    HISQ_TRY(g->ws.get("cg_scalars", (9 * sizeof(double) + 4 * sizeof(int)) * nrhs + 64, &p));
+    // scalars: 10 double arrays + 4 int arrays of nrhs
+    HISQ_TRY(g->ws.get("cg_scalars", (10 * sizeof(double) + 4 * sizeof(int)) * nrhs + 64, &p));
     double *d = static_cast<double *>(p);
     B.dev.rho = d;
     B.dev.rho_pend = d + nrhs;
@@ -63,7 +63,10 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
     B.dev.true_res2 = d + 6 * nrhs;
     B.dev.xp_alpha = d + 7 * nrhs;
     B.dev.xp_beta = d + 8 * nrhs;
-    int *iv = reinterpret_cast<int *>(d + 9 * nrhs);
+    B.dev.rho_ru = d + 9 * nrhs;
+    B.dev.ru_flag = nullptr;
+    B.dev.delta2 = 0.0;
+    int *iv = reinterpret_cast<int *>(d + 10 * nrhs);
     B.dev.status = iv;
     B.dev.iters = iv + nrhs;
     B.dev.checks = iv + 2 * nrhs;
@@ -105,15 +108,20 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
         return fail(HISQ_ERR_INVALID_ARG, "tol must be finite and > 0");
     if (params->max_iter < 0) return fail(HISQ_ERR_INVALID_ARG, "max_iter must be >= 0");
     if (params->check_interval < 0) return fail(HISQ_ERR_INVALID_ARG, "check_interval < 0");
-    if (params->sloppy_prec != HISQ_FP64)
-        return fail(HISQ_ERR_UNSUPPORTED, "only FP64 CG is implemented in this build");
     for (int k = 0; k < 8; ++k)
         if (params->reserved[k]) return fail(HISQ_ERR_INVALID_ARG, "reserved fields must be 0");
-
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t n = 3 * (int64_t)g->geom.vh;
     const double2 *b = static_cast<const double2 *>(b_e_dev);
     double2 *x = static_cast<double2 *>(x_e_dev);
+    if (params->sloppy_prec == HISQ_FP32) return solve_mixed(g, two_m, b, x, nrhs, params, stats_host, s);
+    if (params->sloppy_prec == HISQ_BF16)
+        return fail(HISQ_ERR_UNSUPPORTED, "BF16 sloppy precision is not implemented");
+    if (params->sloppy_prec != HISQ_FP64) return fail(HISQ_ERR_INVALID_ARG, "unknown sloppy_prec");
+    if (params->n_ev != 0 || params->tol_restart != 0.0)
+        return fail(HISQ_ERR_INVALID_ARG,
+                    "re-deflation runs at reliable updates: it needs sloppy_prec = HISQ_FP32");
+
+    const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = params->check_interval > 0 ? params->check_interval : 16;
 
     CgBuffers B{};
@@ -216,6 +224,8 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
             S.iterations = B.host_iters[i];
             S.true_residual_checks = B.host_checks[i];
             S.converged = st == CG_CONVERGED;
+            S.reliable_updates = 0;
+            S.redeflations = 0;
             S.reserved0 = 0;
             S.b_norm = std::sqrt(B.host_b2[i]);
             S.true_residual = B.host_b2[i] > 0.0 ? std::sqrt(B.host_tr2[i] / B.host_b2[i]) : 0.0;

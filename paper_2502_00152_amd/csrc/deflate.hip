@@ -2,7 +2,8 @@
 //   x0 = sum_i v_i (1 / lambda_i) v_i^H b,  lambda_i = eps_i + (2m)^2
 // (Eq. (3): the massive eigenvalue is the massless one shifted by (2m)^2; the
 // eigenvectors do not depend on the mass).  Two contractions on the FP64
-// matrix cores: c = diag(1/lambda) V^H B, then X0 = V c.
+// matrix cores: c = diag(1/lambda) V^H B, then X0 = V c.  The eigenvectors may
+// be stored in FP32 (section 3: single-precision eigenvectors).
 #include <cmath>
 #include <vector>
 
@@ -18,14 +19,16 @@ hisq_status check_mass(double two_m, bool positive);
 using namespace hisq;
 
 extern "C" hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_dev,
-                                    const double *evals_host, double two_m, const void *b_e_dev,
-                                    void *x0_e_dev, int nrhs, void *stream) {
+                                    hisq_prec evec_prec, const double *evals_host, double two_m,
+                                    const void *b_e_dev, void *x0_e_dev, int nrhs, void *stream) {
     HISQ_TRY(check_gauge(g));
     HISQ_TRY(check_nrhs(nrhs));
     HISQ_TRY(check_mass(two_m, false));
     const int64_t N = 3 * (int64_t)g->geom.vh;
     if (n_ev < 1 || n_ev > N) return fail(HISQ_ERR_INVALID_ARG, "n_ev must be in [1, 3*Vh]");
     if (!evals_host) return fail(HISQ_ERR_INVALID_ARG, "evals_host is null");
+    if (evec_prec != HISQ_FP64 && evec_prec != HISQ_FP32)
+        return fail(HISQ_ERR_INVALID_ARG, "evec_prec must be HISQ_FP64 or HISQ_FP32");
     HISQ_TRY(check_vec(evecs_dev, "evecs_dev"));
     HISQ_TRY(check_vec(b_e_dev, "b_e_dev"));
     HISQ_TRY(check_vec(x0_e_dev, "x0_e_dev"));
@@ -45,10 +48,17 @@ extern "C" hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_de
     HISQ_TRY(g->ws.get("deflate_c", sizeof(double2) * (size_t)n_ev * nrhs, &cd));
     // pageable source: the copy has consumed w when the call returns
     HISQ_HIP(hipMemcpyAsync(wd, w.data(), sizeof(double) * n_ev, hipMemcpyHostToDevice, s));
-    const double2 *V = static_cast<const double2 *>(evecs_dev);
     double2 *C = static_cast<double2 *>(cd);
-    HISQ_TRY(gemm_tn(g, V, n_ev, static_cast<const double2 *>(b_e_dev), nrhs, N,
-                     static_cast<const double *>(wd), 1.0, C, s));
-    HISQ_TRY(gemm_nn(V, n_ev, C, nrhs, N, 0.0, static_cast<double2 *>(x0_e_dev), s));
+    const double2 *B = static_cast<const double2 *>(b_e_dev);
+    double2 *X = static_cast<double2 *>(x0_e_dev);
+    if (evec_prec == HISQ_FP32) {
+        const float2 *V = static_cast<const float2 *>(evecs_dev);
+        HISQ_TRY(gemm_tn(g, V, n_ev, B, nrhs, N, static_cast<const double *>(wd), 1.0, C, s));
+        HISQ_TRY(gemm_nn(V, n_ev, C, nrhs, N, 0.0, X, s));
+    } else {
+        const double2 *V = static_cast<const double2 *>(evecs_dev);
+        HISQ_TRY(gemm_tn(g, V, n_ev, B, nrhs, N, static_cast<const double *>(wd), 1.0, C, s));
+        HISQ_TRY(gemm_nn(V, n_ev, C, nrhs, N, 0.0, X, s));
+    }
     return HISQ_OK;
 }

@@ -40,12 +40,32 @@ __device__ __forceinline__ dvec4 mfma(double a, double b, dvec4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Eigenvector (V) storage may be double or float; products and sums are FP64.
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load4(const double *p, double (&o)[4]) {
+    const dvec2 x0 = *reinterpret_cast<const dvec2 *>(p);
+    const dvec2 x1 = *reinterpret_cast<const dvec2 *>(p + 2);
+    o[0] = x0.x; o[1] = x0.y; o[2] = x1.x; o[3] = x1.y;
+}
+__device__ __forceinline__ void load4(const float *p, double (&o)[4]) {
+    const fvec4 x = *reinterpret_cast<const fvec4 *>(p);
+    o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w;
+}
+__device__ __forceinline__ dvec2 load2(const double *p) { return *reinterpret_cast<const dvec2 *>(p); }
+__device__ __forceinline__ dvec2 load2(const float *p) {
+    const fvec2 x = *reinterpret_cast<const fvec2 *>(p);
+    return dvec2{(double)x.x, (double)x.y};
+}
+
 // ------------------------------------------------------------------- tn
 // Grid: x = reduction chunks, y = 64-column tiles of V (i), z = 32-column
 // tiles of the real right-hand-side columns (2n).
 // partials: [gridDim.x][kpad][ncpad] doubles.
+template <typename TV>
 struct TnArgs {
-    const double *V;   // k columns of 2N reals
+    const TV *V;       // k columns of 2N reals
     const double *B;   // n columns of 2N reals
     double *partials;
     int64_t twoN;      // reals per column
@@ -54,8 +74,8 @@ struct TnArgs {
     int64_t steps;     // twoN / kStep
 };
 
-template <int MT, int NT>
-__global__ __launch_bounds__(kBS) void k_gemm_tn(TnArgs a) {
+template <typename TV, int MT, int NT>
+__global__ __launch_bounds__(kBS) void k_gemm_tn(TnArgs<TV> a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, q = lane >> 4;
     const int i0 = blockIdx.y * (16 * MT);
@@ -67,7 +87,7 @@ __global__ __launch_bounds__(kBS) void k_gemm_tn(TnArgs a) {
         for (int t = 0; t < NT; ++t) acc[m][t] = dvec4{0, 0, 0, 0};
 
     // column pointers of this lane (null when past the end: contributes 0)
-    const double *vcol[MT];
+    const TV *vcol[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int i = i0 + 16 * m + lr;
@@ -93,9 +113,7 @@ __global__ __launch_bounds__(kBS) void k_gemm_tn(TnArgs a) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             if (vcol[m]) {
-                const dvec2 x0 = *reinterpret_cast<const dvec2 *>(vcol[m] + off);
-                const dvec2 x1 = *reinterpret_cast<const dvec2 *>(vcol[m] + off + 2);
-                av[m][0] = x0.x; av[m][1] = x0.y; av[m][2] = x1.x; av[m][3] = x1.y;
+                load4(vcol[m] + off, av[m]);
             } else {
                 av[m][0] = av[m][1] = av[m][2] = av[m][3] = 0.0;
             }
@@ -173,8 +191,8 @@ __global__ __launch_bounds__(kBS) void k_tn_reduce(const double *__restrict__ pa
 // Matrix-vector forms for one or two right-hand sides, on the vector units:
 // with so few columns the matrix-core tiles would be mostly padding.
 //   gemv_tn: partial[b][i][j] = sum over the block's sites of conj(V[i][s]) B[j][s]
-template <int NB>
-__global__ __launch_bounds__(kBS) void k_gemv_tn(const dvec2 *__restrict__ V, int k,
+template <typename TV, int NB>
+__global__ __launch_bounds__(kBS) void k_gemv_tn(const TV *__restrict__ V, int k,
                                                  const dvec2 *__restrict__ B, int64_t N,
                                                  double *__restrict__ partials, int ldp) {
     // block: a contiguous chunk of sites; each wave handles columns i = wave, wave+4, ...
@@ -182,12 +200,12 @@ __global__ __launch_bounds__(kBS) void k_gemv_tn(const dvec2 *__restrict__ V, in
     const int64_t per = (N + gridDim.x - 1) / gridDim.x;
     const int64_t s0 = blockIdx.x * per, s1 = min(N, s0 + per);
     for (int i = wave; i < k; i += kBS / kWave) {
-        const dvec2 *v = V + (int64_t)i * N;
+        const TV *v = V + (int64_t)i * 2 * N;
         double acc[NB][2];
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = 0.0;
         for (int64_t s = s0 + lane; s < s1; s += kWave) {
-            const dvec2 a = v[s];
+            const dvec2 a = load2(v + 2 * s);
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const dvec2 b = B[(int64_t)j * N + s];
@@ -232,8 +250,8 @@ __global__ __launch_bounds__(kBS) void k_gemv_reduce(const double *__restrict__ 
 }
 
 //   gemv_nn: X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i], one thread per site
-template <int NB>
-__global__ __launch_bounds__(kBS) void k_gemv_nn(const dvec2 *__restrict__ V, int k,
+template <typename TV, int NB>
+__global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int k,
                                                  const dvec2 *__restrict__ C, int64_t N,
                                                  double beta, dvec2 *__restrict__ X) {
     extern __shared__ dvec2 cs[];  // [NB][k]
@@ -247,7 +265,7 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const dvec2 *__restrict__ V, in
         for (; i + 4 <= k; i += 4) {
             dvec2 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = V[(int64_t)(i + u) * N + s];
+            for (int u = 0; u < 4; ++u) v[u] = load2(V + 2 * ((int64_t)(i + u) * N + s));
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -258,7 +276,7 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const dvec2 *__restrict__ V, in
                 }
         }
         for (; i < k; ++i) {
-            const dvec2 v = V[(int64_t)i * N + s];
+            const dvec2 v = load2(V + 2 * ((int64_t)i * N + s));
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const dvec2 c = cs[j * k + i];
@@ -287,8 +305,9 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const dvec2 *__restrict__ V, in
 // Output rows are right-hand sides (16 per tile), output columns 16 reals of
 // X (8 sites): each store instruction writes 128 contiguous bytes per RHS.
 // Grid: x = column tiles (grid-stride), y = groups of 16*MT right-hand sides.
+template <typename TV>
 struct NnArgs {
-    const double *V;      // k columns of 2N reals
+    const TV *V;          // k columns of 2N reals
     const dvec2 *C;       // [n][k] complex coefficients
     double *X;            // n columns of 2N reals
     int64_t twoN;
@@ -297,8 +316,8 @@ struct NnArgs {
     int64_t tiles;        // twoN / 16
 };
 
-template <int MT>
-__global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs a) {
+template <typename TV, int MT>
+__global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs<TV> a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, q = lane >> 4;
     const int jbase = blockIdx.y * (16 * MT);
@@ -316,7 +335,7 @@ __global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs a) {
             const int i = i0 + (q >> 1);
             double bval = 0.0;
             if (i < a.k) {
-                const dvec2 v = *reinterpret_cast<const dvec2 *>(a.V + (int64_t)i * a.twoN + 2 * site);
+                const dvec2 v = load2(a.V + (int64_t)i * a.twoN + 2 * site);
                 // V_big[2s+c][2i+d]
                 bval = c == 0 ? (dsel == 0 ? v.x : -v.y) : (dsel == 0 ? v.y : v.x);
             }
@@ -351,16 +370,16 @@ int round16(int v) { return (v + 15) / 16 * 16; }
 
 }  // namespace
 
-template <int MT, int NT>
-void launch_tn(const TnArgs &a, int nbx, int mtiles, int ntiles, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_tn<MT, NT>), dim3((unsigned)nbx, mtiles, ntiles), dim3(kBS), 0, s,
-                       a);
+template <typename TV, int MT, int NT>
+void launch_tn(const TnArgs<TV> &a, int nbx, int mtiles, int ntiles, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_tn<TV, MT, NT>), dim3((unsigned)nbx, mtiles, ntiles), dim3(kBS), 0,
+                       s, a);
 }
 
 // C = out_scale * diag(row_scale) * V^H B   (C complex [n][k] on the device)
-hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, int n,
-                    int64_t N, const double *row_scale_dev, double out_scale, double2 *C,
-                    hipStream_t s) {
+template <typename TV>
+hisq_status gemm_tn_t(hisq_gauge_s *g, const TV *V, int k, const double2 *B, int n, int64_t N,
+                      const double *row_scale_dev, double out_scale, double2 *C, hipStream_t s) {
     if (n <= 2) {
         // vector-unit form: ~4 sites per lane, partials [nb][k][2 n]
         int64_t nb = (N + 4 * kBS - 1) / (4 * kBS);
@@ -369,16 +388,15 @@ hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, 
         void *p = nullptr;
         HISQ_TRY(g->ws.get("gemm_partials", sizeof(double) * nb * ldp, &p));
         double *P = static_cast<double *>(p);
-        const dvec2 *Vv = reinterpret_cast<const dvec2 *>(V);
         const dvec2 *Bv = reinterpret_cast<const dvec2 *>(B);
         {
             ProfileScope prof("gemm", s);
             if (n == 1)
-                hipLaunchKernelGGL((k_gemv_tn<1>), dim3((unsigned)nb), dim3(kBS), 0, s, Vv, k, Bv, N, P,
-                                   ldp);
+                hipLaunchKernelGGL((k_gemv_tn<TV, 1>), dim3((unsigned)nb), dim3(kBS), 0, s, V, k, Bv,
+                                   N, P, ldp);
             else
-                hipLaunchKernelGGL((k_gemv_tn<2>), dim3((unsigned)nb), dim3(kBS), 0, s, Vv, k, Bv, N, P,
-                                   ldp);
+                hipLaunchKernelGGL((k_gemv_tn<TV, 2>), dim3((unsigned)nb), dim3(kBS), 0, s, V, k, Bv,
+                                   N, P, ldp);
             HISQ_HIP(hipGetLastError());
         }
         const int waves = k * n;
@@ -387,8 +405,8 @@ hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, 
         HISQ_HIP(hipGetLastError());
         return HISQ_OK;
     }
-    TnArgs a{};
-    a.V = reinterpret_cast<const double *>(V);
+    TnArgs<TV> a{};
+    a.V = V;
     a.B = reinterpret_cast<const double *>(B);
     a.twoN = 2 * N;
     a.k = k;
@@ -408,12 +426,12 @@ hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, 
     a.partials = static_cast<double *>(p);
     {
         ProfileScope prof("gemm", s);
-        if (mt == 4 && NT == 2) launch_tn<4, 2>(a, (int)nbx, mtiles, ntiles, s);
-        else if (mt == 4) launch_tn<4, 1>(a, (int)nbx, mtiles, ntiles, s);
-        else if (mt == 2 && NT == 2) launch_tn<2, 2>(a, (int)nbx, mtiles, ntiles, s);
-        else if (mt == 2) launch_tn<2, 1>(a, (int)nbx, mtiles, ntiles, s);
-        else if (NT == 2) launch_tn<1, 2>(a, (int)nbx, mtiles, ntiles, s);
-        else launch_tn<1, 1>(a, (int)nbx, mtiles, ntiles, s);
+        if (mt == 4 && NT == 2) launch_tn<TV, 4, 2>(a, (int)nbx, mtiles, ntiles, s);
+        else if (mt == 4) launch_tn<TV, 4, 1>(a, (int)nbx, mtiles, ntiles, s);
+        else if (mt == 2 && NT == 2) launch_tn<TV, 2, 2>(a, (int)nbx, mtiles, ntiles, s);
+        else if (mt == 2) launch_tn<TV, 2, 1>(a, (int)nbx, mtiles, ntiles, s);
+        else if (NT == 2) launch_tn<TV, 1, 2>(a, (int)nbx, mtiles, ntiles, s);
+        else launch_tn<TV, 1, 1>(a, (int)nbx, mtiles, ntiles, s);
         HISQ_HIP(hipGetLastError());
     }
     const int waves = k * n;
@@ -424,10 +442,11 @@ hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, 
 }
 
 // X = beta X + V C   (C complex [n][k] on the device)
-hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N, double beta,
-                    double2 *X, hipStream_t s) {
-    NnArgs a{};
-    a.V = reinterpret_cast<const double *>(V);
+template <typename TV>
+hisq_status gemm_nn_t(const TV *V, int k, const double2 *C, int n, int64_t N, double beta,
+                      double2 *X, hipStream_t s) {
+    NnArgs<TV> a{};
+    a.V = V;
     a.C = reinterpret_cast<const dvec2 *>(C);
     a.X = reinterpret_cast<double *>(X);
     a.twoN = 2 * N;
@@ -442,28 +461,48 @@ hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N,
         nb = std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
         const size_t lds = sizeof(dvec2) * n * k;
         if (lds > 64 * 1024) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: too many columns");
-        const dvec2 *Vv = reinterpret_cast<const dvec2 *>(V);
         const dvec2 *Cv = reinterpret_cast<const dvec2 *>(C);
         dvec2 *Xv = reinterpret_cast<dvec2 *>(X);
         if (n == 1)
-            hipLaunchKernelGGL((k_gemv_nn<1>), dim3((unsigned)nb), dim3(kBS), lds, s, Vv, k, Cv, N,
-                               beta, Xv);
+            hipLaunchKernelGGL((k_gemv_nn<TV, 1>), dim3((unsigned)nb), dim3(kBS), lds, s, V, k, Cv,
+                               N, beta, Xv);
         else
-            hipLaunchKernelGGL((k_gemv_nn<2>), dim3((unsigned)nb), dim3(kBS), lds, s, Vv, k, Cv, N,
-                               beta, Xv);
+            hipLaunchKernelGGL((k_gemv_nn<TV, 2>), dim3((unsigned)nb), dim3(kBS), lds, s, V, k, Cv,
+                               N, beta, Xv);
         HISQ_HIP(hipGetLastError());
         return HISQ_OK;
     }
     int64_t nbx = (a.tiles + 3) / 4;
     nbx = std::max<int64_t>(1, std::min<int64_t>(nbx, 2048));
     if (n <= 16) {
-        hipLaunchKernelGGL((k_gemm_nn<1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
+        hipLaunchKernelGGL((k_gemm_nn<TV, 1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
     } else {
         const int groups = (n + 63) / 64;
-        hipLaunchKernelGGL((k_gemm_nn<4>), dim3((unsigned)nbx, groups), dim3(kBS), 0, s, a);
+        hipLaunchKernelGGL((k_gemm_nn<TV, 4>), dim3((unsigned)nbx, groups), dim3(kBS), 0, s, a);
     }
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
+}
+
+hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, int n,
+                    int64_t N, const double *row_scale_dev, double out_scale, double2 *C,
+                    hipStream_t s) {
+    return gemm_tn_t<double>(g, reinterpret_cast<const double *>(V), k, B, n, N, row_scale_dev,
+                             out_scale, C, s);
+}
+hisq_status gemm_tn(hisq_gauge_s *g, const float2 *V, int k, const double2 *B, int n,
+                    int64_t N, const double *row_scale_dev, double out_scale, double2 *C,
+                    hipStream_t s) {
+    return gemm_tn_t<float>(g, reinterpret_cast<const float *>(V), k, B, n, N, row_scale_dev,
+                            out_scale, C, s);
+}
+hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N, double beta,
+                    double2 *X, hipStream_t s) {
+    return gemm_nn_t<double>(reinterpret_cast<const double *>(V), k, C, n, N, beta, X, s);
+}
+hisq_status gemm_nn(const float2 *V, int k, const double2 *C, int n, int64_t N, double beta,
+                    double2 *X, hipStream_t s) {
+    return gemm_nn_t<float>(reinterpret_cast<const float *>(V), k, C, n, N, beta, X, s);
 }
 
 }  // namespace hisq

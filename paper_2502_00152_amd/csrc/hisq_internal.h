@@ -70,6 +70,8 @@ struct hisq_gauge_s {
     int device = 0;
     double2 *fat[2] = {nullptr, nullptr};
     double2 *lng[2] = {nullptr, nullptr};
+    float2 *fat32[2] = {nullptr, nullptr};  // FP32 copies, made on first sloppy use
+    float2 *lng32[2] = {nullptr, nullptr};
     hisq::Workspace ws;
 };
 
@@ -114,6 +116,9 @@ struct CgDev {
     double *xp_alpha;  // the x/p update of this iteration: x += xp_alpha p,
     double *xp_beta;   //   p = r + xp_beta p
     int *xp_mode;      // 0: none, 1: x only, 2: x and p
+    double *rho_ru;    // mixed precision: true ||r||^2 at the last reliable update
+    int *ru_flag;      // mixed precision: set when a reliable update is due
+    double delta2;     // mixed precision: reliable_delta^2 (0: no delta trigger)
     int max_iter;
 };
 
@@ -158,6 +163,11 @@ hisq_status cg_finalize(int64_t n, int nrhs, const double *pap, int nb_pap, cons
                         const Reduce &red, hipStream_t s);
 hisq_status cg_update_xp(int64_t n, int nrhs, double2 *x, const double2 *r, double2 *p,
                          const CgDev &cg, hipStream_t s);
+// FP32 (sloppy) versions: FP32 vectors, FP64 scalars and reductions.
+hisq_status cg_update_r(int64_t n, int nrhs, float2 *r, const float2 *Ap, const double *pap,
+                        int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s);
+hisq_status cg_update_xp(int64_t n, int nrhs, float2 *x, const float2 *r, float2 *p,
+                         const CgDev &cg, hipStream_t s);
 hisq_status cg_true_residual(int64_t n, int nrhs, const double2 *b, const double2 *Ax,
                              double2 *r, const CgDev &cg, const Reduce &red, bool final_only,
                              hipStream_t s);
@@ -180,6 +190,39 @@ hisq_status gemm_tn(hisq_gauge_s *g, const double2 *V, int k, const double2 *B, 
 // X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i]
 hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N, double beta,
                     double2 *X, hipStream_t s);
+// The same with FP32 V (converted to FP64 on load; products and sums FP64).
+hisq_status gemm_tn(hisq_gauge_s *g, const float2 *V, int k, const double2 *B, int n,
+                    int64_t N, const double *row_scale_dev, double out_scale, double2 *C,
+                    hipStream_t s);
+hisq_status gemm_nn(const float2 *V, int k, const double2 *C, int n, int64_t N, double beta,
+                    double2 *X, hipStream_t s);
+
+// FP32 (sloppy) half stencil; partials (optional) as for FIN_CG_ALPHA.
+hisq_status ensure_links_f32(hisq_gauge_s *g, hipStream_t s);
+hisq_status launch_dslash_f32(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
+                              int nrhs, const float2 *aux, double ca, const float2 *aux2, double cb,
+                              double cd, double *partials, hipStream_t s);
+hisq_status apply_mdagm_f32(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,
+                            double *partials, hipStream_t s);
+
+// Mixed-precision CG helpers; mask (nrhs ints, device) selects RHS, null = all.
+hisq_status mixed_to_f32(const double2 *src, float2 *dst, int64_t n, int nrhs, const int *mask,
+                         hipStream_t s);
+// x += xs; xs = 0
+hisq_status mixed_accum_x(double2 *x, float2 *xs, int64_t n, int nrhs, const int *mask,
+                          hipStream_t s);
+// r = b - Ax and out[j] = ||r_j||^2 (0 for unmasked RHS), partials in red as
+// [nrhs][mixed_resid_blocks(n)]
+hisq_status mixed_resid(const double2 *b, const double2 *Ax, double2 *r, int64_t n, int nrhs,
+                        const int *mask, double *out, const Reduce &red, hipStream_t s);
+int mixed_resid_blocks(int64_t n);
+// per RHS by mode[j]: 0 keep p, 1 p = r + beta[j] p, 2 p = r
+hisq_status mixed_p_restart(float2 *p, const float2 *r, int64_t n, int nrhs, const double *beta,
+                            const int *mode, hipStream_t s);
+// zero column j of C ([nrhs][k]) where mask[j] == 0
+hisq_status mixed_mask_rows(double2 *C, int k, int nrhs, const int *mask, hipStream_t s);
+hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
+                        const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s);
 
 // Operators built from dslash.
 hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,

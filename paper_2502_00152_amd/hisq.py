@@ -9,6 +9,7 @@ Layouts (see include/hisq.h):
     links          complex128 [4, T, Z, Y, X, 3, 3]  (device)
     full vectors   complex128 [nrhs, T, Z, Y, X, 3]
     parity vectors complex128 [nrhs, 3, Vh]          (Vh = X*Y*Z*T/2)
+                   complex64 for the FP32 stencil and FP32 eigenvectors
 """
 from __future__ import annotations
 
@@ -35,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED
 HISQ_FP64, HISQ_FP32, HISQ_BF16 = 0, 1, 2
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 # Entry points declared in include/hisq.h (the tests check the library exports them all).
 EXPORTS = (
@@ -56,12 +57,16 @@ class HisqError(RuntimeError):
 class CgParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("check_interval", ctypes.c_int), ("sloppy_prec", ctypes.c_int),
-                ("reserved", ctypes.c_int * 8)]
+                ("reliable_interval", ctypes.c_int), ("reliable_delta", ctypes.c_double),
+                ("n_ev", ctypes.c_int), ("evec_prec", ctypes.c_int),
+                ("evecs_dev", ctypes.c_void_p), ("evals_host", ctypes.POINTER(ctypes.c_double)),
+                ("tol_restart", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
 
 
 class CgStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("true_residual_checks", ctypes.c_int),
-                ("converged", ctypes.c_int), ("reserved0", ctypes.c_int),
+                ("converged", ctypes.c_int), ("reliable_updates", ctypes.c_int),
+                ("redeflations", ctypes.c_int), ("reserved0", ctypes.c_int),
                 ("true_residual", ctypes.c_double), ("b_norm", ctypes.c_double)]
 
 
@@ -108,7 +113,7 @@ def lib():
         "hisq_reconstruct_odd": ([P, D, P, P, P, I, P], I),
         "hisq_cg_solve": ([P, D, P, P, I, ctypes.POINTER(CgParams), ctypes.POINTER(CgStats),
                            P], I),
-        "hisq_deflate": ([P, I, P, ctypes.POINTER(D), D, P, P, I, P], I),
+        "hisq_deflate": ([P, I, P, I, ctypes.POINTER(D), D, P, P, I, P], I),
         "hisq_eigensolve": ([P, D, I, ctypes.POINTER(EigParams), P, ctypes.POINTER(D),
                              ctypes.POINTER(EigStats), P], I),
         "hisq_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], I),
@@ -139,6 +144,17 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+_PREC_OF_DTYPE = {"complex128": HISQ_FP64, "complex64": HISQ_FP32}
+
+
+def _prec_of(t, name):
+    """HISQ_FP64 for complex128 tensors, HISQ_FP32 for complex64."""
+    dt = str(t.dtype).replace("torch.", "")
+    if dt not in _PREC_OF_DTYPE:
+        raise TypeError(f"{name} must be complex128 or complex64, got {t.dtype}")
+    return _PREC_OF_DTYPE[dt]
 
 
 def _ptr(t, name, dtype_ok=("complex128",)):
@@ -232,20 +248,29 @@ def hisq_spinor_merge(g, even, odd, full, stream=None):
            "hisq_spinor_merge")
 
 
-def hisq_dslash_eo(g, out_parity, inp, out, prec=HISQ_FP64, stream=None):
+def _vec_pair(g, inp, out, prec):
+    """nrhs and precision of an (in, out) pair; prec defaults to the tensors' dtype."""
     nrhs = _nrhs(inp, g.vh, "in")
     if _nrhs(out, g.vh, "out") != nrhs:
         raise ValueError("in and out must have the same nrhs")
-    _check(lib().hisq_dslash_eo(_h(g), int(out_parity), _ptr(inp, "in"), _ptr(out, "out"),
-                                nrhs, int(prec), _stream(stream)), "hisq_dslash_eo")
+    if inp.dtype != out.dtype:
+        raise TypeError("in and out must have the same dtype")
+    p = _prec_of(inp, "in")
+    return nrhs, p if prec is None else int(prec)
 
 
-def hisq_mdagm(g, two_m, inp, out, prec=HISQ_FP64, stream=None):
-    nrhs = _nrhs(inp, g.vh, "in")
-    if _nrhs(out, g.vh, "out") != nrhs:
-        raise ValueError("in and out must have the same nrhs")
-    _check(lib().hisq_mdagm(_h(g), float(two_m), _ptr(inp, "in"), _ptr(out, "out"), nrhs,
-                            int(prec), _stream(stream)), "hisq_mdagm")
+def hisq_dslash_eo(g, out_parity, inp, out, prec=None, stream=None):
+    nrhs, prec = _vec_pair(g, inp, out, prec)
+    ok = ("complex128", "complex64")
+    _check(lib().hisq_dslash_eo(_h(g), int(out_parity), _ptr(inp, "in", ok), _ptr(out, "out", ok),
+                                nrhs, prec, _stream(stream)), "hisq_dslash_eo")
+
+
+def hisq_mdagm(g, two_m, inp, out, prec=None, stream=None):
+    nrhs, prec = _vec_pair(g, inp, out, prec)
+    ok = ("complex128", "complex64")
+    _check(lib().hisq_mdagm(_h(g), float(two_m), _ptr(inp, "in", ok), _ptr(out, "out", ok), nrhs,
+                            prec, _stream(stream)), "hisq_mdagm")
 
 
 def hisq_prepare_source(g, two_m, eta_e, eta_o, y_e, stream=None):
@@ -276,15 +301,32 @@ class CgResult:
     converged: list
     checks: list
     b_norm: list
+    reliable_updates: list
+    redeflations: list
 
 
 def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
-                  sloppy_prec=HISQ_FP64, stream=None, raise_on_fail=True) -> CgResult:
+                  sloppy_prec=HISQ_FP64, stream=None, raise_on_fail=True, reliable_interval=0,
+                  reliable_delta=0.0, evecs=None, evals=None, tol_restart=0.0) -> CgResult:
+    """CG on A x = b.  With sloppy_prec=HISQ_FP32: mixed precision with reliable
+    updates; evecs/evals/tol_restart enable re-deflation (evecs complex128 or
+    complex64 [n_ev, 3, Vh])."""
     nrhs = _nrhs(b, g.vh, "b")
     if _nrhs(x, g.vh, "x") != nrhs:
         raise ValueError("b and x must have the same nrhs")
     p = CgParams(tol=float(tol), max_iter=int(max_iter), check_interval=int(check_interval),
-                 sloppy_prec=int(sloppy_prec))
+                 sloppy_prec=int(sloppy_prec), reliable_interval=int(reliable_interval),
+                 reliable_delta=float(reliable_delta), tol_restart=float(tol_restart))
+    ev = None
+    if evecs is not None:
+        n_ev = _nrhs(evecs, g.vh, "evecs")
+        ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+        if ev.shape != (n_ev,):
+            raise ValueError("evals must have one entry per eigenvector")
+        p.n_ev = n_ev
+        p.evec_prec = _prec_of(evecs, "evecs")
+        p.evecs_dev = _ptr(evecs, "evecs", ("complex128", "complex64")).value
+        p.evals_host = ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     stats = (CgStats * nrhs)()
     st = lib().hisq_cg_solve(_h(g), float(two_m), _ptr(b, "b"), _ptr(x, "x"), nrhs,
                              ctypes.byref(p), stats, _stream(stream))
@@ -292,12 +334,15 @@ def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
         _check(st, "hisq_cg_solve")
     elif st not in (HISQ_OK, HISQ_ERR_NOT_CONVERGED, HISQ_ERR_NAN, HISQ_ERR_BREAKDOWN):
         _check(st, "hisq_cg_solve")
+    del ev  # kept alive across the call above
     return CgResult(st, [s.iterations for s in stats], [s.true_residual for s in stats],
                     [bool(s.converged) for s in stats], [s.true_residual_checks for s in stats],
-                    [s.b_norm for s in stats])
+                    [s.b_norm for s in stats], [s.reliable_updates for s in stats],
+                    [s.redeflations for s in stats])
 
 
 def hisq_deflate(g, evecs, evals, two_m, b, x0, stream=None):
+    """x0 = V diag(1/(eps + (2m)^2)) V^H b; evecs complex128 or complex64 (FP32)."""
     n_ev = _nrhs(evecs, g.vh, "evecs")
     nrhs = _nrhs(b, g.vh, "b")
     if _nrhs(x0, g.vh, "x0") != nrhs:
@@ -305,8 +350,8 @@ def hisq_deflate(g, evecs, evals, two_m, b, x0, stream=None):
     ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
     if ev.shape != (n_ev,):
         raise ValueError("evals must have one entry per eigenvector")
-    _check(lib().hisq_deflate(_h(g), n_ev, _ptr(evecs, "evecs"),
-                              ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(two_m),
+    _check(lib().hisq_deflate(_h(g), n_ev, _ptr(evecs, "evecs", ("complex128", "complex64")),
+                              _prec_of(evecs, "evecs"), ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(two_m),
                               _ptr(b, "b"), _ptr(x0, "x0"), nrhs, _stream(stream)),
            "hisq_deflate")
 

@@ -94,3 +94,21 @@ def rel_per_rhs(got, ref):
     ref = np.asarray(ref).reshape(ref.shape[0], -1)
     return [np.linalg.norm(got[i] - ref[i]) / max(np.linalg.norm(ref[i]), 1e-300)
             for i in range(ref.shape[0])]
+
+
+def abs_stencil(F, L, psi):
+    """|D| |psi|: the half-stencil sum with every link entry and field entry
+    replaced by its modulus (all hops added), on the full lattice.  Used for
+    componentwise rounding-error bounds of the reduced-precision stencil.
+    F, L [4][T][Z][Y][X][3][3] folded links; psi [T][Z][Y][X][3]."""
+    aF, aL, ap = np.abs(F), np.abs(L), np.abs(psi)
+    out = np.zeros(ap.shape, dtype=np.float64)
+    for mu in range(4):
+        ax = 3 - mu  # x is the last lattice axis of [T][Z][Y][X]
+        for U, h in ((aF[mu], 1), (aL[mu], 3)):
+            fwd = np.roll(ap, -h, axis=ax)                 # psi(x + h mu)
+            out += np.einsum("...ab,...b->...a", U, fwd)
+            Ub = np.roll(U, h, axis=ax)                    # U(x - h mu)
+            bwd = np.roll(ap, h, axis=ax)                  # psi(x - h mu)
+            out += np.einsum("...ba,...b->...a", Ub, bwd)
+    return out
