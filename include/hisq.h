@@ -120,6 +120,17 @@ hisq_status hisq_spinor_split(hisq_gauge g, const void *full_dev, void *even_dev
 hisq_status hisq_spinor_merge(hisq_gauge g, const void *even_dev, const void *odd_dev,
                               void *full_dev, int nrhs, void *stream);
 
+/*
+ * Change the precision of n_complex complex numbers (any vectors, e.g. the
+ * eigenvectors stored in single precision for multi-deflation, section 3):
+ * HISQ_FP64 -> HISQ_FP32 rounds to nearest even, HISQ_FP32 -> HISQ_FP64 is
+ * exact, equal precisions copy.  src and dst must not overlap.  Asynchronous
+ * on `stream`.  INVALID_ARG for NULL or overlapping buffers, n_complex < 0 or
+ * an unsupported precision.
+ */
+hisq_status hisq_convert_vectors(const void *src_dev, hisq_prec src_prec, void *dst_dev,
+                                 hisq_prec dst_prec, int64_t n_complex, void *stream);
+
 /* ------------------------------------------------------------- operators */
 
 /*
@@ -294,11 +305,18 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
 /*
  * Launch-shape knobs of the kernels, process-wide (for the autotuner and for
  * measurements); results do not depend on them, only speed.  Keys:
- *   "dslash_rhs_per_thread"  right-hand sides one thread carries: 0 = automatic,
+ *   "dslash_rhs_per_thread"  right-hand sides one lane carries: 0 = automatic,
  *                            or one of 1, 2, 3, 4, 6, 12
- *   "dslash_group_order"     0: RHS groups of one site block run next to each
- *                            other; 1: all sites of one group first
- *   "dslash_xcd_remap"       1: give each XCD a contiguous range of sites; 0: off
+ *   "dslash_lanes_per_site"  lanes that share one site's link loads, each with
+ *                            its own RHS: 0 = automatic, 1, 2 or 4 (with 2 or 4,
+ *                            rhs_per_thread must be 1, 3 or 6; otherwise the
+ *                            stencil calls return INVALID_ARG)
+ *   "dslash_group_order"     -1: automatic; 0: RHS groups of one site block run
+ *                            next to each other; 1: all sites of one group first
+ *   "dslash_xcd_remap"       -1: automatic; 1: give each XCD a contiguous range
+ *                            of sites; 0: off
+ * The <aux, out> partial sums of the CG are formed in one fixed order for any
+ * shape, so CG iterates are bitwise independent of these knobs too.
  * Returns INVALID_ARG for an unknown key or value.
  */
 hisq_status hisq_set_tuning(const char *key, int64_t value);
@@ -312,8 +330,11 @@ hisq_status hisq_set_tuning(const char *key, int64_t value);
  * reconstruction), "dslash_aux2" (two epilogue fields: Chebyshev step),
  * "dslash_f32", "dslash_f32_aux", "dslash_f32_aux2" (the same in FP32), "blas"
  * (CG and Lanczos vector kernels), "gemm" (matrix-core contractions); off by
- * default.  hisq_profile_read returns the number of timed launches and their
- * total milliseconds (synchronises the device), and clears the record.
+ * default.  hisq_profile_enable(n): n = 0 off; n >= 1 times every n-th launch
+ * of each class (counting from the call), so that a long run can be sampled
+ * with few events in the stream; n < 0 is INVALID_ARG.  hisq_profile_read
+ * returns the number of timed launches and their total milliseconds
+ * (synchronises the device), and clears the record.
  */
 hisq_status hisq_profile_enable(int on);
 hisq_status hisq_profile_read(const char *kernel_class, int64_t *launches,

@@ -77,12 +77,18 @@ hisq_status hisq_gauge_create(hisq_gauge *out, const int dims[4], const void *fa
         delete g;
         return fail(HISQ_ERR_HIP, "hipGetDevice failed");
     }
-    const size_t per = sizeof(double2) * 36 * (size_t)g->geom.vh;
+    const size_t per = sizeof(double2) * (size_t)link_array_entries(g->geom.vh);
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int p = 0; p < 2; ++p) {
         if (hipMalloc(&g->fat[p], per) != hipSuccess || hipMalloc(&g->lng[p], per) != hipSuccess) {
             hisq_gauge_destroy(g);
             return fail(HISQ_ERR_OOM, "device allocation of the links");
+        }
+        // the padding of the last tile is never read; keep it defined
+        if (hipMemsetAsync(g->fat[p], 0, per, s) != hipSuccess ||
+            hipMemsetAsync(g->lng[p], 0, per, s) != hipSuccess) {
+            hisq_gauge_destroy(g);
+            return fail(HISQ_ERR_HIP, "clearing the link arrays");
         }
     }
     hisq_status st = launch_pack_links(g, static_cast<const double2 *>(fat_dev), g->fat, c_fat,
@@ -140,6 +146,24 @@ hisq_status hisq_spinor_merge(hisq_gauge g, const void *even_dev, const void *od
     return launch_merge(g, static_cast<const double2 *>(even_dev),
                         static_cast<const double2 *>(odd_dev), static_cast<double2 *>(full_dev),
                         nrhs, static_cast<hipStream_t>(stream));
+}
+
+hisq_status hisq_convert_vectors(const void *src_dev, hisq_prec src_prec, void *dst_dev,
+                                 hisq_prec dst_prec, int64_t n_complex, void *stream) {
+    HISQ_TRY(check_vec(src_dev, "src_dev"));
+    HISQ_TRY(check_vec(dst_dev, "dst_dev"));
+    if (n_complex < 0) return fail(HISQ_ERR_INVALID_ARG, "n_complex must be >= 0");
+    auto bytes = [](hisq_prec p) -> size_t {
+        return p == HISQ_FP64 ? sizeof(double2) : p == HISQ_FP32 ? sizeof(float2) : 0;
+    };
+    const size_t sb = bytes(src_prec), db = bytes(dst_prec);
+    if (!sb || !db) return fail(HISQ_ERR_INVALID_ARG, "precision must be HISQ_FP64 or HISQ_FP32");
+    const char *s0 = static_cast<const char *>(src_dev);
+    const char *d0 = static_cast<const char *>(dst_dev);
+    if (n_complex > 0 && s0 < d0 + db * n_complex && d0 < s0 + sb * n_complex)
+        return fail(HISQ_ERR_INVALID_ARG, "src and dst must not overlap");
+    return convert_vectors(src_dev, src_prec, dst_dev, dst_prec, n_complex,
+                           static_cast<hipStream_t>(stream));
 }
 
 hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev, void *out_dev,

@@ -51,9 +51,11 @@ hisq_status Workspace::get(const char *name, size_t bytes, void **ptr) {
 namespace {
 struct ProfRecord {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;
+    int64_t seen = 0;  // launches of the class since profiling was enabled
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+int g_prof_period = 1;  // time every g_prof_period-th launch of each class
 std::map<std::string, ProfRecord> g_prof;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -72,9 +74,10 @@ hipEvent_t take_event() {
 ProfileScope::ProfileScope(const char *cls, hipStream_t s) : s_(s), cls_(cls) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
+    auto &rec = g_prof[cls];
+    if (rec.seen++ % g_prof_period != 0) return;
     hipEvent_t a = take_event(), b = take_event();
     if (!a || !b) return;
-    auto &rec = g_prof[cls];
     rec.pairs.emplace_back(a, b);
     slot_ = (int)rec.pairs.size() - 1;
     (void)hipEventRecord(a, s);
@@ -102,8 +105,11 @@ hisq_status hisq_set_tuning(const char *key, int64_t value) {
 }
 
 hisq_status hisq_profile_enable(int on) {
+    if (on < 0) return fail(HISQ_ERR_INVALID_ARG, "hisq_profile_enable: period must be >= 0");
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    g_prof_period = on > 0 ? on : 1;
+    for (auto &kv : g_prof) kv.second.seen = 0;
     return HISQ_OK;
 }
 

@@ -7,38 +7,91 @@ namespace hisq {
 // Process-wide launch-shape knobs (hisq_set_tuning).
 struct DslashTuning {
     int64_t rhs_per_thread = 0;
-    int64_t group_order = 0;
-    int64_t xcd_remap = 1;
+    int64_t lanes_per_site = 0;
+    int64_t group_order = -1;
+    int64_t xcd_remap = -1;
 };
 DslashTuning g_tune;
-int64_t dslash_tune_xcd_remap() { return g_tune.xcd_remap; }
-int64_t dslash_tune_group_order() { return g_tune.group_order; }
 
-// Right-hand sides per thread: the tuned value, else measured defaults.  With
-// many RHS the input field no longer fits the per-XCD L2 and the neighbour
-// gathers are served from the last-level cache; then occupancy (latency
-// hiding) matters more than link reuse in registers: 2 per thread up to
-// Vh = 2^18 (16^3 x 32 with 12 RHS: 78 us against 93 us with 4), 3 above
-// (32^3 x 64: 1.68 ms against 1.74 ms).  A group may be partly empty; lanes
-// mask r < nr.
-int dslash_pick_nr(int nrhs, int vh) {
-    if (g_tune.rhs_per_thread > 0) return (int)g_tune.rhs_per_thread;
-    if (nrhs <= 2) return nrhs;
-    if (nrhs <= 4) return nrhs;
-    return vh <= (1 << 18) ? 2 : 3;
+namespace {
+bool supported_shape(int nr, int lps) {
+    if (lps == 1) return nr == 1 || nr == 2 || nr == 3 || nr == 4 || nr == 6 || nr == 12;
+    if (lps == 2 || lps == 4) return nr == 1 || nr == 3 || nr == 6;
+    return false;
 }
 
+// Smallest supported NR for lps lanes per site that covers nrhs in one group,
+// else the largest.
+int nr_for(int nrhs, int lps) {
+    const int opts1[] = {1, 2, 3, 4, 6, 12}, optsn[] = {1, 3, 6};
+    const int *o = lps == 1 ? opts1 : optsn;
+    const int n = lps == 1 ? 6 : 3;
+    for (int i = 0; i < n; ++i)
+        if (o[i] * lps >= nrhs) return o[i];
+    return o[n - 1];
+}
+}  // namespace
+
+// Launch shape of the half stencil for nrhs RHS at half volume vh in the
+// given precision: the tuned values where set, else defaults measured on
+// MI355X (16^3 x 32 and 32^3 x 64, 1 to 24 RHS).  One RHS streams at 74-76% of
+// HBM peak either way; with several RHS per site the links are read once per
+// group, and the best grouping depends on whether the group's input field
+// still fits the caches: small volumes favour small groups (occupancy), large
+// volumes with many RHS one wide group with several lanes per site.
+DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes) {
+    const bool f32 = real_bytes == 4, small = vh <= (1 << 18);
+    DslashShape sh{};
+    int xcd = 1;
+    if (nrhs <= 2) {
+        sh.nr = nrhs, sh.lps = 1, xcd = f32 ? 0 : 1;
+    } else if (nrhs <= 4) {
+        sh.nr = 2, sh.lps = 1;
+    } else if (f32) {
+        if (small) sh.nr = 3, sh.lps = 1;
+        else sh.nr = 6, sh.lps = 4, xcd = 0;
+    } else {
+        if (small) sh.nr = 1, sh.lps = 4;
+        else sh.nr = 12, sh.lps = 1;
+    }
+    if (g_tune.rhs_per_thread > 0 || g_tune.lanes_per_site > 0) {
+        sh.lps = g_tune.lanes_per_site > 0 ? (int)g_tune.lanes_per_site : 1;
+        sh.nr = g_tune.rhs_per_thread > 0 ? (int)g_tune.rhs_per_thread : nr_for(nrhs, sh.lps);
+    }
+    sh.xcd_remap = g_tune.xcd_remap >= 0 ? (int)g_tune.xcd_remap : xcd;
+    sh.group_outer = g_tune.group_order >= 0 ? (int)g_tune.group_order : 0;
+    // the per-lane 32-bit offsets must cover the group: shrink it if not
+    while (!dslash_impl::shape_fits(sh.nr, sh.lps, vh, real_bytes) && (sh.lps > 1 || sh.nr > 1)) {
+        if (sh.lps > 1) sh.lps /= 2;
+        else sh.nr = sh.nr == 12 ? 6 : sh.nr == 6 ? 3 : 1;
+    }
+    return sh;
+}
+
+hisq_status dslash_check_shape(const DslashShape &sh) {
+    if (!supported_shape(sh.nr, sh.lps))
+        return fail(HISQ_ERR_INVALID_ARG,
+                    "dslash: unsupported (rhs_per_thread, lanes_per_site) = (" +
+                        std::to_string(sh.nr) + ", " + std::to_string(sh.lps) + ")");
+    return HISQ_OK;
+}
 
 hisq_status dslash_set_tuning(const std::string &key, int64_t v) {
     if (key == "dslash_rhs_per_thread") {
         if (!(v == 0 || v == 1 || v == 2 || v == 3 || v == 4 || v == 6 || v == 12))
             return fail(HISQ_ERR_INVALID_ARG, "dslash_rhs_per_thread must be 0, 1, 2, 3, 4, 6 or 12");
         g_tune.rhs_per_thread = v;
+    } else if (key == "dslash_lanes_per_site") {
+        if (!(v == 0 || v == 1 || v == 2 || v == 4))
+            return fail(HISQ_ERR_INVALID_ARG, "dslash_lanes_per_site must be 0, 1, 2 or 4");
+        g_tune.lanes_per_site = v;
     } else if (key == "dslash_group_order") {
-        if (v != 0 && v != 1) return fail(HISQ_ERR_INVALID_ARG, "dslash_group_order must be 0 or 1");
+        if (v != -1 && v != 0 && v != 1)
+            return fail(HISQ_ERR_INVALID_ARG, "dslash_group_order must be -1, 0 or 1");
         g_tune.group_order = v;
     } else if (key == "dslash_xcd_remap") {
-        if (v != 0 && v != 1) return fail(HISQ_ERR_INVALID_ARG, "dslash_xcd_remap must be 0 or 1");
+        if (v != -1 && v != 0 && v != 1)
+            return fail(HISQ_ERR_INVALID_ARG, "dslash_xcd_remap must be -1, 0 or 1");
         g_tune.xcd_remap = v;
     } else {
         return fail(HISQ_ERR_INVALID_ARG, "unknown tuning key '" + key + "'");
@@ -48,7 +101,7 @@ hisq_status dslash_set_tuning(const std::string &key, int64_t v) {
 
 int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs) {
     (void)nrhs;
-    return (g->geom.vh + dslash_impl::kBS - 1) / dslash_impl::kBS;
+    return (g->geom.vh + dslash_impl::kSites - 1) / dslash_impl::kSites;
 }
 
 hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
@@ -59,12 +112,13 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
     using V = vec2<double>;
     const V *fat[2] = {reinterpret_cast<const V *>(g->fat[0]), reinterpret_cast<const V *>(g->fat[1])};
     const V *lng[2] = {reinterpret_cast<const V *>(g->lng[0]), reinterpret_cast<const V *>(g->lng[1])};
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, sizeof(double));
+    HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux2 ? "dslash_aux2" : aux ? "dslash_aux" : "dslash", s);
     return dslash_impl::launch_dslash_t<double>(
         g->geom, fat, lng, out_parity, reinterpret_cast<const V *>(in), reinterpret_cast<V *>(out),
         nrhs, reinterpret_cast<const V *>(aux), ca, reinterpret_cast<const V *>(aux2), cb, cd,
-        fin == FIN_CG_ALPHA ? red->partials : nullptr, dslash_pick_nr(nrhs, g->geom.vh),
-        (int)g_tune.xcd_remap, (int)g_tune.group_order, s);
+        fin == FIN_CG_ALPHA ? red->partials : nullptr, sh, s);
 }
 
 hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,

@@ -7,9 +7,8 @@
 
 namespace hisq {
 
-int dslash_pick_nr(int nrhs, int vh);
-int64_t dslash_tune_xcd_remap();
-int64_t dslash_tune_group_order();
+DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes);
+hisq_status dslash_check_shape(const DslashShape &sh);
 
 namespace {
 
@@ -27,7 +26,7 @@ __global__ __launch_bounds__(kBS) void k_links_to_f32(const double2 *__restrict_
 
 hisq_status ensure_links_f32(hisq_gauge_s *g, hipStream_t s) {
     if (g->fat32[0]) return HISQ_OK;
-    const int64_t n = 36 * (int64_t)g->geom.vh;
+    const int64_t n = link_array_entries(g->geom.vh);
     for (int p = 0; p < 2; ++p) {
         if (hipMalloc(&g->fat32[p], sizeof(float2) * n) != hipSuccess ||
             hipMalloc(&g->lng32[p], sizeof(float2) * n) != hipSuccess)
@@ -51,12 +50,13 @@ hisq_status launch_dslash_f32(hisq_gauge_s *g, int out_parity, const float2 *in,
                        reinterpret_cast<const V *>(g->fat32[1])};
     const V *lng[2] = {reinterpret_cast<const V *>(g->lng32[0]),
                        reinterpret_cast<const V *>(g->lng32[1])};
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, sizeof(float));
+    HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux2 ? "dslash_f32_aux2" : aux ? "dslash_f32_aux" : "dslash_f32", s);
     return dslash_impl::launch_dslash_t<float>(
         g->geom, fat, lng, out_parity, reinterpret_cast<const V *>(in), reinterpret_cast<V *>(out),
         nrhs, reinterpret_cast<const V *>(aux), ca, reinterpret_cast<const V *>(aux2), cb, cd,
-        partials, dslash_pick_nr(nrhs, g->geom.vh), (int)dslash_tune_xcd_remap(),
-        (int)dslash_tune_group_order(), s);
+        partials, sh, s);
 }
 
 hisq_status apply_mdagm_f32(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,

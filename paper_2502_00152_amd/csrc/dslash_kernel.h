@@ -7,14 +7,29 @@
 // for every site x of parity p (arXiv:2502.00152, section 2: the HISQ matrix
 // D of M = D + 2m; the even-odd split makes D map one parity to the other).
 //
-// One thread owns one output site and NR right-hand sides.  Forward links are
-// read at the thread's own checkerboard index (coalesced); backward links are
-// read at the neighbour's index in the other parity's array, which is
-// coalesced too for y, z, t hops (constant offset) and nearly so for x hops.
-// The HBM traffic per output site is 16 links + (in + out) per RHS, so the
-// kernel is bound by HBM bandwidth.  Included by dslash.hip (FP64) and
-// dslash_f32.hip (FP32) only.
+// Work decomposition.  A block covers kSites consecutive output sites
+// (checkerboard index) for one group of LPS * NR right-hand sides; it has
+// kSites * LPS threads.  Inside a wave, 64 / LPS consecutive sites are served
+// by LPS lanes each, lane slot q holding RHS q*NR .. q*NR+NR-1 of the group.
+// The LPS lanes of one site load the same link entries in the same
+// instruction, so the memory pipeline fetches each link cache line once per
+// wave for all LPS * NR right-hand sides; every RHS plane is still read in
+// runs of 64 / LPS consecutive sites.  Forward links are read at the site's
+// own index; backward links at the neighbour's index in the other parity's
+// array (constant offset for y, z, t hops, nearly so for x hops).
+//
+// Addresses are a wave-uniform base (scalar registers: array, direction,
+// colour entry, RHS) plus a 32-bit per-lane byte offset, so each load needs no
+// 64-bit vector address arithmetic.  The launcher checks that the per-lane
+// offsets fit 32 bits.
+//
+// The <aux, out> partials of one block and RHS are summed over the block's
+// kSites sites in one fixed order, whatever NR and LPS are, so the CG gives
+// bitwise the same iterates for any launch shape and batch size.
+// Included by dslash.hip (FP64) and dslash_f32.hip (FP32) only.
 #pragma once
+
+#include <cstdint>
 
 #include "device_util.h"
 #include "hisq_internal.h"
@@ -24,9 +39,18 @@ namespace hisq {
 template <typename R>
 using vec2 = R __attribute__((ext_vector_type(2)));
 
+// Launch shape of the half stencil: NR RHS per lane, LPS lanes per site, the
+// XCD-contiguous block order and the order of site blocks and RHS groups.
+struct DslashShape {
+    int nr;
+    int lps;
+    int xcd_remap;
+    int group_outer;
+};
+
 namespace dslash_impl {
 
-constexpr int kBS = 256;
+constexpr int kSites = 256;  // output sites per block (and per partial sum)
 
 template <typename R>
 struct DslashArgs {
@@ -44,10 +68,9 @@ struct DslashArgs {
     int xcd_remap;         // 1: contiguous site ranges per XCD
     int group_outer;       // 1: block index = group * nsb + site block
     int nrhs;
-    int ngroups;           // ceil(nrhs / NR)
-    int nsb;               // site blocks
-    // fused reduction (FIN_CG_ALPHA)
-    double *partials;      // [nrhs][nsb]
+    int ngroups;           // ceil(nrhs / (LPS * NR))
+    int nsb;               // site blocks = ceil(Vh / kSites)
+    double *partials;      // [nrhs][nsb] (DOT)
 };
 
 __device__ __forceinline__ int wrap(int c, int L) {
@@ -58,30 +81,81 @@ __device__ __forceinline__ int wrap(int c, int L) {
     return c;
 }
 
+// base + byte_off with the base pinned to scalar registers: the optimiser
+// cannot fold the per-lane offset into the base (which would bring back a
+// 64-bit vector add per load), so the loads use the scalar-base addressing
+// form with a 32-bit vector offset.
+template <typename V>
+__device__ __forceinline__ uint64_t sbase(V *base) {
+    const uint64_t v = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename V>
+using gptr = __attribute__((address_space(1))) V *;  // global memory
+
+template <typename V>
+__device__ __forceinline__ gptr<const V> at(const V *base, uint32_t byte_off) {
+    return reinterpret_cast<gptr<const V>>(sbase(base) + byte_off);
+}
+
+template <typename V>
+__device__ __forceinline__ gptr<V> at(V *base, uint32_t byte_off) {
+    return reinterpret_cast<gptr<V>>(sbase(base) + byte_off);
+}
+
 // Link loads: non-temporal when a launch reads each link once (one RHS group:
 // the links should not evict the input field), plain when several RHS groups
 // read the same links (L2 then serves the later groups).  The choice is a
 // template argument: a runtime select lets the compiler merge the two loads
 // into one plain load.
 template <bool NT, typename V>
-__device__ __forceinline__ V ldlink(const V *p) {
+__device__ __forceinline__ V ldlink(gptr<const V> p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
 
+// Byte offset of entry 0 of the link of checkerboard site cb within one
+// direction's tiled array (entry k follows at k * kLinkTile entries).
+template <typename V>
+__device__ __forceinline__ uint32_t link_off(int cb) {
+    return ((uint32_t)(cb / kLinkTile) * (9 * kLinkTile) + (uint32_t)(cb % kLinkTile)) *
+           (uint32_t)sizeof(V);
+}
+
+// acc += U v for the lane's RHS; U at (base U, offset uoff), v at the
+// neighbour (offset voff within each colour plane of the group).
+// Compiler-only fence (emits no instruction) after each hop: the hop's
+// products must be complete and the next hop's loads cannot move above it.
+// This bounds the register footprint - without it the compiler issues the
+// loads of all 16 hops first and spills.
+template <int NR, typename V>
+__device__ __forceinline__ void hop_fence(V (&acc)[NR][3]) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) __asm__ __volatile__("" : "+v"(acc[r][c])::"memory");
+}
+
+// roff[r]: byte offset of the lane's r-th RHS plane from the group's first
+// (clamped to its last valid RHS in a ragged group, so that no lane branches).
 template <int NR, bool NT, typename R>
-__device__ __forceinline__ void hop_forward(const vec2<R> *__restrict__ U, int vh, int cbU,
-                                            const vec2<R> *__restrict__ in, int64_t rstride,
-                                            int cbN, int nr, vec2<R> (&acc)[NR][3]) {
+__device__ __forceinline__ void hop_forward(const vec2<R> *__restrict__ U, int vh, uint32_t uoff,
+                                            const vec2<R> *__restrict__ in, uint32_t voff,
+                                            const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
     using V = vec2<R>;
     V u[9];
+    const gptr<const V> up = at(U, uoff);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(U + (int64_t)k * vh + cbU);
+    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(up + k * kLinkTile);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        if (r < nr) {
-            const V *v = in + r * rstride + cbN;
-            const V v0 = v[0], v1 = v[vh], v2 = v[2 * (int64_t)vh];
+        {
+            const V v0 = *at(in, roff[r] + voff);
+            const V v1 = *at(in + vh, roff[r] + voff);
+            const V v2 = *at(in + 2 * (int64_t)vh, roff[r] + voff);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 V s = acc[r][a];
@@ -95,22 +169,25 @@ __device__ __forceinline__ void hop_forward(const vec2<R> *__restrict__ U, int v
             }
         }
     }
+    hop_fence<NR>(acc);
 }
 
-// acc -= U^H v, with U read at the neighbour's index.
+// acc -= U^H v, with U read at the neighbour's index (offset noff for both).
 template <int NR, bool NT, typename R>
-__device__ __forceinline__ void hop_backward(const vec2<R> *__restrict__ U, int vh, int cbN,
-                                             const vec2<R> *__restrict__ in, int64_t rstride,
-                                             int nr, vec2<R> (&acc)[NR][3]) {
+__device__ __forceinline__ void hop_backward(const vec2<R> *__restrict__ U, int vh, uint32_t uoff,
+                                             const vec2<R> *__restrict__ in, uint32_t voff,
+                                             const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
     using V = vec2<R>;
     V u[9];
+    const gptr<const V> up = at(U, uoff);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(U + (int64_t)k * vh + cbN);
+    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(up + k * kLinkTile);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        if (r < nr) {
-            const V *v = in + r * rstride + cbN;
-            const V v0 = v[0], v1 = v[vh], v2 = v[2 * (int64_t)vh];
+        {
+            const V v0 = *at(in, roff[r] + voff);
+            const V v1 = *at(in + vh, roff[r] + voff);
+            const V v2 = *at(in + 2 * (int64_t)vh, roff[r] + voff);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 // (U^H)_{ab} = conj(U_{ba})
@@ -125,11 +202,27 @@ __device__ __forceinline__ void hop_backward(const vec2<R> *__restrict__ U, int 
             }
         }
     }
+    hop_fence<NR>(acc);
 }
 
-template <typename R, int NR, bool AUX, bool AUX2, bool DOT, bool NT>
-__global__ __launch_bounds__(kBS) void k_dslash(DslashArgs<R> a) {
+// Sum of x[0 .. kSites) in the canonical order, by one full wave (result in
+// every lane): lane l adds x[l], x[l+64], x[l+128], x[l+192] in that order,
+// then the fixed butterfly over the wave.
+__device__ __forceinline__ double chunk_sum(const double *x) {
+    static_assert(kSites == 4 * kWave, "canonical chunk is four waves of sites");
+    const int l = threadIdx.x & (kWave - 1);
+    double v = x[l];
+    v += x[l + kWave];
+    v += x[l + 2 * kWave];
+    v += x[l + 3 * kWave];
+    return wave_sum(v);
+}
+
+template <typename R, int NR, int LPS, bool AUX, bool AUX2, bool DOT, bool NT>
+__global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
     using V = vec2<R>;
+    constexpr int SPW = kWave / LPS;  // sites per wave
+    constexpr int RG = LPS * NR;      // RHS per group
     const Geom g = a.geom;
     const int vh = g.vh;
     const int lb = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -141,16 +234,20 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs<R> a) {
         sb = lb / a.ngroups;
         grp = lb - sb * a.ngroups;
     }
-    const int cb = sb * kBS + threadIdx.x;
-    const int r0 = grp * NR;
-    const int nr = min(NR, a.nrhs - r0);
-    const int64_t rstride = 3 * (int64_t)vh;
+    const int w = threadIdx.x / kWave, l = threadIdx.x & (kWave - 1);
+    const int q = l / SPW;                    // RHS slot of this lane
+    const int sl = w * SPW + (l - q * SPW);   // site within the block
+    const int cb = sb * kSites + sl;
+    const int rg0 = grp * RG;                 // first RHS of the group
+    const int nr = min(NR, a.nrhs - rg0 - q * NR);
+    // byte offset of this lane's first RHS plane within the group
+    const uint32_t qoff = (uint32_t)(q * NR * 3) * (uint32_t)vh * (uint32_t)sizeof(V);
 
     double dotv[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) dotv[r] = 0.0;
 
-    if (cb < vh) {
+    if (cb < vh && nr > 0) {
         // coordinates of the output site
         int t = cb / g.Xh;
         const int xh = cb - t * g.Xh;
@@ -167,8 +264,14 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs<R> a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[r][c] = V{R(0), R(0)};
 
-        const V *in = a.in + r0 * rstride;
-        const int64_t lstride = 9 * (int64_t)vh;
+        const V *in = a.in + (int64_t)rg0 * 3 * vh;
+        uint32_t roff[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            roff[r] = qoff + (uint32_t)(3 * min(r, nr - 1)) * (uint32_t)vh * (uint32_t)sizeof(V);
+        const int64_t lstride = 9 * kLinkTile * link_tiles(vh);  // one direction
+        const uint32_t own = (uint32_t)cb * (uint32_t)sizeof(V);
+        const uint32_t own_l = link_off<V>(cb);
 
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -179,29 +282,33 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs<R> a) {
             {
                 const int f = (rowYZT * g.X + wrap(x + hop, g.X)) >> 1;
                 const int b = (rowYZT * g.X + wrap(x - hop, g.X)) >> 1;
-                hop_forward<NR, NT, R>(Uo, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR, NT, R>(Ui, vh, b, in, rstride, nr, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
+                hop_forward<NR, NT, R>(Uo, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
+                hop_backward<NR, NT, R>(Ui, vh, link_off<V>(b), in, bo, roff, acc);
             }
             // mu = 1 (y)
             {
                 const int f = ((((t * g.Z + z) * g.Y + wrap(y + hop, g.Y)) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + z) * g.Y + wrap(y - hop, g.Y)) * g.X) + x) >> 1;
-                hop_forward<NR, NT, R>(Uo + lstride, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR, NT, R>(Ui + lstride, vh, b, in, rstride, nr, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
+                hop_forward<NR, NT, R>(Uo + lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
+                hop_backward<NR, NT, R>(Ui + lstride, vh, link_off<V>(b), in, bo, roff, acc);
             }
             // mu = 2 (z)
             {
                 const int f = ((((t * g.Z + wrap(z + hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + wrap(z - hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
-                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, b, in, rstride, nr, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
+                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
+                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, link_off<V>(b), in, bo, roff, acc);
             }
             // mu = 3 (t)
             {
                 const int f = ((((wrap(t + hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((wrap(t - hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
-                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, cb, in, rstride, f, nr, acc);
-                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, b, in, rstride, nr, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
+                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
+                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<V>(b), in, bo, roff, acc);
             }
         }
 
@@ -209,16 +316,17 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs<R> a) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r < nr) {
-                const int64_t base = (r0 + r) * rstride + cb;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
+                    const int64_t plane = (int64_t)(rg0 * 3 + 3 * r + c) * vh;
+                    const uint32_t off = qoff + own;
                     V o = acc[r][c] * a.cd;
                     if (AUX) {
-                        const V ax = a.aux[base + c * (int64_t)vh];
+                        const V ax = *at(a.aux + plane, off);
                         o.x = fma(a.ca, ax.x, o.x);
                         o.y = fma(a.ca, ax.y, o.y);
                         if (AUX2) {
-                            const V a2 = a.aux2[base + c * (int64_t)vh];
+                            const V a2 = *at(a.aux2 + plane, off);
                             o.x = fma(a.cb, a2.x, o.x);
                             o.y = fma(a.cb, a2.y, o.y);
                         }
@@ -226,61 +334,70 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs<R> a) {
                             dotv[r] = fma((double)ax.x, (double)o.x,
                                           fma((double)ax.y, (double)o.y, dotv[r]));
                     }
-                    a.out[base + c * (int64_t)vh] = o;
+                    *at(a.out + plane, off) = o;
                 }
             }
         }
     }
 
     if (DOT) {
-        // per-block partial sums of Re<aux, out>; the CG update kernel adds them
-        // up in block order (no cross-block synchronisation in this kernel)
-        __shared__ double lds[NR * (kBS / kWave)];
-        block_sum<NR, kBS>(dotv, lds);
-        if (threadIdx.x == 0) {
+        // per-block partial sums of Re<aux, out> for each RHS of the group, in
+        // the canonical order over the block's sites; the CG update kernel adds
+        // the blocks' partials in block order
+        __shared__ double red[RG * kSites];
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (r < nr) a.partials[(int64_t)(r0 + r) * a.nsb + sb] = dotv[r];
+        for (int r = 0; r < NR; ++r) red[(q * NR + r) * kSites + sl] = dotv[r];
+        __syncthreads();
+        constexpr int NW = kSites * LPS / kWave;
+        for (int j = w; j < RG; j += NW) {
+            const double s = chunk_sum(red + j * kSites);
+            if (l == 0 && rg0 + j < a.nrhs) a.partials[(int64_t)(rg0 + j) * a.nsb + sb] = s;
         }
     }
 }
 
-template <typename R, int NR, bool NT>
+template <typename R, int NR, int LPS, bool NT>
 void launch_variant(const DslashArgs<R> &args, int nblocks, bool aux, bool aux2, bool dot,
                     hipStream_t s) {
+    const dim3 grid(nblocks), block(kSites * LPS);
     if (dot)
-        hipLaunchKernelGGL((k_dslash<R, NR, true, false, true, NT>), dim3(nblocks), dim3(kBS), 0, s,
-                           args);
+        hipLaunchKernelGGL((k_dslash<R, NR, LPS, true, false, true, NT>), grid, block, 0, s, args);
     else if (aux2)
-        hipLaunchKernelGGL((k_dslash<R, NR, true, true, false, NT>), dim3(nblocks), dim3(kBS), 0, s,
-                           args);
+        hipLaunchKernelGGL((k_dslash<R, NR, LPS, true, true, false, NT>), grid, block, 0, s, args);
     else if (aux)
-        hipLaunchKernelGGL((k_dslash<R, NR, true, false, false, NT>), dim3(nblocks), dim3(kBS), 0, s,
-                           args);
+        hipLaunchKernelGGL((k_dslash<R, NR, LPS, true, false, false, NT>), grid, block, 0, s, args);
     else
-        hipLaunchKernelGGL((k_dslash<R, NR, false, false, false, NT>), dim3(nblocks), dim3(kBS), 0,
-                           s, args);
+        hipLaunchKernelGGL((k_dslash<R, NR, LPS, false, false, false, NT>), grid, block, 0, s,
+                           args);
 }
 
-template <typename R, int NR>
-hisq_status launch_nr(const DslashArgs<R> &args, int nblocks, bool aux, bool aux2, bool dot,
-                      hipStream_t s) {
+template <typename R, int NR, int LPS>
+hisq_status launch_shape(const DslashArgs<R> &args, int nblocks, bool aux, bool aux2, bool dot,
+                         hipStream_t s) {
     if (args.ngroups == 1)
-        launch_variant<R, NR, true>(args, nblocks, aux, aux2, dot, s);
+        launch_variant<R, NR, LPS, true>(args, nblocks, aux, aux2, dot, s);
     else
-        launch_variant<R, NR, false>(args, nblocks, aux, aux2, dot, s);
+        launch_variant<R, NR, LPS, false>(args, nblocks, aux, aux2, dot, s);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
-// Fill the argument block and launch with NR right-hand sides per thread.
+// True if the per-lane 32-bit byte offsets of the shape fit for this volume.
+inline bool shape_fits(int nr, int lps, int vh, size_t real_bytes) {
+    const uint64_t span = (uint64_t)(lps * nr * 3) * (uint64_t)vh * 2 * real_bytes;
+    return span < (1ull << 32);
+}
+
+// Fill the argument block and launch with the given shape.
 template <typename R>
 hisq_status launch_dslash_t(const Geom &geom, const vec2<R> *const fat[2],
                             const vec2<R> *const lng[2], int out_parity, const vec2<R> *in,
                             vec2<R> *out, int nrhs, const vec2<R> *aux, double ca,
-                            const vec2<R> *aux2, double cb, double cd, double *partials, int nr,
-                            int xcd_remap, int group_outer, hipStream_t s) {
+                            const vec2<R> *aux2, double cb, double cd, double *partials,
+                            DslashShape sh, hipStream_t s) {
     if (aux2 && !aux) return fail(HISQ_ERR_INVALID_ARG, "dslash: aux2 needs aux");
+    if (!shape_fits(sh.nr, sh.lps, geom.vh, sizeof(R)))
+        return fail(HISQ_ERR_INVALID_ARG, "dslash: RHS group too large for this volume");
     DslashArgs<R> a{};
     const int p = out_parity;
     a.fat_out = fat[p];
@@ -296,25 +413,32 @@ hisq_status launch_dslash_t(const Geom &geom, const vec2<R> *const fat[2],
     a.cd = (R)cd;
     a.geom = geom;
     a.out_parity = p;
-    a.xcd_remap = xcd_remap;
-    a.group_outer = group_outer;
+    a.xcd_remap = sh.xcd_remap;
+    a.group_outer = sh.group_outer;
     a.nrhs = nrhs;
-    a.ngroups = (nrhs + nr - 1) / nr;
-    a.nsb = (geom.vh + kBS - 1) / kBS;
+    a.ngroups = (nrhs + sh.lps * sh.nr - 1) / (sh.lps * sh.nr);
+    a.nsb = (geom.vh + kSites - 1) / kSites;
     a.partials = partials;
     const bool dot = partials != nullptr;
     const int nblocks = a.nsb * a.ngroups;
-    switch (nr) {
-        case 1: return launch_nr<R, 1>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
-        case 2: return launch_nr<R, 2>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
-        case 3: return launch_nr<R, 3>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
-        case 4: return launch_nr<R, 4>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
-        case 6: return launch_nr<R, 6>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
-        case 12: return launch_nr<R, 12>(a, nblocks, aux != nullptr, aux2 != nullptr, dot, s);
-        default: return fail(HISQ_ERR_INVALID_ARG, "dslash: bad RHS grouping");
-    }
+    const bool x = aux != nullptr, x2 = aux2 != nullptr;
+#define HISQ_SHAPE(NR_, LPS_) \
+    if (sh.nr == NR_ && sh.lps == LPS_) return launch_shape<R, NR_, LPS_>(a, nblocks, x, x2, dot, s)
+    HISQ_SHAPE(1, 1);
+    HISQ_SHAPE(2, 1);
+    HISQ_SHAPE(3, 1);
+    HISQ_SHAPE(4, 1);
+    HISQ_SHAPE(6, 1);
+    HISQ_SHAPE(12, 1);
+    HISQ_SHAPE(1, 2);
+    HISQ_SHAPE(3, 2);
+    HISQ_SHAPE(6, 2);
+    HISQ_SHAPE(1, 4);
+    HISQ_SHAPE(3, 4);
+    HISQ_SHAPE(6, 4);
+#undef HISQ_SHAPE
+    return fail(HISQ_ERR_INVALID_ARG, "dslash: unsupported launch shape");
 }
-
 
 }  // namespace dslash_impl
 }  // namespace hisq

@@ -62,9 +62,23 @@ private:
 
 }  // namespace hisq
 
+namespace hisq {
+// Link storage is tiled by kLinkTile consecutive checkerboard sites: within a
+// tile the 9 entries of the colour matrix are kLinkTile apart, so a wave reads
+// entry k of its sites at a constant offset from entry 0.
+constexpr int kLinkTile = 16;
+__host__ __device__ inline int64_t link_tiles(int vh) { return (vh + kLinkTile - 1) / kLinkTile; }
+// complex entries per parity array (4 directions, padded to whole tiles)
+inline int64_t link_array_entries(int vh) { return 4 * 9 * kLinkTile * link_tiles(vh); }
+__host__ __device__ inline int64_t link_index(int mu, int k, int cb, int64_t ntiles) {
+    return (((int64_t)mu * ntiles + (cb / kLinkTile)) * 9 + k) * kLinkTile + (cb % kLinkTile);
+}
+}  // namespace hisq
+
 // The gauge handle: links in kernel layout plus scratch.
-//   fat[p], lng[p]: links living on sites of parity p, complex double SoA
-//   [4 mu][9 = 3x3 row-major][Vh]; the entry (mu, k, cb) is at (mu*9 + k)*Vh + cb.
+//   fat[p], lng[p]: links living on sites of parity p, complex, entry k of the
+//   3x3 row-major matrix of direction mu at checkerboard site cb is at
+//   link_index(mu, k, cb, link_tiles(Vh)): [4 mu][tile][9 k][kLinkTile].
 struct hisq_gauge_s {
     hisq::Geom geom;
     int device = 0;
@@ -221,6 +235,9 @@ hisq_status mixed_p_restart(float2 *p, const float2 *r, int64_t n, int nrhs, con
                             const int *mode, hipStream_t s);
 // zero column j of C ([nrhs][k]) where mask[j] == 0
 hisq_status mixed_mask_rows(double2 *C, int k, int nrhs, const int *mask, hipStream_t s);
+// Precision change of n complex numbers (FP64 <-> FP32, or a copy).
+hisq_status convert_vectors(const void *src, hisq_prec sp, void *dst, hisq_prec dp, int64_t n,
+                            hipStream_t s);
 hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s);
 

@@ -50,12 +50,13 @@ __global__ __launch_bounds__(kBS) void k_accum_x(dvec2 *__restrict__ x, fvec2 *_
     }
 }
 
-// r = b - Ax and ||r||^2 for masked RHS; out[rhs] receives the norms (0 for
-// unmasked RHS), summed in block order by the last block to arrive.
+// r = b - Ax and per-block partials of ||r||^2 for masked RHS (0 for the
+// others); k_resid_sum adds each RHS's partials in block order.  (No
+// cross-block synchronisation: a device-scope fence per block writes back L2
+// on this multi-XCD chip and costs more than the pass itself.)
 __global__ __launch_bounds__(kBS) void k_resid(const dvec2 *__restrict__ b, const dvec2 *__restrict__ Ax,
-                                               dvec2 *__restrict__ r, int64_t n, int nrhs,
-                                               const int *__restrict__ mask, double *out,
-                                               Reduce red) {
+                                               dvec2 *__restrict__ r, int64_t n,
+                                               const int *__restrict__ mask, double *partials) {
     const int rhs = blockIdx.y;
     const int64_t off = rhs * n;
     double v[1] = {0.0};
@@ -68,15 +69,29 @@ __global__ __launch_bounds__(kBS) void k_resid(const dvec2 *__restrict__ b, cons
     }
     __shared__ double lds[kBS / kWave];
     block_sum<1, kBS>(v, lds);
-    const int nb = gridDim.x;
-    if (threadIdx.x == 0) red.partials[(int64_t)rhs * nb + blockIdx.x] = v[0];
-    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
-        __shared__ double w[kBS / kWave];
-        for (int q = 0; q < nrhs; ++q) {
-            const double t = sum_partials<kBS>(red.partials + (int64_t)q * nb, nb, w);
-            if (threadIdx.x == 0) out[q] = t;
-        }
-        last_block_done(red.counter);
+    if (threadIdx.x == 0) partials[(int64_t)rhs * gridDim.x + blockIdx.x] = v[0];
+}
+
+// out[q] = sum of the nb partials of RHS q in block order; one wave per RHS.
+__global__ __launch_bounds__(kBS) void k_resid_sum(const double *__restrict__ partials, int nb,
+                                                   int nrhs, double *out) {
+    const int q = blockIdx.x * (kBS / kWave) + threadIdx.x / kWave;
+    if (q >= nrhs) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    double v = 0.0;
+    for (int i = lane; i < nb; i += kWave) v += partials[(int64_t)q * nb + i];
+    v = wave_sum(v);
+    if (lane == 0) out[q] = v;
+}
+
+// dst = src with a change of precision (grid-stride over n complex numbers)
+template <typename S, typename D>
+__global__ __launch_bounds__(kBS) void k_convert(const S *__restrict__ src, D *__restrict__ dst,
+                                                 int64_t n) {
+    using R = decltype(D{}.x);
+    GRID_STRIDE(i) {
+        const S v = src[i];
+        dst[i] = D{(R)v.x, (R)v.y};
     }
 }
 
@@ -122,6 +137,23 @@ hisq_status mixed_to_f32(const double2 *src, float2 *dst, int64_t n, int nrhs, c
     return HISQ_OK;
 }
 
+hisq_status convert_vectors(const void *src, hisq_prec sp, void *dst, hisq_prec dp, int64_t n,
+                            hipStream_t s) {
+    if (n == 0) return HISQ_OK;
+    const int nb = (int)std::min<int64_t>((n + kBS - 1) / kBS, 16384);
+    if (sp == HISQ_FP64 && dp == HISQ_FP32)
+        hipLaunchKernelGGL((k_convert<dvec2, fvec2>), dim3(nb), dim3(kBS), 0, s,
+                           static_cast<const dvec2 *>(src), static_cast<fvec2 *>(dst), n);
+    else if (sp == HISQ_FP32 && dp == HISQ_FP64)
+        hipLaunchKernelGGL((k_convert<fvec2, dvec2>), dim3(nb), dim3(kBS), 0, s,
+                           static_cast<const fvec2 *>(src), static_cast<dvec2 *>(dst), n);
+    else
+        HISQ_HIP(hipMemcpyAsync(dst, src, n * (sp == HISQ_FP64 ? sizeof(double2) : sizeof(float2)),
+                                hipMemcpyDeviceToDevice, s));
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
 hisq_status mixed_accum_x(double2 *x, float2 *xs, int64_t n, int nrhs, const int *mask,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_accum_x, dim3(grid_x(n), nrhs), dim3(kBS), 0, s, AS_D(x), AS_F(xs), n,
@@ -132,8 +164,12 @@ hisq_status mixed_accum_x(double2 *x, float2 *xs, int64_t n, int nrhs, const int
 
 hisq_status mixed_resid(const double2 *b, const double2 *Ax, double2 *r, int64_t n, int nrhs,
                         const int *mask, double *out, const Reduce &red, hipStream_t s) {
-    hipLaunchKernelGGL(k_resid, dim3(grid_x(n), nrhs), dim3(kBS), 0, s, AS_CD(b), AS_CD(Ax), AS_D(r),
-                       n, nrhs, mask, out, red);
+    const int nb = grid_x(n);
+    hipLaunchKernelGGL(k_resid, dim3(nb, nrhs), dim3(kBS), 0, s, AS_CD(b), AS_CD(Ax), AS_D(r), n,
+                       mask, red.partials);
+    const int per = kBS / kWave;
+    hipLaunchKernelGGL(k_resid_sum, dim3((nrhs + per - 1) / per), dim3(kBS), 0, s, red.partials, nb,
+                       nrhs, out);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }

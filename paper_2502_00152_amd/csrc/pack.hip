@@ -28,7 +28,8 @@ __device__ __forceinline__ SiteCoords from_lex(int lex, const Geom &g) {
     return c;
 }
 
-// One thread per (mu, site).  canon: [4][V][9] complex; soa[p]: [4][9][Vh].
+// One thread per (mu, site).  canon: [4][V][9] complex; soa[p]: tiled link
+// layout (link_index).
 __global__ __launch_bounds__(kBS) void k_pack_links(const double2 *__restrict__ canon,
                                                     double2 *__restrict__ soa_even,
                                                     double2 *__restrict__ soa_odd, Geom g,
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(kBS) void k_pack_links(const double2 *__restrict__ 
         double2 v = src[k];
         v.x *= s;
         v.y *= s;
-        dst[((int64_t)mu * 9 + k) * g.vh + c.cb] = v;
+        dst[link_index(mu, k, c.cb, link_tiles(g.vh))] = v;
     }
 }
 

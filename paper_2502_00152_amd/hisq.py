@@ -44,7 +44,7 @@ EXPORTS = (
     "hisq_gauge_half_volume", "hisq_spinor_split", "hisq_spinor_merge", "hisq_dslash_eo",
     "hisq_mdagm", "hisq_prepare_source", "hisq_reconstruct_odd", "hisq_cg_solve",
     "hisq_deflate", "hisq_eigensolve", "hisq_set_tuning", "hisq_profile_enable",
-    "hisq_profile_read",
+    "hisq_profile_read", "hisq_convert_vectors",
 )
 
 
@@ -117,6 +117,7 @@ def lib():
         "hisq_eigensolve": ([P, D, I, ctypes.POINTER(EigParams), P, ctypes.POINTER(D),
                              ctypes.POINTER(EigStats), P], I),
         "hisq_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], I),
+        "hisq_convert_vectors": ([P, I, P, I, ctypes.c_int64, P], I),
         "hisq_profile_enable": ([I], I),
         "hisq_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(D)], I),
@@ -341,6 +342,16 @@ def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
                     [s.redeflations for s in stats])
 
 
+def hisq_convert_vectors(src, dst, stream=None):
+    """dst = src in dst's precision (complex128 <-> complex64, same shape)."""
+    if tuple(src.shape) != tuple(dst.shape):
+        raise ValueError("src and dst must have the same shape")
+    ok = ("complex128", "complex64")
+    _check(lib().hisq_convert_vectors(_ptr(src, "src", ok), _prec_of(src, "src"),
+                                      _ptr(dst, "dst", ok), _prec_of(dst, "dst"),
+                                      int(src.numel()), _stream(stream)), "hisq_convert_vectors")
+
+
 def hisq_deflate(g, evecs, evals, two_m, b, x0, stream=None):
     """x0 = V diag(1/(eps + (2m)^2)) V^H b; evecs complex128 or complex64 (FP32)."""
     n_ev = _nrhs(evecs, g.vh, "evecs")
@@ -378,8 +389,9 @@ def hisq_set_tuning(key: str, value: int):
     _check(lib().hisq_set_tuning(key.encode(), int(value)), "hisq_set_tuning")
 
 
-def hisq_profile_enable(on: bool):
-    _check(lib().hisq_profile_enable(1 if on else 0), "hisq_profile_enable")
+def hisq_profile_enable(on, period: int = 1):
+    """Time launches per kernel class: off if not on, else every period-th launch."""
+    _check(lib().hisq_profile_enable(int(period) if on else 0), "hisq_profile_enable")
 
 
 def hisq_profile_read(kernel_class: str):

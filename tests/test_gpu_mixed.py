@@ -93,18 +93,22 @@ def test_fp32_stencil_grouping_is_bitwise_invariant():
     v = torch.from_numpy(to_parity(sources(dims, 12, 700), dims, 1).astype(np.complex64)).cuda()
     ref = torch.empty_like(v)
     hisq.hisq_dslash_eo(g, 0, v, ref)
+    shapes = [(nr, 1) for nr in (1, 2, 3, 4, 6, 12)] + [(nr, l) for l in (2, 4) for nr in (1, 3, 6)]
     try:
-        for nr in (1, 2, 3, 4, 6, 12):
+        for nr, lps in shapes:
             hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
+            hisq.hisq_set_tuning("dslash_lanes_per_site", lps)
             out = torch.empty_like(v)
             hisq.hisq_dslash_eo(g, 0, v, out)
-            assert torch.equal(out, ref), nr
+            assert torch.equal(out, ref), (nr, lps)
         one = torch.empty_like(v[:1])
         hisq.hisq_set_tuning("dslash_rhs_per_thread", 0)
+        hisq.hisq_set_tuning("dslash_lanes_per_site", 0)
         hisq.hisq_dslash_eo(g, 0, v[5:6].clone(), one)
         assert torch.equal(one[0], ref[5])
     finally:
         hisq.hisq_set_tuning("dslash_rhs_per_thread", 0)
+        hisq.hisq_set_tuning("dslash_lanes_per_site", 0)
         g.close()
 
 
@@ -230,3 +234,23 @@ def test_mixed_cg_edge_cases(w8):
         hisq.hisq_cg_solve(pr.g, pr.two_m, b[:1].clone(), torch.zeros_like(b[:1]),
                            evecs=ev, evals=[0.5], tol_restart=1e-3)
     assert e.value.status == hisq.HISQ_ERR_INVALID_ARG
+
+
+def test_convert_vectors_rounds_to_nearest():
+    """FP64 -> FP32 rounds each real to nearest (as numpy's cast does),
+    FP32 -> FP64 is exact; bad arguments are rejected."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    rng = np.random.default_rng(3)
+    v = (rng.standard_normal((5, 3, 1001)) + 1j * rng.standard_normal((5, 3, 1001))) * \
+        np.exp(rng.uniform(-30, 30, (5, 3, 1001)))
+    a = torch.from_numpy(v).cuda()
+    b = torch.empty(a.shape, dtype=torch.complex64, device="cuda")
+    hisq.hisq_convert_vectors(a, b)
+    assert np.array_equal(host(b), v.astype(np.complex64))
+    c = torch.empty_like(a)
+    hisq.hisq_convert_vectors(b, c)
+    assert np.array_equal(host(c), v.astype(np.complex64).astype(np.complex128))
+    with pytest.raises(hisq.HisqError):
+        hisq.hisq_convert_vectors(a, a)
+    assert hisq.lib().hisq_convert_vectors(None, 0, None, 1, 4, None) == hisq.HISQ_ERR_INVALID_ARG

@@ -157,22 +157,79 @@ def test_launch_shape_knobs_do_not_change_results():
     v = dev(to_parity(sources(dims, 12, 500), dims, 1))
     ref = torch.empty_like(v)
     hisq.hisq_dslash_eo(g, 0, v, ref)
+    shapes = [(nr, 1) for nr in (1, 2, 3, 4, 6, 12)] + [(nr, l) for l in (2, 4) for nr in (1, 3, 6)]
     try:
-        for nr in (1, 2, 3, 4, 6, 12):
+        for nr, lps in shapes:
             for order in (0, 1):
                 for xcd in (0, 1):
                     hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
+                    hisq.hisq_set_tuning("dslash_lanes_per_site", lps)
                     hisq.hisq_set_tuning("dslash_group_order", order)
                     hisq.hisq_set_tuning("dslash_xcd_remap", xcd)
                     out = torch.empty_like(v)
                     hisq.hisq_dslash_eo(g, 0, v, out)
-                    assert torch.equal(out, ref), (nr, order, xcd)
+                    assert torch.equal(out, ref), (nr, lps, order, xcd)
+        # a shape the kernel does not provide is an error, not a silent fallback
+        hisq.hisq_set_tuning("dslash_rhs_per_thread", 2)
+        hisq.hisq_set_tuning("dslash_lanes_per_site", 4)
+        with pytest.raises(hisq.HisqError) as e:
+            hisq.hisq_dslash_eo(g, 0, v, torch.empty_like(v))
+        assert e.value.status == hisq.HISQ_ERR_INVALID_ARG
         with pytest.raises(hisq.HisqError):
             hisq.hisq_set_tuning("dslash_rhs_per_thread", 5)
         with pytest.raises(hisq.HisqError):
+            hisq.hisq_set_tuning("dslash_lanes_per_site", 3)
+        with pytest.raises(hisq.HisqError):
             hisq.hisq_set_tuning("no_such_knob", 1)
     finally:
-        for k, val in (("dslash_rhs_per_thread", 0), ("dslash_group_order", 0),
-                       ("dslash_xcd_remap", 1)):
+        for k, val in (("dslash_rhs_per_thread", 0), ("dslash_lanes_per_site", 0),
+                       ("dslash_group_order", -1), ("dslash_xcd_remap", -1)):
             hisq.hisq_set_tuning(k, val)
+        g.close()
+
+
+def test_cg_partials_do_not_depend_on_the_launch_shape():
+    """The fused <p, Ap> partial sums use one summation order for every shape:
+    a batched CG gives bitwise the same iterates under any tuning."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (4, 6, 8, 10)
+    pr = Problem(dims, 0.5, 45, 46)
+    g = pr.gauge()
+    b = dev(to_parity(sources(dims, 6, 900), dims, 0))
+    ref = torch.zeros_like(b)
+    r0 = hisq.hisq_cg_solve(g, 0.2, b, ref, tol=1e-10)
+    try:
+        for nr, lps in ((1, 1), (3, 1), (6, 1), (3, 2), (1, 4), (6, 4)):
+            hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
+            hisq.hisq_set_tuning("dslash_lanes_per_site", lps)
+            x = torch.zeros_like(b)
+            r = hisq.hisq_cg_solve(g, 0.2, b, x, tol=1e-10)
+            assert r.iterations == r0.iterations, (nr, lps)
+            assert torch.equal(x, ref), (nr, lps)
+    finally:
+        hisq.hisq_set_tuning("dslash_rhs_per_thread", 0)
+        hisq.hisq_set_tuning("dslash_lanes_per_site", 0)
+        g.close()
+
+
+def test_profile_sampling_counts_every_nth_launch():
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (4, 4, 4, 8)
+    pr = Problem(dims, 0.3, 5, 6)
+    g = pr.gauge()
+    v = dev(to_parity(sources(dims, 2, 11), dims, 1))
+    out = torch.empty_like(v)
+    try:
+        hisq.hisq_profile_enable(True, 4)
+        hisq.hisq_profile_read("dslash")
+        for _ in range(9):
+            hisq.hisq_dslash_eo(g, 0, v, out)
+        n, ms = hisq.hisq_profile_read("dslash")
+        assert n == 3 and ms > 0.0          # launches 0, 4 and 8 of the class
+        assert hisq.hisq_profile_read("dslash") == (0, 0.0)
+        assert hisq.lib().hisq_profile_enable(-1) == hisq.HISQ_ERR_INVALID_ARG
+    finally:
+        hisq.hisq_profile_enable(False)
         g.close()

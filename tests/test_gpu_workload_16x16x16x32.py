@@ -124,3 +124,53 @@ def test_plain_cg_iterations(wl):
     res = hisq.hisq_cg_solve(wl.g, wl.cfg["two_m"], wl.y[:1].clone(), x, tol=1e-10)
     it0 = GOLDEN["cg_iterations_undeflated"]
     assert abs(res.iterations[0] - it0) <= max(2, 0.01 * it0)
+
+
+def test_fp32_eigenvectors_stall_and_multi_deflation_recovers(wl, eig):
+    """Section 3, Fig. 2 on the synthetic workload: with single-precision
+    eigenvectors a single deflation leaves low-mode components at the FP32
+    rounding level and the mixed-precision CG needs more iterations than with
+    FP64 eigenvectors; re-deflating whenever the residual has fallen by
+    delta_tr = 1e-3 recovers the FP64 iteration count.  Every solve meets the
+    FP64 true residual 1e-10 (oracle-evaluated on two sources) and differs
+    from the FP64 path's solution by at most the residual bound
+    ||x - x'|| <= (||r|| + ||r'||) / lambda_1."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    ev, lam, stats = eig
+    cfg = wl.cfg
+    two_m = cfg["two_m"]
+    eps = lam - two_m ** 2
+    ev32 = torch.empty(ev.shape, dtype=torch.complex64, device="cuda")
+    hisq.hisq_convert_vectors(ev, ev32)
+    F32 = hisq.HISQ_FP32
+
+    def solve(defl, **kw):
+        x = torch.empty_like(wl.y)
+        hisq.hisq_deflate(wl.g, defl, eps, two_m, wl.y, x)
+        r = hisq.hisq_cg_solve(wl.g, two_m, wl.y, x, tol=1e-10, **kw)
+        assert all(r.converged)
+        return x, r
+
+    x64, r64 = solve(ev)                                       # FP64 path
+    _, r_e64 = solve(ev, sloppy_prec=F32)                      # FP64 eigenvectors
+    _, r_e32 = solve(ev32, sloppy_prec=F32)                    # FP32, one deflation
+    x_m, r_m = solve(ev32, sloppy_prec=F32, evecs=ev32, evals=eps, tol_restart=1e-3)
+    it64, ite64, ite32, itm = (max(r.iterations) for r in (r64, r_e64, r_e32, r_m))
+    print(f"[16x16x16x32] iterations: FP64 {it64}, mixed+FP64 evecs {ite64}, "
+          f"mixed+FP32 evecs {ite32}, multi-deflation {itm} ({r_m.redeflations[0]} re-deflations)",
+          flush=True)
+    assert ite32 > ite64 + 10                  # the stall of single-precision eigenvectors
+    assert itm <= it64 * 1.05 + 5              # multi-deflation recovers the FP64 count
+    assert itm < ite32 - 30
+    assert min(r_m.redeflations) >= 1
+    xs, ys, x64s = host(x_m), host(wl.y), host(x64)
+    for r in (0, 7):
+        xe = from_parity(xs[r:r + 1], wl.dims, 0)[0]
+        ye = from_parity(ys[r:r + 1], wl.dims, 0)[0]
+        tr = O.norm(ye - O.apply_A(wl.F, wl.L, two_m, xe)) / O.norm(ye)
+        assert tr <= 1e-10, (r, tr)
+    lam1 = GOLDEN["eigenvalues"][0]
+    for r in range(12):
+        bound = (r_m.true_residual[r] + r64.true_residual[r]) * np.linalg.norm(ys[r]) / lam1
+        assert np.linalg.norm(xs[r] - x64s[r]) <= bound * 1.01, r
