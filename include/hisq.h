@@ -78,7 +78,7 @@ const char *hisq_last_error(void);
 
 /* ABI revision of this header; bumped on any incompatible change. */
 int hisq_abi_version(void);
-#define HISQ_ABI_VERSION 2
+#define HISQ_ABI_VERSION 3
 
 /* ------------------------------------------------------------------ gauge */
 
@@ -260,6 +260,15 @@ hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_dev, hisq_pre
 
 /* --------------------------------------------------------- eigensolver */
 
+/*
+ * Progress report of hisq_eigensolve, called on the calling thread after each
+ * Lanczos step: restart = -1 during the pilot, else the restart count; step =
+ * the basis index just completed; matvecs = applications of A so far;
+ * seconds = wall time since the call began.  It must not call the library.
+ */
+typedef void (*hisq_eig_progress_fn)(void *user, int restart, int step, int matvecs,
+                                     double seconds);
+
 typedef struct hisq_eig_params {
     int n_kr;              /* Krylov basis size (0 = auto: max(2*n_ev, n_ev + 32)) */
     int cheb_degree;       /* Chebyshev filter degree (0 = auto) */
@@ -269,6 +278,8 @@ typedef struct hisq_eig_params {
     int max_restarts;      /* 0 = default 200 */
     int reserved0;
     uint64_t seed;         /* seed of the counter-based start vector */
+    hisq_eig_progress_fn progress; /* optional progress report (NULL: none) */
+    void *progress_user;   /* passed to progress */
     int reserved[8];       /* must be zero */
 } hisq_eig_params;
 

@@ -263,6 +263,12 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
     Solver S(g, two_m, s);
     HISQ_TRY(S.alloc(nkr, n_ev));
     const uint64_t seed = params->seed;
+    auto report = [&](int restart, int step) {
+        if (!params->progress) return;
+        const double sec =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        params->progress(params->progress_user, restart, step, (int)S.matvecs_, sec);
+    };
 
     // ---------------------------------------------------------------- pilot
     HISQ_TRY(vec_random(S.col(S.V_, 0), N, seed, s));
@@ -284,6 +290,7 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
                             j > 0 ? -be[j - 1] : 0.0, N, s));
         HISQ_TRY(S.orthogonalise(S.w_, j + 1));
         HISQ_TRY(S.next_vector(j, scale, seed + 1000 + j, &be[j]));
+        report(-1, j);
     }
     double lam_max = 0.0, cut = 0.0;
     std::vector<cd> Vstart_coef;
@@ -352,6 +359,7 @@ extern "C" hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
             HISQ_TRY(vec_axpby2(S.w_, 1.0, S.col(S.V_, j), -alpha[j], nullptr, 0.0, N, s));
             HISQ_TRY(S.orthogonalise(S.w_, j + 1));
             HISQ_TRY(S.next_vector(j, fscale, seed + 7777 + 131 * restarts + j, &beta[j]));
+            report(restarts, j);
         }
         HISQ_TRY(S.check_cols());
         // projected matrix: arrowhead (kept Ritz values + couplings) + tridiagonal

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED
 HISQ_FP64, HISQ_FP32, HISQ_BF16 = 0, 1, 2
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 # Entry points declared in include/hisq.h (the tests check the library exports them all).
 EXPORTS = (
@@ -70,11 +70,16 @@ class CgStats(ctypes.Structure):
                 ("true_residual", ctypes.c_double), ("b_norm", ctypes.c_double)]
 
 
+EIG_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_double)
+
+
 class EigParams(ctypes.Structure):
     _fields_ = [("n_kr", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("cheb_a", ctypes.c_double), ("cheb_b", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
                 ("reserved0", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("progress", EIG_PROGRESS), ("progress_user", ctypes.c_void_p),
                 ("reserved", ctypes.c_int * 8)]
 
 
@@ -368,18 +373,26 @@ def hisq_deflate(g, evecs, evals, two_m, b, x0, stream=None):
 
 
 def hisq_eigensolve(g, two_m, n_ev, evecs, n_kr=0, cheb_degree=0, cheb_a=0.0, cheb_b=0.0,
-                    tol=1e-10, max_restarts=0, seed=0, stream=None, raise_on_fail=True):
+                    tol=1e-10, max_restarts=0, seed=0, stream=None, raise_on_fail=True,
+                    progress=None):
+    """progress: optional callable(restart, step, matvecs, seconds), called after
+    every Lanczos step (restart -1 = pilot)."""
     if _nrhs(evecs, g.vh, "evecs") != n_ev:
         raise ValueError("evecs must hold n_ev vectors")
     p = EigParams(n_kr=int(n_kr), cheb_degree=int(cheb_degree), cheb_a=float(cheb_a),
                   cheb_b=float(cheb_b), tol=float(tol), max_restarts=int(max_restarts),
                   seed=int(seed))
+    cb = None
+    if progress is not None:
+        cb = EIG_PROGRESS(lambda _u, r, j, mv, sec: progress(r, j, mv, sec))
+        p.progress = cb
     evals = np.zeros(n_ev, dtype=np.float64)
     stats = EigStats()
     st = lib().hisq_eigensolve(_h(g), float(two_m), int(n_ev), ctypes.byref(p),
                                _ptr(evecs, "evecs"),
                                evals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                ctypes.byref(stats), _stream(stream))
+    del cb  # kept alive across the call above
     if raise_on_fail:
         _check(st, "hisq_eigensolve")
     return st, evals, stats

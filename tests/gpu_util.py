@@ -112,3 +112,20 @@ def abs_stencil(F, L, psi):
             bwd = np.roll(ap, h, axis=ax)                  # psi(x - h mu)
             out += np.einsum("...ba,...b->...a", Ub, bwd)
     return out
+
+
+def abs_stencil_site(F, L, psi, site_xyzt):
+    """(|D| |psi|)(x) at one site: the 16 hop terms with moduli, added."""
+    X, Y, Z, T = (int(F.shape[4]), int(F.shape[3]), int(F.shape[2]), int(F.shape[1]))
+    dims = (X, Y, Z, T)
+    c = list(site_xyzt)
+    out = np.zeros(3)
+    for mu in range(4):
+        for U, h in ((F, 1), (L, 3)):
+            cf, cb = list(c), list(c)
+            cf[mu] = (c[mu] + h) % dims[mu]
+            cb[mu] = (c[mu] - h) % dims[mu]
+            at = lambda q: (q[3], q[2], q[1], q[0])
+            out += np.abs(U[mu][at(c)]) @ np.abs(psi[at(cf)])
+            out += np.abs(U[mu][at(cb)]).T @ np.abs(psi[at(cb)])
+    return out
