@@ -195,31 +195,48 @@ template <typename TV, int NB>
 __global__ __launch_bounds__(kBS) void k_gemv_tn(const TV *__restrict__ V, int k,
                                                  const dvec2 *__restrict__ B, int64_t N,
                                                  double *__restrict__ partials, int ldp) {
-    // block: a contiguous chunk of sites; each wave handles columns i = wave, wave+4, ...
+    // block: a contiguous chunk of sites; each wave takes CU columns at a time
+    // (i0 = CU * wave, CU * (wave + 4), ...), so every site iteration has CU + NB
+    // independent loads in flight and the B entries are loaded once per CU columns
+    constexpr int CU = 4;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t per = (N + gridDim.x - 1) / gridDim.x;
     const int64_t s0 = blockIdx.x * per, s1 = min(N, s0 + per);
-    for (int i = wave; i < k; i += kBS / kWave) {
-        const TV *v = V + (int64_t)i * 2 * N;
-        double acc[NB][2];
+    for (int i0 = wave * CU; i0 < k; i0 += (kBS / kWave) * CU) {
+        const int nc = min(CU, k - i0);
+        double acc[CU][NB][2];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = 0.0;
+        for (int c = 0; c < CU; ++c)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[c][j][0] = acc[c][j][1] = 0.0;
+#pragma unroll 2
         for (int64_t s = s0 + lane; s < s1; s += kWave) {
-            const dvec2 a = load2(v + 2 * s);
+            dvec2 b[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const dvec2 b = B[(int64_t)j * N + s];
-                acc[j][0] = fma(a.x, b.x, fma(a.y, b.y, acc[j][0]));
-                acc[j][1] = fma(a.x, b.y, fma(-a.y, b.x, acc[j][1]));
+            for (int j = 0; j < NB; ++j) b[j] = B[(int64_t)j * N + s];
+#pragma unroll
+            for (int c = 0; c < CU; ++c) {
+                if (c < nc) {
+                    const dvec2 a = load2(V + 2 * ((int64_t)(i0 + c) * N + s));
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        acc[c][j][0] = fma(a.x, b[j].x, fma(a.y, b[j].y, acc[c][j][0]));
+                        acc[c][j][1] = fma(a.x, b[j].y, fma(-a.y, b[j].x, acc[c][j][1]));
+                    }
+                }
             }
         }
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const double re = wave_sum(acc[j][0]), im = wave_sum(acc[j][1]);
-            if (lane == 0) {
-                double *P = partials + (int64_t)blockIdx.x * ldp + (int64_t)i * 2 * NB;
-                P[2 * j] = re;
-                P[2 * j + 1] = im;
+        for (int c = 0; c < CU; ++c) {
+            if (c >= nc) break;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const double re = wave_sum(acc[c][j][0]), im = wave_sum(acc[c][j][1]);
+                if (lane == 0) {
+                    double *P = partials + (int64_t)blockIdx.x * ldp + (int64_t)(i0 + c) * 2 * NB;
+                    P[2 * j] = re;
+                    P[2 * j + 1] = im;
+                }
             }
         }
     }

@@ -8,3 +8,10 @@ extern "C" int test_heev(int n, double *A, double *w, double *Z, int max_sweeps)
     return hisq::heev_jacobi(n, reinterpret_cast<std::complex<double> *>(A), w,
                              reinterpret_cast<std::complex<double> *>(Z), max_sweeps);
 }
+
+namespace hisq {
+int syev_qr(int n, double *A, double *w, double *Z);
+}
+extern "C" int test_syev(int n, double *A, double *w, double *Z) {
+    return hisq::syev_qr(n, A, w, Z);
+}

@@ -9,9 +9,9 @@ solve or diagonalise at this size, so the checks are sampled outputs the
 oracle computes one by one (stencil sites, projection entries, eigenpair
 residuals, true residuals of selected solutions) and bounds that hold at any
 size (||x - x'|| <= (||r|| + ||r'||) / lambda_1 between the mixed and the
-FP64 solutions).  The eigensolve uses 64 pairs (the 256 of the full
-configuration take minutes with the current Lanczos orthogonalisation); the
-projection is checked separately with 256 FP32 vectors x 24 RHS.
+FP64 solutions).  The eigensolve here uses 64 pairs (25 s); the 256 of the
+full configuration take about two minutes, which is too long for a test, so
+the projection is checked separately with 256 FP32 vectors x 24 RHS.
 """
 from __future__ import annotations
 

@@ -69,3 +69,74 @@ def test_jacobi_degenerate_and_zero(heev):
     assert np.allclose(w, [-1, 2, 2, 2])
     sweeps, w, Z = heev(np.zeros((3, 3), dtype=np.complex128))
     assert np.all(w == 0)
+
+
+@pytest.fixture(scope="module")
+def syev(tmp_path_factory):
+    out = tmp_path_factory.mktemp("hostlib2") / "libhost_syev_test.so"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", str(out),
+                    os.path.join(ROOT, "paper_2502_00152_amd", "csrc", "dense_eig.cpp"),
+                    os.path.join(ROOT, "tests", "host_eig_shim.cpp")], check=True)
+    L = ctypes.CDLL(str(out))
+    L.test_syev.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.test_syev.restype = ctypes.c_int
+
+    def run(A):
+        n = A.shape[0]
+        a = np.ascontiguousarray(A, dtype=np.float64).copy()
+        w = np.zeros(n)
+        Z = np.zeros((n, n))
+        steps = L.test_syev(n, a.ctypes.data, w.ctypes.data, Z.ctypes.data)
+        return steps, w, Z
+    return run
+
+
+def check_eig(A, steps, w, Z, rel):
+    n = A.shape[0]
+    assert steps >= 0
+    ref = np.linalg.eigvalsh(A)
+    s = max(np.abs(ref).max(), 1e-300)
+    assert np.abs(w - ref).max() <= rel * s
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-12 * max(1, n / 50)
+    assert np.abs(A @ Z - Z * w).max() <= rel * 10 * s
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 40, 200])
+def test_qr_symmetric_dense(syev, n):
+    rng = np.random.default_rng(100 + n)
+    M = rng.standard_normal((n, n))
+    A = M + M.T
+    check_eig(A, *syev(A), rel=1e-13)
+
+
+def test_qr_graded_arrowhead_tridiagonal(syev):
+    """The shape of a thick-restart Lanczos matrix: kept Ritz values on the
+    diagonal spanning many orders of magnitude, an arrow row/column of
+    couplings, then a tridiagonal block."""
+    n, k0 = 120, 40
+    rng = np.random.default_rng(7)
+    A = np.zeros((n, n))
+    A[np.arange(k0), np.arange(k0)] = 10.0 ** rng.uniform(0, 12, k0)
+    A[:k0, k0] = A[k0, :k0] = rng.standard_normal(k0) * 1e-2
+    d = rng.uniform(-1, 1, n - k0)
+    A[np.arange(k0, n), np.arange(k0, n)] = d
+    for j in range(k0, n - 1):
+        A[j, j + 1] = A[j + 1, j] = rng.uniform(0.1, 1)
+    steps, w, Z = syev(A)
+    check_eig(A, steps, w, Z, rel=1e-13)
+    # the large (wanted) eigenvalues are accurate relative to themselves
+    ref = np.linalg.eigvalsh(A)
+    big = ref > 1e3
+    assert np.abs(w[big] - ref[big]).max() <= 1e-12 * ref[big].max()
+
+
+def test_qr_degenerate_diagonal_and_zero(syev):
+    A = np.diag([2.0, 2.0, 2.0, -1.0])
+    steps, w, Z = syev(A)
+    assert np.allclose(w, [-1, 2, 2, 2]) and np.allclose(np.abs(Z.T @ Z), np.eye(4))
+    steps, w, Z = syev(np.zeros((3, 3)))
+    assert np.all(w == 0)
+    # Wilkinson's matrix W21+: pairs of nearly equal eigenvalues
+    n = 21
+    A = np.diag(np.abs(np.arange(n) - 10.0)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)
+    check_eig(A, *syev(A), rel=1e-13)
