@@ -78,7 +78,7 @@ const char *hisq_last_error(void);
 
 /* ABI revision of this header; bumped on any incompatible change. */
 int hisq_abi_version(void);
-#define HISQ_ABI_VERSION 3
+#define HISQ_ABI_VERSION 4
 
 /* ------------------------------------------------------------------ gauge */
 
@@ -195,7 +195,11 @@ typedef struct hisq_cg_params {
     double tol_restart;    /* re-deflate at a reliable update when the true residual has
                               fallen by this factor since the last deflation
                               (the paper's delta_tr, e.g. 1e-3; 0 = never) */
-    int reserved[8];       /* must be zero */
+    int parity;            /* 0: the even system A = (2m)^2 - D_eo D_oe (default);
+                              1: the odd one, (2m)^2 - D_oe D_eo = (M^H M)_oo, used
+                              to polish the reconstructed odd solution (section 2);
+                              re-deflation needs parity 0 */
+    int reserved[7];       /* must be zero */
 } hisq_cg_params;
 
 typedef struct hisq_cg_stats {
@@ -212,7 +216,8 @@ typedef struct hisq_cg_stats {
 /*
  * Solve A x = b on even sites, A = (2m)^2 - D_eo D_oe, for nrhs right-hand
  * sides at once (section 2: the even-odd preconditioned CG, the paper's
- * baseline; Eq. (1)).  x_e_dev holds the initial guess on entry (zeros, or a
+ * baseline; Eq. (1)); with params->parity = 1 the odd system
+ * ((2m)^2 - D_oe D_eo) x_o = b_o instead (vectors of odd parity).  x_e_dev holds the initial guess on entry (zeros, or a
  * deflation guess from hisq_deflate) and the solution on return.  Each
  * right-hand side follows its own CG recurrence with FP64 global reductions
  * in a fixed order, so results are bitwise reproducible run to run.  A
@@ -257,6 +262,44 @@ hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e_dev, void 
 hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_dev, hisq_prec evec_prec,
                          const double *evals_host, double two_m, const void *b_e_dev,
                          void *x0_e_dev, int nrhs, void *stream);
+
+/* ------------------------------------------------------ full propagator */
+
+typedef struct hisq_prop_params {
+    hisq_cg_params cg;     /* the even solve; with cg.n_ev > 0 the eigenvectors also
+                              give the initial guess (Eq. (4)) */
+    double polish_tol;     /* > 0: polish the reconstructed odd solution by CG on
+                              (M^H M)_oo psi_o = (M^H eta)_o to this tolerance,
+                              from psi_o (section 2's workflow); 0: no polish */
+    int polish_max_iter;   /* 0 = cg.max_iter */
+    int reserved[7];       /* must be zero */
+} hisq_prop_params;
+
+typedef struct hisq_prop_stats {
+    hisq_cg_stats even;    /* the even CG */
+    hisq_cg_stats polish;  /* the odd polish CG (zero if none) */
+    double residual;       /* ||eta - M psi|| / ||eta|| over the full lattice, FP64 */
+    double residual_even;  /* the even rows' part of it (the odd rows vanish before
+                              the polish) */
+    double reserved[2];
+} hisq_prop_stats;
+
+/*
+ * Full propagator solve of M psi = eta, M = D + 2m, for nrhs full-lattice
+ * sources (e.g. 3 colours x 2 propagators, the paper's workflow in section
+ * 2): split eta, y_e = (M^H eta)_e, optional deflation guess, CG on the even
+ * system (FP64 or mixed precision, with re-deflation, per params->cg),
+ * psi_o = (eta_o - D_oe psi_e) / (2m), optional odd polish, merge, and the
+ * final FP64 residual.
+ *   eta_dev, psi_dev  [nrhs][T][Z][Y][X][3] complex double, device; must not
+ *                     overlap.
+ *   stats_host        nrhs structs (may be NULL).
+ * Returns the status of the first failing stage (NOT_CONVERGED etc., with psi
+ * holding the last iterate), INVALID_ARG for bad arguments.  Synchronises.
+ */
+hisq_status hisq_propagator_solve(hisq_gauge g, double two_m, const void *eta_dev, void *psi_dev,
+                                  int nrhs, const hisq_prop_params *params,
+                                  hisq_prop_stats *stats_host, void *stream);
 
 /* --------------------------------------------------------- eigensolver */
 

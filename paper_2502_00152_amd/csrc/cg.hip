@@ -108,8 +108,12 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
         return fail(HISQ_ERR_INVALID_ARG, "tol must be finite and > 0");
     if (params->max_iter < 0) return fail(HISQ_ERR_INVALID_ARG, "max_iter must be >= 0");
     if (params->check_interval < 0) return fail(HISQ_ERR_INVALID_ARG, "check_interval < 0");
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 7; ++k)
         if (params->reserved[k]) return fail(HISQ_ERR_INVALID_ARG, "reserved fields must be 0");
+    if (params->parity != 0 && params->parity != 1)
+        return fail(HISQ_ERR_INVALID_ARG, "parity must be 0 (even) or 1 (odd)");
+    if (params->parity == 1 && (params->n_ev != 0 || params->tol_restart != 0.0))
+        return fail(HISQ_ERR_INVALID_ARG, "re-deflation uses even eigenvectors: parity must be 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double2 *b = static_cast<const double2 *>(b_e_dev);
     double2 *x = static_cast<double2 *>(x_e_dev);
@@ -123,6 +127,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
 
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = params->check_interval > 0 ? params->check_interval : 16;
+    const int par = params->parity;
 
     CgBuffers B{};
     HISQ_TRY(alloc_cg(g, nrhs, B));
@@ -147,7 +152,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     };
 
     // r = b - A x0, p = r, rho = <r, r>, ||b||
-    HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s));
+    HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par));
     HISQ_TRY(cg_init(n, nrhs, b, B.Ap, B.r, B.p, params->tol, B.dev, B.red, s));
     HISQ_TRY(fetch_state());
 
@@ -164,9 +169,9 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     const int nb_pap = dslash_reduce_blocks(g, nrhs);
 
     auto iterate = [&]() -> hisq_status {
-        HISQ_TRY(launch_dslash(g, 1, B.p, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE, nullptr,
-                               nullptr, s));
-        HISQ_TRY(launch_dslash(g, 0, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA,
+        HISQ_TRY(launch_dslash(g, 1 - par, B.p, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
+                               nullptr, nullptr, s));
+        HISQ_TRY(launch_dslash(g, par, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA,
                                nullptr, &B.pap, s));
         HISQ_TRY(cg_update_r(n, nrhs, B.r, B.Ap, B.pap.partials, nb_pap, B.dev, B.red, s));
         HISQ_TRY(cg_finalize(n, nrhs, B.pap.partials, nb_pap, B.dev, B.red, s));
@@ -181,7 +186,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     int64_t enqueued = 0;
     for (;;) {
         if (count(CG_PENDING) > 0) {
-            HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s));
+            HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par));
             HISQ_TRY(cg_true_residual(n, nrhs, b, B.Ap, B.r, B.dev, B.red, false, s));
             HISQ_TRY(cg_restart_p(n, nrhs, B.r, B.p, B.dev, B.red, s));
             HISQ_TRY(fetch_state());
@@ -208,7 +213,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     bool need_final = false;
     for (int i = 0; i < nrhs; ++i) need_final |= B.host_status[i] != CG_CONVERGED;
     if (need_final) {
-        HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s));
+        HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par));
         HISQ_TRY(cg_true_residual(n, nrhs, b, B.Ap, B.r, B.dev, B.red, true, s));
         HISQ_HIP(hipMemcpyAsync(B.host_tr2, B.dev.true_res2, sizeof(double) * nrhs,
                                 hipMemcpyDeviceToHost, s));

@@ -45,6 +45,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s) {
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = P->check_interval > 0 ? P->check_interval : 16;
+    const int par = P->parity;
     const int ru_interval = P->reliable_interval;  // 0: delta trigger only
     const double delta = P->reliable_delta > 0.0 ? P->reliable_delta : 0.1;
     if (!(delta < 1.0)) return fail(HISQ_ERR_INVALID_ARG, "reliable_delta must be < 1");
@@ -171,7 +172,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     // ------------------------------------------------------------- start
     // r = b - A x0 in FP64; rho = ||r||^2; statuses
-    HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s));
+    HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s, par));
     HISQ_TRY(cg_init(n, nrhs, b, Ax, r, p64, P->tol, dev, red, s));
     HISQ_HIP(hipMemcpyAsync(dev.rho_ru, dev.rho, dn, hipMemcpyDeviceToDevice, s));
     HISQ_TRY(mixed_to_f32(r, rs, n, nrhs, nullptr, s));
@@ -194,8 +195,10 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     const double m2 = two_m * two_m;
 
     auto iterate = [&]() -> hisq_status {
-        HISQ_TRY(launch_dslash_f32(g, 1, ps, t32, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, nullptr, s));
-        HISQ_TRY(launch_dslash_f32(g, 0, t32, Aps, nrhs, ps, m2, nullptr, 0.0, -1.0, pap.partials, s));
+        HISQ_TRY(launch_dslash_f32(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, nullptr,
+                                   s));
+        HISQ_TRY(launch_dslash_f32(g, par, t32, Aps, nrhs, ps, m2, nullptr, 0.0, -1.0, pap.partials,
+                                   s));
         HISQ_TRY(cg_update_r(n, nrhs, rs, Aps, pap.partials, nb_pap, dev, red, s));
         HISQ_TRY(cg_finalize(n, nrhs, pap.partials, nb_pap, dev, red, s));
         HISQ_TRY(cg_update_xp(n, nrhs, xs, rs, ps, dev, s));
@@ -204,7 +207,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     // r = b - A x for the masked RHS, rho_t on the host
     auto true_residual = [&](const int *mask_dev) -> hisq_status {
-        HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s));
+        HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s, par));
         HISQ_TRY(mixed_resid(b, Ax, r, n, nrhs, mask_dev, d_rho_t, red, s));
         HISQ_TRY(d2h(h_rho_t, d_rho_t, dn));
         return sync();

@@ -122,14 +122,14 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
 }
 
 hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,
-                        int nrhs, hipStream_t s) {
+                        int nrhs, hipStream_t s, int parity) {
     void *tmp = nullptr;
     HISQ_TRY(g->ws.get("mdagm_tmp", sizeof(double2) * 3 * (size_t)g->geom.vh * nrhs, &tmp));
     double2 *t = static_cast<double2 *>(tmp);
-    HISQ_TRY(launch_dslash(g, 1, in, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
+    HISQ_TRY(launch_dslash(g, 1 - parity, in, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
                            nullptr, nullptr, s));
-    HISQ_TRY(launch_dslash(g, 0, t, out, nrhs, in, two_m * two_m, nullptr, 0.0, -1.0, FIN_NONE,
-                           nullptr, nullptr, s));
+    HISQ_TRY(launch_dslash(g, parity, t, out, nrhs, in, two_m * two_m, nullptr, 0.0, -1.0,
+                           FIN_NONE, nullptr, nullptr, s));
     return HISQ_OK;
 }
 

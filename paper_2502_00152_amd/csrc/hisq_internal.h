@@ -242,7 +242,8 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s);
 
 // Operators built from dslash.
+// out = ((2m)^2 - D_{p,1-p} D_{1-p,p}) in on parity p (p = 0: the even operator A)
 hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,
-                        int nrhs, hipStream_t s);
+                        int nrhs, hipStream_t s, int parity = 0);
 
 }  // namespace hisq

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED
 HISQ_FP64, HISQ_FP32, HISQ_BF16 = 0, 1, 2
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 # Entry points declared in include/hisq.h (the tests check the library exports them all).
 EXPORTS = (
@@ -44,7 +44,7 @@ EXPORTS = (
     "hisq_gauge_half_volume", "hisq_spinor_split", "hisq_spinor_merge", "hisq_dslash_eo",
     "hisq_mdagm", "hisq_prepare_source", "hisq_reconstruct_odd", "hisq_cg_solve",
     "hisq_deflate", "hisq_eigensolve", "hisq_set_tuning", "hisq_profile_enable",
-    "hisq_profile_read", "hisq_convert_vectors",
+    "hisq_profile_read", "hisq_convert_vectors", "hisq_propagator_solve",
 )
 
 
@@ -60,7 +60,8 @@ class CgParams(ctypes.Structure):
                 ("reliable_interval", ctypes.c_int), ("reliable_delta", ctypes.c_double),
                 ("n_ev", ctypes.c_int), ("evec_prec", ctypes.c_int),
                 ("evecs_dev", ctypes.c_void_p), ("evals_host", ctypes.POINTER(ctypes.c_double)),
-                ("tol_restart", ctypes.c_double), ("reserved", ctypes.c_int * 8)]
+                ("tol_restart", ctypes.c_double), ("parity", ctypes.c_int),
+                ("reserved", ctypes.c_int * 7)]
 
 
 class CgStats(ctypes.Structure):
@@ -68,6 +69,16 @@ class CgStats(ctypes.Structure):
                 ("converged", ctypes.c_int), ("reliable_updates", ctypes.c_int),
                 ("redeflations", ctypes.c_int), ("reserved0", ctypes.c_int),
                 ("true_residual", ctypes.c_double), ("b_norm", ctypes.c_double)]
+
+
+class PropParams(ctypes.Structure):
+    _fields_ = [("cg", CgParams), ("polish_tol", ctypes.c_double),
+                ("polish_max_iter", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+
+
+class PropStats(ctypes.Structure):
+    _fields_ = [("even", CgStats), ("polish", CgStats), ("residual", ctypes.c_double),
+                ("residual_even", ctypes.c_double), ("reserved", ctypes.c_double * 2)]
 
 
 EIG_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -123,6 +134,8 @@ def lib():
                              ctypes.POINTER(EigStats), P], I),
         "hisq_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], I),
         "hisq_convert_vectors": ([P, I, P, I, ctypes.c_int64, P], I),
+        "hisq_propagator_solve": ([P, D, P, P, I, ctypes.POINTER(PropParams),
+                                   ctypes.POINTER(PropStats), P], I),
         "hisq_profile_enable": ([I], I),
         "hisq_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(D)], I),
@@ -313,7 +326,8 @@ class CgResult:
 
 def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
                   sloppy_prec=HISQ_FP64, stream=None, raise_on_fail=True, reliable_interval=0,
-                  reliable_delta=0.0, evecs=None, evals=None, tol_restart=0.0) -> CgResult:
+                  reliable_delta=0.0, evecs=None, evals=None, tol_restart=0.0,
+                  parity=0) -> CgResult:
     """CG on A x = b.  With sloppy_prec=HISQ_FP32: mixed precision with reliable
     updates; evecs/evals/tol_restart enable re-deflation (evecs complex128 or
     complex64 [n_ev, 3, Vh])."""
@@ -322,7 +336,8 @@ def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
         raise ValueError("b and x must have the same nrhs")
     p = CgParams(tol=float(tol), max_iter=int(max_iter), check_interval=int(check_interval),
                  sloppy_prec=int(sloppy_prec), reliable_interval=int(reliable_interval),
-                 reliable_delta=float(reliable_delta), tol_restart=float(tol_restart))
+                 reliable_delta=float(reliable_delta), tol_restart=float(tol_restart),
+                 parity=int(parity))
     ev = None
     if evecs is not None:
         n_ev = _nrhs(evecs, g.vh, "evecs")
@@ -345,6 +360,69 @@ def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
                     [bool(s.converged) for s in stats], [s.true_residual_checks for s in stats],
                     [s.b_norm for s in stats], [s.reliable_updates for s in stats],
                     [s.redeflations for s in stats])
+
+
+@dataclass
+class PropResult:
+    status: int
+    even: CgResult
+    polish: CgResult
+    residual: list
+    residual_even: list
+
+
+def _cg_params(tol, max_iter, check_interval, sloppy_prec, reliable_interval, reliable_delta,
+               evecs, evals, tol_restart, parity, vh):
+    p = CgParams(tol=float(tol), max_iter=int(max_iter), check_interval=int(check_interval),
+                 sloppy_prec=int(sloppy_prec), reliable_interval=int(reliable_interval),
+                 reliable_delta=float(reliable_delta), tol_restart=float(tol_restart),
+                 parity=int(parity))
+    ev = None
+    if evecs is not None:
+        n_ev = _nrhs(evecs, vh, "evecs")
+        ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+        if ev.shape != (n_ev,):
+            raise ValueError("evals must have one entry per eigenvector")
+        p.n_ev = n_ev
+        p.evec_prec = _prec_of(evecs, "evecs")
+        p.evecs_dev = _ptr(evecs, "evecs", ("complex128", "complex64")).value
+        p.evals_host = ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return p, ev
+
+
+def _cg_result(st, stats):
+    return CgResult(st, [s.iterations for s in stats], [s.true_residual for s in stats],
+                    [bool(s.converged) for s in stats], [s.true_residual_checks for s in stats],
+                    [s.b_norm for s in stats], [s.reliable_updates for s in stats],
+                    [s.redeflations for s in stats])
+
+
+def hisq_propagator_solve(g, two_m, eta, psi, tol=1e-10, max_iter=100000, sloppy_prec=HISQ_FP64,
+                          reliable_delta=0.0, evecs=None, evals=None, tol_restart=0.0,
+                          polish_tol=0.0, polish_max_iter=0, stream=None,
+                          raise_on_fail=True) -> PropResult:
+    """M psi = eta for full-lattice sources eta [nrhs, T, Z, Y, X, 3] (complex128):
+    even solve (FP64 or mixed, optional deflation and re-deflation), odd
+    reconstruction, optional odd polish to polish_tol."""
+    X, Y, Z, T = g.dims
+    nrhs = int(eta.shape[0])
+    for t, nm in ((eta, "eta"), (psi, "psi")):
+        if tuple(t.shape) != (nrhs, T, Z, Y, X, 3):
+            raise ValueError(f"{nm} must have shape [nrhs, T, Z, Y, X, 3]")
+    cg, ev = _cg_params(tol, max_iter, 0, sloppy_prec, 0, reliable_delta, evecs, evals,
+                        tol_restart, 0, g.vh)
+    p = PropParams(cg=cg, polish_tol=float(polish_tol), polish_max_iter=int(polish_max_iter))
+    stats = (PropStats * nrhs)()
+    st = lib().hisq_propagator_solve(_h(g), float(two_m), _ptr(eta, "eta"), _ptr(psi, "psi"), nrhs,
+                                     ctypes.byref(p), stats, _stream(stream))
+    del ev  # kept alive across the call above
+    if raise_on_fail:
+        _check(st, "hisq_propagator_solve")
+    elif st not in (HISQ_OK, HISQ_ERR_NOT_CONVERGED, HISQ_ERR_NAN, HISQ_ERR_BREAKDOWN):
+        _check(st, "hisq_propagator_solve")
+    return PropResult(st, _cg_result(st, [s.even for s in stats]),
+                      _cg_result(st, [s.polish for s in stats]),
+                      [s.residual for s in stats], [s.residual_even for s in stats])
 
 
 def hisq_convert_vectors(src, dst, stream=None):

@@ -62,6 +62,8 @@ STRUCTS = {
     "hisq_cg_stats": hisq.CgStats,
     "hisq_eig_params": hisq.EigParams,
     "hisq_eig_stats": hisq.EigStats,
+    "hisq_prop_params": hisq.PropParams,
+    "hisq_prop_stats": hisq.PropStats,
 }
 
 
