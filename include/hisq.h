@@ -78,7 +78,7 @@ const char *hisq_last_error(void);
 
 /* ABI revision of this header; bumped on any incompatible change. */
 int hisq_abi_version(void);
-#define HISQ_ABI_VERSION 4
+#define HISQ_ABI_VERSION 7
 
 /* ------------------------------------------------------------------ gauge */
 
@@ -195,6 +195,10 @@ typedef struct hisq_cg_params {
     double tol_restart;    /* re-deflate at a reliable update when the true residual has
                               fallen by this factor since the last deflation
                               (the paper's delta_tr, e.g. 1e-3; 0 = never) */
+    const double *two_m_rhs; /* optional host array of nrhs masses 2m, one per
+                              right-hand side (several masses in one batched
+                              solve, sharing every link load); replaces the
+                              two_m argument; not with re-deflation */
     int parity;            /* 0: the even system A = (2m)^2 - D_eo D_oe (default);
                               1: the odd one, (2m)^2 - D_oe D_eo = (M^H M)_oo, used
                               to polish the reconstructed odd solution (section 2);
@@ -262,6 +266,34 @@ hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e_dev, void 
 hisq_status hisq_deflate(hisq_gauge g, int n_ev, const void *evecs_dev, hisq_prec evec_prec,
                          const double *evals_host, double two_m, const void *b_e_dev,
                          void *x0_e_dev, int nrhs, void *stream);
+
+/* ------------------------------------------------- many systems at once */
+
+typedef struct hisq_system {
+    hisq_gauge g;          /* lattice and links of this system */
+    double two_m;          /* its mass */
+    const void *b_dev;     /* [nrhs][3][Vh] right-hand sides (parity of params) */
+    void *x_dev;           /* [nrhs][3][Vh] initial guess in, solution out */
+    int nrhs;
+    int reserved;          /* must be zero */
+} hisq_system;
+
+/*
+ * Solve n_systems independent systems (different lattices, masses and
+ * numbers of RHS; the paper's future-work batching of uneven solves, section
+ * 4) concurrently: systems on different gauge handles run at the same time,
+ * each on its handle's own stream driven by its own host thread; systems
+ * sharing a handle run one after another.  Each system follows exactly the
+ * iterates of hisq_cg_solve with params[i] (bitwise), so only the wall time
+ * changes.
+ *   params      n_systems parameter sets (one per system).
+ *   stats_host  sum of nrhs structs, the systems' in order (may be NULL).
+ * Returns the first failing system's status (its message names it).
+ * Synchronises.
+ */
+hisq_status hisq_cg_solve_multi(int n_systems, const hisq_system *systems,
+                                const hisq_cg_params *params, hisq_cg_stats *stats_host,
+                                void *stream);
 
 /* ------------------------------------------------------ full propagator */
 
@@ -369,11 +401,41 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            next to each other; 1: all sites of one group first
  *   "dslash_xcd_remap"       -1: automatic; 1: give each XCD a contiguous range
  *                            of sites; 0: off
+ *   "dslash_autotune_clear"  any value: forget the autotuner's choices
+ *   "cg_graphs"              -1 automatic (off), 0 off, 1: replay the CG's
+ *                            chunks of iterations from a captured HIP graph
+ *                            (measured: no gain on MI355X, kept as an option)
  * The <aux, out> partial sums of the CG are formed in one fixed order for any
  * shape, so CG iterates are bitwise independent of these knobs too.
  * Returns INVALID_ARG for an unknown key or value.
  */
 hisq_status hisq_set_tuning(const char *key, int64_t value);
+
+typedef struct hisq_tune_result {
+    int rhs_per_thread;    /* the chosen shape */
+    int lanes_per_site;
+    int group_order;
+    int xcd_remap;
+    double us_best;        /* average launch time of the chosen shape */
+    double us_default;     /* and of the shape in use before the call */
+    int shapes_timed;
+    int reserved[3];
+} hisq_tune_result;
+
+/*
+ * Autotuner of the half stencil: time every launch shape the kernel provides
+ * (RHS per lane x lanes per site x block order x XCD remap) for this handle's
+ * volume, nrhs right-hand sides and precision prec (HISQ_FP64 or HISQ_FP32),
+ * `reps` launches each (0 = 20) on scratch vectors, with HIP events on
+ * `stream`; remember the fastest for (volume, nrhs, prec) for the rest of the
+ * process (every later stencil, M^H M, CG and eigensolver launch of that size
+ * uses it, unless a "dslash_*" knob is set).  Results do not change, only
+ * speed.  Leaves the "dslash_*" knobs at automatic.  Not safe to run
+ * concurrently with other library calls.
+ * Synchronises; result_host may be NULL.
+ */
+hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec prec, int reps,
+                                 hisq_tune_result *result_host, void *stream);
 
 /* ------------------------------------------------------ instrumentation */
 

@@ -118,6 +118,7 @@ hisq_status hisq_gauge_destroy(hisq_gauge g) {
         if (g->lng32[p]) (void)hipFree(g->lng32[p]);
     }
     g->ws.release();
+    if (g->cg_stream) (void)hipStreamDestroy(g->cg_stream);
     delete g;
     return HISQ_OK;
 }

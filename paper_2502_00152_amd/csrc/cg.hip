@@ -38,6 +38,8 @@ struct CgBuffers {
     int *host_status;   // pinned
     int *host_iters;
     int *host_checks;
+    int *host_skip;     // pinned: 0 = compute A x for this RHS
+    int *dev_skip;
     double *host_tr2;
     double *host_b2;
 };
@@ -51,8 +53,8 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
     B.p = static_cast<double2 *>(p);
     HISQ_TRY(g->ws.get("cg_Ap", vec, &p));
     B.Ap = static_cast<double2 *>(p);
-    // scalars: 10 double arrays + 4 int arrays of nrhs
-    HISQ_TRY(g->ws.get("cg_scalars", (10 * sizeof(double) + 4 * sizeof(int)) * nrhs + 64, &p));
+    // scalars: 10 double arrays + 5 int arrays of nrhs
+    HISQ_TRY(g->ws.get("cg_scalars", (10 * sizeof(double) + 5 * sizeof(int)) * nrhs + 64, &p));
     double *d = static_cast<double *>(p);
     B.dev.rho = d;
     B.dev.rho_pend = d + nrhs;
@@ -71,6 +73,7 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
     B.dev.iters = iv + nrhs;
     B.dev.checks = iv + 2 * nrhs;
     B.dev.xp_mode = iv + 3 * nrhs;
+    B.dev_skip = iv + 4 * nrhs;
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const size_t nparts = std::max<size_t>((size_t)nrhs * dslash_reduce_blocks(g, nrhs),
                                            (size_t)2 * nrhs * blas_reduce_blocks(n));
@@ -99,11 +102,18 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
                                      hisq_cg_stats *stats_host, void *stream) {
     HISQ_TRY(check_gauge(g));
     HISQ_TRY(check_nrhs(nrhs));
-    HISQ_TRY(check_mass(two_m, true));
+    if (!params) return fail(HISQ_ERR_INVALID_ARG, "params is null");
+    if (params->two_m_rhs) {
+        for (int q = 0; q < nrhs; ++q) HISQ_TRY(check_mass(params->two_m_rhs[q], true));
+        if (params->n_ev != 0 || params->tol_restart != 0.0)
+            return fail(HISQ_ERR_INVALID_ARG, "per-RHS masses do not combine with re-deflation");
+        two_m = params->two_m_rhs[0];
+    } else {
+        HISQ_TRY(check_mass(two_m, true));
+    }
     HISQ_TRY(check_vec(b_e_dev, "b_e_dev"));
     HISQ_TRY(check_vec(x_e_dev, "x_e_dev"));
     if (b_e_dev == x_e_dev) return fail(HISQ_ERR_INVALID_ARG, "b and x must not overlap");
-    if (!params) return fail(HISQ_ERR_INVALID_ARG, "params is null");
     if (!(params->tol > 0.0) || !std::isfinite(params->tol))
         return fail(HISQ_ERR_INVALID_ARG, "tol must be finite and > 0");
     if (params->max_iter < 0) return fail(HISQ_ERR_INVALID_ARG, "max_iter must be >= 0");
@@ -114,10 +124,27 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
         return fail(HISQ_ERR_INVALID_ARG, "parity must be 0 (even) or 1 (odd)");
     if (params->parity == 1 && (params->n_ev != 0 || params->tol_restart != 0.0))
         return fail(HISQ_ERR_INVALID_ARG, "re-deflation uses even eigenvectors: parity must be 0");
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipStream_t caller = static_cast<hipStream_t>(stream);
+    hipStream_t s = nullptr;
+    HISQ_TRY(solver_stream(g, caller, &s));
+    struct Rejoin {  // order the caller's stream after everything enqueued here
+        hisq_gauge_s *g;
+        hipStream_t c;
+        ~Rejoin() { (void)solver_stream_done(g, c); }
+    } rejoin{g, caller};
     const double2 *b = static_cast<const double2 *>(b_e_dev);
     double2 *x = static_cast<double2 *>(x_e_dev);
-    if (params->sloppy_prec == HISQ_FP32) return solve_mixed(g, two_m, b, x, nrhs, params, stats_host, s);
+    const double *m2_rhs = nullptr;  // (2m)^2 per RHS on the device, if given
+    if (params->two_m_rhs) {
+        std::vector<double> m2(nrhs);
+        for (int q = 0; q < nrhs; ++q) m2[q] = params->two_m_rhs[q] * params->two_m_rhs[q];
+        void *pm = nullptr;
+        HISQ_TRY(g->ws.get("cg_m2", sizeof(double) * nrhs, &pm));
+        HISQ_HIP(hipMemcpyAsync(pm, m2.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+        HISQ_HIP(hipStreamSynchronize(s));  // m2 is a local array
+        m2_rhs = static_cast<const double *>(pm);
+    }
+    if (params->sloppy_prec == HISQ_FP32) return solve_mixed(g, two_m, b, x, nrhs, params, stats_host, s, m2_rhs);
     if (params->sloppy_prec == HISQ_BF16)
         return fail(HISQ_ERR_UNSUPPORTED, "BF16 sloppy precision is not implemented");
     if (params->sloppy_prec != HISQ_FP64) return fail(HISQ_ERR_INVALID_ARG, "unknown sloppy_prec");
@@ -135,7 +162,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
 
     // pinned host mirror of the per-RHS state
     PinnedHost pin;
-    const size_t host_bytes = (3 * sizeof(int) + 2 * sizeof(double)) * nrhs + 64;
+    const size_t host_bytes = (4 * sizeof(int) + 2 * sizeof(double)) * nrhs + 64;
     HISQ_HIP(hipHostMalloc(&pin.ptr, host_bytes, hipHostMallocDefault));
     double *hd = static_cast<double *>(pin.ptr);
     B.host_tr2 = hd;
@@ -143,6 +170,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     B.host_status = reinterpret_cast<int *>(hd + 2 * nrhs);
     B.host_iters = B.host_status + nrhs;
     B.host_checks = B.host_iters + nrhs;
+    B.host_skip = B.host_checks + nrhs;
 
     auto fetch_state = [&]() -> hisq_status {
         HISQ_HIP(hipMemcpyAsync(B.host_status, B.dev.status, 3 * sizeof(int) * nrhs,
@@ -152,7 +180,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     };
 
     // r = b - A x0, p = r, rho = <r, r>, ||b||
-    HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par));
+    HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par, m2_rhs));
     HISQ_TRY(cg_init(n, nrhs, b, B.Ap, B.r, B.p, params->tol, B.dev, B.red, s));
     HISQ_TRY(fetch_state());
 
@@ -170,9 +198,9 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
 
     auto iterate = [&]() -> hisq_status {
         HISQ_TRY(launch_dslash(g, 1 - par, B.p, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
-                               nullptr, nullptr, s));
+                               &B.dev, nullptr, s));
         HISQ_TRY(launch_dslash(g, par, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA,
-                               nullptr, &B.pap, s));
+                               &B.dev, &B.pap, s, m2_rhs));
         HISQ_TRY(cg_update_r(n, nrhs, B.r, B.Ap, B.pap.partials, nb_pap, B.dev, B.red, s));
         HISQ_TRY(cg_finalize(n, nrhs, B.pap.partials, nb_pap, B.dev, B.red, s));
         HISQ_TRY(cg_update_xp(n, nrhs, x, B.r, B.p, B.dev, s));
@@ -184,9 +212,15 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     // guards against a device state that never changes.
     const int64_t cap = 4 * (int64_t)params->max_iter + 4 * (int64_t)interval + 16;
     int64_t enqueued = 0;
+    const bool graphs = cg_use_graphs(g, nrhs);
+    GraphChunk chunk;
     for (;;) {
         if (count(CG_PENDING) > 0) {
-            HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par));
+            // A x for the groups holding a pending RHS only
+            for (int i = 0; i < nrhs; ++i) B.host_skip[i] = B.host_status[i] == CG_PENDING ? 0 : 1;
+            HISQ_HIP(hipMemcpyAsync(B.dev_skip, B.host_skip, sizeof(int) * nrhs,
+                                    hipMemcpyHostToDevice, s));
+            HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par, m2_rhs, B.dev_skip));
             HISQ_TRY(cg_true_residual(n, nrhs, b, B.Ap, B.r, B.dev, B.red, false, s));
             HISQ_TRY(cg_restart_p(n, nrhs, B.r, B.p, B.dev, B.red, s));
             HISQ_TRY(fetch_state());
@@ -194,7 +228,14 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
         }
         if (count(CG_ACTIVE) + count(CG_RESTART) == 0) break;
         if (params->max_iter == 0 || enqueued >= cap) break;
-        for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+        if (graphs) {
+            HISQ_TRY(chunk.run(s, [&]() -> hisq_status {
+                for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+                return HISQ_OK;
+            }));
+        } else {
+            for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+        }
         enqueued += interval;
         HISQ_TRY(fetch_state());
     }
@@ -213,7 +254,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     bool need_final = false;
     for (int i = 0; i < nrhs; ++i) need_final |= B.host_status[i] != CG_CONVERGED;
     if (need_final) {
-        HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par));
+        HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par, m2_rhs));
         HISQ_TRY(cg_true_residual(n, nrhs, b, B.Ap, B.r, B.dev, B.red, true, s));
         HISQ_HIP(hipMemcpyAsync(B.host_tr2, B.dev.true_res2, sizeof(double) * nrhs,
                                 hipMemcpyDeviceToHost, s));

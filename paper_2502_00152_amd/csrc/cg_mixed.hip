@@ -42,7 +42,8 @@ T *carve(char *&p, size_t count) {
 }  // namespace
 
 hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
-                        const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s) {
+                        const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s,
+                        const double *m2_rhs) {
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = P->check_interval > 0 ? P->check_interval : 16;
     const int par = P->parity;
@@ -72,6 +73,9 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
         }
     }
 
+    // the FP32 links are made here, not inside a captured iteration chunk
+    HISQ_TRY(ensure_links_f32(g, s));
+
     // ------------------------------------------------------------ buffers
     const size_t v64 = sizeof(double2) * (size_t)n * nrhs, v32 = sizeof(float2) * (size_t)n * nrhs;
     void *p = nullptr;
@@ -92,7 +96,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     HISQ_TRY(g->ws.get("mx_t", v32, &p));
     float2 *t32 = static_cast<float2 *>(p);
     // device scalars: CgDev arrays + masks
-    const size_t nd = 12, ni = 7;
+    const size_t nd = 12, ni = 8;
     HISQ_TRY(g->ws.get("mx_scalars", (nd * sizeof(double) + ni * sizeof(int)) * nrhs + 64 * (nd + ni), &p));
     char *cp = static_cast<char *>(p);
     CgDev dev{};
@@ -114,6 +118,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     dev.xp_mode = carve<int>(cp, nrhs);
     dev.ru_flag = carve<int>(cp, nrhs);
     int *d_mask = carve<int>(cp, nrhs);
+    int *d_skip = carve<int>(cp, nrhs);
     int *d_mode = carve<int>(cp, nrhs);
     dev.delta2 = delta * delta;
     dev.max_iter = P->max_iter;
@@ -144,7 +149,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     // host mirror (pinned): doubles rho, rho_ru, rho_t, bnorm2, true_res2, rbeta; ints
     // status, iters, defl, mask, mode, ru_flag
     Pinned pin;
-    HISQ_HIP(hipHostMalloc(&pin.ptr, (6 * sizeof(double) + 6 * sizeof(int)) * nrhs + 64 * 12,
+    HISQ_HIP(hipHostMalloc(&pin.ptr, (6 * sizeof(double) + 7 * sizeof(int)) * nrhs + 64 * 13,
                            hipHostMallocDefault));
     char *hp = static_cast<char *>(pin.ptr);
     double *h_rho = carve<double>(hp, nrhs), *h_rho_ru = carve<double>(hp, nrhs);
@@ -153,6 +158,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     int *h_status = carve<int>(hp, nrhs), *h_iters = carve<int>(hp, nrhs);
     int *h_defl = carve<int>(hp, nrhs), *h_mask = carve<int>(hp, nrhs);
     int *h_mode = carve<int>(hp, nrhs), *h_flag = carve<int>(hp, nrhs);
+    int *h_skip = carve<int>(hp, nrhs);
     std::vector<int> ru_count(nrhs, 0), defl_count(nrhs, 0), iters_at_ru(nrhs, 0);
     std::vector<double> rho_defl(nrhs, 0.0);
 
@@ -172,7 +178,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     // ------------------------------------------------------------- start
     // r = b - A x0 in FP64; rho = ||r||^2; statuses
-    HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s, par));
+    HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s, par, m2_rhs));
     HISQ_TRY(cg_init(n, nrhs, b, Ax, r, p64, P->tol, dev, red, s));
     HISQ_HIP(hipMemcpyAsync(dev.rho_ru, dev.rho, dn, hipMemcpyDeviceToDevice, s));
     HISQ_TRY(mixed_to_f32(r, rs, n, nrhs, nullptr, s));
@@ -196,9 +202,9 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     auto iterate = [&]() -> hisq_status {
         HISQ_TRY(launch_dslash_f32(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, nullptr,
-                                   s));
+                                   s, nullptr, dev.status));
         HISQ_TRY(launch_dslash_f32(g, par, t32, Aps, nrhs, ps, m2, nullptr, 0.0, -1.0, pap.partials,
-                                   s));
+                                   s, m2_rhs, dev.status));
         HISQ_TRY(cg_update_r(n, nrhs, rs, Aps, pap.partials, nb_pap, dev, red, s));
         HISQ_TRY(cg_finalize(n, nrhs, pap.partials, nb_pap, dev, red, s));
         HISQ_TRY(cg_update_xp(n, nrhs, xs, rs, ps, dev, s));
@@ -206,8 +212,16 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     };
 
     // r = b - A x for the masked RHS, rho_t on the host
-    auto true_residual = [&](const int *mask_dev) -> hisq_status {
-        HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s, par));
+    // r = b - A x for the RHS with host_mask[q] != 0 (all if null); A x is
+    // computed for those RHS groups only
+    auto true_residual = [&](const int *mask_dev, const int *host_mask) -> hisq_status {
+        const int *skip = nullptr;
+        if (host_mask) {
+            for (int q = 0; q < nrhs; ++q) h_skip[q] = host_mask[q] ? 0 : 1;
+            HISQ_TRY(h2d(d_skip, h_skip, in_));
+            skip = d_skip;
+        }
+        HISQ_TRY(apply_mdagm(g, two_m, x, Ax, nrhs, s, par, m2_rhs, skip));
         HISQ_TRY(mixed_resid(b, Ax, r, n, nrhs, mask_dev, d_rho_t, red, s));
         HISQ_TRY(d2h(h_rho_t, d_rho_t, dn));
         return sync();
@@ -215,6 +229,8 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     const int64_t cap = 4 * (int64_t)P->max_iter + 4 * (int64_t)interval + 16;
     int64_t enqueued = 0;
+    const bool graphs = cg_use_graphs(g, nrhs);
+    GraphChunk chunk;
     for (;;) {
         HISQ_TRY(d2h(h_status, dev.status, in_));
         HISQ_TRY(d2h(h_iters, dev.iters, in_));
@@ -234,14 +250,21 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
         }
         if (nru == 0) {
             if (nactive == 0 || P->max_iter == 0 || enqueued >= cap) break;
-            for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+            if (graphs) {
+                HISQ_TRY(chunk.run(s, [&]() -> hisq_status {
+                    for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+                    return HISQ_OK;
+                }));
+            } else {
+                for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+            }
             enqueued += interval;
             continue;
         }
         // ------------------------------------------------ reliable update
         HISQ_TRY(h2d(d_mask, h_mask, in_));
         HISQ_TRY(mixed_accum_x(x, xs, n, nrhs, d_mask, s));
-        HISQ_TRY(true_residual(d_mask));
+        HISQ_TRY(true_residual(d_mask, h_mask));
         int ndefl = 0;
         for (int q = 0; q < nrhs; ++q) {
             h_defl[q] = 0;
@@ -290,7 +313,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
                 HISQ_TRY(mixed_mask_rows(d_C, P->n_ev, nrhs, d_mask, s));
                 HISQ_TRY(gemm_nn(V, P->n_ev, d_C, nrhs, n, 1.0, x, s));
             }
-            HISQ_TRY(true_residual(d_mask));
+            HISQ_TRY(true_residual(d_mask, h_defl));
             HISQ_TRY(mixed_to_f32(r, rs, n, nrhs, d_mask, s));
             for (int q = 0; q < nrhs; ++q) {
                 if (!h_defl[q]) continue;
@@ -333,7 +356,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
         need_final |= h_status[q] != CG_CONVERGED;
     }
     if (need_final) {
-        HISQ_TRY(true_residual(nullptr));
+        HISQ_TRY(true_residual(nullptr, nullptr));
         for (int q = 0; q < nrhs; ++q)
             if (h_status[q] != CG_CONVERGED) h_tr2[q] = h_rho_t[q];
     }

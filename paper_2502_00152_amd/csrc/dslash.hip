@@ -13,6 +13,20 @@ struct DslashTuning {
 };
 DslashTuning g_tune;
 
+// Shapes chosen by the autotuner, keyed by (Vh, nrhs, bytes per real).
+struct TunedKey {
+    int vh, nrhs, rb;
+    bool operator<(const TunedKey &o) const {
+        return vh != o.vh ? vh < o.vh : nrhs != o.nrhs ? nrhs < o.nrhs : rb < o.rb;
+    }
+};
+std::map<TunedKey, DslashShape> g_tuned;
+
+void dslash_tuned_set(int vh, int nrhs, size_t real_bytes, const DslashShape &sh) {
+    g_tuned[TunedKey{vh, nrhs, (int)real_bytes}] = sh;
+}
+void dslash_tuned_clear() { g_tuned.clear(); }
+
 namespace {
 bool supported_shape(int nr, int lps) {
     if (lps == 1) return nr == 1 || nr == 2 || nr == 3 || nr == 4 || nr == 6 || nr == 12;
@@ -54,12 +68,20 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes) {
         if (small) sh.nr = 1, sh.lps = 4;
         else sh.nr = 12, sh.lps = 1;
     }
+    int order = 0;
+    // the autotuner's choice for this volume and batch, if any
+    const auto it = g_tuned.find(TunedKey{vh, nrhs, (int)real_bytes});
+    if (it != g_tuned.end()) {
+        sh.nr = it->second.nr, sh.lps = it->second.lps;
+        xcd = it->second.xcd_remap, order = it->second.group_outer;
+    }
+    // explicit knobs override both
     if (g_tune.rhs_per_thread > 0 || g_tune.lanes_per_site > 0) {
         sh.lps = g_tune.lanes_per_site > 0 ? (int)g_tune.lanes_per_site : 1;
         sh.nr = g_tune.rhs_per_thread > 0 ? (int)g_tune.rhs_per_thread : nr_for(nrhs, sh.lps);
     }
     sh.xcd_remap = g_tune.xcd_remap >= 0 ? (int)g_tune.xcd_remap : xcd;
-    sh.group_outer = g_tune.group_order >= 0 ? (int)g_tune.group_order : 0;
+    sh.group_outer = g_tune.group_order >= 0 ? (int)g_tune.group_order : order;
     // the per-lane 32-bit offsets must cover the group: shrink it if not
     while (!dslash_impl::shape_fits(sh.nr, sh.lps, vh, real_bytes) && (sh.lps > 1 || sh.nr > 1)) {
         if (sh.lps > 1) sh.lps /= 2;
@@ -89,6 +111,8 @@ hisq_status dslash_set_tuning(const std::string &key, int64_t v) {
         if (v != -1 && v != 0 && v != 1)
             return fail(HISQ_ERR_INVALID_ARG, "dslash_group_order must be -1, 0 or 1");
         g_tune.group_order = v;
+    } else if (key == "dslash_autotune_clear") {
+        dslash_tuned_clear();
     } else if (key == "dslash_xcd_remap") {
         if (v != -1 && v != 0 && v != 1)
             return fail(HISQ_ERR_INVALID_ARG, "dslash_xcd_remap must be -1, 0 or 1");
@@ -107,8 +131,8 @@ int dslash_reduce_blocks(const hisq_gauge_s *g, int nrhs) {
 hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
                           double2 *out, int nrhs, const double2 *aux, double ca,
                           const double2 *aux2, double cb, double cd, DslashFinal fin,
-                          const CgDev *cg, const Reduce *red, hipStream_t s) {
-    (void)cg;
+                          const CgDev *cg, const Reduce *red, hipStream_t s,
+                          const double *ca_rhs) {
     using V = vec2<double>;
     const V *fat[2] = {reinterpret_cast<const V *>(g->fat[0]), reinterpret_cast<const V *>(g->fat[1])};
     const V *lng[2] = {reinterpret_cast<const V *>(g->lng[0]), reinterpret_cast<const V *>(g->lng[1])};
@@ -118,18 +142,24 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
     return dslash_impl::launch_dslash_t<double>(
         g->geom, fat, lng, out_parity, reinterpret_cast<const V *>(in), reinterpret_cast<V *>(out),
         nrhs, reinterpret_cast<const V *>(aux), ca, reinterpret_cast<const V *>(aux2), cb, cd,
-        fin == FIN_CG_ALPHA ? red->partials : nullptr, sh, s);
+        fin == FIN_CG_ALPHA ? red->partials : nullptr, sh, s, ca_rhs, cg ? cg->status : nullptr);
 }
 
 hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,
-                        int nrhs, hipStream_t s, int parity) {
+                        int nrhs, hipStream_t s, int parity, const double *m2_rhs,
+                        const int *skip) {
     void *tmp = nullptr;
     HISQ_TRY(g->ws.get("mdagm_tmp", sizeof(double2) * 3 * (size_t)g->geom.vh * nrhs, &tmp));
     double2 *t = static_cast<double2 *>(tmp);
+    // the stencil skips groups whose status entries are all non-active; skip
+    // uses the same convention (0 = compute)
+    CgDev sel{};
+    sel.status = const_cast<int *>(skip);
+    const CgDev *cg = skip ? &sel : nullptr;
     HISQ_TRY(launch_dslash(g, 1 - parity, in, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
-                           nullptr, nullptr, s));
+                           cg, nullptr, s));
     HISQ_TRY(launch_dslash(g, parity, t, out, nrhs, in, two_m * two_m, nullptr, 0.0, -1.0,
-                           FIN_NONE, nullptr, nullptr, s));
+                           FIN_NONE, cg, nullptr, s, m2_rhs));
     return HISQ_OK;
 }
 

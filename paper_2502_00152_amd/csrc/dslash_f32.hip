@@ -43,7 +43,8 @@ hisq_status ensure_links_f32(hisq_gauge_s *g, hipStream_t s) {
 
 hisq_status launch_dslash_f32(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
                               int nrhs, const float2 *aux, double ca, const float2 *aux2, double cb,
-                              double cd, double *partials, hipStream_t s) {
+                              double cd, double *partials, hipStream_t s, const double *ca_rhs,
+                              const int *rhs_status) {
     HISQ_TRY(ensure_links_f32(g, s));
     using V = vec2<float>;
     const V *fat[2] = {reinterpret_cast<const V *>(g->fat32[0]),
@@ -56,7 +57,7 @@ hisq_status launch_dslash_f32(hisq_gauge_s *g, int out_parity, const float2 *in,
     return dslash_impl::launch_dslash_t<float>(
         g->geom, fat, lng, out_parity, reinterpret_cast<const V *>(in), reinterpret_cast<V *>(out),
         nrhs, reinterpret_cast<const V *>(aux), ca, reinterpret_cast<const V *>(aux2), cb, cd,
-        partials, sh, s);
+        partials, sh, s, ca_rhs, rhs_status);
 }
 
 hisq_status apply_mdagm_f32(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,

@@ -63,6 +63,9 @@ struct DslashArgs {
     const vec2<R> *aux;      // [nrhs][3][Vh], parity p (optional)
     const vec2<R> *aux2;     // [nrhs][3][Vh], parity p (optional; may alias out)
     R ca, cb, cd;
+    const double *ca_rhs;  // per-RHS ca (device, indexed by RHS), or null for ca
+    const int *rhs_status; // CG state per RHS (device) or null: a block whose RHS
+                           // are all inactive (converged, frozen) does nothing
     Geom geom;
     int out_parity;
     int xcd_remap;         // 1: contiguous site ranges per XCD
@@ -247,6 +250,17 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) dotv[r] = 0.0;
 
+    if (a.rhs_status) {
+        // skip a group whose right-hand sides no longer iterate (block-uniform)
+        bool any = false;
+        for (int j = rg0; j < min(rg0 + RG, a.nrhs); ++j) any = any || a.rhs_status[j] == CG_ACTIVE;
+        if (!any) {
+            if (DOT && threadIdx.x < RG && rg0 + (int)threadIdx.x < a.nrhs)
+                a.partials[(int64_t)(rg0 + threadIdx.x) * a.nsb + sb] = 0.0;
+            return;
+        }
+    }
+
     if (cb < vh && nr > 0) {
         // coordinates of the output site
         int t = cb / g.Xh;
@@ -323,8 +337,9 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
                     V o = acc[r][c] * a.cd;
                     if (AUX) {
                         const V ax = *at(a.aux + plane, off);
-                        o.x = fma(a.ca, ax.x, o.x);
-                        o.y = fma(a.ca, ax.y, o.y);
+                        const R ca = a.ca_rhs ? (R)a.ca_rhs[rg0 + q * NR + r] : a.ca;
+                        o.x = fma(ca, ax.x, o.x);
+                        o.y = fma(ca, ax.y, o.y);
                         if (AUX2) {
                             const V a2 = *at(a.aux2 + plane, off);
                             o.x = fma(a.cb, a2.x, o.x);
@@ -394,7 +409,8 @@ hisq_status launch_dslash_t(const Geom &geom, const vec2<R> *const fat[2],
                             const vec2<R> *const lng[2], int out_parity, const vec2<R> *in,
                             vec2<R> *out, int nrhs, const vec2<R> *aux, double ca,
                             const vec2<R> *aux2, double cb, double cd, double *partials,
-                            DslashShape sh, hipStream_t s) {
+                            DslashShape sh, hipStream_t s, const double *ca_rhs = nullptr,
+                            const int *rhs_status = nullptr) {
     if (aux2 && !aux) return fail(HISQ_ERR_INVALID_ARG, "dslash: aux2 needs aux");
     if (!shape_fits(sh.nr, sh.lps, geom.vh, sizeof(R)))
         return fail(HISQ_ERR_INVALID_ARG, "dslash: RHS group too large for this volume");
@@ -411,6 +427,8 @@ hisq_status launch_dslash_t(const Geom &geom, const vec2<R> *const fat[2],
     a.ca = (R)ca;
     a.cb = (R)cb;
     a.cd = (R)cd;
+    a.ca_rhs = ca_rhs;
+    a.rhs_status = rhs_status;
     a.geom = geom;
     a.out_parity = p;
     a.xcd_remap = sh.xcd_remap;

@@ -86,6 +86,7 @@ struct hisq_gauge_s {
     double2 *lng[2] = {nullptr, nullptr};
     float2 *fat32[2] = {nullptr, nullptr};  // FP32 copies, made on first sloppy use
     float2 *lng32[2] = {nullptr, nullptr};
+    hipStream_t cg_stream = nullptr;        // the solvers' own stream (capturable)
     hisq::Workspace ws;
 };
 
@@ -150,12 +151,15 @@ enum DslashFinal : int {
 
 // out = ca * aux + cb * aux2 + cd * D_{p,1-p} in.  aux/aux2 may be null (their
 // coefficient is then ignored; aux2 needs aux); aux and aux2 may alias out.
+// ca_rhs (device, nrhs doubles), if set, replaces ca by a value per RHS.
 // With fin == FIN_CG_ALPHA, also stores per-block partials of Re<aux, out>
-// in red->partials as [nrhs][dslash_reduce_blocks()].
+// in red->partials as [nrhs][dslash_reduce_blocks()].  With cg set, groups
+// of RHS none of which is CG_ACTIVE are skipped (their output is left as is).
 hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *in,
                           double2 *out, int nrhs, const double2 *aux, double ca,
                           const double2 *aux2, double cb, double cd, DslashFinal fin,
-                          const CgDev *cg, const Reduce *red, hipStream_t s);
+                          const CgDev *cg, const Reduce *red, hipStream_t s,
+                          const double *ca_rhs = nullptr);
 
 // Launch-shape knobs of the half stencil (hisq_set_tuning).
 hisq_status dslash_set_tuning(const std::string &key, int64_t value);
@@ -215,9 +219,49 @@ hisq_status gemm_nn(const float2 *V, int k, const double2 *C, int n, int64_t N, 
 hisq_status ensure_links_f32(hisq_gauge_s *g, hipStream_t s);
 hisq_status launch_dslash_f32(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
                               int nrhs, const float2 *aux, double ca, const float2 *aux2, double cb,
-                              double cd, double *partials, hipStream_t s);
+                              double cd, double *partials, hipStream_t s,
+                              const double *ca_rhs = nullptr, const int *rhs_status = nullptr);
 hisq_status apply_mdagm_f32(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,
                             double *partials, hipStream_t s);
+
+// The CG drivers run on the handle's own non-blocking stream (created on first
+// use, default priority), ordered after the caller's stream on entry and
+// before it on exit.  Chunks of iterations can then be captured into a HIP
+// graph and replayed (one launch instead of five per iteration).
+hisq_status solver_stream(hisq_gauge_s *g, hipStream_t caller, hipStream_t *out);
+hisq_status solver_stream_done(hisq_gauge_s *g, hipStream_t caller);
+// True if the iteration chunks of a solve of nrhs RHS should be graph-captured.
+bool cg_use_graphs(const hisq_gauge_s *g, int nrhs);
+
+// A captured chunk of iterations, replayed with one launch.
+class GraphChunk {
+public:
+    ~GraphChunk();
+    // Capture `body` (stream-ordered launches on s, nothing else) on first use,
+    // then launch the instantiated graph.
+    template <typename F>
+    hisq_status run(hipStream_t s, F &&body) {
+        if (!exec_) {
+            HISQ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            const hisq_status st = body();
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &graph);
+            if (st != HISQ_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            HISQ_HIP(e);
+            graph_ = graph;
+            HISQ_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        }
+        HISQ_HIP(hipGraphLaunch(exec_, s));
+        return HISQ_OK;
+    }
+
+private:
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+};
 
 // Mixed-precision CG helpers; mask (nrhs ints, device) selects RHS, null = all.
 hisq_status mixed_to_f32(const double2 *src, float2 *dst, int64_t n, int nrhs, const int *mask,
@@ -239,11 +283,16 @@ hisq_status mixed_mask_rows(double2 *C, int k, int nrhs, const int *mask, hipStr
 hisq_status convert_vectors(const void *src, hisq_prec sp, void *dst, hisq_prec dp, int64_t n,
                             hipStream_t s);
 hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
-                        const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s);
+                        const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s,
+                        const double *m2_rhs = nullptr);
 
 // Operators built from dslash.
-// out = ((2m)^2 - D_{p,1-p} D_{1-p,p}) in on parity p (p = 0: the even operator A)
+// out = ((2m)^2 - D_{p,1-p} D_{1-p,p}) in on parity p (p = 0: the even operator A);
+// m2_rhs (device, nrhs doubles), if set, gives (2m)^2 per RHS; skip (device,
+// nrhs ints), if set, lets RHS groups whose entries are all nonzero be skipped
+// (their output is left as is).
 hisq_status apply_mdagm(hisq_gauge_s *g, double two_m, const double2 *in, double2 *out,
-                        int nrhs, hipStream_t s, int parity = 0);
+                        int nrhs, hipStream_t s, int parity = 0, const double *m2_rhs = nullptr,
+                        const int *skip = nullptr);
 
 }  // namespace hisq

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED
 HISQ_FP64, HISQ_FP32, HISQ_BF16 = 0, 1, 2
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
-ABI_VERSION = 4
+ABI_VERSION = 7
 
 # Entry points declared in include/hisq.h (the tests check the library exports them all).
 EXPORTS = (
@@ -45,6 +45,7 @@ EXPORTS = (
     "hisq_mdagm", "hisq_prepare_source", "hisq_reconstruct_odd", "hisq_cg_solve",
     "hisq_deflate", "hisq_eigensolve", "hisq_set_tuning", "hisq_profile_enable",
     "hisq_profile_read", "hisq_convert_vectors", "hisq_propagator_solve",
+    "hisq_autotune_dslash", "hisq_cg_solve_multi",
 )
 
 
@@ -60,7 +61,8 @@ class CgParams(ctypes.Structure):
                 ("reliable_interval", ctypes.c_int), ("reliable_delta", ctypes.c_double),
                 ("n_ev", ctypes.c_int), ("evec_prec", ctypes.c_int),
                 ("evecs_dev", ctypes.c_void_p), ("evals_host", ctypes.POINTER(ctypes.c_double)),
-                ("tol_restart", ctypes.c_double), ("parity", ctypes.c_int),
+                ("tol_restart", ctypes.c_double),
+                ("two_m_rhs", ctypes.POINTER(ctypes.c_double)), ("parity", ctypes.c_int),
                 ("reserved", ctypes.c_int * 7)]
 
 
@@ -71,6 +73,11 @@ class CgStats(ctypes.Structure):
                 ("true_residual", ctypes.c_double), ("b_norm", ctypes.c_double)]
 
 
+class System(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("two_m", ctypes.c_double), ("b_dev", ctypes.c_void_p),
+                ("x_dev", ctypes.c_void_p), ("nrhs", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
 class PropParams(ctypes.Structure):
     _fields_ = [("cg", CgParams), ("polish_tol", ctypes.c_double),
                 ("polish_max_iter", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
@@ -79,6 +86,13 @@ class PropParams(ctypes.Structure):
 class PropStats(ctypes.Structure):
     _fields_ = [("even", CgStats), ("polish", CgStats), ("residual", ctypes.c_double),
                 ("residual_even", ctypes.c_double), ("reserved", ctypes.c_double * 2)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("rhs_per_thread", ctypes.c_int), ("lanes_per_site", ctypes.c_int),
+                ("group_order", ctypes.c_int), ("xcd_remap", ctypes.c_int),
+                ("us_best", ctypes.c_double), ("us_default", ctypes.c_double),
+                ("shapes_timed", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 EIG_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -136,6 +150,9 @@ def lib():
         "hisq_convert_vectors": ([P, I, P, I, ctypes.c_int64, P], I),
         "hisq_propagator_solve": ([P, D, P, P, I, ctypes.POINTER(PropParams),
                                    ctypes.POINTER(PropStats), P], I),
+        "hisq_autotune_dslash": ([P, I, I, I, ctypes.POINTER(TuneResult), P], I),
+        "hisq_cg_solve_multi": ([I, ctypes.POINTER(System), ctypes.POINTER(CgParams),
+                                 ctypes.POINTER(CgStats), P], I),
         "hisq_profile_enable": ([I], I),
         "hisq_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(D)], I),
@@ -334,32 +351,17 @@ def hisq_cg_solve(g, two_m, b, x, tol=1e-10, max_iter=100000, check_interval=0,
     nrhs = _nrhs(b, g.vh, "b")
     if _nrhs(x, g.vh, "x") != nrhs:
         raise ValueError("b and x must have the same nrhs")
-    p = CgParams(tol=float(tol), max_iter=int(max_iter), check_interval=int(check_interval),
-                 sloppy_prec=int(sloppy_prec), reliable_interval=int(reliable_interval),
-                 reliable_delta=float(reliable_delta), tol_restart=float(tol_restart),
-                 parity=int(parity))
-    ev = None
-    if evecs is not None:
-        n_ev = _nrhs(evecs, g.vh, "evecs")
-        ev = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
-        if ev.shape != (n_ev,):
-            raise ValueError("evals must have one entry per eigenvector")
-        p.n_ev = n_ev
-        p.evec_prec = _prec_of(evecs, "evecs")
-        p.evecs_dev = _ptr(evecs, "evecs", ("complex128", "complex64")).value
-        p.evals_host = ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p, keep = _cg_params(tol, max_iter, check_interval, sloppy_prec, reliable_interval,
+                         reliable_delta, evecs, evals, tol_restart, parity, g.vh, two_m, nrhs)
     stats = (CgStats * nrhs)()
-    st = lib().hisq_cg_solve(_h(g), float(two_m), _ptr(b, "b"), _ptr(x, "x"), nrhs,
+    st = lib().hisq_cg_solve(_h(g), _scalar_mass(two_m), _ptr(b, "b"), _ptr(x, "x"), nrhs,
                              ctypes.byref(p), stats, _stream(stream))
     if raise_on_fail:
         _check(st, "hisq_cg_solve")
     elif st not in (HISQ_OK, HISQ_ERR_NOT_CONVERGED, HISQ_ERR_NAN, HISQ_ERR_BREAKDOWN):
         _check(st, "hisq_cg_solve")
-    del ev  # kept alive across the call above
-    return CgResult(st, [s.iterations for s in stats], [s.true_residual for s in stats],
-                    [bool(s.converged) for s in stats], [s.true_residual_checks for s in stats],
-                    [s.b_norm for s in stats], [s.reliable_updates for s in stats],
-                    [s.redeflations for s in stats])
+    del keep  # host arrays kept alive across the call above
+    return _cg_result(st, stats)
 
 
 @dataclass
@@ -371,12 +373,24 @@ class PropResult:
     residual_even: list
 
 
+def _scalar_mass(two_m):
+    return float(np.asarray(two_m, dtype=np.float64).ravel()[0])
+
+
 def _cg_params(tol, max_iter, check_interval, sloppy_prec, reliable_interval, reliable_delta,
-               evecs, evals, tol_restart, parity, vh):
+               evecs, evals, tol_restart, parity, vh, two_m=None, nrhs=None):
+    """CgParams and the host arrays it points to (keep them alive for the call)."""
     p = CgParams(tol=float(tol), max_iter=int(max_iter), check_interval=int(check_interval),
                  sloppy_prec=int(sloppy_prec), reliable_interval=int(reliable_interval),
                  reliable_delta=float(reliable_delta), tol_restart=float(tol_restart),
                  parity=int(parity))
+    keep = []
+    if two_m is not None and np.ndim(two_m) > 0:
+        ms = np.ascontiguousarray(np.asarray(two_m, dtype=np.float64))
+        if ms.shape != (nrhs,):
+            raise ValueError("two_m must be a scalar or have one entry per RHS")
+        p.two_m_rhs = ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        keep.append(ms)
     ev = None
     if evecs is not None:
         n_ev = _nrhs(evecs, vh, "evecs")
@@ -387,7 +401,8 @@ def _cg_params(tol, max_iter, check_interval, sloppy_prec, reliable_interval, re
         p.evec_prec = _prec_of(evecs, "evecs")
         p.evecs_dev = _ptr(evecs, "evecs", ("complex128", "complex64")).value
         p.evals_host = ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    return p, ev
+        keep.append(ev)
+    return p, keep
 
 
 def _cg_result(st, stats):
@@ -409,13 +424,13 @@ def hisq_propagator_solve(g, two_m, eta, psi, tol=1e-10, max_iter=100000, sloppy
     for t, nm in ((eta, "eta"), (psi, "psi")):
         if tuple(t.shape) != (nrhs, T, Z, Y, X, 3):
             raise ValueError(f"{nm} must have shape [nrhs, T, Z, Y, X, 3]")
-    cg, ev = _cg_params(tol, max_iter, 0, sloppy_prec, 0, reliable_delta, evecs, evals,
-                        tol_restart, 0, g.vh)
+    cg, keep = _cg_params(tol, max_iter, 0, sloppy_prec, 0, reliable_delta, evecs, evals,
+                          tol_restart, 0, g.vh)
     p = PropParams(cg=cg, polish_tol=float(polish_tol), polish_max_iter=int(polish_max_iter))
     stats = (PropStats * nrhs)()
     st = lib().hisq_propagator_solve(_h(g), float(two_m), _ptr(eta, "eta"), _ptr(psi, "psi"), nrhs,
                                      ctypes.byref(p), stats, _stream(stream))
-    del ev  # kept alive across the call above
+    del keep  # kept alive across the call above
     if raise_on_fail:
         _check(st, "hisq_propagator_solve")
     elif st not in (HISQ_OK, HISQ_ERR_NOT_CONVERGED, HISQ_ERR_NAN, HISQ_ERR_BREAKDOWN):
@@ -423,6 +438,38 @@ def hisq_propagator_solve(g, two_m, eta, psi, tol=1e-10, max_iter=100000, sloppy
     return PropResult(st, _cg_result(st, [s.even for s in stats]),
                       _cg_result(st, [s.polish for s in stats]),
                       [s.residual for s in stats], [s.residual_even for s in stats])
+
+
+def hisq_cg_solve_multi(systems, tol=1e-10, max_iter=100000, sloppy_prec=HISQ_FP64,
+                        reliable_delta=0.0, stream=None, raise_on_fail=True):
+    """Solve independent systems [(gauge, two_m, b, x), ...] concurrently (one
+    parameter set for all; two_m a scalar or one mass per RHS); returns one
+    CgResult per system."""
+    n = len(systems)
+    arr = (System * n)()
+    prm = (CgParams * n)()
+    total, keep = 0, []
+    for i, (g, two_m, b, x) in enumerate(systems):
+        nr = _nrhs(b, g.vh, "b")
+        if _nrhs(x, g.vh, "x") != nr:
+            raise ValueError("b and x must have the same nrhs")
+        arr[i] = System(g=_h(g), two_m=_scalar_mass(two_m), b_dev=_ptr(b, "b").value,
+                        x_dev=_ptr(x, "x").value, nrhs=nr)
+        prm[i], k = _cg_params(tol, max_iter, 0, sloppy_prec, 0, reliable_delta, None, None, 0.0,
+                               0, g.vh, two_m, nr)
+        keep += k
+        total += nr
+    stats = (CgStats * total)()
+    st = lib().hisq_cg_solve_multi(n, arr, prm, stats, _stream(stream))
+    del keep
+    if raise_on_fail:
+        _check(st, "hisq_cg_solve_multi")
+    out, k = [], 0
+    for i in range(n):
+        nr = arr[i].nrhs
+        out.append(_cg_result(st, stats[k:k + nr]))
+        k += nr
+    return out
 
 
 def hisq_convert_vectors(src, dst, stream=None):
@@ -474,6 +521,15 @@ def hisq_eigensolve(g, two_m, n_ev, evecs, n_kr=0, cheb_degree=0, cheb_a=0.0, ch
     if raise_on_fail:
         _check(st, "hisq_eigensolve")
     return st, evals, stats
+
+
+def hisq_autotune_dslash(g, nrhs, prec=HISQ_FP64, reps=0, stream=None) -> TuneResult:
+    """Time every half-stencil launch shape for this volume, nrhs and precision
+    and keep the fastest for later launches of that size."""
+    r = TuneResult()
+    _check(lib().hisq_autotune_dslash(_h(g), int(nrhs), int(prec), int(reps), ctypes.byref(r),
+                                      _stream(stream)), "hisq_autotune_dslash")
+    return r
 
 
 def hisq_set_tuning(key: str, value: int):

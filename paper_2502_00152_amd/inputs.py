@@ -129,6 +129,13 @@ WORKLOADS = {
 C_FAT = 1.0
 C_LONG = -1.0 / 24.0
 
+# Uneven batch: four lattices x three masses, fewer RHS on larger lattices.
+# Seeds of lattice l: fat 30000+1000l+1, long +2, source j of mass k
+# 30000+1000l+100+10k+j.
+UNEVEN_BATCH = dict(name="uneven-batch", eps=0.3, masses=(0.1, 0.02, 0.005), tol=1e-10,
+                    lattices=(((8, 8, 8, 8), 32), ((12, 12, 12, 12), 16),
+                              ((16, 16, 16, 32), 8), ((24, 24, 24, 48), 4)))
+
 
 def workload(c: int) -> dict:
     """Recipe of workload c, with its seeds."""

@@ -64,6 +64,8 @@ STRUCTS = {
     "hisq_eig_stats": hisq.EigStats,
     "hisq_prop_params": hisq.PropParams,
     "hisq_prop_stats": hisq.PropStats,
+    "hisq_tune_result": hisq.TuneResult,
+    "hisq_system": hisq.System,
 }
 
 

@@ -143,3 +143,83 @@ def test_cg_check_interval_does_not_change_iterates(interval):
     assert r0.iterations == r1.iterations
     assert np.array_equal(host(x), host(ref))
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_captured_chunks_give_identical_iterates(w8, prec):
+    """Iteration chunks replayed from a captured HIP graph (several replays per
+    solve, host polls in between) give bitwise the iterates of eager launches."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = w8
+    b = dev(np.stack([to_parity(pr.y, pr.dims, 0)[0]] * 2))
+    sp = hisq.HISQ_FP64 if prec == "fp64" else hisq.HISQ_FP32
+    out = {}
+    try:
+        for mode in (0, 1):
+            hisq.hisq_set_tuning("cg_graphs", mode)
+            x = torch.zeros_like(b)
+            r = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=1e-10, sloppy_prec=sp, check_interval=8)
+            assert all(r.converged) and r.iterations[0] > 40  # several chunk replays
+            out[mode] = (r.iterations, x.clone())
+    finally:
+        hisq.hisq_set_tuning("cg_graphs", -1)
+    assert out[0][0] == out[1][0]
+    assert torch.equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_system_solve_equals_separate_solves(prec):
+    """Three systems on two lattices and two masses solved concurrently give
+    bitwise the solutions of separate hisq_cg_solve calls."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pa = Problem((8, 8, 8, 8), 0.3, 301, 302)
+    pb = Problem((4, 6, 8, 10), 0.5, 303, 304)
+    ga, gb = pa.gauge(), pb.gauge()
+    sp = hisq.HISQ_FP64 if prec == "fp64" else hisq.HISQ_FP32
+    systems = []
+    for g, pr, two_m, n, seed in ((ga, pa, 0.1, 2, 500), (ga, pa, 0.05, 3, 510), (gb, pb, 0.2, 4, 520)):
+        b = dev(to_parity(np.stack([I.gaussian_source(pr.dims, seed + j) for j in range(n)]),
+                          pr.dims, 0))
+        systems.append((g, two_m, b, torch.zeros_like(b)))
+    try:
+        res = hisq.hisq_cg_solve_multi(systems, tol=1e-10, sloppy_prec=sp)
+        for (g, two_m, b, x), r in zip(systems, res):
+            assert all(r.converged)
+            x1 = torch.zeros_like(b)
+            r1 = hisq.hisq_cg_solve(g, two_m, b, x1, tol=1e-10, sloppy_prec=sp)
+            assert r1.iterations == r.iterations
+            assert torch.equal(x1, x)
+        with pytest.raises(hisq.HisqError) as e:
+            bad = [(ga, 0.1, systems[0][2], systems[0][3]), (gb, -1.0, systems[2][2], systems[2][3])]
+            hisq.hisq_cg_solve_multi(bad)
+        assert "system 1" in str(e.value)
+    finally:
+        ga.close()
+        gb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_several_masses_in_one_batch(w8, prec):
+    """One batched solve with a mass per RHS gives bitwise the solutions of
+    single-mass solves (the stencil is shared, the (2m)^2 term is per RHS)."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = w8
+    masses = [0.1, 0.05, 0.2]
+    b = dev(np.stack([to_parity(pr.y, pr.dims, 0)[0]] * 3))
+    sp = hisq.HISQ_FP64 if prec == "fp64" else hisq.HISQ_FP32
+    x = torch.zeros_like(b)
+    r = hisq.hisq_cg_solve(pr.g, masses, b, x, tol=1e-10, sloppy_prec=sp)
+    assert all(r.converged)
+    for j, m in enumerate(masses):
+        xj = torch.zeros_like(b[j:j + 1])
+        rj = hisq.hisq_cg_solve(pr.g, m, b[j:j + 1].clone(), xj, tol=1e-10, sloppy_prec=sp)
+        assert rj.iterations[0] == r.iterations[j]
+        assert torch.equal(xj[0], x[j])
+    # the oracle's residual for the lightest mass
+    xe = from_parity(host(x)[1:2], pr.dims, 0)[0]
+    assert O.norm(pr.y - O.apply_A(pr.F, pr.L, 0.05, xe)) / O.norm(pr.y) <= 1e-10
+    with pytest.raises(hisq.HisqError):
+        hisq.hisq_cg_solve(pr.g, [0.1, -0.1, 0.2], b, torch.zeros_like(b))

@@ -233,3 +233,30 @@ def test_profile_sampling_counts_every_nth_launch():
     finally:
         hisq.hisq_profile_enable(False)
         g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotuner_picks_a_valid_shape_and_keeps_results(prec):
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (4, 6, 8, 10)
+    pr = Problem(dims, 0.5, 47, 48)
+    g = pr.gauge()
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    p = hisq.HISQ_FP64 if prec == "fp64" else hisq.HISQ_FP32
+    v = torch.from_numpy(to_parity(sources(dims, 12, 910), dims, 1)).to(dt).cuda()
+    ref = torch.empty_like(v)
+    hisq.hisq_dslash_eo(g, 0, v, ref)
+    try:
+        r = hisq.hisq_autotune_dslash(g, 12, p, reps=3)
+        assert r.shapes_timed > 10 and 0 < r.us_best <= r.us_default
+        assert (r.rhs_per_thread, r.lanes_per_site) in \
+            [(n, 1) for n in (1, 2, 3, 4, 6, 12)] + [(n, l) for l in (2, 4) for n in (1, 3, 6)]
+        out = torch.empty_like(v)
+        hisq.hisq_dslash_eo(g, 0, v, out)
+        assert torch.equal(out, ref)
+        with pytest.raises(hisq.HisqError):
+            hisq.hisq_autotune_dslash(g, 12, hisq.HISQ_BF16)
+    finally:
+        hisq.hisq_set_tuning("dslash_autotune_clear", 1)
+        g.close()

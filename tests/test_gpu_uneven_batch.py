@@ -1,0 +1,86 @@
+"""GPU parity of the uneven batch at its full sizes: 8^4 (32 RHS), 12^4 (16),
+16^3 x 32 (8) and 24^3 x 48 (4), each at 2m = 0.1, 0.02 and 0.005, eps 0.3
+(batching of uneven solves, the paper's future work in section 4).  Each
+lattice is one system with its three masses in one batched solve (a mass per
+RHS, shared link loads); the four systems run concurrently.
+
+Links are drawn on the device and copied to the host for the oracle (the
+host draw of 24^3 x 48 takes about a minute).  Checks: every RHS converges;
+the oracle's true residual of one RHS per (lattice, mass) meets tol; the
+concurrent batched solve equals separate single-mass solves bitwise for the
+smallest lattice.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from oracle import hisq_oracle as O
+from paper_2502_00152_amd import inputs as I
+from tests.gpu_util import from_parity, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def batch():
+    import torch
+    from paper_2502_00152_amd import hisq
+    B = I.UNEVEN_BATCH
+    t0 = time.time()
+    lat = []
+    for l, (dims, nrhs) in enumerate(B["lattices"]):
+        Wd = I.random_su3_field_device(dims, B["eps"], 30000 + 1000 * l + 1)
+        Nd = I.random_su3_field_device(dims, B["eps"], 30000 + 1000 * l + 2)
+        g = hisq.Gauge(dims, Wd, Nd, I.C_FAT, I.C_LONG)
+        F, L = O.fold_links(Wd.cpu().numpy(), Nd.cpu().numpy(), I.C_FAT, I.C_LONG)
+        del Wd, Nd
+        bs = []
+        for k in range(len(B["masses"])):
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(30000 + 1000 * l + 100 + 10 * k)
+            bs.append(torch.randn((nrhs, 3, g.vh), dtype=torch.complex128, device="cuda",
+                                  generator=gen))
+        lat.append(dict(dims=dims, nrhs=nrhs, g=g, F=F, L=L, b=torch.cat(bs),
+                        masses=np.repeat(B["masses"], nrhs)))
+    torch.cuda.empty_cache()
+    print(f"[uneven] setup {time.time() - t0:.0f}s", flush=True)
+    yield lat
+    for d in lat:
+        d["g"].close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_uneven_batch_concurrent(batch, prec):
+    import torch
+    from paper_2502_00152_amd import hisq
+    sp = hisq.HISQ_FP64 if prec == "fp64" else hisq.HISQ_FP32
+    systems = [(d["g"], d["masses"], d["b"], torch.zeros_like(d["b"])) for d in batch]
+    t0 = time.time()
+    res = hisq.hisq_cg_solve_multi(systems, tol=1e-10, sloppy_prec=sp)
+    torch.cuda.synchronize()
+    n = sum(d["b"].shape[0] for d in batch)
+    print(f"[uneven] {prec}: {n} solves in {time.time() - t0:.2f}s, iterations "
+          f"{[max(r.iterations) for r in res]}", flush=True)
+    for d, (g, ms, b, x), r in zip(batch, systems, res):
+        assert all(r.converged)
+        xs, bs = host(x), host(b)
+        nr = d["nrhs"]
+        for k in range(3):
+            j = k * nr + (k % nr)
+            xe = from_parity(xs[j:j + 1], d["dims"], 0)[0]
+            be = from_parity(bs[j:j + 1], d["dims"], 0)[0]
+            tr = O.norm(be - O.apply_A(d["F"], d["L"], ms[j], xe)) / O.norm(be)
+            assert tr <= 1e-10, (d["dims"], ms[j], tr)
+    # the smallest lattice: equal to separate single-mass solves
+    d = batch[0]
+    x = systems[0][3]
+    nr = d["nrhs"]
+    for k, m in enumerate(I.UNEVEN_BATCH["masses"]):
+        xk = torch.zeros_like(d["b"][k * nr:(k + 1) * nr])
+        rk = hisq.hisq_cg_solve(d["g"], m, d["b"][k * nr:(k + 1) * nr].clone(), xk, tol=1e-10,
+                                sloppy_prec=sp)
+        assert rk.iterations == res[0].iterations[k * nr:(k + 1) * nr]
+        assert torch.equal(xk, x[k * nr:(k + 1) * nr])
