@@ -179,3 +179,18 @@ def random_su3_field_device(dims, eps: float, seed: int, device="cuda"):
             E = torch.matmul(E, E)
         out[mu] = E
     return out
+
+
+def nn_initial_params(seed: int, channels: int = 8) -> np.ndarray:
+    """Initial parameters of the learned-guess network, float32, in the order
+    W1 [9][C][1], W2 [9][C][C], W3 [9][1][C], g1 [C][2], g2 [C][2]: Gaussian
+    weights scaled by 1/sqrt(9 fan_in), gates (a, b) = (0, 2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    C = channels
+    parts = [rng.standard_normal(9 * C * 1) / np.sqrt(9 * 1),
+             rng.standard_normal(9 * C * C) / np.sqrt(9 * C),
+             rng.standard_normal(9 * 1 * C) / np.sqrt(9 * C)]
+    g = np.zeros((C, 2))
+    g[:, 1] = 2.0
+    parts += [g.ravel(), g.ravel()]
+    return np.concatenate(parts).astype(np.float32)
