@@ -78,7 +78,7 @@ const char *hisq_last_error(void);
 
 /* ABI revision of this header; bumped on any incompatible change. */
 int hisq_abi_version(void);
-#define HISQ_ABI_VERSION 7
+#define HISQ_ABI_VERSION 8
 
 /* ------------------------------------------------------------------ gauge */
 
@@ -437,6 +437,98 @@ typedef struct hisq_tune_result {
 hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec prec, int reps,
                                  hisq_tune_result *result_host, void *stream);
 
+/* ------------------------------------------------- learned initial guess */
+
+/*
+ * A small gauge-covariant network N that maps the residual r0 = b - A x0 of an
+ * initial guess x0 (normally the deflation guess of Eq. (4)) to a correction
+ * of it.  This goes beyond arXiv:2502.00152, whose solver is deflated CG
+ * (section 2): CG stays the solver with its true-residual stop unchanged, and
+ * hisq_nn_guess keeps a correction only for the RHS whose ||b - A x|| it lowers.
+ *
+ * N has HISQ_NN_CHANNELS = 8 channels, each a colour-vector field on every
+ * site, and three layers
+ *
+ *   layer(W, psi)^o = sum_{d=0..8} sum_c W[d][o][c] T_d psi^c,
+ *   T_0 = 1,  (T_{1+mu} psi)(x) = F_mu(x) psi(x+mu),
+ *   (T_{5+mu} psi)(x) = F_mu(x-mu)^H psi(x-mu)
+ *
+ * (F: the handle's fat links with their folded phases, rounded to FP32; real
+ * weights, so N commutes with gauge transformations) with norm gates
+ *
+ *   gate(g, psi)^c(x) = psi^c(x) / (1 + exp(-(a_c |psi^c(x)| + b_c)))
+ *
+ * between them: N(r) = even part of layer(W3, gate(g2, layer(W2, gate(g1,
+ * layer(W1, r))))), with r on the even sites and zero on the odd ones.  The
+ * HISQ_NN_PARAMS = 752 parameters are floats in the order W1 [9][8][1],
+ * W2 [9][8][8], W3 [9][1][8], g1 [8][2] = (a_c, b_c), g2 [8][2], row-major.
+ * Activations are FP32; gradients of weights and gates, norms and the loss are
+ * summed in FP64 in a fixed order, so results repeat bit for bit.
+ *
+ * Flags: HISQ_NN_NORMALIZE - the network sees r_s / ||r_s|| and its output is
+ * scaled back by ||r_s|| (per sample; the loss then compares with
+ * e_s / ||r_s||).  HISQ_NN_BF16 - inference with the parameters rounded to
+ * bfloat16 (nearest even), FP32 arithmetic (hisq_nn_apply, hisq_nn_guess).
+ *
+ * Even parity vectors use the layout of every other entry point; a batch of
+ * nsamp of them is [nsamp][3][Vh] complex double.  A network handle belongs to
+ * the gauge handle it was created on (which must outlive it); calls on one
+ * network must not overlap.  The network owns its parameters, Adam moments
+ * and activation scratch: 2448 * Vh bytes per sample in training (51 FP32
+ * channel fields), 816 * Vh in inference.
+ */
+#define HISQ_NN_CHANNELS 8
+#define HISQ_NN_PARAMS 752
+enum { HISQ_NN_NORMALIZE = 1u, HISQ_NN_BF16 = 2u };
+
+typedef struct hisq_nn_s *hisq_nn;
+
+/* Create a network on g.  params_host: HISQ_NN_PARAMS finite floats, or NULL
+ * for all zeros (N = 0).  Adam moments start at zero. */
+hisq_status hisq_nn_create(hisq_nn *out, hisq_gauge g, const float *params_host);
+hisq_status hisq_nn_destroy(hisq_nn n);  /* NULL is a no-op; synchronises */
+/* Replace the parameters (and reset Adam); read them back.  Both synchronise. */
+hisq_status hisq_nn_set_params(hisq_nn n, const float *params_host);
+hisq_status hisq_nn_get_params(hisq_nn n, float *params_host);
+
+/* out_s = N(r_s) for nsamp (1..4096) even vectors; out must not overlap r.
+ * Enqueued on stream, no synchronisation. */
+hisq_status hisq_nn_apply(hisq_nn n, const void *r_dev, void *out_dev, int nsamp,
+                          unsigned flags, void *stream);
+
+/* Loss of a batch, loss = (1/nsamp) sum_s ||N(r_s) - e_s||^2 / ||e_s||^2, and
+ * its gradient with respect to the parameters (grad_host: HISQ_NN_PARAMS
+ * doubles, or NULL; it is also kept for hisq_nn_adam_step).  e_s must be
+ * nonzero (else HISQ_ERR_NAN).  FP32 parameters only (no HISQ_NN_BF16).
+ * Synchronises. */
+hisq_status hisq_nn_loss_grad(hisq_nn n, const void *r_dev, const void *e_dev, int nsamp,
+                              unsigned flags, double *loss_host, double *grad_host,
+                              void *stream);
+
+/* One Adam step (Kingma and Ba) from the last gradient: t += 1,
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), in FP32.
+ * INVALID_ARG before the first hisq_nn_loss_grad or for lr <= 0,
+ * b outside [0, 1), eps <= 0. */
+hisq_status hisq_nn_adam_step(hisq_nn n, double lr, double beta1, double beta2, double eps,
+                              void *stream);
+
+/* Train on npairs (r, e) pairs: `steps` Adam steps (beta1 0.9, beta2 0.999,
+ * eps 1e-8); step k uses the mini-batch of `batch` consecutive pairs number
+ * k mod floor(npairs / batch) (pairs past the last whole batch are unused).
+ * loss_host[k] (steps doubles, or NULL) = the loss of step k's batch before
+ * its update.  Synchronises. */
+hisq_status hisq_nn_train(hisq_nn n, const void *r_dev, const void *e_dev, int npairs,
+                          int batch, int steps, double lr, unsigned flags,
+                          double *loss_host, void *stream);
+
+/* The initial guess: for each RHS j, r = b_j - A x_j (A = (2m)^2 - D_eo D_oe,
+ * FP64), d = N(r), and x_j += d where ||r - A d|| < ||r||.  kept_host (nrhs
+ * ints, or NULL) receives 1 where the correction was kept (then the call
+ * synchronises).  b and x must not overlap. */
+hisq_status hisq_nn_guess(hisq_nn n, double two_m, const void *b_dev, void *x_dev, int nrhs,
+                          unsigned flags, int *kept_host, void *stream);
+
 /* ------------------------------------------------------ instrumentation */
 
 /*
@@ -445,7 +537,8 @@ hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec prec, int rep
  * "dslash_aux" (with one epilogue field: M^H M second half, source, odd
  * reconstruction), "dslash_aux2" (two epilogue fields: Chebyshev step),
  * "dslash_f32", "dslash_f32_aux", "dslash_f32_aux2" (the same in FP32), "blas"
- * (CG and Lanczos vector kernels), "gemm" (matrix-core contractions); off by
+ * (CG and Lanczos vector kernels), "gemm" (matrix-core contractions),
+ * "nn_layer" (the learned guess's layer kernel, forward and backward); off by
  * default.  hisq_profile_enable(n): n = 0 off; n >= 1 times every n-th launch
  * of each class (counting from the call), so that a long run can be sampled
  * with few events in the stream; n < 0 is INVALID_ARG.  hisq_profile_read

@@ -36,7 +36,10 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED
 HISQ_FP64, HISQ_FP32, HISQ_BF16 = 0, 1, 2
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
-ABI_VERSION = 7
+ABI_VERSION = 8
+HISQ_NN_CHANNELS = 8
+HISQ_NN_PARAMS = 752
+HISQ_NN_NORMALIZE, HISQ_NN_BF16 = 1, 2
 
 # Entry points declared in include/hisq.h (the tests check the library exports them all).
 EXPORTS = (
@@ -45,7 +48,9 @@ EXPORTS = (
     "hisq_mdagm", "hisq_prepare_source", "hisq_reconstruct_odd", "hisq_cg_solve",
     "hisq_deflate", "hisq_eigensolve", "hisq_set_tuning", "hisq_profile_enable",
     "hisq_profile_read", "hisq_convert_vectors", "hisq_propagator_solve",
-    "hisq_autotune_dslash", "hisq_cg_solve_multi",
+    "hisq_autotune_dslash", "hisq_cg_solve_multi", "hisq_nn_create", "hisq_nn_destroy",
+    "hisq_nn_set_params", "hisq_nn_get_params", "hisq_nn_apply", "hisq_nn_loss_grad",
+    "hisq_nn_adam_step", "hisq_nn_train", "hisq_nn_guess",
 )
 
 
@@ -153,6 +158,15 @@ def lib():
         "hisq_autotune_dslash": ([P, I, I, I, ctypes.POINTER(TuneResult), P], I),
         "hisq_cg_solve_multi": ([I, ctypes.POINTER(System), ctypes.POINTER(CgParams),
                                  ctypes.POINTER(CgStats), P], I),
+        "hisq_nn_create": ([ctypes.POINTER(P), P, ctypes.POINTER(ctypes.c_float)], I),
+        "hisq_nn_destroy": ([P], I),
+        "hisq_nn_set_params": ([P, ctypes.POINTER(ctypes.c_float)], I),
+        "hisq_nn_get_params": ([P, ctypes.POINTER(ctypes.c_float)], I),
+        "hisq_nn_apply": ([P, P, P, I, U, P], I),
+        "hisq_nn_loss_grad": ([P, P, P, I, U, ctypes.POINTER(D), ctypes.POINTER(D), P], I),
+        "hisq_nn_adam_step": ([P, D, D, D, D, P], I),
+        "hisq_nn_train": ([P, P, P, I, I, I, D, U, ctypes.POINTER(D), P], I),
+        "hisq_nn_guess": ([P, D, P, P, I, U, ctypes.POINTER(I), P], I),
         "hisq_profile_enable": ([I], I),
         "hisq_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(D)], I),
@@ -530,6 +544,131 @@ def hisq_autotune_dslash(g, nrhs, prec=HISQ_FP64, reps=0, stream=None) -> TuneRe
     _check(lib().hisq_autotune_dslash(_h(g), int(nrhs), int(prec), int(reps), ctypes.byref(r),
                                       _stream(stream)), "hisq_autotune_dslash")
     return r
+
+
+# ------------------------------------------------------- learned guess
+def _params_f32(params):
+    if params is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+    if a.size != HISQ_NN_PARAMS:
+        raise ValueError(f"network parameters must have {HISQ_NN_PARAMS} entries, got {a.size}")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Network:
+    """Owns a hisq_nn handle (the learned initial guess) on a gauge handle."""
+
+    def __init__(self, g, params=None):
+        self.gauge = g
+        self.handle = hisq_nn_create(g, params)
+
+    def close(self):
+        if self.handle:
+            hisq_nn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _nn(n):
+    return n.handle if isinstance(n, Network) else n
+
+
+def hisq_nn_create(g, params=None):
+    a, ptr = _params_f32(params)
+    h = ctypes.c_void_p()
+    _check(lib().hisq_nn_create(ctypes.byref(h), _h(g), ptr), "hisq_nn_create")
+    return h
+
+
+def hisq_nn_destroy(n):
+    _check(lib().hisq_nn_destroy(_nn(n)), "hisq_nn_destroy")
+
+
+def hisq_nn_set_params(n, params):
+    a, ptr = _params_f32(params)
+    _check(lib().hisq_nn_set_params(_nn(n), ptr), "hisq_nn_set_params")
+
+
+def hisq_nn_get_params(n):
+    out = np.zeros(HISQ_NN_PARAMS, dtype=np.float32)
+    _check(lib().hisq_nn_get_params(_nn(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+           "hisq_nn_get_params")
+    return out
+
+
+def _nn_vh(n):
+    g = n.gauge if isinstance(n, Network) else None
+    return g.vh if isinstance(g, Gauge) else None
+
+
+def _samples(n, t, name):
+    vh = _nn_vh(n)
+    if vh is not None:
+        return _nrhs(t, vh, name)
+    return int(t.shape[0])
+
+
+def hisq_nn_apply(n, r, out, flags=HISQ_NN_NORMALIZE, stream=None):
+    S = _samples(n, r, "r")
+    if tuple(out.shape) != tuple(r.shape):
+        raise ValueError("out must have the shape of r")
+    _check(lib().hisq_nn_apply(_nn(n), _ptr(r, "r"), _ptr(out, "out"), S, int(flags),
+                               _stream(stream)), "hisq_nn_apply")
+
+
+def hisq_nn_loss_grad(n, r, e, flags=HISQ_NN_NORMALIZE, stream=None):
+    """(loss, gradient as float64 numpy [752]) of the batch (r, e)."""
+    S = _samples(n, r, "r")
+    if tuple(e.shape) != tuple(r.shape):
+        raise ValueError("e must have the shape of r")
+    loss = ctypes.c_double()
+    grad = np.zeros(HISQ_NN_PARAMS, dtype=np.float64)
+    _check(lib().hisq_nn_loss_grad(_nn(n), _ptr(r, "r"), _ptr(e, "e"), S, int(flags),
+                                   ctypes.byref(loss),
+                                   grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   _stream(stream)), "hisq_nn_loss_grad")
+    return float(loss.value), grad
+
+
+def hisq_nn_adam_step(n, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().hisq_nn_adam_step(_nn(n), float(lr), float(beta1), float(beta2), float(eps),
+                                   _stream(stream)), "hisq_nn_adam_step")
+
+
+def hisq_nn_train(n, r, e, batch, steps, lr, flags=HISQ_NN_NORMALIZE, stream=None):
+    """Adam training over the pairs (r, e); returns the per-step losses."""
+    S = _samples(n, r, "r")
+    if tuple(e.shape) != tuple(r.shape):
+        raise ValueError("e must have the shape of r")
+    losses = np.zeros(max(int(steps), 1), dtype=np.float64)
+    _check(lib().hisq_nn_train(_nn(n), _ptr(r, "r"), _ptr(e, "e"), S, int(batch), int(steps),
+                               float(lr), int(flags),
+                               losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               _stream(stream)), "hisq_nn_train")
+    return losses[:int(steps)]
+
+
+def hisq_nn_guess(n, two_m, b, x, flags=HISQ_NN_NORMALIZE, stream=None):
+    """x += N(b - A x) per RHS where that lowers the residual; returns the kept flags."""
+    S = _samples(n, b, "b")
+    if tuple(x.shape) != tuple(b.shape):
+        raise ValueError("x must have the shape of b")
+    kept = (ctypes.c_int * S)()
+    _check(lib().hisq_nn_guess(_nn(n), _scalar_mass(two_m), _ptr(b, "b"), _ptr(x, "x"), S,
+                               int(flags), kept, _stream(stream)), "hisq_nn_guess")
+    return [int(k) for k in kept]
 
 
 def hisq_set_tuning(key: str, value: int):
