@@ -45,6 +45,8 @@ sys.path.insert(0, ROOT)
 METRIC = "solves/s at 1e-10 true residual (learned+mixed+batched vs plain CG); Dslash GB/s"
 HBM_PEAK_GBS = 8000.0
 PROFILE_PERIOD = 16
+LEARNED_PAIRS = 128   # training pairs the solver generates for the learned guess
+LEARNED_STEPS = 400   # Adam steps, mini-batches of 8
 
 
 def dslash_alg_bytes(vh, nrhs, aux_fields, real_bytes=8):
@@ -194,6 +196,46 @@ def cpu_baseline(cfg, golden):
                        f"deflated solve takes, odd reconstruction")}
 
 
+def train_learned_guess(g, evecs, eps, two_m, seed):
+    """Train the learned guess on pairs the solver generates: r = the residual
+    of the deflation guess of a prepared random source, e = the remaining
+    error from an FP64 solve to 1e-12.  Returns the network and timings."""
+    import torch
+    from paper_2502_00152_amd import hisq, inputs as I
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed + 500)
+    R, E = [], []
+    t0 = time.perf_counter()
+    for _ in range(LEARNED_PAIRS // 16):
+        a = torch.randn((16, 3, g.vh), dtype=torch.complex128, device="cuda", generator=gen)
+        c = torch.randn((16, 3, g.vh), dtype=torch.complex128, device="cuda", generator=gen)
+        b = torch.empty_like(a)
+        hisq.hisq_prepare_source(g, two_m, a, c, b)
+        xd = torch.empty_like(b)
+        hisq.hisq_deflate(g, evecs, eps, two_m, b, xd)
+        xs = xd.clone()
+        hisq.hisq_cg_solve(g, two_m, b, xs, tol=1e-12)
+        hisq.hisq_mdagm(g, two_m, xd, a)
+        R.append(b - a)
+        E.append(xs - xd)
+    R = torch.cat(R)
+    E = torch.cat(E)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    net = hisq.Network(g, I.nn_initial_params(seed + 501))
+    t0 = time.perf_counter()
+    losses = hisq.hisq_nn_train(net, R, E, batch=8, steps=LEARNED_STEPS, lr=1e-2,
+                                flags=hisq.HISQ_NN_NORMALIZE)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"[bench] learned guess: {LEARNED_PAIRS} pairs in {t_pairs:.2f} s, {LEARNED_STEPS} "
+          f"Adam steps in {t_train:.2f} s, loss {losses[0]:.3f} -> {np.mean(losses[-20:]):.3f}",
+          flush=True)
+    return net, {"training_pairs": LEARNED_PAIRS, "pairs_seconds": t_pairs,
+                 "train_steps": LEARNED_STEPS, "batch": 8, "train_seconds": t_train,
+                 "loss_first": float(losses[0]), "loss_last20_mean": float(np.mean(losses[-20:]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +244,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dslash-scan", action="store_true")
     ap.add_argument("--no-plain-cg", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -241,13 +284,26 @@ def main():
     po = torch.empty_like(eo)
     F32 = hisq.HISQ_FP32
 
-    def step():
+    # learned initial guess (an extension beyond the paper), trained like the
+    # eigensolve once per gauge field, outside the step
+    net, learn_info = (None, None) if args.no_learned else \
+        train_learned_guess(g, evecs, eps, two_m, cfg["seed_eig"])
+    kept = []
+
+    def step_core(with_guess):
         hisq.hisq_prepare_source(g, two_m, ee, eo, y)
         hisq.hisq_deflate(g, ev32, eps, two_m, y, x)
+        if with_guess:
+            kept[:] = hisq.hisq_nn_guess(net, two_m, y, x,
+                                         flags=hisq.HISQ_NN_NORMALIZE | hisq.HISQ_NN_BF16,
+                                         evecs=ev32, evals=eps)
         res = hisq.hisq_cg_solve(g, two_m, y, x, tol=tol, sloppy_prec=F32, reliable_delta=0.1,
                                  evecs=ev32, evals=eps, tol_restart=1e-3)
         hisq.hisq_reconstruct_odd(g, two_m, x, eo, po)
         return res
+
+    def step():
+        return step_core(net is not None)
 
     def step_fp64(xo):
         hisq.hisq_prepare_source(g, two_m, ee, eo, y)
@@ -325,6 +381,36 @@ def main():
                  "seconds": t_plain}
         print(f"[bench] plain CG {nrhs} solves in {t_plain:.3f} s", flush=True)
 
+    # the same step without the learned guess, and the guess's held-out loss
+    learned = None
+    if net is not None:
+        xd = torch.empty_like(y)
+        hisq.hisq_prepare_source(g, two_m, ee, eo, y)
+        hisq.hisq_deflate(g, evecs, eps, two_m, y, xd)
+        Ax = torch.empty_like(y)
+        hisq.hisq_mdagm(g, two_m, xd, Ax)
+        held_out, _ = hisq.hisq_nn_loss_grad(net, y - Ax, x64 - xd, hisq.HISQ_NN_NORMALIZE)
+        del xd, Ax
+        step_core(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r0 = step_core(False)
+        torch.cuda.synchronize()
+        t_without = time.perf_counter() - t0
+        learned = dict(learn_info)
+        learned.update({
+            "held_out_loss": held_out, "kept": list(kept),
+            "iterations_per_source_with": last.iterations,
+            "iterations_per_source_without": r0.iterations,
+            "solves_per_s_with": nrhs * args.steps / t_steps,
+            "solves_per_s_without": nrhs * args.steps / t_without,
+        })
+        net.close()
+        print(f"[bench] without the learned guess: {learned['solves_per_s_without']:.1f} solves/s,"
+              f" mean iterations {np.mean(r0.iterations):.1f} (with: "
+              f"{np.mean(last.iterations):.1f})", flush=True)
+
     scan = None if args.no_dslash_scan else dslash_scan()
     if scan:
         print(f"[bench] dslash 32^3x64: {scan['f64']['GB_s']:.0f} GB/s (f64), "
@@ -353,9 +439,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "deflated-cg-16^3x32", "lattice": "16x16x16x32", "eps": 0.5,
                    "two_m": two_m, "sources_per_step": nrhs, "n_ev": n_ev, "tol": tol,
-                   "path": ("FP32 eigenvectors, batched mixed-precision CG (FP32 stencil and "
-                            "vectors, FP64 reductions and reliable updates, delta_rd 0.1), "
-                            "re-deflation at delta_tr 1e-3")},
+                   "path": ("FP32 eigenvectors; learned correction (BF16 weights, projected "
+                            "off the deflation space) unless --no-learned; batched "
+                            "mixed-precision CG (FP32 stencil and vectors, FP64 reductions "
+                            "and reliable updates, delta_rd 0.1), re-deflation at "
+                            "delta_tr 1e-3"),
+                   "learned_guess": net is not None},
         "roofline": {"bound": "hbm", "kernel": "k_dslash<float> (FP32 half stencil, 12 RHS)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
@@ -370,6 +459,7 @@ def main():
         "max_rel_diff_vs_fp64_solution": diff,
         "deflated_fp64_cg": fp64,
         "plain_fp64_cg": plain,
+        "learned_guess": learned,
         "speedup_vs_plain_fp64_cg": value / plain["solves_per_s"] if plain else None,
         "eigensolve": {"seconds": t_eig, "matvecs": est.matvecs, "restarts": est.restarts,
                        "cheb_degree": est.cheb_degree, "max_residual": est.max_residual,

@@ -523,11 +523,19 @@ hisq_status hisq_nn_train(hisq_nn n, const void *r_dev, const void *e_dev, int n
                           double *loss_host, void *stream);
 
 /* The initial guess: for each RHS j, r = b_j - A x_j (A = (2m)^2 - D_eo D_oe,
- * FP64), d = N(r), and x_j += d where ||r - A d|| < ||r||.  kept_host (nrhs
- * ints, or NULL) receives 1 where the correction was kept (then the call
- * synchronises).  b and x must not overlap. */
+ * FP64) and d = N(r); with n_ev > 0 eigenpairs (the arguments of
+ * hisq_deflate: evecs_dev, evec_prec, evals_host = eps_i) the Galerkin
+ * correction d += V diag(1/(eps_i + (2m)^2)) V^H (r - A d) follows, which
+ * for a deflated x (V^H r = 0) removes the component of d in the deflation
+ * space (without it, error put back into the lowest modes makes CG slower
+ * than from the deflation guess alone).  Then x_j += d where
+ * ||r - A d|| < ||r||.  n_ev = 0 skips the projection (evecs_dev and
+ * evals_host are then not read).  kept_host (nrhs ints, or NULL) receives 1
+ * where the correction was kept (then the call synchronises).  b and x must
+ * not overlap. */
 hisq_status hisq_nn_guess(hisq_nn n, double two_m, const void *b_dev, void *x_dev, int nrhs,
-                          unsigned flags, int *kept_host, void *stream);
+                          unsigned flags, int n_ev, const void *evecs_dev, hisq_prec evec_prec,
+                          const double *evals_host, int *kept_host, void *stream);
 
 /* ------------------------------------------------------ instrumentation */
 

@@ -1,5 +1,7 @@
-// The HISQ half stencil kernel, generic in the storage precision R (double or
-// float; arithmetic in R, the <aux, out> partials of the CG always in double).
+// The HISQ half stencil kernel, generic in the arithmetic precision R (double
+// or float) and in the storage of vectors and links (complex R, or bfloat16
+// pairs with float arithmetic); the <aux, out> partials of the CG are always
+// double.
 //
 //   out(x) = ca * aux(x) + cb * aux2(x) + cd * sum_mu [ F_mu(x) in(x+mu) - F_mu(x-mu)^H in(x-mu)
 //                                                   + L_mu(x) in(x+3mu) - L_mu(x-3mu)^H in(x-3mu) ]
@@ -39,6 +41,46 @@ namespace hisq {
 template <typename R>
 using vec2 = R __attribute__((ext_vector_type(2)));
 
+// One complex number stored as two bfloat16 (real part in the low half).
+using bf16c = uint32_t;
+
+// Conversion between a stored complex S and the arithmetic type vec2<A>.
+template <typename S>
+struct Conv;
+
+template <typename R>
+struct Conv<vec2<R>> {
+    template <typename A>
+    static __device__ __forceinline__ vec2<A> ld(vec2<R> v) {
+        return vec2<A>{(A)v.x, (A)v.y};
+    }
+    template <typename A>
+    static __device__ __forceinline__ vec2<R> st(vec2<A> v) {
+        return vec2<R>{(R)v.x, (R)v.y};
+    }
+};
+
+// bfloat16 <-> float: a bfloat16 is the high half of a float's bits; stores
+// round to nearest, ties to even.
+__host__ __device__ __forceinline__ uint32_t bf16_bits(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+template <>
+struct Conv<bf16c> {
+    template <typename A>
+    static __device__ __forceinline__ vec2<A> ld(bf16c v) {
+        return vec2<A>{(A)__uint_as_float(v << 16), (A)__uint_as_float(v & 0xffff0000u)};
+    }
+    template <typename A>
+    static __device__ __forceinline__ bf16c st(vec2<A> v) {
+        return bf16_bits((float)v.x) | (bf16_bits((float)v.y) << 16);
+    }
+};
+
 // Launch shape of the half stencil: NR RHS per lane, LPS lanes per site, the
 // XCD-contiguous block order and the order of site blocks and RHS groups.
 struct DslashShape {
@@ -52,16 +94,17 @@ namespace dslash_impl {
 
 constexpr int kSites = 256;  // output sites per block (and per partial sum)
 
-template <typename R>
+// R: arithmetic; VS: stored complex of the vectors; LS: of the links.
+template <typename R, typename VS, typename LS>
 struct DslashArgs {
-    const vec2<R> *fat_out;  // links on output-parity sites  [4][9][Vh]
-    const vec2<R> *fat_in;   // links on input-parity sites   [4][9][Vh]
-    const vec2<R> *lng_out;
-    const vec2<R> *lng_in;
-    const vec2<R> *in;       // [nrhs][3][Vh], parity 1-p
-    vec2<R> *out;            // [nrhs][3][Vh], parity p
-    const vec2<R> *aux;      // [nrhs][3][Vh], parity p (optional)
-    const vec2<R> *aux2;     // [nrhs][3][Vh], parity p (optional; may alias out)
+    const LS *fat_out;       // links on output-parity sites  [4][9][Vh]
+    const LS *fat_in;        // links on input-parity sites   [4][9][Vh]
+    const LS *lng_out;
+    const LS *lng_in;
+    const VS *in;            // [nrhs][3][Vh], parity 1-p
+    VS *out;                 // [nrhs][3][Vh], parity p
+    const VS *aux;           // [nrhs][3][Vh], parity p (optional)
+    const VS *aux2;          // [nrhs][3][Vh], parity p (optional; may alias out)
     R ca, cb, cd;
     const double *ca_rhs;  // per-RHS ca (device, indexed by RHS), or null for ca
     const int *rhs_status; // CG state per RHS (device) or null: a block whose RHS
@@ -144,21 +187,21 @@ __device__ __forceinline__ void hop_fence(V (&acc)[NR][3]) {
 
 // roff[r]: byte offset of the lane's r-th RHS plane from the group's first
 // (clamped to its last valid RHS in a ragged group, so that no lane branches).
-template <int NR, bool NT, typename R>
-__device__ __forceinline__ void hop_forward(const vec2<R> *__restrict__ U, int vh, uint32_t uoff,
-                                            const vec2<R> *__restrict__ in, uint32_t voff,
+template <int NR, bool NT, typename R, typename VS, typename LS>
+__device__ __forceinline__ void hop_forward(const LS *__restrict__ U, int vh, uint32_t uoff,
+                                            const VS *__restrict__ in, uint32_t voff,
                                             const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
     using V = vec2<R>;
     V u[9];
-    const gptr<const V> up = at(U, uoff);
+    const gptr<const LS> up = at(U, uoff);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(up + k * kLinkTile);
+    for (int k = 0; k < 9; ++k) u[k] = Conv<LS>::template ld<R>(ldlink<NT>(up + k * kLinkTile));
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         {
-            const V v0 = *at(in, roff[r] + voff);
-            const V v1 = *at(in + vh, roff[r] + voff);
-            const V v2 = *at(in + 2 * (int64_t)vh, roff[r] + voff);
+            const V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
+            const V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
+            const V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 V s = acc[r][a];
@@ -176,21 +219,21 @@ __device__ __forceinline__ void hop_forward(const vec2<R> *__restrict__ U, int v
 }
 
 // acc -= U^H v, with U read at the neighbour's index (offset noff for both).
-template <int NR, bool NT, typename R>
-__device__ __forceinline__ void hop_backward(const vec2<R> *__restrict__ U, int vh, uint32_t uoff,
-                                             const vec2<R> *__restrict__ in, uint32_t voff,
+template <int NR, bool NT, typename R, typename VS, typename LS>
+__device__ __forceinline__ void hop_backward(const LS *__restrict__ U, int vh, uint32_t uoff,
+                                             const VS *__restrict__ in, uint32_t voff,
                                              const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
     using V = vec2<R>;
     V u[9];
-    const gptr<const V> up = at(U, uoff);
+    const gptr<const LS> up = at(U, uoff);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(up + k * kLinkTile);
+    for (int k = 0; k < 9; ++k) u[k] = Conv<LS>::template ld<R>(ldlink<NT>(up + k * kLinkTile));
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         {
-            const V v0 = *at(in, roff[r] + voff);
-            const V v1 = *at(in + vh, roff[r] + voff);
-            const V v2 = *at(in + 2 * (int64_t)vh, roff[r] + voff);
+            const V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
+            const V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
+            const V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 // (U^H)_{ab} = conj(U_{ba})
@@ -221,8 +264,9 @@ __device__ __forceinline__ double chunk_sum(const double *x) {
     return wave_sum(v);
 }
 
-template <typename R, int NR, int LPS, bool AUX, bool AUX2, bool DOT, bool NT>
-__global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
+template <typename R, typename VS, typename LS, int NR, int LPS, bool AUX, bool AUX2, bool DOT,
+          bool NT>
+__global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a) {
     using V = vec2<R>;
     constexpr int SPW = kWave / LPS;  // sites per wave
     constexpr int RG = LPS * NR;      // RHS per group
@@ -244,7 +288,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
     const int rg0 = grp * RG;                 // first RHS of the group
     const int nr = min(NR, a.nrhs - rg0 - q * NR);
     // byte offset of this lane's first RHS plane within the group
-    const uint32_t qoff = (uint32_t)(q * NR * 3) * (uint32_t)vh * (uint32_t)sizeof(V);
+    const uint32_t qoff = (uint32_t)(q * NR * 3) * (uint32_t)vh * (uint32_t)sizeof(VS);
 
     double dotv[NR];
 #pragma unroll
@@ -278,51 +322,51 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[r][c] = V{R(0), R(0)};
 
-        const V *in = a.in + (int64_t)rg0 * 3 * vh;
+        const VS *in = a.in + (int64_t)rg0 * 3 * vh;
         uint32_t roff[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            roff[r] = qoff + (uint32_t)(3 * min(r, nr - 1)) * (uint32_t)vh * (uint32_t)sizeof(V);
+            roff[r] = qoff + (uint32_t)(3 * min(r, nr - 1)) * (uint32_t)vh * (uint32_t)sizeof(VS);
         const int64_t lstride = 9 * kLinkTile * link_tiles(vh);  // one direction
-        const uint32_t own = (uint32_t)cb * (uint32_t)sizeof(V);
-        const uint32_t own_l = link_off<V>(cb);
+        const uint32_t own = (uint32_t)cb * (uint32_t)sizeof(VS);
+        const uint32_t own_l = link_off<LS>(cb);
 
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int hop = h == 0 ? 1 : 3;
-            const V *Uo = h == 0 ? a.fat_out : a.lng_out;
-            const V *Ui = h == 0 ? a.fat_in : a.lng_in;
+            const LS *Uo = h == 0 ? a.fat_out : a.lng_out;
+            const LS *Ui = h == 0 ? a.fat_in : a.lng_in;
             // mu = 0 (x)
             {
                 const int f = (rowYZT * g.X + wrap(x + hop, g.X)) >> 1;
                 const int b = (rowYZT * g.X + wrap(x - hop, g.X)) >> 1;
-                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
-                hop_forward<NR, NT, R>(Uo, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
-                hop_backward<NR, NT, R>(Ui, vh, link_off<V>(b), in, bo, roff, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
+                hop_forward<NR, NT, R>(Uo, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui, vh, link_off<LS>(b), in, bo, roff, acc);
             }
             // mu = 1 (y)
             {
                 const int f = ((((t * g.Z + z) * g.Y + wrap(y + hop, g.Y)) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + z) * g.Y + wrap(y - hop, g.Y)) * g.X) + x) >> 1;
-                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
-                hop_forward<NR, NT, R>(Uo + lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
-                hop_backward<NR, NT, R>(Ui + lstride, vh, link_off<V>(b), in, bo, roff, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
+                hop_forward<NR, NT, R>(Uo + lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui + lstride, vh, link_off<LS>(b), in, bo, roff, acc);
             }
             // mu = 2 (z)
             {
                 const int f = ((((t * g.Z + wrap(z + hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + wrap(z - hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
-                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
-                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
-                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, link_off<V>(b), in, bo, roff, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
+                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, link_off<LS>(b), in, bo, roff, acc);
             }
             // mu = 3 (t)
             {
                 const int f = ((((wrap(t + hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((wrap(t - hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
-                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(V);
-                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(V), roff, acc);
-                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<V>(b), in, bo, roff, acc);
+                const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
+                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<LS>(b), in, bo, roff, acc);
             }
         }
 
@@ -336,12 +380,12 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
                     const uint32_t off = qoff + own;
                     V o = acc[r][c] * a.cd;
                     if (AUX) {
-                        const V ax = *at(a.aux + plane, off);
+                        const V ax = Conv<VS>::template ld<R>(*at(a.aux + plane, off));
                         const R ca = a.ca_rhs ? (R)a.ca_rhs[rg0 + q * NR + r] : a.ca;
                         o.x = fma(ca, ax.x, o.x);
                         o.y = fma(ca, ax.y, o.y);
                         if (AUX2) {
-                            const V a2 = *at(a.aux2 + plane, off);
+                            const V a2 = Conv<VS>::template ld<R>(*at(a.aux2 + plane, off));
                             o.x = fma(a.cb, a2.x, o.x);
                             o.y = fma(a.cb, a2.y, o.y);
                         }
@@ -349,7 +393,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
                             dotv[r] = fma((double)ax.x, (double)o.x,
                                           fma((double)ax.y, (double)o.y, dotv[r]));
                     }
-                    *at(a.out + plane, off) = o;
+                    *at(a.out + plane, off) = Conv<VS>::template st<R>(o);
                 }
             }
         }
@@ -371,50 +415,53 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R> a) {
     }
 }
 
-template <typename R, int NR, int LPS, bool NT>
-void launch_variant(const DslashArgs<R> &args, int nblocks, bool aux, bool aux2, bool dot,
+template <typename R, typename VS, typename LS, int NR, int LPS, bool NT>
+void launch_variant(const DslashArgs<R, VS, LS> &args, int nblocks, bool aux, bool aux2, bool dot,
                     hipStream_t s) {
     const dim3 grid(nblocks), block(kSites * LPS);
     if (dot)
-        hipLaunchKernelGGL((k_dslash<R, NR, LPS, true, false, true, NT>), grid, block, 0, s, args);
-    else if (aux2)
-        hipLaunchKernelGGL((k_dslash<R, NR, LPS, true, true, false, NT>), grid, block, 0, s, args);
-    else if (aux)
-        hipLaunchKernelGGL((k_dslash<R, NR, LPS, true, false, false, NT>), grid, block, 0, s, args);
-    else
-        hipLaunchKernelGGL((k_dslash<R, NR, LPS, false, false, false, NT>), grid, block, 0, s,
+        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, true, false, true, NT>), grid, block, 0, s,
                            args);
+    else if (aux2)
+        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, true, true, false, NT>), grid, block, 0, s,
+                           args);
+    else if (aux)
+        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, true, false, false, NT>), grid, block, 0,
+                           s, args);
+    else
+        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, false, false, false, NT>), grid, block, 0,
+                           s, args);
 }
 
-template <typename R, int NR, int LPS>
-hisq_status launch_shape(const DslashArgs<R> &args, int nblocks, bool aux, bool aux2, bool dot,
-                         hipStream_t s) {
+template <typename R, typename VS, typename LS, int NR, int LPS>
+hisq_status launch_shape(const DslashArgs<R, VS, LS> &args, int nblocks, bool aux, bool aux2,
+                         bool dot, hipStream_t s) {
     if (args.ngroups == 1)
-        launch_variant<R, NR, LPS, true>(args, nblocks, aux, aux2, dot, s);
+        launch_variant<R, VS, LS, NR, LPS, true>(args, nblocks, aux, aux2, dot, s);
     else
-        launch_variant<R, NR, LPS, false>(args, nblocks, aux, aux2, dot, s);
+        launch_variant<R, VS, LS, NR, LPS, false>(args, nblocks, aux, aux2, dot, s);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
-// True if the per-lane 32-bit byte offsets of the shape fit for this volume.
+// True if the per-lane 32-bit byte offsets of the shape fit for this volume
+// (real_bytes: bytes of one stored real, 8, 4 or 2).
 inline bool shape_fits(int nr, int lps, int vh, size_t real_bytes) {
     const uint64_t span = (uint64_t)(lps * nr * 3) * (uint64_t)vh * 2 * real_bytes;
     return span < (1ull << 32);
 }
 
 // Fill the argument block and launch with the given shape.
-template <typename R>
-hisq_status launch_dslash_t(const Geom &geom, const vec2<R> *const fat[2],
-                            const vec2<R> *const lng[2], int out_parity, const vec2<R> *in,
-                            vec2<R> *out, int nrhs, const vec2<R> *aux, double ca,
-                            const vec2<R> *aux2, double cb, double cd, double *partials,
+template <typename R, typename VS = vec2<R>, typename LS = vec2<R>>
+hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *const lng[2],
+                            int out_parity, const VS *in, VS *out, int nrhs, const VS *aux,
+                            double ca, const VS *aux2, double cb, double cd, double *partials,
                             DslashShape sh, hipStream_t s, const double *ca_rhs = nullptr,
                             const int *rhs_status = nullptr) {
     if (aux2 && !aux) return fail(HISQ_ERR_INVALID_ARG, "dslash: aux2 needs aux");
-    if (!shape_fits(sh.nr, sh.lps, geom.vh, sizeof(R)))
+    if (!shape_fits(sh.nr, sh.lps, geom.vh, sizeof(VS) / 2))
         return fail(HISQ_ERR_INVALID_ARG, "dslash: RHS group too large for this volume");
-    DslashArgs<R> a{};
+    DslashArgs<R, VS, LS> a{};
     const int p = out_parity;
     a.fat_out = fat[p];
     a.fat_in = fat[1 - p];
@@ -440,8 +487,9 @@ hisq_status launch_dslash_t(const Geom &geom, const vec2<R> *const fat[2],
     const bool dot = partials != nullptr;
     const int nblocks = a.nsb * a.ngroups;
     const bool x = aux != nullptr, x2 = aux2 != nullptr;
-#define HISQ_SHAPE(NR_, LPS_) \
-    if (sh.nr == NR_ && sh.lps == LPS_) return launch_shape<R, NR_, LPS_>(a, nblocks, x, x2, dot, s)
+#define HISQ_SHAPE(NR_, LPS_)                                                            \
+    if (sh.nr == NR_ && sh.lps == LPS_)                                                  \
+    return launch_shape<R, VS, LS, NR_, LPS_>(a, nblocks, x, x2, dot, s)
     HISQ_SHAPE(1, 1);
     HISQ_SHAPE(2, 1);
     HISQ_SHAPE(3, 1);

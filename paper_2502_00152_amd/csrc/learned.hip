@@ -2,7 +2,8 @@
 // residual r0 = b - A x0 of a (deflation) initial guess to a correction of
 // x0.  An extension beyond arXiv:2502.00152, whose solver is deflated CG
 // (section 2): CG stays the solver, its true-residual stop is unchanged, and
-// hisq_nn_guess keeps a correction only where it lowers ||b - A x||.
+// hisq_nn_guess keeps a correction only where it lowers ||b - A x||; given the
+// eigenpairs, it first projects the correction off the deflation space.
 //
 //   layer(W, psi)^o = sum_{d=0..8} sum_c W[d][o][c] T_d psi^c
 //     T_0 = 1, (T_{1+mu} psi)(x) = F_mu(x) psi(x+mu),
@@ -444,6 +445,13 @@ __global__ __launch_bounds__(kBS) void k_keep_add(dvec2 *__restrict__ x, const d
         x[j * n + q] += d[j * n + q];
 }
 
+// y += x (complex double)
+__global__ __launch_bounds__(kBS) void k_axpy(dvec2 *__restrict__ y, const dvec2 *__restrict__ x,
+                                              int64_t n) {
+    for (int64_t q = (int64_t)blockIdx.x * kBS + threadIdx.x; q < n; q += (int64_t)gridDim.x * kBS)
+        y[q] += x[q];
+}
+
 int blocks_for(int64_t n, int cap) {
     const int64_t b = (n + kBS - 1) / kBS;
     return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
@@ -865,7 +873,8 @@ hisq_status hisq_nn_train(hisq_nn n, const void *r_dev, const void *e_dev, int n
 }
 
 hisq_status hisq_nn_guess(hisq_nn n, double two_m, const void *b_dev, void *x_dev, int nrhs,
-                          unsigned flags, int *kept_host, void *stream) {
+                          unsigned flags, int n_ev, const void *evecs_dev, hisq_prec evec_prec,
+                          const double *evals_host, int *kept_host, void *stream) {
     HISQ_TRY(check_nn(n));
     HISQ_TRY(check_nrhs(nrhs));
     HISQ_TRY(check_mass(two_m, true));
@@ -876,6 +885,7 @@ hisq_status hisq_nn_guess(hisq_nn n, double two_m, const void *b_dev, void *x_de
     const int64_t n3 = 3 * (int64_t)g->geom.vh;
     const size_t vb = sizeof(double2) * (size_t)n3 * nrhs;
     HISQ_TRY(check_pair_overlap(b_dev, x_dev, vb, "b and x must not overlap"));
+    if (n_ev < 0) return fail(HISQ_ERR_INVALID_ARG, "n_ev must be >= 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *p = nullptr;
     HISQ_TRY(ws_get(n, "guess_t", vb, &p));
@@ -898,6 +908,21 @@ hisq_status hisq_nn_guess(hisq_nn n, double two_m, const void *b_dev, void *x_de
     HISQ_TRY(apply_net(n, reinterpret_cast<const dvec2 *>(r), reinterpret_cast<dvec2 *>(d), nrhs,
                        flags, s));
     HISQ_TRY(apply_mdagm(g, two_m, d, t, nrhs, s));
+    if (n_ev > 0) {
+        // Galerkin correction on the deflation space: d += V L^-1 V^H (r - A d).
+        // With x deflated, V^H r = 0 and this removes V V^H d: the network
+        // must not put error back into the lowest modes, where CG is slowest.
+        void *q = nullptr;
+        HISQ_TRY(ws_get(n, "guess_c", vb, &q));
+        double2 *c = static_cast<double2 *>(q);
+        HISQ_TRY(mixed_resid(r, t, t, n3, nrhs, nullptr, r2 + nrhs, red, s));
+        HISQ_TRY(hisq_deflate(g, n_ev, evecs_dev, evec_prec, evals_host, two_m, t, c, nrhs, s));
+        hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n3 * nrhs, 4096)), dim3(kBS), 0, s,
+                           reinterpret_cast<dvec2 *>(d), reinterpret_cast<const dvec2 *>(c),
+                           n3 * nrhs);
+        HISQ_HIP(hipGetLastError());
+        HISQ_TRY(apply_mdagm(g, two_m, d, t, nrhs, s));
+    }
     HISQ_TRY(mixed_resid(r, t, t, n3, nrhs, nullptr, r2 + nrhs, red, s));
     hipLaunchKernelGGL(k_keep_add, dim3(blocks_for(n3, 2048), nrhs), dim3(kBS), 0, s,
                        reinterpret_cast<dvec2 *>(x), reinterpret_cast<const dvec2 *>(d), r2, r2 + nrhs,

@@ -166,7 +166,8 @@ def lib():
         "hisq_nn_loss_grad": ([P, P, P, I, U, ctypes.POINTER(D), ctypes.POINTER(D), P], I),
         "hisq_nn_adam_step": ([P, D, D, D, D, P], I),
         "hisq_nn_train": ([P, P, P, I, I, I, D, U, ctypes.POINTER(D), P], I),
-        "hisq_nn_guess": ([P, D, P, P, I, U, ctypes.POINTER(I), P], I),
+        "hisq_nn_guess": ([P, D, P, P, I, U, I, P, I, ctypes.POINTER(D), ctypes.POINTER(I), P],
+                          I),
         "hisq_profile_enable": ([I], I),
         "hisq_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(D)], I),
@@ -660,14 +661,28 @@ def hisq_nn_train(n, r, e, batch, steps, lr, flags=HISQ_NN_NORMALIZE, stream=Non
     return losses[:int(steps)]
 
 
-def hisq_nn_guess(n, two_m, b, x, flags=HISQ_NN_NORMALIZE, stream=None):
-    """x += N(b - A x) per RHS where that lowers the residual; returns the kept flags."""
+def hisq_nn_guess(n, two_m, b, x, flags=HISQ_NN_NORMALIZE, evecs=None, evals=None,
+                  stream=None):
+    """x += N(b - A x) per RHS where that lowers the residual, projected off the
+    deflation space first when evecs (complex128/complex64) and evals (eps_i)
+    are given; returns the kept flags."""
     S = _samples(n, b, "b")
     if tuple(x.shape) != tuple(b.shape):
         raise ValueError("x must have the shape of b")
     kept = (ctypes.c_int * S)()
+    n_ev, ev_ptr, prec, ev_host = 0, None, HISQ_FP64, None
+    if evecs is not None:
+        n_ev = int(evecs.shape[0])
+        ev_ptr = _ptr(evecs, "evecs", ("complex128", "complex64"))
+        prec = _prec_of(evecs, "evecs")
+        ev_host = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+        if ev_host.shape != (n_ev,):
+            raise ValueError("evals must have one entry per eigenvector")
     _check(lib().hisq_nn_guess(_nn(n), _scalar_mass(two_m), _ptr(b, "b"), _ptr(x, "x"), S,
-                               int(flags), kept, _stream(stream)), "hisq_nn_guess")
+                               int(flags), n_ev, ev_ptr, prec,
+                               None if ev_host is None
+                               else ev_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               kept, _stream(stream)), "hisq_nn_guess")
     return [int(k) for k in kept]
 
 

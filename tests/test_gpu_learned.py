@@ -203,6 +203,50 @@ def test_guess_keeps_only_improving_corrections(lat):
         assert np.array_equal(host(x), x0)
 
 
+def test_guess_projects_off_the_deflation_space():
+    """With eigenpairs, x_new = x + d + V L^-1 V^H (r - A d), d = N(r): the
+    composition written out with the oracle's network, A and Eq. (4); and the
+    new residual has no component on the deflation space (Galerkin)."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = Problem(RAGGED, 0.5, 5101, 5102)
+    g = pr.gauge()
+    dims, two_m, k = pr.dims, 0.05, 12
+    mask = O.even_mask(dims)
+    lam, Vc = O.lowest_eigenpairs(pr.F, pr.L, two_m, k, method="dense")
+    evecs = np.concatenate([to_parity(O.from_compact(Vc[:, i], dims), dims, 0) for i in range(k)])
+    eps = lam - two_m ** 2
+    b_full = even_sources(dims, [91, 92])
+    x0_full = np.stack([O.from_compact(O.deflation_guess(Vc, lam, O.to_compact(b, dims)), dims)
+                        for b in b_full])
+    th = params(17)
+    try:
+        for ev in (dev(evecs), dev(evecs.astype(np.complex64))):
+            with hisq.Network(g, th) as net:
+                x = dev(to_parity(x0_full, dims, 0))
+                kept = hisq.hisq_nn_guess(net, two_m, dev(to_parity(b_full, dims, 0)), x,
+                                          evecs=ev, evals=eps)
+                got = host(x)
+            for j in range(2):
+                r = b_full[j] - O.apply_A(pr.F, pr.L, two_m, x0_full[j])
+                s = np.linalg.norm(r)
+                d = N.apply(np.float64(th), pr.F, r / s, mask) * s
+                r1 = r - O.apply_A(pr.F, pr.L, two_m, d)
+                c = O.from_compact(O.deflation_guess(Vc, lam, O.to_compact(r1, dims)), dims)
+                x_ref = x0_full[j] + d + c
+                r_new = b_full[j] - O.apply_A(pr.F, pr.L, two_m, x_ref)
+                assert np.linalg.norm(Vc.conj().T @ O.to_compact(r_new, dims)) \
+                    <= 1e-10 * np.linalg.norm(r)
+                want = int(np.linalg.norm(r_new) < np.linalg.norm(r))
+                assert kept[j] == want
+                ref = to_parity(x_ref if want else x0_full[j], dims, 0)[0]
+                # FP32 network and (second pass) FP32 eigenvectors: relative to |d|
+                err = np.linalg.norm(got[j] - ref) / np.linalg.norm(to_parity(d, dims, 0))
+                assert err < (1e-5 if ev.dtype == torch.complex128 else 1e-4)
+    finally:
+        g.close()
+
+
 def _full(x_even, dims):
     from tests.gpu_util import from_parity
     return from_parity(x_even, dims, 0)
@@ -235,3 +279,67 @@ def test_argument_errors(lat):
             hisq.hisq_nn_set_params(net, bad)
         assert L.hisq_nn_apply(net.handle, r.data_ptr(), e.data_ptr(), 0, 0, None) == \
             hisq.HISQ_ERR_INVALID_ARG
+
+
+def test_forward_48x48x48x96_sampled_sites():
+    """The network at the size of one GPU's share of a large-lattice solve
+    (48^3 x 96), in the launch configuration of inference, on sampled output
+    sites.  N(r) at x depends on r and the links within three hops of x, so
+    the oracle evaluates it on an 8^4 periodic window whose centre is x (index
+    4 in each direction): wrapping corrupts one more layer of window sites per
+    network layer, which after three layers leaves indices 3 and 4 exact.
+    Centres have even coordinates (the window's staggered phases then equal
+    the lattice's) and 4 <= t <= T - 4 (no antiperiodic time boundary inside
+    the window), so folding the window's raw links reproduces the lattice's
+    folded links there."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (48, 48, 48, 96)
+    X, Y, Z, T = dims
+    print(f"[48^3x96] drawing links", flush=True)
+    W = I.random_su3_field_device(dims, 0.5, 48001)
+    Nl = I.random_su3_field_device(dims, 0.5, 48002)
+    g = hisq.Gauge(dims, W, Nl, I.C_FAT, I.C_LONG, 3)
+    try:
+        vh = g.vh
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(48003)
+        r = torch.randn((1, 3, vh), dtype=torch.complex128, device="cuda", generator=gen)
+        out = torch.zeros_like(r)
+        th = params(18)
+        with hisq.Network(g, th) as net:
+            hisq.hisq_nn_apply(net, r, out, 0)
+        torch.cuda.synchronize()
+        print(f"[48^3x96] network applied", flush=True)
+        rng = np.random.default_rng(48004)
+        wdims = (8, 8, 8, 8)
+        wmask = O.even_mask(wdims)
+        off = np.arange(-4, 4)
+        for _ in range(6):
+            xc = [2 * int(rng.integers(0, L // 2)) for L in (X, Y, Z)]
+            tc = 2 * int(rng.integers(2, T // 2 - 1))          # 4 <= tc <= T - 4
+            cx = (xc[0] + off) % X
+            cy = (xc[1] + off) % Y
+            cz = (xc[2] + off) % Z
+            ct = tc + off
+            it, iz, iy, ix = np.meshgrid(ct, cz, cy, cx, indexing="ij")
+            lex = ((it * Z + iz) * Y + iy) * X + ix              # [8][8][8][8]
+            par = (ix + iy + iz + it) % 2
+            li = torch.from_numpy(lex.reshape(-1)).cuda()
+            Wwin = W.reshape(4, -1, 3, 3)[:, li].reshape(4, 8, 8, 8, 8, 3, 3).cpu().numpy()
+            Nwin = Nl.reshape(4, -1, 3, 3)[:, li].reshape(4, 8, 8, 8, 8, 3, 3).cpu().numpy()
+            Fw, _ = O.fold_links(Wwin, Nwin, I.C_FAT, I.C_LONG)
+            cb = torch.from_numpy((lex.reshape(-1) >> 1)).cuda()
+            rw = r[0][:, cb].T.reshape(8, 8, 8, 8, 3).cpu().numpy()
+            rw = rw * (par == 0)[..., None]
+            ref = N.apply(np.float64(th), Fw, rw, wmask)
+            got = out[0][:, int(lex[4, 4, 4, 4]) >> 1].cpu().numpy()
+            want = ref[4, 4, 4, 4]
+            # scale: the typical output vector in the window's exact core
+            scale = np.sqrt(np.mean(np.sum(np.abs(ref[3:5, 3:5, 3:5, 3:5]) ** 2, axis=-1)))
+            assert np.linalg.norm(got - want) <= 1e-5 * max(np.linalg.norm(want), scale), \
+                (xc, tc, got, want)
+    finally:
+        g.close()
+        del W, Nl
+        torch.cuda.empty_cache()
