@@ -129,7 +129,7 @@ def pmc_probe(cfg):
 
 def dslash_scan(dims=(32, 32, 32, 64), reps=20):
     """Half-stencil GB/s at a lattice whose working set exceeds the LLC, one
-    RHS, FP64 and FP32."""
+    RHS, FP64, FP32 and BF16 storage."""
     import torch
     from paper_2502_00152_amd import hisq, inputs as I
     W = I.random_su3_field_device(dims, 0.5, 20001)
@@ -138,8 +138,10 @@ def dslash_scan(dims=(32, 32, 32, 64), reps=20):
     del W, N
     torch.cuda.empty_cache()
     out = {"lattice": "x".join(map(str, dims)), "nrhs": 1}
-    for name, dt, rb in (("f64", torch.complex128, 8), ("f32", torch.complex64, 4)):
-        a = torch.randn((1, 3, g.vh), dtype=dt, device="cuda")
+    for name, dt, rb in (("f64", torch.complex128, 8), ("f32", torch.complex64, 4),
+                         ("bf16", torch.bfloat16, 2)):
+        shape = (1, 3, g.vh, 2) if dt == torch.bfloat16 else (1, 3, g.vh)
+        a = torch.randn(shape, dtype=dt, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
             hisq.hisq_dslash_eo(g, 0, a, b)
@@ -414,7 +416,8 @@ def main():
     scan = None if args.no_dslash_scan else dslash_scan()
     if scan:
         print(f"[bench] dslash 32^3x64: {scan['f64']['GB_s']:.0f} GB/s (f64), "
-              f"{scan['f32']['GB_s']:.0f} GB/s (f32)", flush=True)
+              f"{scan['f32']['GB_s']:.0f} GB/s (f32), {scan['bf16']['GB_s']:.0f} GB/s (bf16)",
+              flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

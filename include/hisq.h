@@ -123,8 +123,11 @@ hisq_status hisq_spinor_merge(hisq_gauge g, const void *even_dev, const void *od
 /*
  * Change the precision of n_complex complex numbers (any vectors, e.g. the
  * eigenvectors stored in single precision for multi-deflation, section 3):
- * HISQ_FP64 -> HISQ_FP32 rounds to nearest even, HISQ_FP32 -> HISQ_FP64 is
- * exact, equal precisions copy.  src and dst must not overlap.  Asynchronous
+ * a narrowing conversion (HISQ_FP64 -> HISQ_FP32 or HISQ_BF16, HISQ_FP32 ->
+ * HISQ_BF16) rounds to nearest even (FP64 -> BF16 in one rounding), a
+ * widening one is exact, equal precisions copy.  HISQ_BF16 vectors hold a
+ * complex number as two bfloat16 (real part first, 4 bytes).  src and dst
+ * must not overlap.  Asynchronous
  * on `stream`.  INVALID_ARG for NULL or overlapping buffers, n_complex < 0 or
  * an unsupported precision.
  */
@@ -140,7 +143,9 @@ hisq_status hisq_convert_vectors(const void *src_dev, hisq_prec src_prec, void *
  * Section 2 (the HISQ matrix D; even-odd split).  prec: HISQ_FP64 (vectors
  * of complex double) or HISQ_FP32 (vectors of complex float, same layout,
  * 8 bytes per complex; FP32 links and FP32 arithmetic, the FP32 links made
- * from the FP64 ones on first use).  HISQ_BF16 returns UNSUPPORTED.
+ * from the FP64 ones on first use) or HISQ_BF16 (vectors of bfloat16 pairs,
+ * 4 bytes per complex; BF16 links, FP32 arithmetic, each output rounded to
+ * nearest even once; the BF16 links made from the FP64 ones on first use).
  */
 hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
                            void *out_dev, int nrhs, hisq_prec prec, void *stream);
@@ -180,11 +185,13 @@ typedef struct hisq_cg_params {
                               (0 = default 16).  It does not change the iterates of the
                               FP64 solve. */
     hisq_prec sloppy_prec; /* HISQ_FP64: plain FP64 CG.  HISQ_FP32: mixed precision,
-                              the iteration in FP32 with FP64 reliable updates */
-    int reliable_interval; /* FP32 only: also a reliable update after this many
+                              the iteration in FP32 with FP64 reliable updates.
+                              HISQ_BF16: the same with the sloppy operator reading
+                              BF16 links (vectors still FP32) */
+    int reliable_interval; /* mixed only: also a reliable update after this many
                               iterations since the last one (0 = only the delta
                               trigger, as in the paper) */
-    double reliable_delta; /* FP32 only: reliable update when the iterated residual
+    double reliable_delta; /* mixed only: reliable update when the iterated residual
                               falls below reliable_delta times the true residual of
                               the last update (0 = default 0.1, the paper's delta_rd) */
     /* multi-deflation (section 3): re-deflate the residual during the solve */
@@ -229,7 +236,7 @@ typedef struct hisq_cg_stats {
  * recomputed true residual confirms it; if the true residual does not, CG
  * continues from it with the search direction kept.  b = 0 gives x = 0.
  *   stats_host: array of nrhs structs, filled on return (may be NULL).
- * With sloppy_prec = HISQ_FP32 (section 2: the conventional solve is
+ * With sloppy_prec = HISQ_FP32 or HISQ_BF16 (section 2: the conventional solve is
  * mixed-precision CG; reliable updates as in section 3) the recurrence runs
  * on FP32 vectors with the FP32 operator and FP64-accumulated dot products;
  * the solution accumulates in FP64, and a reliable update (x += x_sloppy,

@@ -29,8 +29,7 @@ hisq_status check_nrhs(int nrhs) {
 }
 
 hisq_status check_prec(hisq_prec p) {
-    if (p == HISQ_FP64 || p == HISQ_FP32) return HISQ_OK;
-    if (p == HISQ_BF16) return fail(HISQ_ERR_UNSUPPORTED, "BF16 is not implemented for this call");
+    if (p == HISQ_FP64 || p == HISQ_FP32 || p == HISQ_BF16) return HISQ_OK;
     return fail(HISQ_ERR_INVALID_ARG, "unknown precision");
 }
 
@@ -116,6 +115,8 @@ hisq_status hisq_gauge_destroy(hisq_gauge g) {
         if (g->lng[p]) (void)hipFree(g->lng[p]);
         if (g->fat32[p]) (void)hipFree(g->fat32[p]);
         if (g->lng32[p]) (void)hipFree(g->lng32[p]);
+        if (g->fat16[p]) (void)hipFree(g->fat16[p]);
+        if (g->lng16[p]) (void)hipFree(g->lng16[p]);
     }
     g->ws.release();
     if (g->cg_stream) (void)hipStreamDestroy(g->cg_stream);
@@ -155,10 +156,13 @@ hisq_status hisq_convert_vectors(const void *src_dev, hisq_prec src_prec, void *
     HISQ_TRY(check_vec(dst_dev, "dst_dev"));
     if (n_complex < 0) return fail(HISQ_ERR_INVALID_ARG, "n_complex must be >= 0");
     auto bytes = [](hisq_prec p) -> size_t {
-        return p == HISQ_FP64 ? sizeof(double2) : p == HISQ_FP32 ? sizeof(float2) : 0;
+        return p == HISQ_FP64 ? sizeof(double2)
+             : p == HISQ_FP32 ? sizeof(float2)
+             : p == HISQ_BF16 ? sizeof(uint32_t) : 0;
     };
     const size_t sb = bytes(src_prec), db = bytes(dst_prec);
-    if (!sb || !db) return fail(HISQ_ERR_INVALID_ARG, "precision must be HISQ_FP64 or HISQ_FP32");
+    if (!sb || !db)
+        return fail(HISQ_ERR_INVALID_ARG, "precision must be HISQ_FP64, HISQ_FP32 or HISQ_BF16");
     const char *s0 = static_cast<const char *>(src_dev);
     const char *d0 = static_cast<const char *>(dst_dev);
     if (n_complex > 0 && s0 < d0 + db * n_complex && d0 < s0 + sb * n_complex)
@@ -181,6 +185,10 @@ hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev, voi
         return launch_dslash_f32(g, out_parity, static_cast<const float2 *>(in_dev),
                                  static_cast<float2 *>(out_dev), nrhs, nullptr, 0.0, nullptr, 0.0,
                                  1.0, nullptr, static_cast<hipStream_t>(stream));
+    if (prec == HISQ_BF16)
+        return launch_dslash_bf16(g, out_parity, static_cast<const uint32_t *>(in_dev),
+                                  static_cast<uint32_t *>(out_dev), nrhs, nullptr, 0.0, nullptr,
+                                  0.0, 1.0, static_cast<hipStream_t>(stream));
     return launch_dslash(g, out_parity, static_cast<const double2 *>(in_dev),
                          static_cast<double2 *>(out_dev), nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
                          nullptr, nullptr, static_cast<hipStream_t>(stream));
@@ -199,6 +207,10 @@ hisq_status hisq_mdagm(hisq_gauge g, double two_m, const void *in_e_dev, void *o
         return apply_mdagm_f32(g, two_m, static_cast<const float2 *>(in_e_dev),
                                static_cast<float2 *>(out_e_dev), nrhs, nullptr,
                                static_cast<hipStream_t>(stream));
+    if (prec == HISQ_BF16)
+        return apply_mdagm_bf16(g, two_m, static_cast<const uint32_t *>(in_e_dev),
+                                static_cast<uint32_t *>(out_e_dev), nrhs,
+                                static_cast<hipStream_t>(stream));
     return apply_mdagm(g, two_m, static_cast<const double2 *>(in_e_dev),
                        static_cast<double2 *>(out_e_dev), nrhs, static_cast<hipStream_t>(stream));
 }

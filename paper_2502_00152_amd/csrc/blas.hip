@@ -167,7 +167,10 @@ __global__ __launch_bounds__(kBS) void k_cg_finalize(int nrhs, const double *__r
     cg.iters[q] += 1;
     if (!isfinite(rn)) {
         cg.status[q] = CG_NAN;
-    } else if (rn <= cg.tol2b[q]) {
+    } else if (rn <= cg.tol2b[q] ||
+               (cg.ru_freeze && cg.delta2 > 0.0 && rn <= cg.delta2 * cg.rho_ru[q])) {
+        // converged in the recurrence, or (ru_freeze) due for a reliable
+        // update: the RHS waits for the host's FP64 true residual
         cg.rho_pend[q] = rn;
         cg.status[q] = CG_PENDING;
     } else {

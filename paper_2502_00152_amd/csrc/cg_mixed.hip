@@ -4,8 +4,9 @@
 // single-precision eigenvectors whenever the residual has fallen by 1/delta_tr
 // since the last deflation).
 //
-// The recurrence runs on FP32 vectors with the FP32 operator; its dot products
-// and all scalars are FP64.  The solution accumulates in FP64: the FP32
+// The recurrence runs on FP32 vectors with the FP32 operator (links in FP32,
+// or in BF16 at sloppy_prec = HISQ_BF16); its dot products and all scalars
+// are FP64.  The solution accumulates in FP64: the FP32
 // correction x_s is added to x at every reliable update, where the residual is
 // recomputed in FP64 with the FP64 operator, r = b - A x, and replaces the
 // iterated one.  A right-hand side gets a reliable update
@@ -43,7 +44,7 @@ T *carve(char *&p, size_t count) {
 
 hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s,
-                        const double *m2_rhs) {
+                        const double *m2_rhs, bool bf16_links) {
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = P->check_interval > 0 ? P->check_interval : 16;
     const int par = P->parity;
@@ -73,8 +74,9 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
         }
     }
 
-    // the FP32 links are made here, not inside a captured iteration chunk
-    HISQ_TRY(ensure_links_f32(g, s));
+    // the sloppy links are made here, not inside a captured iteration chunk
+    if (bf16_links) HISQ_TRY(ensure_links_bf16(g, s));
+    else HISQ_TRY(ensure_links_f32(g, s));
 
     // ------------------------------------------------------------ buffers
     const size_t v64 = sizeof(double2) * (size_t)n * nrhs, v32 = sizeof(float2) * (size_t)n * nrhs;
@@ -121,6 +123,11 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     int *d_skip = carve<int>(cp, nrhs);
     int *d_mode = carve<int>(cp, nrhs);
     dev.delta2 = delta * delta;
+    // With BF16 links the sloppy operator is accurate to ~1e-3 only: a
+    // recurrence run on past the delta trigger (until the next poll) can make
+    // the FP64 correction diverge on ill-conditioned systems, so the RHS stops
+    // at the trigger, as in the paper's reliable update.  FP32 goes on.
+    dev.ru_freeze = bf16_links ? 1 : 0;
     dev.max_iter = P->max_iter;
 
     const int nb_pap = dslash_reduce_blocks(g, nrhs);
@@ -201,10 +208,17 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     const double m2 = two_m * two_m;
 
     auto iterate = [&]() -> hisq_status {
-        HISQ_TRY(launch_dslash_f32(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, nullptr,
-                                   s, nullptr, dev.status));
-        HISQ_TRY(launch_dslash_f32(g, par, t32, Aps, nrhs, ps, m2, nullptr, 0.0, -1.0, pap.partials,
-                                   s, m2_rhs, dev.status));
+        if (bf16_links) {
+            HISQ_TRY(launch_dslash_f32_bl(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, 1.0, nullptr, s,
+                                          nullptr, dev.status));
+            HISQ_TRY(launch_dslash_f32_bl(g, par, t32, Aps, nrhs, ps, m2, -1.0, pap.partials, s,
+                                          m2_rhs, dev.status));
+        } else {
+            HISQ_TRY(launch_dslash_f32(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0,
+                                       nullptr, s, nullptr, dev.status));
+            HISQ_TRY(launch_dslash_f32(g, par, t32, Aps, nrhs, ps, m2, nullptr, 0.0, -1.0,
+                                       pap.partials, s, m2_rhs, dev.status));
+        }
         HISQ_TRY(cg_update_r(n, nrhs, rs, Aps, pap.partials, nb_pap, dev, red, s));
         HISQ_TRY(cg_finalize(n, nrhs, pap.partials, nb_pap, dev, red, s));
         HISQ_TRY(cg_update_xp(n, nrhs, xs, rs, ps, dev, s));

@@ -54,7 +54,7 @@ int nr_for(int nrhs, int lps) {
 // still fits the caches: small volumes favour small groups (occupancy), large
 // volumes with many RHS one wide group with several lanes per site.
 DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes) {
-    const bool f32 = real_bytes == 4, small = vh <= (1 << 18);
+    const bool f32 = real_bytes <= 4, small = vh <= (1 << 18);  // FP32 and BF16
     DslashShape sh{};
     int xcd = 1;
     if (nrhs <= 2) {

@@ -86,6 +86,8 @@ struct hisq_gauge_s {
     double2 *lng[2] = {nullptr, nullptr};
     float2 *fat32[2] = {nullptr, nullptr};  // FP32 copies, made on first sloppy use
     float2 *lng32[2] = {nullptr, nullptr};
+    uint32_t *fat16[2] = {nullptr, nullptr}; // BF16 copies (two bfloat16 per complex),
+    uint32_t *lng16[2] = {nullptr, nullptr}; //   made on first BF16 use
     hipStream_t cg_stream = nullptr;        // the solvers' own stream (capturable)
     hisq::Workspace ws;
 };
@@ -134,6 +136,9 @@ struct CgDev {
     double *rho_ru;    // mixed precision: true ||r||^2 at the last reliable update
     int *ru_flag;      // mixed precision: set when a reliable update is due
     double delta2;     // mixed precision: reliable_delta^2 (0: no delta trigger)
+    int ru_freeze;     // mixed precision: 1 = a delta trigger stops the RHS's
+                       // recurrence until the reliable update (0: it goes on
+                       // until the host's next poll)
     int max_iter;
 };
 
@@ -224,6 +229,23 @@ hisq_status launch_dslash_f32(hisq_gauge_s *g, int out_parity, const float2 *in,
 hisq_status apply_mdagm_f32(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,
                             double *partials, hipStream_t s);
 
+// BF16 storage (uint32_t = two bfloat16: real part low, imaginary part high).
+hisq_status ensure_links_bf16(hisq_gauge_s *g, hipStream_t s);
+// FP64 -> BF16, rounded to nearest even (n complex numbers)
+hisq_status convert_double_to_bf16(const double2 *src, uint32_t *dst, int64_t n, hipStream_t s);
+// half stencil with BF16 vectors and links (FP32 arithmetic)
+hisq_status launch_dslash_bf16(hisq_gauge_s *g, int out_parity, const uint32_t *in, uint32_t *out,
+                               int nrhs, const uint32_t *aux, double ca, const uint32_t *aux2,
+                               double cb, double cd, hipStream_t s);
+hisq_status apply_mdagm_bf16(hisq_gauge_s *g, double two_m, const uint32_t *in, uint32_t *out,
+                             int nrhs, hipStream_t s);
+// half stencil with FP32 vectors and BF16 links: the sloppy operator at
+// sloppy_prec = HISQ_BF16 (arguments as launch_dslash_f32, without aux2)
+hisq_status launch_dslash_f32_bl(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
+                                 int nrhs, const float2 *aux, double ca, double cd,
+                                 double *partials, hipStream_t s, const double *ca_rhs = nullptr,
+                                 const int *rhs_status = nullptr);
+
 // The CG drivers run on the handle's own non-blocking stream (created on first
 // use, default priority), ordered after the caller's stream on entry and
 // before it on exit.  Chunks of iterations can then be captured into a HIP
@@ -284,7 +306,7 @@ hisq_status convert_vectors(const void *src, hisq_prec sp, void *dst, hisq_prec 
                             hipStream_t s);
 hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s,
-                        const double *m2_rhs = nullptr);
+                        const double *m2_rhs = nullptr, bool bf16_links = false);
 
 // Operators built from dslash.
 // out = ((2m)^2 - D_{p,1-p} D_{1-p,p}) in on parity p (p = 0: the even operator A);

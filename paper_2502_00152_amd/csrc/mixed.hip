@@ -95,6 +95,29 @@ __global__ __launch_bounds__(kBS) void k_convert(const S *__restrict__ src, D *_
     }
 }
 
+// bfloat16 pairs (real part in the low half) <-> float or double
+__global__ __launch_bounds__(kBS) void k_bf16_to(const uint32_t *__restrict__ src, fvec2 *__restrict__ f,
+                                                 dvec2 *__restrict__ d, int64_t n) {
+    GRID_STRIDE(i) {
+        const uint32_t u = src[i];
+        const float re = __uint_as_float(u << 16), im = __uint_as_float(u & 0xffff0000u);
+        if (f) f[i] = fvec2{re, im};
+        else d[i] = dvec2{(double)re, (double)im};
+    }
+}
+
+// float -> bfloat16, round to nearest even
+__global__ __launch_bounds__(kBS) void k_f32_to_bf16(const fvec2 *__restrict__ src,
+                                                     uint32_t *__restrict__ dst, int64_t n) {
+    GRID_STRIDE(i) {
+        const fvec2 v = src[i];
+        uint32_t a = __float_as_uint(v.x), b = __float_as_uint(v.y);
+        a = (a + 0x7fffu + ((a >> 16) & 1u)) >> 16;
+        b = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+        dst[i] = a | (b << 16);
+    }
+}
+
 // p = r + beta p (mode 1) or p = r (mode 2), per RHS
 __global__ __launch_bounds__(kBS) void k_p_restart(fvec2 *__restrict__ p, const fvec2 *__restrict__ r,
                                                    int64_t n, const double *__restrict__ beta,
@@ -141,6 +164,26 @@ hisq_status convert_vectors(const void *src, hisq_prec sp, void *dst, hisq_prec 
                             hipStream_t s) {
     if (n == 0) return HISQ_OK;
     const int nb = (int)std::min<int64_t>((n + kBS - 1) / kBS, 16384);
+    if (sp == HISQ_BF16 && dp != HISQ_BF16) {
+        hipLaunchKernelGGL(k_bf16_to, dim3(nb), dim3(kBS), 0, s, static_cast<const uint32_t *>(src),
+                           dp == HISQ_FP32 ? static_cast<fvec2 *>(dst) : nullptr,
+                           dp == HISQ_FP64 ? static_cast<dvec2 *>(dst) : nullptr, n);
+        HISQ_HIP(hipGetLastError());
+        return HISQ_OK;
+    }
+    if (dp == HISQ_BF16 && sp == HISQ_FP64)
+        return convert_double_to_bf16(static_cast<const double2 *>(src),
+                                      static_cast<uint32_t *>(dst), n, s);
+    if (dp == HISQ_BF16 && sp == HISQ_FP32) {
+        hipLaunchKernelGGL(k_f32_to_bf16, dim3(nb), dim3(kBS), 0, s,
+                           static_cast<const fvec2 *>(src), static_cast<uint32_t *>(dst), n);
+        HISQ_HIP(hipGetLastError());
+        return HISQ_OK;
+    }
+    if (sp == HISQ_BF16 && dp == HISQ_BF16) {
+        HISQ_HIP(hipMemcpyAsync(dst, src, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        return HISQ_OK;
+    }
     if (sp == HISQ_FP64 && dp == HISQ_FP32)
         hipLaunchKernelGGL((k_convert<dvec2, fvec2>), dim3(nb), dim3(kBS), 0, s,
                            static_cast<const dvec2 *>(src), static_cast<fvec2 *>(dst), n);

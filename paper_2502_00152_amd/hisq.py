@@ -10,6 +10,7 @@ Layouts (see include/hisq.h):
     full vectors   complex128 [nrhs, T, Z, Y, X, 3]
     parity vectors complex128 [nrhs, 3, Vh]          (Vh = X*Y*Z*T/2)
                    complex64 for the FP32 stencil and FP32 eigenvectors
+                   bfloat16 [nrhs, 3, Vh, 2] (real, imaginary) for BF16 storage
 """
 from __future__ import annotations
 
@@ -197,15 +198,24 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-_PREC_OF_DTYPE = {"complex128": HISQ_FP64, "complex64": HISQ_FP32}
+_PREC_OF_DTYPE = {"complex128": HISQ_FP64, "complex64": HISQ_FP32, "bfloat16": HISQ_BF16}
+_VEC_DTYPES = ("complex128", "complex64", "bfloat16")
 
 
 def _prec_of(t, name):
-    """HISQ_FP64 for complex128 tensors, HISQ_FP32 for complex64."""
+    """HISQ_FP64 for complex128 tensors, HISQ_FP32 for complex64, HISQ_BF16 for
+    bfloat16 tensors with a trailing (real, imaginary) axis of 2."""
     dt = str(t.dtype).replace("torch.", "")
     if dt not in _PREC_OF_DTYPE:
-        raise TypeError(f"{name} must be complex128 or complex64, got {t.dtype}")
+        raise TypeError(f"{name} must be complex128, complex64 or bfloat16, got {t.dtype}")
+    if dt == "bfloat16" and (t.dim() < 1 or t.shape[-1] != 2):
+        raise ValueError(f"{name}: a bfloat16 vector needs a trailing axis of 2 (re, im)")
     return _PREC_OF_DTYPE[dt]
+
+
+def _complex_view_shape(t):
+    """Shape of t as complex numbers (drops the (re, im) axis of bfloat16)."""
+    return tuple(t.shape[:-1]) if str(t.dtype) == "torch.bfloat16" else tuple(t.shape)
 
 
 def _ptr(t, name, dtype_ok=("complex128",)):
@@ -299,10 +309,17 @@ def hisq_spinor_merge(g, even, odd, full, stream=None):
            "hisq_spinor_merge")
 
 
+def _nrhs_any(t, vh, name):
+    shp = _complex_view_shape(t)
+    if len(shp) != 3 or shp[1] != 3 or shp[2] != vh:
+        raise ValueError(f"{name} must hold [nrhs, 3, {vh}] complex numbers, got {tuple(t.shape)}")
+    return int(shp[0])
+
+
 def _vec_pair(g, inp, out, prec):
     """nrhs and precision of an (in, out) pair; prec defaults to the tensors' dtype."""
-    nrhs = _nrhs(inp, g.vh, "in")
-    if _nrhs(out, g.vh, "out") != nrhs:
+    nrhs = _nrhs_any(inp, g.vh, "in")
+    if _nrhs_any(out, g.vh, "out") != nrhs:
         raise ValueError("in and out must have the same nrhs")
     if inp.dtype != out.dtype:
         raise TypeError("in and out must have the same dtype")
@@ -312,16 +329,16 @@ def _vec_pair(g, inp, out, prec):
 
 def hisq_dslash_eo(g, out_parity, inp, out, prec=None, stream=None):
     nrhs, prec = _vec_pair(g, inp, out, prec)
-    ok = ("complex128", "complex64")
-    _check(lib().hisq_dslash_eo(_h(g), int(out_parity), _ptr(inp, "in", ok), _ptr(out, "out", ok),
-                                nrhs, prec, _stream(stream)), "hisq_dslash_eo")
+    _check(lib().hisq_dslash_eo(_h(g), int(out_parity), _ptr(inp, "in", _VEC_DTYPES),
+                                _ptr(out, "out", _VEC_DTYPES), nrhs, prec, _stream(stream)),
+           "hisq_dslash_eo")
 
 
 def hisq_mdagm(g, two_m, inp, out, prec=None, stream=None):
     nrhs, prec = _vec_pair(g, inp, out, prec)
-    ok = ("complex128", "complex64")
-    _check(lib().hisq_mdagm(_h(g), float(two_m), _ptr(inp, "in", ok), _ptr(out, "out", ok), nrhs,
-                            prec, _stream(stream)), "hisq_mdagm")
+    _check(lib().hisq_mdagm(_h(g), float(two_m), _ptr(inp, "in", _VEC_DTYPES),
+                            _ptr(out, "out", _VEC_DTYPES), nrhs, prec, _stream(stream)),
+           "hisq_mdagm")
 
 
 def hisq_prepare_source(g, two_m, eta_e, eta_o, y_e, stream=None):
@@ -488,13 +505,15 @@ def hisq_cg_solve_multi(systems, tol=1e-10, max_iter=100000, sloppy_prec=HISQ_FP
 
 
 def hisq_convert_vectors(src, dst, stream=None):
-    """dst = src in dst's precision (complex128 <-> complex64, same shape)."""
-    if tuple(src.shape) != tuple(dst.shape):
-        raise ValueError("src and dst must have the same shape")
-    ok = ("complex128", "complex64")
-    _check(lib().hisq_convert_vectors(_ptr(src, "src", ok), _prec_of(src, "src"),
-                                      _ptr(dst, "dst", ok), _prec_of(dst, "dst"),
-                                      int(src.numel()), _stream(stream)), "hisq_convert_vectors")
+    """dst = src in dst's precision (complex128, complex64 or bfloat16 pairs; the
+    same number of complex entries), rounded to nearest even."""
+    ps, pd = _prec_of(src, "src"), _prec_of(dst, "dst")
+    n = int(np.prod(_complex_view_shape(src)))
+    if _complex_view_shape(src) != _complex_view_shape(dst):
+        raise ValueError("src and dst must hold the same shape of complex numbers")
+    _check(lib().hisq_convert_vectors(_ptr(src, "src", _VEC_DTYPES), ps,
+                                      _ptr(dst, "dst", _VEC_DTYPES), pd, n, _stream(stream)),
+           "hisq_convert_vectors")
 
 
 def hisq_deflate(g, evecs, evals, two_m, b, x0, stream=None):
