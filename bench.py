@@ -49,22 +49,24 @@ LEARNED_PAIRS = 128   # training pairs the solver generates for the learned gues
 LEARNED_STEPS = 400   # Adam steps, mini-batches of 8
 
 
-def dslash_alg_bytes(vh, nrhs, aux_fields, real_bytes=8):
+def dslash_alg_bytes(vh, nrhs, aux_fields, real_bytes=8, link_bytes=None):
     """Algorithmic HBM bytes of one half-stencil launch: 16 links of 18 reals
     per output site once, the input field once, the output once and each
-    epilogue field once, per RHS (one colour vector = 6 reals per site)."""
-    return vh * (16 * 18 * real_bytes + nrhs * 6 * real_bytes * (2 + aux_fields))
+    epilogue field once, per RHS (one colour vector = 6 reals per site).
+    link_bytes: bytes per stored link real (default real_bytes)."""
+    lb = real_bytes if link_bytes is None else link_bytes
+    return vh * (16 * 18 * lb + nrhs * 6 * real_bytes * (2 + aux_fields))
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dslash_kernel.h", "dslash.hip", "dslash_f32.hip", "device_util.h"):
+    for f in ("dslash_kernel.h", "dslash.hip", "dslash_f32.hip", "dslash_q16.hip", "device_util.h"):
         with open(os.path.join(ROOT, "paper_2502_00152_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(name="dslash_f32_traffic_16x16x16x32.md"):
+def read_traffic(name="dslash_q16_traffic_16x16x16x32.md"):
     """HBM traffic per half-stencil launch from the committed counter summary,
     if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", name)
@@ -106,17 +108,19 @@ def build_problem(cfg):
 
 def pmc_probe(cfg):
     """Light run for hardware-counter passes: the half-stencil launches of one
-    CG iteration at the timed configuration (FP32, then FP64), and a plain
-    1 GiB copy whose counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    CG iteration at the timed configuration (FP32 vectors with 16-bit links,
+    then FP32 links, then FP64), and a plain 1 GiB copy whose counter readings
+    calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2502_00152_amd import hisq
     g, ee, eo, _ = build_problem(cfg)
-    for a in (ee.to(torch.complex64), ee):
+    for a, prec in ((ee.to(torch.complex64), hisq.HISQ_Q16), (ee.to(torch.complex64), hisq.HISQ_FP32),
+                    (ee, hisq.HISQ_FP64)):
         t = torch.empty_like(a)
         out = torch.empty_like(a)
         for _ in range(3):
-            hisq.hisq_dslash_eo(g, 1, a, t)
-            hisq.hisq_mdagm(g, cfg["two_m"], a, out)
+            hisq.hisq_dslash_eo(g, 1, a, t, prec=prec)
+            hisq.hisq_mdagm(g, cfg["two_m"], a, out, prec=prec)
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
     a.fill_(1.0)
     b = torch.empty_like(a)
@@ -247,6 +251,7 @@ def main():
     ap.add_argument("--no-dslash-scan", action="store_true")
     ap.add_argument("--no-plain-cg", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -285,6 +290,7 @@ def main():
     x = torch.empty_like(ee)
     po = torch.empty_like(eo)
     F32 = hisq.HISQ_FP32
+    SLOPPY = hisq.HISQ_Q16  # the sloppy operator reads 16-bit fixed-point links
 
     # learned initial guess (an extension beyond the paper), trained like the
     # eigensolve once per gauge field, outside the step
@@ -292,20 +298,20 @@ def main():
         train_learned_guess(g, evecs, eps, two_m, cfg["seed_eig"])
     kept = []
 
-    def step_core(with_guess):
+    def step_core(with_guess, sloppy=SLOPPY):
         hisq.hisq_prepare_source(g, two_m, ee, eo, y)
         hisq.hisq_deflate(g, ev32, eps, two_m, y, x)
         if with_guess:
             kept[:] = hisq.hisq_nn_guess(net, two_m, y, x,
                                          flags=hisq.HISQ_NN_NORMALIZE | hisq.HISQ_NN_BF16,
                                          evecs=ev32, evals=eps)
-        res = hisq.hisq_cg_solve(g, two_m, y, x, tol=tol, sloppy_prec=F32, reliable_delta=0.1,
+        res = hisq.hisq_cg_solve(g, two_m, y, x, tol=tol, sloppy_prec=sloppy, reliable_delta=0.1,
                                  evecs=ev32, evals=eps, tol_restart=1e-3)
         hisq.hisq_reconstruct_odd(g, two_m, x, eo, po)
         return res
 
     def step():
-        return step_core(net is not None)
+        return step_core(False)
 
     def step_fp64(xo):
         hisq.hisq_prepare_source(g, two_m, ee, eo, y)
@@ -315,7 +321,7 @@ def main():
         return res
 
     classes = ("dslash", "dslash_aux", "dslash_aux2", "dslash_f32", "dslash_f32_aux",
-               "dslash_f32_aux2", "blas", "gemm")
+               "dslash_f32_aux2", "dslash_q16", "dslash_q16_aux", "blas", "gemm")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -339,10 +345,10 @@ def main():
     assert all(all(r.converged) for r in results), "a timed solve did not converge"
 
     # live FP32 half-stencil roofline over the timed region (the CG's stencil)
-    n_plain, ms_plain = prof["dslash_f32"]
-    n_aux, ms_aux = prof["dslash_f32_aux"]
-    bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0, 4)
-                   + n_aux * dslash_alg_bytes(g.vh, nrhs, 1, 4))
+    n_plain, ms_plain = prof["dslash_q16"]
+    n_aux, ms_aux = prof["dslash_q16_aux"]
+    bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0, 4, 2)
+                   + n_aux * dslash_alg_bytes(g.vh, nrhs, 1, 4, 2))
     launches = n_plain + n_aux
     avg_ms = (ms_plain + ms_aux) / max(launches, 1)
     # GB/s = (bytes per launch) / (ms per launch * 1e-3) / 1e9
@@ -383,7 +389,8 @@ def main():
                  "seconds": t_plain}
         print(f"[bench] plain CG {nrhs} solves in {t_plain:.3f} s", flush=True)
 
-    # the same step without the learned guess, and the guess's held-out loss
+    # the step with the learned guess between deflation and CG, and the
+    # guess's held-out loss
     learned = None
     if net is not None:
         xd = torch.empty_like(y)
@@ -393,25 +400,48 @@ def main():
         hisq.hisq_mdagm(g, two_m, xd, Ax)
         held_out, _ = hisq.hisq_nn_loss_grad(net, y - Ax, x64 - xd, hisq.HISQ_NN_NORMALIZE)
         del xd, Ax
-        step_core(False)
+        step_core(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            r0 = step_core(False)
+            rl = step_core(True)
         torch.cuda.synchronize()
-        t_without = time.perf_counter() - t0
+        t_with = time.perf_counter() - t0
+        assert all(rl.converged), "a learned-guess solve did not converge"
         learned = dict(learn_info)
         learned.update({
             "held_out_loss": held_out, "kept": list(kept),
-            "iterations_per_source_with": last.iterations,
-            "iterations_per_source_without": r0.iterations,
-            "solves_per_s_with": nrhs * args.steps / t_steps,
-            "solves_per_s_without": nrhs * args.steps / t_without,
+            "iterations_per_source_with": rl.iterations,
+            "iterations_per_source_without": last.iterations,
+            "solves_per_s_with": nrhs * args.steps / t_with,
+            "solves_per_s_without": nrhs * args.steps / t_steps,
+            "path": ("the timed step plus the network correction (BF16 weights) projected "
+                     "off the deflation space, between the deflation and the CG"),
         })
         net.close()
-        print(f"[bench] without the learned guess: {learned['solves_per_s_without']:.1f} solves/s,"
-              f" mean iterations {np.mean(r0.iterations):.1f} (with: "
+        print(f"[bench] with the learned guess: {learned['solves_per_s_with']:.1f} solves/s,"
+              f" mean iterations {np.mean(rl.iterations):.1f} (without: "
               f"{np.mean(last.iterations):.1f})", flush=True)
+
+    # the timed step with the sloppy operator reading FP32 or BF16 links
+    sloppy_links = {}
+    for name, sp, skip in (("fp32_links", F32, False), ("bf16_links", hisq.HISQ_BF16, args.no_bf16)):
+        if skip:
+            continue
+        step_core(False, sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rb = step_core(False, sp)
+        torch.cuda.synchronize()
+        t_var = time.perf_counter() - t0
+        assert all(rb.converged), f"a {name} solve did not converge"
+        sloppy_links[name] = {"solves_per_s": nrhs * args.steps / t_var,
+                              "iterations_per_source": rb.iterations,
+                              "reliable_updates_per_source": rb.reliable_updates,
+                              "max_true_residual": max(rb.true_residual)}
+        print(f"[bench] sloppy operator with {name}: {nrhs * args.steps / t_var:.1f} solves/s, "
+              f"mean iterations {np.mean(rb.iterations):.1f}", flush=True)
 
     scan = None if args.no_dslash_scan else dslash_scan()
     if scan:
@@ -442,13 +472,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "deflated-cg-16^3x32", "lattice": "16x16x16x32", "eps": 0.5,
                    "two_m": two_m, "sources_per_step": nrhs, "n_ev": n_ev, "tol": tol,
-                   "path": ("FP32 eigenvectors; learned correction (BF16 weights, projected "
-                            "off the deflation space) unless --no-learned; batched "
-                            "mixed-precision CG (FP32 stencil and vectors, FP64 reductions "
-                            "and reliable updates, delta_rd 0.1), re-deflation at "
-                            "delta_tr 1e-3"),
-                   "learned_guess": net is not None},
-        "roofline": {"bound": "hbm", "kernel": "k_dslash<float> (FP32 half stencil, 12 RHS)",
+                   "path": ("FP32 eigenvectors; batched mixed-precision CG (FP32 vectors and "
+                            "arithmetic, 16-bit fixed-point links in the sloppy operator, "
+                            "FP64 reductions and reliable updates, delta_rd 0.1), "
+                            "re-deflation at delta_tr 1e-3")},
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_dslash<float, fvec2, q16c> (half stencil, FP32 vectors, "
+                               "16-bit links, 12 RHS)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic, "launches_timed": launches, "timed_every": PROFILE_PERIOD,
@@ -463,6 +493,7 @@ def main():
         "deflated_fp64_cg": fp64,
         "plain_fp64_cg": plain,
         "learned_guess": learned,
+        "sloppy_links_variants": sloppy_links,
         "speedup_vs_plain_fp64_cg": value / plain["solves_per_s"] if plain else None,
         "eigensolve": {"seconds": t_eig, "matvecs": est.matvecs, "restarts": est.restarts,
                        "cheb_degree": est.cheb_degree, "max_residual": est.max_residual,

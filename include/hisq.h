@@ -61,7 +61,10 @@ typedef enum hisq_status {
     HISQ_ERR_UNSUPPORTED = 7   /* valid request that this build does not implement */
 } hisq_status;
 
-typedef enum hisq_prec { HISQ_FP64 = 0, HISQ_FP32 = 1, HISQ_BF16 = 2 } hisq_prec;
+/* HISQ_Q16: 16-bit fixed-point links (one scale per gauge handle: the largest
+ * link component / 32767) with FP32 vectors and arithmetic, for the stencil,
+ * M^H M and the CG's sloppy operator only. */
+typedef enum hisq_prec { HISQ_FP64 = 0, HISQ_FP32 = 1, HISQ_BF16 = 2, HISQ_Q16 = 3 } hisq_prec;
 
 /* hisq_gauge_create flags */
 enum {
@@ -145,7 +148,10 @@ hisq_status hisq_convert_vectors(const void *src_dev, hisq_prec src_prec, void *
  * 8 bytes per complex; FP32 links and FP32 arithmetic, the FP32 links made
  * from the FP64 ones on first use) or HISQ_BF16 (vectors of bfloat16 pairs,
  * 4 bytes per complex; BF16 links, FP32 arithmetic, each output rounded to
- * nearest even once; the BF16 links made from the FP64 ones on first use).
+ * nearest even once; the BF16 links made from the FP64 ones on first use) or
+ * HISQ_Q16 (vectors of complex float as for HISQ_FP32; links in 16-bit fixed
+ * point, made from the FP64 ones on first use: absolute error <= step / 2 per
+ * component, step = the largest link component of the handle / 32767).
  */
 hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
                            void *out_dev, int nrhs, hisq_prec prec, void *stream);
@@ -186,8 +192,9 @@ typedef struct hisq_cg_params {
                               FP64 solve. */
     hisq_prec sloppy_prec; /* HISQ_FP64: plain FP64 CG.  HISQ_FP32: mixed precision,
                               the iteration in FP32 with FP64 reliable updates.
-                              HISQ_BF16: the same with the sloppy operator reading
-                              BF16 links (vectors still FP32) */
+                              HISQ_BF16 / HISQ_Q16: the same with the sloppy
+                              operator reading BF16 / 16-bit fixed-point links
+                              (vectors still FP32) */
     int reliable_interval; /* mixed only: also a reliable update after this many
                               iterations since the last one (0 = only the delta
                               trigger, as in the paper) */
@@ -236,7 +243,7 @@ typedef struct hisq_cg_stats {
  * recomputed true residual confirms it; if the true residual does not, CG
  * continues from it with the search direction kept.  b = 0 gives x = 0.
  *   stats_host: array of nrhs structs, filled on return (may be NULL).
- * With sloppy_prec = HISQ_FP32 or HISQ_BF16 (section 2: the conventional solve is
+ * With sloppy_prec = HISQ_FP32, HISQ_BF16 or HISQ_Q16 (section 2: the conventional solve is
  * mixed-precision CG; reliable updates as in section 3) the recurrence runs
  * on FP32 vectors with the FP32 operator and FP64-accumulated dot products;
  * the solution accumulates in FP64, and a reliable update (x += x_sloppy,

@@ -29,7 +29,7 @@ hisq_status check_nrhs(int nrhs) {
 }
 
 hisq_status check_prec(hisq_prec p) {
-    if (p == HISQ_FP64 || p == HISQ_FP32 || p == HISQ_BF16) return HISQ_OK;
+    if (p == HISQ_FP64 || p == HISQ_FP32 || p == HISQ_BF16 || p == HISQ_Q16) return HISQ_OK;
     return fail(HISQ_ERR_INVALID_ARG, "unknown precision");
 }
 
@@ -117,6 +117,8 @@ hisq_status hisq_gauge_destroy(hisq_gauge g) {
         if (g->lng32[p]) (void)hipFree(g->lng32[p]);
         if (g->fat16[p]) (void)hipFree(g->fat16[p]);
         if (g->lng16[p]) (void)hipFree(g->lng16[p]);
+        if (g->fatq[p]) (void)hipFree(g->fatq[p]);
+        if (g->lngq[p]) (void)hipFree(g->lngq[p]);
     }
     g->ws.release();
     if (g->cg_stream) (void)hipStreamDestroy(g->cg_stream);
@@ -185,6 +187,10 @@ hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev, voi
         return launch_dslash_f32(g, out_parity, static_cast<const float2 *>(in_dev),
                                  static_cast<float2 *>(out_dev), nrhs, nullptr, 0.0, nullptr, 0.0,
                                  1.0, nullptr, static_cast<hipStream_t>(stream));
+    if (prec == HISQ_Q16)
+        return launch_dslash_f32_q16(g, out_parity, static_cast<const float2 *>(in_dev),
+                                     static_cast<float2 *>(out_dev), nrhs, nullptr, 0.0, 1.0,
+                                     nullptr, static_cast<hipStream_t>(stream));
     if (prec == HISQ_BF16)
         return launch_dslash_bf16(g, out_parity, static_cast<const uint32_t *>(in_dev),
                                   static_cast<uint32_t *>(out_dev), nrhs, nullptr, 0.0, nullptr,
@@ -206,6 +212,10 @@ hisq_status hisq_mdagm(hisq_gauge g, double two_m, const void *in_e_dev, void *o
     if (prec == HISQ_FP32)
         return apply_mdagm_f32(g, two_m, static_cast<const float2 *>(in_e_dev),
                                static_cast<float2 *>(out_e_dev), nrhs, nullptr,
+                               static_cast<hipStream_t>(stream));
+    if (prec == HISQ_Q16)
+        return apply_mdagm_q16(g, two_m, static_cast<const float2 *>(in_e_dev),
+                               static_cast<float2 *>(out_e_dev), nrhs,
                                static_cast<hipStream_t>(stream));
     if (prec == HISQ_BF16)
         return apply_mdagm_bf16(g, two_m, static_cast<const uint32_t *>(in_e_dev),

@@ -145,14 +145,15 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
         HISQ_HIP(hipStreamSynchronize(s));  // m2 is a local array
         m2_rhs = static_cast<const double *>(pm);
     }
-    if (params->sloppy_prec == HISQ_FP32 || params->sloppy_prec == HISQ_BF16)
+    if (params->sloppy_prec == HISQ_FP32 || params->sloppy_prec == HISQ_BF16 ||
+        params->sloppy_prec == HISQ_Q16)
         return solve_mixed(g, two_m, b, x, nrhs, params, stats_host, s, m2_rhs,
-                           params->sloppy_prec == HISQ_BF16);
+                           params->sloppy_prec);
     if (params->sloppy_prec != HISQ_FP64) return fail(HISQ_ERR_INVALID_ARG, "unknown sloppy_prec");
     if (params->n_ev != 0 || params->tol_restart != 0.0)
         return fail(HISQ_ERR_INVALID_ARG,
-                    "re-deflation runs at reliable updates: it needs sloppy_prec = HISQ_FP32 "
-                    "or HISQ_BF16");
+                    "re-deflation runs at reliable updates: it needs a mixed-precision "
+                    "sloppy_prec");
 
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = params->check_interval > 0 ? params->check_interval : 16;

@@ -5,8 +5,8 @@
 // since the last deflation).
 //
 // The recurrence runs on FP32 vectors with the FP32 operator (links in FP32,
-// or in BF16 at sloppy_prec = HISQ_BF16); its dot products and all scalars
-// are FP64.  The solution accumulates in FP64: the FP32
+// in BF16 at sloppy_prec = HISQ_BF16, or 16-bit fixed point at HISQ_Q16); its
+// dot products and all scalars are FP64.  The solution accumulates in FP64: the FP32
 // correction x_s is added to x at every reliable update, where the residual is
 // recomputed in FP64 with the FP64 operator, r = b - A x, and replaces the
 // iterated one.  A right-hand side gets a reliable update
@@ -44,7 +44,8 @@ T *carve(char *&p, size_t count) {
 
 hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s,
-                        const double *m2_rhs, bool bf16_links) {
+                        const double *m2_rhs, hisq_prec links) {
+    const bool bf16_links = links == HISQ_BF16, q16_links = links == HISQ_Q16;
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = P->check_interval > 0 ? P->check_interval : 16;
     const int par = P->parity;
@@ -76,6 +77,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     // the sloppy links are made here, not inside a captured iteration chunk
     if (bf16_links) HISQ_TRY(ensure_links_bf16(g, s));
+    else if (q16_links) HISQ_TRY(ensure_links_q16(g, s));
     else HISQ_TRY(ensure_links_f32(g, s));
 
     // ------------------------------------------------------------ buffers
@@ -213,6 +215,11 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
                                           nullptr, dev.status));
             HISQ_TRY(launch_dslash_f32_bl(g, par, t32, Aps, nrhs, ps, m2, -1.0, pap.partials, s,
                                           m2_rhs, dev.status));
+        } else if (q16_links) {
+            HISQ_TRY(launch_dslash_f32_q16(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, 1.0, nullptr,
+                                           s, nullptr, dev.status));
+            HISQ_TRY(launch_dslash_f32_q16(g, par, t32, Aps, nrhs, ps, m2, -1.0, pap.partials, s,
+                                           m2_rhs, dev.status));
         } else {
             HISQ_TRY(launch_dslash_f32(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0,
                                        nullptr, s, nullptr, dev.status));

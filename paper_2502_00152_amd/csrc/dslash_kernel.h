@@ -43,6 +43,10 @@ using vec2 = R __attribute__((ext_vector_type(2)));
 
 // One complex number stored as two bfloat16 (real part in the low half).
 using bf16c = uint32_t;
+// One complex number stored as two 16-bit fixed-point integers (real part in
+// the low half); the value is the integer times a scale that the launcher
+// folds into the stencil's coefficient cd (links only).
+using q16c = int32_t;
 
 // Conversion between a stored complex S and the arithmetic type vec2<A>.
 template <typename S>
@@ -68,6 +72,14 @@ __host__ __device__ __forceinline__ uint32_t bf16_bits(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return u >> 16;
 }
+
+template <>
+struct Conv<q16c> {
+    template <typename A>
+    static __device__ __forceinline__ vec2<A> ld(q16c v) {
+        return vec2<A>{(A)(float)(int16_t)(v & 0xffff), (A)(float)(v >> 16)};
+    }
+};
 
 template <>
 struct Conv<bf16c> {

@@ -1,0 +1,121 @@
+// 16-bit fixed-point links for the sloppy operator of the mixed-precision CG
+// (arXiv:2502.00152, section 2: the conventional solve is mixed-precision CG;
+// the reliable updates it cites were introduced with such a half-precision
+// format).  Every link component is stored as round(x / step), step = (largest
+// |component| over fat and long links of the handle) / 32767, an absolute
+// error <= step / 2 per component; vectors stay FP32 and the arithmetic is
+// FP32.  The kernel multiplies the integers as floats and the launcher folds
+// step into the stencil coefficient cd.  Half the link bytes of FP32, about
+// 4e-5 relative accuracy for unitary links (BF16: 2e-3).
+#include <algorithm>
+#include <vector>
+
+#include "dslash_kernel.h"
+
+namespace hisq {
+
+DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes);
+hisq_status dslash_check_shape(const DslashShape &sh);
+
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kMaxBlocks = 1024;
+
+// per-block max |component| (re and im) of n complex numbers
+__global__ __launch_bounds__(kBS) void k_absmax(const double2 *__restrict__ src, int64_t n,
+                                                double *__restrict__ partials) {
+    __shared__ double m[kBS];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+        const double2 a = src[i];
+        v = fmax(v, fmax(fabs(a.x), fabs(a.y)));
+    }
+    m[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBS / 2; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = m[0];
+}
+
+__device__ __forceinline__ uint32_t q16_of(double x, double inv_step) {
+    const long long q = llrint(x * inv_step);
+    const int c = (int)(q > 32767 ? 32767 : (q < -32767 ? -32767 : q));
+    return (uint32_t)c & 0xffffu;
+}
+
+__global__ __launch_bounds__(kBS) void k_links_to_q16(const double2 *__restrict__ src,
+                                                      q16c *__restrict__ dst, int64_t n,
+                                                      double inv_step) {
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+        const double2 v = src[i];
+        dst[i] = (q16c)(q16_of(v.x, inv_step) | (q16_of(v.y, inv_step) << 16));
+    }
+}
+
+}  // namespace
+
+hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s) {
+    if (g->fatq[0]) return HISQ_OK;
+    const int64_t n = link_array_entries(g->geom.vh);
+    const int nb = (int)std::min<int64_t>((n + kBS - 1) / kBS, kMaxBlocks);
+    void *p = nullptr;
+    HISQ_TRY(g->ws.get("q16_absmax", sizeof(double) * 4 * kMaxBlocks, &p));
+    double *part = static_cast<double *>(p);
+    const double2 *arrays[4] = {g->fat[0], g->fat[1], g->lng[0], g->lng[1]};
+    for (int a = 0; a < 4; ++a)
+        hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(kBS), 0, s, arrays[a], n, part + a * kMaxBlocks);
+    HISQ_HIP(hipGetLastError());
+    std::vector<double> h(4 * (size_t)kMaxBlocks);
+    HISQ_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HISQ_HIP(hipStreamSynchronize(s));
+    double mx = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < nb; ++b) mx = std::max(mx, h[(size_t)a * kMaxBlocks + b]);
+    const double step = mx > 0.0 ? mx / 32767.0 : 1.0;
+    for (int q = 0; q < 2; ++q) {
+        if (hipMalloc(&g->fatq[q], sizeof(q16c) * n) != hipSuccess ||
+            hipMalloc(&g->lngq[q], sizeof(q16c) * n) != hipSuccess)
+            return fail(HISQ_ERR_OOM, "device allocation of the 16-bit links");
+    }
+    const int nc = (int)std::min<int64_t>((n + kBS - 1) / kBS, 8192);
+    for (int q = 0; q < 2; ++q) {
+        hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->fat[q], g->fatq[q], n,
+                           1.0 / step);
+        hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->lng[q], g->lngq[q], n,
+                           1.0 / step);
+    }
+    HISQ_HIP(hipGetLastError());
+    g->q16_step = step;
+    return HISQ_OK;
+}
+
+hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
+                                  int nrhs, const float2 *aux, double ca, double cd,
+                                  double *partials, hipStream_t s, const double *ca_rhs,
+                                  const int *rhs_status) {
+    HISQ_TRY(ensure_links_q16(g, s));
+    using V = vec2<float>;
+    const q16c *fat[2] = {g->fatq[0], g->fatq[1]};
+    const q16c *lng[2] = {g->lngq[0], g->lngq[1]};
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 4);
+    HISQ_TRY(dslash_check_shape(sh));
+    ProfileScope prof(aux ? "dslash_q16_aux" : "dslash_q16", s);
+    return dslash_impl::launch_dslash_t<float, V, q16c>(
+        g->geom, fat, lng, out_parity, reinterpret_cast<const V *>(in), reinterpret_cast<V *>(out),
+        nrhs, reinterpret_cast<const V *>(aux), ca, nullptr, 0.0, cd * g->q16_step, partials, sh, s,
+        ca_rhs, rhs_status);
+}
+
+hisq_status apply_mdagm_q16(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,
+                            hipStream_t s) {
+    void *tmp = nullptr;
+    HISQ_TRY(g->ws.get("mdagm_tmp32", sizeof(float2) * 3 * (size_t)g->geom.vh * nrhs, &tmp));
+    float2 *t = static_cast<float2 *>(tmp);
+    HISQ_TRY(launch_dslash_f32_q16(g, 1, in, t, nrhs, nullptr, 0.0, 1.0, nullptr, s));
+    return launch_dslash_f32_q16(g, 0, t, out, nrhs, in, two_m * two_m, -1.0, nullptr, s);
+}
+
+}  // namespace hisq

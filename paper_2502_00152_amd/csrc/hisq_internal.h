@@ -88,6 +88,9 @@ struct hisq_gauge_s {
     float2 *lng32[2] = {nullptr, nullptr};
     uint32_t *fat16[2] = {nullptr, nullptr}; // BF16 copies (two bfloat16 per complex),
     uint32_t *lng16[2] = {nullptr, nullptr}; //   made on first BF16 use
+    int32_t *fatq[2] = {nullptr, nullptr};   // 16-bit fixed-point copies (two int16
+    int32_t *lngq[2] = {nullptr, nullptr};   //   per complex), made on first use,
+    double q16_step = 0.0;                   //   value = integer * q16_step
     hipStream_t cg_stream = nullptr;        // the solvers' own stream (capturable)
     hisq::Workspace ws;
 };
@@ -245,6 +248,14 @@ hisq_status launch_dslash_f32_bl(hisq_gauge_s *g, int out_parity, const float2 *
                                  int nrhs, const float2 *aux, double ca, double cd,
                                  double *partials, hipStream_t s, const double *ca_rhs = nullptr,
                                  const int *rhs_status = nullptr);
+// 16-bit fixed-point links (HISQ_Q16): FP32 vectors and arithmetic
+hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s);
+hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
+                                  int nrhs, const float2 *aux, double ca, double cd,
+                                  double *partials, hipStream_t s, const double *ca_rhs = nullptr,
+                                  const int *rhs_status = nullptr);
+hisq_status apply_mdagm_q16(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,
+                            hipStream_t s);
 
 // The CG drivers run on the handle's own non-blocking stream (created on first
 // use, default priority), ordered after the caller's stream on entry and
@@ -306,7 +317,7 @@ hisq_status convert_vectors(const void *src, hisq_prec sp, void *dst, hisq_prec 
                             hipStream_t s);
 hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2 *x, int nrhs,
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s,
-                        const double *m2_rhs = nullptr, bool bf16_links = false);
+                        const double *m2_rhs = nullptr, hisq_prec links = HISQ_FP32);
 
 // Operators built from dslash.
 // out = ((2m)^2 - D_{p,1-p} D_{1-p,p}) in on parity p (p = 0: the even operator A);

@@ -1,7 +1,16 @@
-"""GPU parity of BF16 storage: conversions, the half stencil and M^H M with
-BF16 vectors and links (FP32 arithmetic), and the mixed-precision CG whose
-sloppy operator reads BF16 links (section 3: the bulk of the operator in
-reduced precision, FP64 restored at reliable updates).
+"""GPU parity of the reduced-precision storage formats: BF16 (conversions,
+the half stencil and M^H M with BF16 vectors and links, FP32 arithmetic) and
+16-bit fixed-point links (HISQ_Q16: FP32 vectors and arithmetic), and the
+mixed-precision CG whose sloppy operator reads BF16 or 16-bit links (sections
+2-3: the bulk of the operator in reduced precision, FP64 restored at
+reliable updates).
+
+Q16 bar: each link component carries an absolute error <= step / 2 (step =
+largest link component / 32767), i.e. <= step / sqrt(2) per complex entry,
+so |out - D psi| <= (step / sqrt(2)) T + 300 u32 S with T = sum over the 16
+hops and 3 colours of |psi| (the stencil with unit-modulus links) and the
+FP32 arithmetic bound of the FP32 stencil; for M^H M both stencils and the
+FP32 temporary enter, see the test.
 
 Bars, derived from the arithmetic.  bfloat16 keeps 8 significant bits: round
 to nearest gives a relative error u = 2^-8 per stored real.  The tests feed
@@ -216,3 +225,89 @@ def test_cg_with_bf16_links_meets_fp64_residual(w8):
     # a bounded iteration cost
     assert sum(res.reliable_updates) >= sum(r32.reliable_updates)
     assert max(res.iterations) <= 2 * max(r32.iterations) + 32
+
+
+# ---------------------------------------------------- 16-bit fixed-point links
+U32 = 2.0 ** -24
+
+
+def q16_step(pr):
+    return max(np.abs(pr.F.real).max(), np.abs(pr.F.imag).max(),
+               np.abs(pr.L.real).max(), np.abs(pr.L.imag).max()) / 32767.0
+
+
+@pytest.mark.parametrize("nrhs", [1, 5, 12])
+@pytest.mark.parametrize("out_parity", [0, 1])
+def test_dslash_q16_within_quantisation_bound(prob, nrhs, out_parity):
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = prob.dims
+    in_par = 1 - out_parity
+    v32 = to_parity(sources(dims, nrhs, 440), dims, in_par).astype(np.complex64)
+    inp = torch.from_numpy(v32).cuda()
+    out = torch.empty_like(inp)
+    hisq.hisq_dslash_eo(prob.g, out_parity, inp, out, prec=hisq.HISQ_Q16)
+    got = host(out).astype(np.complex128)
+    step = q16_step(prob)
+    ones = np.ones_like(prob.F)
+    worst = 0.0
+    for j in range(nrhs):
+        full = from_parity(v32[j:j + 1].astype(np.complex128), dims, in_par)[0]
+        ref = to_parity(O.dslash(prob.F, prob.L, full, out_parity), dims, out_parity)[0]
+        S = to_parity(abs_stencil(prob.F, prob.L, full), dims, out_parity)[0].real
+        T = to_parity(abs_stencil(ones, ones, full), dims, out_parity)[0].real
+        err = np.abs(got[j] - ref)
+        bound = step / np.sqrt(2) * T + 300 * U32 * S
+        assert (err <= bound + 1e-30).all(), (j, float((err / bound).max()))
+        worst = max(worst, float((err / (step * T + 1e-300)).max()))
+    assert worst > 0.01  # the links really are quantised (FP32 links: ~1e-3 of this)
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_mdagm_q16_within_quantisation_bound(prob, nrhs):
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = prob.dims
+    two_m = 0.07
+    v32 = to_parity(sources(dims, nrhs, 460), dims, 0).astype(np.complex64)
+    inp = torch.from_numpy(v32).cuda()
+    out = torch.empty_like(inp)
+    hisq.hisq_mdagm(prob.g, two_m, inp, out, prec=hisq.HISQ_Q16)
+    got = host(out).astype(np.complex128)
+    step = q16_step(prob)
+    ones = np.ones_like(prob.F)
+    odd = O.even_mask(dims)[..., None] == 0
+    even = ~odd
+    for j in range(nrhs):
+        full = from_parity(v32[j:j + 1].astype(np.complex128), dims, 0)[0]
+        ref = to_parity(O.apply_A(prob.F, prob.L, two_m, full), dims, 0)[0]
+        s1 = abs_stencil(prob.F, prob.L, full) * odd                 # |D_oe| |v|
+        t1 = abs_stencil(ones, ones, full) * odd                     # T_oe |v|
+        S2 = abs_stencil(prob.F, prob.L, s1) + two_m ** 2 * np.abs(full)
+        Tq = abs_stencil(prob.F, prob.L, t1) + abs_stencil(ones, ones, s1)
+        bound = to_parity((step / np.sqrt(2) * Tq * 1.01 + 600 * U32 * S2) * even, dims, 0)[0].real
+        err = np.abs(got[j] - ref)
+        assert (err <= bound + 1e-30).all(), j
+
+
+def test_cg_with_q16_links_keeps_fp32_iterations(w8):
+    """With links accurate to ~4e-5 the sloppy recurrence loses almost nothing
+    against FP32 links, and the answer is still decided by the FP64 true
+    residual."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = w8
+    tol = 1e-10
+    bs = to_parity(pr.y, pr.dims, 0)
+    b = dev(bs)
+    x = torch.zeros_like(b)
+    res = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=tol, sloppy_prec=hisq.HISQ_Q16)
+    assert all(res.converged)
+    x32 = torch.zeros_like(b)
+    r32 = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x32, tol=tol, sloppy_prec=hisq.HISQ_FP32)
+    xs = host(x)
+    for j in range(3):
+        full = from_parity(xs[j:j + 1], pr.dims, 0)[0]
+        tr = O.norm(pr.y[j] - O.apply_A(pr.F, pr.L, pr.two_m, full)) / O.norm(pr.y[j])
+        assert tr <= tol
+    assert max(res.iterations) <= 1.05 * max(r32.iterations) + 8, (res.iterations, r32.iterations)

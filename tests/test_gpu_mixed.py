@@ -226,7 +226,7 @@ def test_mixed_cg_edge_cases(w8):
         assert e.value.status == hisq.HISQ_ERR_INVALID_ARG, kw
     with pytest.raises(hisq.HisqError) as e:
         hisq.hisq_cg_solve(pr.g, pr.two_m, b[:1].clone(), torch.zeros_like(b[:1]),
-                           sloppy_prec=hisq.HISQ_BF16 + 1)
+                           sloppy_prec=99)
     assert e.value.status == hisq.HISQ_ERR_INVALID_ARG
     ev = torch.zeros((1, 3, pr.g.vh), dtype=torch.complex128, device="cuda")
     ev[0, 0, 0] = 1.0

@@ -174,3 +174,77 @@ def test_fp32_eigenvectors_stall_and_multi_deflation_recovers(wl, eig):
     for r in range(12):
         bound = (r_m.true_residual[r] + r64.true_residual[r]) * np.linalg.norm(ys[r]) / lam1
         assert np.linalg.norm(xs[r] - x64s[r]) <= bound * 1.01, r
+
+
+def test_q16_stencil_sampled_sites(wl):
+    """The timed sloppy operator: 12-RHS half stencil with FP32 vectors and
+    16-bit fixed-point links, at 300 random sites, within the quantisation
+    bound (step / sqrt(2)) T + 300 u32 S (see tests/test_gpu_lowp.py)."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    from tests.gpu_util import abs_stencil_site
+    dims = wl.dims
+    e32 = wl.eo.to(torch.complex64)
+    out = torch.empty_like(e32)
+    hisq.hisq_dslash_eo(wl.g, 0, e32, out, prec=hisq.HISQ_Q16)
+    got = host(out).astype(np.complex128)
+    eo32 = host(e32).astype(np.complex128)
+    step = max(np.abs(wl.F.real).max(), np.abs(wl.F.imag).max(),
+               np.abs(wl.L.real).max(), np.abs(wl.L.imag).max()) / 32767.0
+    ones = np.ones((4,) + wl.F.shape[1:], dtype=np.complex128)
+    rng = np.random.default_rng(6)
+    lex_even = np.nonzero(O.even_mask(dims).ravel())[0]
+    X, Y, Z, T = dims
+    worst = 0.0
+    for r in (0, 5, 11):
+        psi = from_parity(eo32[r:r + 1], dims, 1)[0]
+        for lex in rng.choice(lex_even, 100, replace=False):
+            site = (lex % X, (lex // X) % Y, (lex // (X * Y)) % Z, lex // (X * Y * Z))
+            ref = O.dslash_site(wl.F, wl.L, psi, site)
+            S = abs_stencil_site(wl.F, wl.L, psi, site)
+            Tq = abs_stencil_site(ones, ones, psi, site)
+            err = np.abs(got[r, :, lex >> 1] - ref)
+            bound = step / np.sqrt(2) * Tq + 300 * 2.0 ** -24 * S
+            assert (err <= bound).all(), (r, site)
+            worst = max(worst, float((err / bound).max()))
+    print(f"[16x16x16x32] q16 stencil: worst error / bound {worst:.3f}", flush=True)
+
+
+def test_timed_step_q16_links_multi_deflation(wl, eig):
+    """The timed step of the benchmark: FP32 eigenvectors, mixed CG whose
+    sloppy operator reads 16-bit links, re-deflation at delta_tr = 1e-3.
+    Oracle-evaluated FP64 true residual <= 1e-10 on two sources, the solution
+    within (||r|| + ||r'||) / lambda_1 of the FP64 path's, and the iteration
+    count of the FP32-link path."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    ev, lam, stats = eig
+    two_m = wl.cfg["two_m"]
+    eps = lam - two_m ** 2
+    ev32 = torch.empty(ev.shape, dtype=torch.complex64, device="cuda")
+    hisq.hisq_convert_vectors(ev, ev32)
+
+    def solve(defl, **kw):
+        x = torch.empty_like(wl.y)
+        hisq.hisq_deflate(wl.g, defl, eps, two_m, wl.y, x)
+        r = hisq.hisq_cg_solve(wl.g, two_m, wl.y, x, tol=1e-10, **kw)
+        assert all(r.converged)
+        return x, r
+
+    x64, r64 = solve(ev)
+    kw = dict(reliable_delta=0.1, evecs=ev32, evals=eps, tol_restart=1e-3)
+    xq, rq = solve(ev32, sloppy_prec=hisq.HISQ_Q16, **kw)
+    _, rf = solve(ev32, sloppy_prec=hisq.HISQ_FP32, **kw)
+    print(f"[16x16x16x32] timed step iterations: q16 {max(rq.iterations)}, "
+          f"fp32 links {max(rf.iterations)}, fp64 {max(r64.iterations)}", flush=True)
+    assert max(rq.iterations) <= max(rf.iterations) + 3
+    xs, ys, x64s = host(xq), host(wl.y), host(x64)
+    for r in (0, 11):
+        xe = from_parity(xs[r:r + 1], wl.dims, 0)[0]
+        ye = from_parity(ys[r:r + 1], wl.dims, 0)[0]
+        tr = O.norm(ye - O.apply_A(wl.F, wl.L, two_m, xe)) / O.norm(ye)
+        assert tr <= 1e-10, (r, tr)
+    lam1 = GOLDEN["eigenvalues"][0]
+    for r in range(12):
+        bound = (rq.true_residual[r] + r64.true_residual[r]) * np.linalg.norm(ys[r]) / lam1
+        assert np.linalg.norm(xs[r] - x64s[r]) <= bound * 1.01, r
