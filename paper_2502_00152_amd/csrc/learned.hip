@@ -47,6 +47,9 @@ constexpr int OFF_W1 = 0, OFF_W2 = OFF_W1 + 9 * C, OFF_W3 = OFF_W2 + 9 * C * C,
               OFF_G1 = OFF_W3 + 9 * C, OFF_G2 = OFF_G1 + 2 * C, NPARAM = OFF_G2 + 2 * C;
 static_assert(NPARAM == HISQ_NN_PARAMS, "parameter count");
 constexpr int kMaxRedBlocks = 512;  // cap on the site blocks of a reduction
+constexpr int kWgradBlocks = 96;    // site blocks of a weight-gradient launch: each
+                                    // lane sums several sites before the 64-value
+                                    // block reduction, which dominates otherwise
 
 typedef float fvec2 __attribute__((ext_vector_type(2)));
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -631,7 +634,7 @@ template <int CI, int CO>
 hisq_status wgrad(hisq_nn n, const fvec2 *in, const fvec2 *gout, int S, double *partials,
                   double *out, hipStream_t s) {
     const Geom &g = n->g->geom;
-    const int nb = blocks_for(2 * (int64_t)g.vh, kMaxRedBlocks);
+    const int nb = blocks_for(2 * (int64_t)g.vh, kWgradBlocks);
     hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(nb, 9, S), dim3(kBS), 0, s, in, gout,
                        reinterpret_cast<const fvec2 *>(n->g->fat32[0]),
                        reinterpret_cast<const fvec2 *>(n->g->fat32[1]), link_tiles(g.vh), g,
