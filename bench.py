@@ -202,6 +202,119 @@ def cpu_baseline(cfg, golden):
                        f"deflated solve takes, odd reconstruction")}
 
 
+def learned_large():
+    """The learned guess on one GPU's share of a large lattice (48^3 x 96,
+    2m = 0.002): eigensolve, training pairs from the production solver,
+    training, then the production step on 12 fresh sources without and with
+    the guess.  Prints one JSON line."""
+    import torch
+    from paper_2502_00152_amd import hisq, inputs as I
+    cfg = I.workload(4)
+    dims, two_m, tol, n_ev, nrhs = cfg["dims"], cfg["two_m"], cfg["tol"], cfg["n_ev"], cfg["nrhs"]
+    t_all = time.perf_counter()
+    W = I.random_su3_field_device(dims, cfg["eps"], cfg["seed_fat"])
+    N = I.random_su3_field_device(dims, cfg["eps"], cfg["seed_long"])
+    g = hisq.Gauge(dims, W, N, cfg["c_fat"], cfg["c_long"])
+    del W, N
+    torch.cuda.empty_cache()
+    print(f"[learned-48] gauge ready {time.perf_counter() - t_all:.1f} s", flush=True)
+    evecs = torch.empty((n_ev, 3, g.vh), dtype=torch.complex128, device="cuda")
+    last = [0.0]
+
+    def prog(r, j, mv, sec):
+        if sec - last[0] >= 10.0:
+            last[0] = sec
+            print(f"[learned-48] eigensolve restart {r} step {j} matvecs {mv} {sec:.0f} s", flush=True)
+
+    t0 = time.perf_counter()
+    st, lam, est = hisq.hisq_eigensolve(g, two_m, n_ev, evecs, tol=tol, seed=cfg["seed_eig"],
+                                        progress=prog)
+    t_eig = time.perf_counter() - t0
+    eps = lam - two_m * two_m
+    ev32 = torch.empty(evecs.shape, dtype=torch.complex64, device="cuda")
+    hisq.hisq_convert_vectors(evecs, ev32)
+    del evecs
+    torch.cuda.empty_cache()
+    print(f"[learned-48] eigensolve {t_eig:.1f} s, lambda_1 {lam[0]:.4e}, lambda_64 {lam[-1]:.4e}",
+          flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(cfg["seed_eig"] + 500)
+
+    def sources(n):
+        a = torch.randn((n, 3, g.vh), dtype=torch.complex128, device="cuda", generator=gen)
+        c = torch.randn((n, 3, g.vh), dtype=torch.complex128, device="cuda", generator=gen)
+        b = torch.empty_like(a)
+        hisq.hisq_prepare_source(g, two_m, a, c, b)
+        return b
+
+    kw = dict(sloppy_prec=hisq.HISQ_Q16, reliable_delta=0.1, evecs=ev32, evals=eps,
+              tol_restart=1e-3)
+    R, E = [], []
+    t0 = time.perf_counter()
+    for k in range(cfg["n_pairs"] // nrhs):
+        b = sources(nrhs)
+        xd = torch.empty_like(b)
+        hisq.hisq_deflate(g, ev32, eps, two_m, b, xd)
+        xs = xd.clone()
+        hisq.hisq_cg_solve(g, two_m, b, xs, tol=1e-12, **kw)
+        Ax = torch.empty_like(b)
+        hisq.hisq_mdagm(g, two_m, xd, Ax)
+        R.append(b - Ax)
+        E.append(xs - xd)
+        del b, xd, xs, Ax
+        print(f"[learned-48] training pairs {(k + 1) * nrhs}", flush=True)
+    R = torch.cat(R)
+    E = torch.cat(E)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    net = hisq.Network(g, I.nn_initial_params(cfg["seed_eig"] + 501))
+    t0 = time.perf_counter()
+    steps = 200
+    losses = hisq.hisq_nn_train(net, R, E, batch=2, steps=steps, lr=1e-2,
+                                flags=hisq.HISQ_NN_NORMALIZE)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del R, E
+    torch.cuda.empty_cache()
+    print(f"[learned-48] training {t_train:.1f} s, loss {losses[0]:.3f} -> "
+          f"{np.mean(losses[-20:]):.3f}", flush=True)
+    b = sources(nrhs)
+    x = torch.empty_like(b)
+
+    def step(with_guess):
+        hisq.hisq_deflate(g, ev32, eps, two_m, b, x)
+        kept = None
+        if with_guess:
+            kept = hisq.hisq_nn_guess(net, two_m, b, x,
+                                      flags=hisq.HISQ_NN_NORMALIZE | hisq.HISQ_NN_BF16,
+                                      evecs=ev32, evals=eps)
+        r = hisq.hisq_cg_solve(g, two_m, b, x, tol=tol, **kw)
+        return r, kept
+
+    out = {}
+    for name, wg in (("without", False), ("with", True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, kept = step(wg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert all(r.converged), f"a solve {name} the guess did not converge"
+        out[name] = {"solves_per_s": nrhs / dt, "mean_iterations": float(np.mean(r.iterations)),
+                     "max_true_residual": max(r.true_residual), "kept": kept}
+        print(f"[learned-48] {name} the guess: {nrhs / dt:.2f} solves/s, mean iterations "
+              f"{np.mean(r.iterations):.1f}", flush=True)
+    net.close()
+    g.close()
+    print(json.dumps({"workload": cfg["name"], "lattice": "x".join(map(str, dims)),
+                      "two_m": two_m, "n_ev": n_ev, "training_pairs": cfg["n_pairs"],
+                      "train_steps": steps, "batch": 2, "eigensolve_seconds": t_eig,
+                      "pairs_seconds": t_pairs, "train_seconds": t_train,
+                      "loss_first": float(losses[0]),
+                      "loss_last20_mean": float(np.mean(losses[-20:])),
+                      "lambda_1": float(lam[0]), "lambda_64": float(lam[-1]),
+                      "sloppy_links": "q16", "unit": "solves/s", **out}), flush=True)
+
+
 def train_learned_guess(g, evecs, eps, two_m, seed):
     """Train the learned guess on pairs the solver generates: r = the residual
     of the deflation guess of a prepared random source, e = the remaining
@@ -253,6 +366,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true")
+    ap.add_argument("--learned-large", action="store_true",
+                    help="measure the learned guess at 48^3 x 96 instead (one JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -268,6 +383,9 @@ def main():
     cfg = I.workload(1)
     if args.pmc_probe:
         pmc_probe(cfg)
+        return
+    if args.learned_large:
+        learned_large()
         return
     two_m, tol, nrhs, n_ev = cfg["two_m"], cfg["tol"], cfg["nrhs"], cfg["n_ev"]
     print(f"[bench] setup {cfg['name']}", flush=True)

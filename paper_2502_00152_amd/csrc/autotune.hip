@@ -8,7 +8,6 @@
 namespace hisq {
 hisq_status check_gauge(hisq_gauge g);
 hisq_status check_nrhs(int nrhs);
-DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes);
 void dslash_tuned_set(int vh, int nrhs, size_t real_bytes, const DslashShape &sh);
 hisq_status dslash_set_tuning(const std::string &key, int64_t value);
 }  // namespace hisq

@@ -48,12 +48,16 @@ int nr_for(int nrhs, int lps) {
 
 // Launch shape of the half stencil for nrhs RHS at half volume vh in the
 // given precision: the tuned values where set, else defaults measured on
-// MI355X (16^3 x 32 and 32^3 x 64, 1 to 24 RHS).  One RHS streams at 74-76% of
+// MI355X (16^3 x 32 to 48^3 x 96, 1 to 24 RHS).  One RHS streams at 73-76% of
 // HBM peak either way; with several RHS per site the links are read once per
-// group, and the best grouping depends on whether the group's input field
-// still fits the caches: small volumes favour small groups (occupancy), large
-// volumes with many RHS one wide group with several lanes per site.
-DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes) {
+// group and the sites of a block spread over the XCD's L2.  Measured with 12
+// and 24 RHS: FP32 vectors with 16-bit links run best (or within 10%) with 3
+// RHS per lane at every volume; FP32 links with 3 per lane on small volumes
+// and up to 12 per lane on large ones (the (6 per lane, 4 lanes) shape chosen
+// earlier for 32^3 x 64 was up to 1.6x slower elsewhere); FP64 with 4 lanes
+// of 1 RHS on small volumes and 12 RHS per lane on large ones.  q16_links
+// selects the 16-bit-link defaults (FP32 vectors, real_bytes 4).
+DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links) {
     const bool f32 = real_bytes <= 4, small = vh <= (1 << 18);  // FP32 and BF16
     DslashShape sh{};
     int xcd = 1;
@@ -62,15 +66,15 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes) {
     } else if (nrhs <= 4) {
         sh.nr = 2, sh.lps = 1;
     } else if (f32) {
-        if (small) sh.nr = 3, sh.lps = 1;
-        else sh.nr = 6, sh.lps = 4, xcd = 0;
+        if (small || q16_links) sh.nr = 3, sh.lps = 1;
+        else sh.nr = nr_for(nrhs, 1), sh.lps = 1;
     } else {
         if (small) sh.nr = 1, sh.lps = 4;
         else sh.nr = 12, sh.lps = 1;
     }
     int order = 0;
     // the autotuner's choice for this volume and batch, if any
-    const auto it = g_tuned.find(TunedKey{vh, nrhs, (int)real_bytes});
+    const auto it = g_tuned.find(TunedKey{vh, nrhs, q16_links ? 3 : (int)real_bytes});
     if (it != g_tuned.end()) {
         sh.nr = it->second.nr, sh.lps = it->second.lps;
         xcd = it->second.xcd_remap, order = it->second.group_outer;
@@ -136,7 +140,7 @@ hisq_status launch_dslash(const hisq_gauge_s *g, int out_parity, const double2 *
     using V = vec2<double>;
     const V *fat[2] = {reinterpret_cast<const V *>(g->fat[0]), reinterpret_cast<const V *>(g->fat[1])};
     const V *lng[2] = {reinterpret_cast<const V *>(g->lng[0]), reinterpret_cast<const V *>(g->lng[1])};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, sizeof(double));
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, sizeof(double), false);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux2 ? "dslash_aux2" : aux ? "dslash_aux" : "dslash", s);
     return dslash_impl::launch_dslash_t<double>(

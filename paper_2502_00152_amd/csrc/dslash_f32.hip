@@ -7,7 +7,6 @@
 
 namespace hisq {
 
-DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes);
 hisq_status dslash_check_shape(const DslashShape &sh);
 
 namespace {

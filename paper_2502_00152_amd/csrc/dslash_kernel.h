@@ -102,6 +102,11 @@ struct DslashShape {
     int group_outer;
 };
 
+// Launch shape of the half stencil (tuned or default) for nrhs RHS at half
+// volume vh, real_bytes per stored vector real (8, 4 or 2); q16_links: FP32
+// vectors with 16-bit links.
+DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links = false);
+
 namespace dslash_impl {
 
 constexpr int kSites = 256;  // output sites per block (and per partial sum)

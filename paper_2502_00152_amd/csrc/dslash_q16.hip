@@ -14,7 +14,6 @@
 
 namespace hisq {
 
-DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes);
 hisq_status dslash_check_shape(const DslashShape &sh);
 
 namespace {
@@ -100,7 +99,7 @@ hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 
     using V = vec2<float>;
     const q16c *fat[2] = {g->fatq[0], g->fatq[1]};
     const q16c *lng[2] = {g->lngq[0], g->lngq[1]};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 4);
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 4, true);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux ? "dslash_q16_aux" : "dslash_q16", s);
     return dslash_impl::launch_dslash_t<float, V, q16c>(
