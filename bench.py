@@ -49,24 +49,28 @@ LEARNED_PAIRS = 128   # training pairs the solver generates for the learned gues
 LEARNED_STEPS = 400   # Adam steps, mini-batches of 8
 
 
-def dslash_alg_bytes(vh, nrhs, aux_fields, real_bytes=8, link_bytes=None):
+def dslash_alg_bytes(vh, nrhs, aux_fields, real_bytes=8, link_bytes=None, site_bytes=None):
     """Algorithmic HBM bytes of one half-stencil launch: 16 links of 18 reals
     per output site once, the input field once, the output once and each
     epilogue field once, per RHS (one colour vector = 6 reals per site).
-    link_bytes: bytes per stored link real (default real_bytes)."""
+    link_bytes: bytes per stored link real (default real_bytes); site_bytes:
+    bytes of one RHS's colour vector at one site (default 6 real_bytes; 16 for
+    16-bit vectors with their norm)."""
     lb = real_bytes if link_bytes is None else link_bytes
-    return vh * (16 * 18 * lb + nrhs * 6 * real_bytes * (2 + aux_fields))
+    sb = 6 * real_bytes if site_bytes is None else site_bytes
+    return vh * (16 * 18 * lb + nrhs * sb * (2 + aux_fields))
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dslash_kernel.h", "dslash.hip", "dslash_f32.hip", "dslash_q16.hip", "device_util.h"):
+    for f in ("dslash_kernel.h", "dslash.hip", "dslash_f32.hip", "dslash_q16.hip", "cg_half.hip",
+              "device_util.h"):
         with open(os.path.join(ROOT, "paper_2502_00152_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(name="dslash_q16_traffic_16x16x16x32.md"):
+def read_traffic(name="dslash_h16_traffic_16x16x16x32.md"):
     """HBM traffic per half-stencil launch from the committed counter summary,
     if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", name)
@@ -107,13 +111,17 @@ def build_problem(cfg):
 
 
 def pmc_probe(cfg):
-    """Light run for hardware-counter passes: the half-stencil launches of one
-    CG iteration at the timed configuration (FP32 vectors with 16-bit links,
-    then FP32 links, then FP64), and a plain 1 GiB copy whose counter readings
-    calibrate FETCH_SIZE / WRITE_SIZE."""
+    """Light run for hardware-counter passes: three iterations of the timed CG
+    (12 RHS, 16-bit vectors and links), the half-stencil launches of one CG
+    iteration with FP32 vectors and 16-bit links, FP32 links, then FP64, and a
+    plain 1 GiB copy whose counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2502_00152_amd import hisq
     g, ee, eo, _ = build_problem(cfg)
+    y = torch.empty_like(ee)
+    hisq.hisq_prepare_source(g, cfg["two_m"], ee, eo, y)
+    hisq.hisq_cg_solve(g, cfg["two_m"], y, torch.zeros_like(y), tol=cfg["tol"], max_iter=3,
+                       check_interval=3, sloppy_prec=hisq.HISQ_HALF, raise_on_fail=False)
     for a, prec in ((ee.to(torch.complex64), hisq.HISQ_Q16), (ee.to(torch.complex64), hisq.HISQ_FP32),
                     (ee, hisq.HISQ_FP64)):
         t = torch.empty_like(a)
@@ -408,7 +416,7 @@ def main():
     x = torch.empty_like(ee)
     po = torch.empty_like(eo)
     F32 = hisq.HISQ_FP32
-    SLOPPY = hisq.HISQ_Q16  # the sloppy operator reads 16-bit fixed-point links
+    SLOPPY = hisq.HISQ_HALF  # 16-bit links, 16-bit p and A p in the sloppy recurrence
 
     # learned initial guess (an extension beyond the paper), trained like the
     # eigensolve once per gauge field, outside the step
@@ -439,7 +447,8 @@ def main():
         return res
 
     classes = ("dslash", "dslash_aux", "dslash_aux2", "dslash_f32", "dslash_f32_aux",
-               "dslash_f32_aux2", "dslash_q16", "dslash_q16_aux", "blas", "gemm")
+               "dslash_f32_aux2", "dslash_q16", "dslash_q16_aux", "dslash_h16", "dslash_h16_aux",
+               "blas", "gemm")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -463,10 +472,10 @@ def main():
     assert all(all(r.converged) for r in results), "a timed solve did not converge"
 
     # live FP32 half-stencil roofline over the timed region (the CG's stencil)
-    n_plain, ms_plain = prof["dslash_q16"]
-    n_aux, ms_aux = prof["dslash_q16_aux"]
-    bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0, 4, 2)
-                   + n_aux * dslash_alg_bytes(g.vh, nrhs, 1, 4, 2))
+    n_plain, ms_plain = prof["dslash_h16"]
+    n_aux, ms_aux = prof["dslash_h16_aux"]
+    bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0, 4, 2, 16)
+                   + n_aux * dslash_alg_bytes(g.vh, nrhs, 1, 4, 2, 16))
     launches = n_plain + n_aux
     avg_ms = (ms_plain + ms_aux) / max(launches, 1)
     # GB/s = (bytes per launch) / (ms per launch * 1e-3) / 1e9
@@ -543,7 +552,8 @@ def main():
 
     # the timed step with the sloppy operator reading FP32 or BF16 links
     sloppy_links = {}
-    for name, sp, skip in (("fp32_links", F32, False), ("bf16_links", hisq.HISQ_BF16, args.no_bf16)):
+    for name, sp, skip in (("fp32_vectors_16bit_links", hisq.HISQ_Q16, False),
+                           ("fp32_links", F32, False), ("bf16_links", hisq.HISQ_BF16, args.no_bf16)):
         if skip:
             continue
         step_core(False, sp)
@@ -590,13 +600,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "deflated-cg-16^3x32", "lattice": "16x16x16x32", "eps": 0.5,
                    "two_m": two_m, "sources_per_step": nrhs, "n_ev": n_ev, "tol": tol,
-                   "path": ("FP32 eigenvectors; batched mixed-precision CG (FP32 vectors and "
-                            "arithmetic, 16-bit fixed-point links in the sloppy operator, "
-                            "FP64 reductions and reliable updates, delta_rd 0.1), "
-                            "re-deflation at delta_tr 1e-3")},
+                   "path": ("FP32 eigenvectors; batched mixed-precision CG (FP32 arithmetic; "
+                            "16-bit fixed-point links, search direction and A p with a norm "
+                            "per site; FP32 residual and correction; FP64 reductions and "
+                            "reliable updates, delta_rd 0.1), re-deflation at delta_tr "
+                            "1e-3")},
         "roofline": {"bound": "hbm",
-                     "kernel": "k_dslash<float, fvec2, q16c> (half stencil, FP32 vectors, "
-                               "16-bit links, 12 RHS)",
+                     "kernel": "k_dslash<float, h16c, q16c> (half stencil, 16-bit vectors "
+                               "and links, FP32 arithmetic, 12 RHS)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic, "launches_timed": launches, "timed_every": PROFILE_PERIOD,

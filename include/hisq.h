@@ -63,8 +63,18 @@ typedef enum hisq_status {
 
 /* HISQ_Q16: 16-bit fixed-point links (one scale per gauge handle: the largest
  * link component / 32767) with FP32 vectors and arithmetic, for the stencil,
- * M^H M and the CG's sloppy operator only. */
-typedef enum hisq_prec { HISQ_FP64 = 0, HISQ_FP32 = 1, HISQ_BF16 = 2, HISQ_Q16 = 3 } hisq_prec;
+ * M^H M and the CG's sloppy operator only.
+ * HISQ_HALF: as HISQ_Q16, and the CG's search direction p, A p and the odd
+ * temporary held in 16-bit fixed point with one scale per RHS and site (the
+ * largest |component| of its three colours; relative accuracy ~3e-5); for
+ * sloppy_prec only. */
+typedef enum hisq_prec {
+    HISQ_FP64 = 0,
+    HISQ_FP32 = 1,
+    HISQ_BF16 = 2,
+    HISQ_Q16 = 3,
+    HISQ_HALF = 4
+} hisq_prec;
 
 /* hisq_gauge_create flags */
 enum {
@@ -194,7 +204,8 @@ typedef struct hisq_cg_params {
                               the iteration in FP32 with FP64 reliable updates.
                               HISQ_BF16 / HISQ_Q16: the same with the sloppy
                               operator reading BF16 / 16-bit fixed-point links
-                              (vectors still FP32) */
+                              (vectors still FP32).  HISQ_HALF: 16-bit links and
+                              16-bit p, A p (residual and correction FP32) */
     int reliable_interval; /* mixed only: also a reliable update after this many
                               iterations since the last one (0 = only the delta
                               trigger, as in the paper) */
@@ -243,7 +254,7 @@ typedef struct hisq_cg_stats {
  * recomputed true residual confirms it; if the true residual does not, CG
  * continues from it with the search direction kept.  b = 0 gives x = 0.
  *   stats_host: array of nrhs structs, filled on return (may be NULL).
- * With sloppy_prec = HISQ_FP32, HISQ_BF16 or HISQ_Q16 (section 2: the conventional solve is
+ * With sloppy_prec = HISQ_FP32, HISQ_BF16, HISQ_Q16 or HISQ_HALF (section 2: the conventional solve is
  * mixed-precision CG; reliable updates as in section 3) the recurrence runs
  * on FP32 vectors with the FP32 operator and FP64-accumulated dot products;
  * the solution accumulates in FP64, and a reliable update (x += x_sloppy,

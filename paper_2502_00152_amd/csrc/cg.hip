@@ -146,7 +146,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
         m2_rhs = static_cast<const double *>(pm);
     }
     if (params->sloppy_prec == HISQ_FP32 || params->sloppy_prec == HISQ_BF16 ||
-        params->sloppy_prec == HISQ_Q16)
+        params->sloppy_prec == HISQ_Q16 || params->sloppy_prec == HISQ_HALF)
         return solve_mixed(g, two_m, b, x, nrhs, params, stats_host, s, m2_rhs,
                            params->sloppy_prec);
     if (params->sloppy_prec != HISQ_FP64) return fail(HISQ_ERR_INVALID_ARG, "unknown sloppy_prec");

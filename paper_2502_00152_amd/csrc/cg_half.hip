@@ -1,0 +1,177 @@
+// CG vector updates on 16-bit fixed-point fields (h16c with one norm per RHS
+// and site; see dslash_kernel.h) for the mixed-precision CG at sloppy_prec =
+// HISQ_HALF: the search direction p and A p are stored in 16 bits, the
+// residual and the solution correction stay FP32, scalars and partial sums
+// FP64 (the same fixed-order reductions as the FP32 and FP64 updates).
+#include "dslash_kernel.h"
+
+namespace hisq {
+namespace {
+
+constexpr int kBS = 256;
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load_site(const h16c *__restrict__ d, const float *__restrict__ nrm,
+                                          int64_t vh, int j, int64_t cb, fvec2 (&v)[3]) {
+    const float sc = nrm[(int64_t)j * vh + cb] * (1.0f / kQ16);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h16c h = d[((int64_t)j * 3 + c) * vh + cb];
+        v[c] = fvec2{(float)h.x * sc, (float)h.y * sc};
+    }
+}
+
+__device__ __forceinline__ void store_site(h16c *__restrict__ d, float *__restrict__ nrm, int64_t vh,
+                                           int j, int64_t cb, const fvec2 (&v)[3]) {
+    float m = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].x), fabsf(v[c].y)));
+    const float qs = m > 0.0f ? kQ16 / m : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        d[((int64_t)j * 3 + c) * vh + cb] =
+            h16c{(short)rintf(v[c].x * qs), (short)rintf(v[c].y * qs)};
+    nrm[(int64_t)j * vh + cb] = m;
+}
+
+__device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p, int nb) {
+    const int lane = threadIdx.x & (kWave - 1);
+    double v = 0.0;
+    for (int i = lane; i < nb; i += kWave) v += p[i];
+    return wave_sum(v);
+}
+
+// alpha = rho / <p, Ap> (the stencil's fixed-order partials), r -= alpha Ap,
+// per-block partials of ||r||^2.  Grid (blas_reduce_blocks(3 Vh), nrhs).
+__global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restrict__ r,
+                                                    const h16c *__restrict__ ap,
+                                                    const float *__restrict__ apn,
+                                                    const double *__restrict__ pap, int nb_pap,
+                                                    CgDev cg, Reduce red) {
+    const int j = blockIdx.y;
+    __shared__ double pq_s;
+    if (threadIdx.x < kWave) {
+        const double v = wave_sum_partials(pap + (int64_t)j * nb_pap, nb_pap);
+        if (threadIdx.x == 0) pq_s = v;
+    }
+    __syncthreads();
+    const double pq = pq_s;
+    double v[1] = {0.0};
+    if (cg.status[j] == CG_ACTIVE && isfinite(pq) && pq > 0.0) {
+        const float al = (float)(cg.rho[j] / pq);
+        for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
+             cb += (int64_t)gridDim.x * kBS) {
+            fvec2 q[3];
+            load_site(ap, apn, vh, j, cb, q);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int64_t i = ((int64_t)j * 3 + c) * vh + cb;
+                fvec2 rr = r[i];
+                rr.x = fmaf(-al, q[c].x, rr.x);
+                rr.y = fmaf(-al, q[c].y, rr.y);
+                r[i] = rr;
+                v[0] = fma((double)rr.x, (double)rr.x, fma((double)rr.y, (double)rr.y, v[0]));
+            }
+        }
+    }
+    __shared__ double lds[kBS / kWave];
+    block_sum<1, kBS>(v, lds);
+    if (threadIdx.x == 0) red.partials[(int64_t)j * gridDim.x + blockIdx.x] = v[0];
+}
+
+// x += alpha p_old; p = r + beta p_old (mode 2), or only the x update (mode 1)
+__global__ __launch_bounds__(kBS) void k_update_xp_h(int64_t vh, fvec2 *__restrict__ x,
+                                                     const fvec2 *__restrict__ r,
+                                                     h16c *__restrict__ p, float *__restrict__ pn,
+                                                     CgDev cg) {
+    const int j = blockIdx.y;
+    const int mode = cg.xp_mode[j];
+    if (mode == 0) return;
+    const float al = (float)cg.xp_alpha[j], be = (float)cg.xp_beta[j];
+    for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
+         cb += (int64_t)gridDim.x * kBS) {
+        fvec2 pp[3];
+        load_site(p, pn, vh, j, cb, pp);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t i = ((int64_t)j * 3 + c) * vh + cb;
+            fvec2 xx = x[i];
+            xx.x = fmaf(al, pp[c].x, xx.x);
+            xx.y = fmaf(al, pp[c].y, xx.y);
+            x[i] = xx;
+            if (mode == 2) {
+                const fvec2 rr = r[i];
+                pp[c] = fvec2{fmaf(be, pp[c].x, rr.x), fmaf(be, pp[c].y, rr.y)};
+            }
+        }
+        if (mode == 2) store_site(p, pn, vh, j, cb, pp);
+    }
+}
+
+// p = r + beta p (mode 1) or p = r (mode 2) per RHS; mode == null: p = r for all
+__global__ __launch_bounds__(kBS) void k_p_restart_h(int64_t vh, h16c *__restrict__ p,
+                                                     float *__restrict__ pn,
+                                                     const fvec2 *__restrict__ r,
+                                                     const double *__restrict__ beta,
+                                                     const int *__restrict__ mode) {
+    const int j = blockIdx.y;
+    const int m = mode ? mode[j] : 2;
+    if (m == 0) return;
+    const float be = m == 1 ? (float)beta[j] : 0.0f;
+    for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
+         cb += (int64_t)gridDim.x * kBS) {
+        fvec2 pp[3];
+        if (m == 1) load_site(p, pn, vh, j, cb, pp);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const fvec2 rr = r[((int64_t)j * 3 + c) * vh + cb];
+            pp[c] = m == 1 ? fvec2{fmaf(be, pp[c].x, rr.x), fmaf(be, pp[c].y, rr.y)} : rr;
+        }
+        store_site(p, pn, vh, j, cb, pp);
+    }
+}
+
+int site_blocks(int64_t vh) {
+    const int64_t b = (vh + kBS - 1) / kBS;
+    return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+}  // namespace
+
+int64_t half_field_bytes(int64_t vh, int nrhs) { return (int64_t)nrhs * vh * (3 * 4 + 4); }
+
+hisq_status half_update_r(int64_t vh, int nrhs, float2 *r, const void *ap, const double *pap,
+                          int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s) {
+    const h16c *d = static_cast<const h16c *>(ap);
+    const float *nrm = reinterpret_cast<const float *>(d + (int64_t)nrhs * 3 * vh);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_update_r_h, dim3(blas_reduce_blocks(3 * vh), nrhs), dim3(kBS), 0, s, vh,
+                       reinterpret_cast<fvec2 *>(r), d, nrm, pap, nb_pap, cg, red);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status half_update_xp(int64_t vh, int nrhs, float2 *x, const float2 *r, void *p,
+                           const CgDev &cg, hipStream_t s) {
+    h16c *d = static_cast<h16c *>(p);
+    float *nrm = reinterpret_cast<float *>(d + (int64_t)nrhs * 3 * vh);
+    ProfileScope prof("blas", s);
+    hipLaunchKernelGGL(k_update_xp_h, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh,
+                       reinterpret_cast<fvec2 *>(x), reinterpret_cast<const fvec2 *>(r), d, nrm,
+                       cg);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status half_p_restart(int64_t vh, int nrhs, void *p, const float2 *r, const double *beta,
+                           const int *mode, hipStream_t s) {
+    h16c *d = static_cast<h16c *>(p);
+    float *nrm = reinterpret_cast<float *>(d + (int64_t)nrhs * 3 * vh);
+    hipLaunchKernelGGL(k_p_restart_h, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh, d, nrm,
+                       reinterpret_cast<const fvec2 *>(r), beta, mode);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+}  // namespace hisq

@@ -5,8 +5,9 @@
 // since the last deflation).
 //
 // The recurrence runs on FP32 vectors with the FP32 operator (links in FP32,
-// in BF16 at sloppy_prec = HISQ_BF16, or 16-bit fixed point at HISQ_Q16); its
-// dot products and all scalars are FP64.  The solution accumulates in FP64: the FP32
+// in BF16 at sloppy_prec = HISQ_BF16, or 16-bit fixed point at HISQ_Q16; at
+// HISQ_HALF also p, A p and the odd temporary in 16-bit fixed point with a
+// norm per site); its dot products and all scalars are FP64.  The solution accumulates in FP64: the FP32
 // correction x_s is added to x at every reliable update, where the residual is
 // recomputed in FP64 with the FP64 operator, r = b - A x, and replaces the
 // iterated one.  A right-hand side gets a reliable update
@@ -46,6 +47,11 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
                         const hisq_cg_params *P, hisq_cg_stats *stats, hipStream_t s,
                         const double *m2_rhs, hisq_prec links) {
     const bool bf16_links = links == HISQ_BF16, q16_links = links == HISQ_Q16;
+    // HISQ_HALF: p, A p and the odd temporary in 16-bit fixed point (one norm
+    // per RHS and site, in the same buffers: 16 of their 24 bytes per site),
+    // 16-bit links; r and the correction x_s stay FP32
+    const bool half = links == HISQ_HALF;
+    const int64_t vh = g->geom.vh;
     const int64_t n = 3 * (int64_t)g->geom.vh;
     const int interval = P->check_interval > 0 ? P->check_interval : 16;
     const int par = P->parity;
@@ -77,7 +83,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     // the sloppy links are made here, not inside a captured iteration chunk
     if (bf16_links) HISQ_TRY(ensure_links_bf16(g, s));
-    else if (q16_links) HISQ_TRY(ensure_links_q16(g, s));
+    else if (q16_links || half) HISQ_TRY(ensure_links_q16(g, s));
     else HISQ_TRY(ensure_links_f32(g, s));
 
     // ------------------------------------------------------------ buffers
@@ -191,7 +197,8 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     HISQ_TRY(cg_init(n, nrhs, b, Ax, r, p64, P->tol, dev, red, s));
     HISQ_HIP(hipMemcpyAsync(dev.rho_ru, dev.rho, dn, hipMemcpyDeviceToDevice, s));
     HISQ_TRY(mixed_to_f32(r, rs, n, nrhs, nullptr, s));
-    HISQ_HIP(hipMemcpyAsync(ps, rs, v32, hipMemcpyDeviceToDevice, s));
+    if (half) HISQ_TRY(half_p_restart(vh, nrhs, ps, rs, nullptr, nullptr, s));
+    else HISQ_HIP(hipMemcpyAsync(ps, rs, v32, hipMemcpyDeviceToDevice, s));
     HISQ_HIP(hipMemsetAsync(xs, 0, v32, s));
     HISQ_TRY(d2h(h_rho, dev.rho, dn));
     HISQ_TRY(d2h(h_b2, dev.bnorm2, dn));
@@ -210,6 +217,16 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     const double m2 = two_m * two_m;
 
     auto iterate = [&]() -> hisq_status {
+        if (half) {
+            HISQ_TRY(launch_dslash_h16(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, 1.0, nullptr, s,
+                                       nullptr, dev.status));
+            HISQ_TRY(launch_dslash_h16(g, par, t32, Aps, nrhs, ps, m2, -1.0, pap.partials, s,
+                                       m2_rhs, dev.status));
+            HISQ_TRY(half_update_r(vh, nrhs, rs, Aps, pap.partials, nb_pap, dev, red, s));
+            HISQ_TRY(cg_finalize(n, nrhs, pap.partials, nb_pap, dev, red, s));
+            HISQ_TRY(half_update_xp(vh, nrhs, xs, rs, ps, dev, s));
+            return HISQ_OK;
+        }
         if (bf16_links) {
             HISQ_TRY(launch_dslash_f32_bl(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, 1.0, nullptr, s,
                                           nullptr, dev.status));
@@ -362,7 +379,8 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
         HISQ_TRY(h2d(d_rbeta, h_rbeta, dn));
         HISQ_TRY(h2d(d_mode, h_mode, in_));
         HISQ_TRY(h2d(dev.ru_flag, h_flag, in_));
-        HISQ_TRY(mixed_p_restart(ps, rs, n, nrhs, d_rbeta, d_mode, s));
+        if (half) HISQ_TRY(half_p_restart(vh, nrhs, ps, rs, d_rbeta, d_mode, s));
+        else HISQ_TRY(mixed_p_restart(ps, rs, n, nrhs, d_rbeta, d_mode, s));
     }
 
     // fold any remaining FP32 correction into x; b = 0 gives x = 0

@@ -32,6 +32,7 @@
 #pragma once
 
 #include <cstdint>
+#include <type_traits>
 
 #include "device_util.h"
 #include "hisq_internal.h"
@@ -93,6 +94,15 @@ struct Conv<bf16c> {
     }
 };
 
+// A colour vector field in 16-bit fixed point: each complex as two int16
+// (vec2<short>), and after the [nrhs][3][Vh] entries one float per (RHS, site),
+// [nrhs][Vh]: the largest |component| of the site's three colours.  Value =
+// integer * norm / 32767 (relative accuracy ~3e-5 per site, any magnitude).
+using h16c = vec2<short>;
+template <typename VS>
+constexpr bool is_normed() { return std::is_same<VS, h16c>::value; }
+constexpr float kQ16 = 32767.0f;
+
 // Launch shape of the half stencil: NR RHS per lane, LPS lanes per site, the
 // XCD-contiguous block order and the order of site blocks and RHS groups.
 struct DslashShape {
@@ -122,6 +132,9 @@ struct DslashArgs {
     VS *out;                 // [nrhs][3][Vh], parity p
     const VS *aux;           // [nrhs][3][Vh], parity p (optional)
     const VS *aux2;          // [nrhs][3][Vh], parity p (optional; may alias out)
+    const float *in_norm;    // per-site norms of in, aux and out (h16c fields only)
+    const float *aux_norm;
+    float *out_norm;
     R ca, cb, cd;
     const double *ca_rhs;  // per-RHS ca (device, indexed by RHS), or null for ca
     const int *rhs_status; // CG state per RHS (device) or null: a block whose RHS
@@ -207,7 +220,8 @@ __device__ __forceinline__ void hop_fence(V (&acc)[NR][3]) {
 template <int NR, bool NT, typename R, typename VS, typename LS>
 __device__ __forceinline__ void hop_forward(const LS *__restrict__ U, int vh, uint32_t uoff,
                                             const VS *__restrict__ in, uint32_t voff,
-                                            const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
+                                            const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3],
+                                            const float *__restrict__ nrm) {
     using V = vec2<R>;
     V u[9];
     const gptr<const LS> up = at(U, uoff);
@@ -216,9 +230,16 @@ __device__ __forceinline__ void hop_forward(const LS *__restrict__ U, int vh, ui
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         {
-            const V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
-            const V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
-            const V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
+            V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
+            V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
+            V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
+            if constexpr (is_normed<VS>()) {
+                // the norm plane: one float per (RHS, site), RHS offset roff / 3
+                const R sc = (R)(*at(nrm, roff[r] / 3 + voff) * (1.0f / kQ16));
+                v0 *= sc;
+                v1 *= sc;
+                v2 *= sc;
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 V s = acc[r][a];
@@ -239,7 +260,8 @@ __device__ __forceinline__ void hop_forward(const LS *__restrict__ U, int vh, ui
 template <int NR, bool NT, typename R, typename VS, typename LS>
 __device__ __forceinline__ void hop_backward(const LS *__restrict__ U, int vh, uint32_t uoff,
                                              const VS *__restrict__ in, uint32_t voff,
-                                             const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
+                                             const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3],
+                                             const float *__restrict__ nrm) {
     using V = vec2<R>;
     V u[9];
     const gptr<const LS> up = at(U, uoff);
@@ -248,9 +270,16 @@ __device__ __forceinline__ void hop_backward(const LS *__restrict__ U, int vh, u
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         {
-            const V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
-            const V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
-            const V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
+            V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
+            V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
+            V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
+            if constexpr (is_normed<VS>()) {
+                // the norm plane: one float per (RHS, site), RHS offset roff / 3
+                const R sc = (R)(*at(nrm, roff[r] / 3 + voff) * (1.0f / kQ16));
+                v0 *= sc;
+                v1 *= sc;
+                v2 *= sc;
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 // (U^H)_{ab} = conj(U_{ba})
@@ -340,6 +369,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
             for (int c = 0; c < 3; ++c) acc[r][c] = V{R(0), R(0)};
 
         const VS *in = a.in + (int64_t)rg0 * 3 * vh;
+        const float *nrm_in = is_normed<VS>() ? a.in_norm + (int64_t)rg0 * vh : nullptr;
         uint32_t roff[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -358,36 +388,73 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
                 const int f = (rowYZT * g.X + wrap(x + hop, g.X)) >> 1;
                 const int b = (rowYZT * g.X + wrap(x - hop, g.X)) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
-                hop_backward<NR, NT, R>(Ui, vh, link_off<LS>(b), in, bo, roff, acc);
+                hop_forward<NR, NT, R>(Uo, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
+                hop_backward<NR, NT, R>(Ui, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
             }
             // mu = 1 (y)
             {
                 const int f = ((((t * g.Z + z) * g.Y + wrap(y + hop, g.Y)) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + z) * g.Y + wrap(y - hop, g.Y)) * g.X) + x) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo + lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
-                hop_backward<NR, NT, R>(Ui + lstride, vh, link_off<LS>(b), in, bo, roff, acc);
+                hop_forward<NR, NT, R>(Uo + lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
+                hop_backward<NR, NT, R>(Ui + lstride, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
             }
             // mu = 2 (z)
             {
                 const int f = ((((t * g.Z + wrap(z + hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + wrap(z - hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
-                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, link_off<LS>(b), in, bo, roff, acc);
+                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
+                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
             }
             // mu = 3 (t)
             {
                 const int f = ((((wrap(t + hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((wrap(t - hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
-                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<LS>(b), in, bo, roff, acc);
+                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
+                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
             }
         }
 
         // epilogue
+        if constexpr (is_normed<VS>()) {
+            // a site's three colours share one norm: form them all, then round
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r < nr) {
+                    const uint32_t off = qoff + own, noff = qoff / 3 + own;
+                    V o[3], ax[3];
+                    R asc = 0;
+                    if (AUX) asc = (R)(*at(a.aux_norm + (int64_t)(rg0 + r) * vh, noff) * (1.0f / kQ16));
+                    R m = 0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int64_t plane = (int64_t)(rg0 * 3 + 3 * r + c) * vh;
+                        o[c] = acc[r][c] * a.cd;
+                        if (AUX) {
+                            ax[c] = Conv<VS>::template ld<R>(*at(a.aux + plane, off)) * asc;
+                            const R ca = a.ca_rhs ? (R)a.ca_rhs[rg0 + q * NR + r] : a.ca;
+                            o[c].x = fma(ca, ax[c].x, o[c].x);
+                            o[c].y = fma(ca, ax[c].y, o[c].y);
+                        }
+                        m = fmax(m, fmax(fabs(o[c].x), fabs(o[c].y)));
+                    }
+                    const R qs = m > 0 ? (R)kQ16 / m : (R)0, ds = m * (R)(1.0f / kQ16);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int64_t plane = (int64_t)(rg0 * 3 + 3 * r + c) * vh;
+                        const short qx = (short)rintf((float)(o[c].x * qs));
+                        const short qy = (short)rintf((float)(o[c].y * qs));
+                        *at(a.out + plane, off) = VS{qx, qy};
+                        if (AUX && DOT)  // the partial of the stored (rounded) output
+                            dotv[r] = fma((double)ax[c].x, (double)(qx * ds),
+                                          fma((double)ax[c].y, (double)(qy * ds), dotv[r]));
+                    }
+                    *at(a.out_norm + (int64_t)(rg0 + r) * vh, noff) = (float)m;
+                }
+            }
+        } else {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r < nr) {
@@ -413,6 +480,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
                     *at(a.out + plane, off) = Conv<VS>::template st<R>(o);
                 }
             }
+        }
         }
     }
 
@@ -476,6 +544,8 @@ hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *
                             DslashShape sh, hipStream_t s, const double *ca_rhs = nullptr,
                             const int *rhs_status = nullptr) {
     if (aux2 && !aux) return fail(HISQ_ERR_INVALID_ARG, "dslash: aux2 needs aux");
+    if (is_normed<VS>() && aux2)
+        return fail(HISQ_ERR_INVALID_ARG, "dslash: no second epilogue field for 16-bit vectors");
     if (!shape_fits(sh.nr, sh.lps, geom.vh, sizeof(VS) / 2))
         return fail(HISQ_ERR_INVALID_ARG, "dslash: RHS group too large for this volume");
     DslashArgs<R, VS, LS> a{};
@@ -488,6 +558,12 @@ hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *
     a.out = out;
     a.aux = aux;
     a.aux2 = aux2;
+    if (is_normed<VS>()) {  // norm planes follow the nrhs x 3 x Vh entries
+        const int64_t ne = (int64_t)nrhs * 3 * geom.vh;
+        a.in_norm = reinterpret_cast<const float *>(in + ne);
+        a.aux_norm = aux ? reinterpret_cast<const float *>(aux + ne) : nullptr;
+        a.out_norm = reinterpret_cast<float *>(out + ne);
+    }
     a.ca = (R)ca;
     a.cb = (R)cb;
     a.cd = (R)cd;

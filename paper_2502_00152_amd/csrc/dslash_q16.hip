@@ -118,3 +118,24 @@ hisq_status apply_mdagm_q16(hisq_gauge_s *g, double two_m, const float2 *in, flo
 }
 
 }  // namespace hisq
+
+namespace hisq {
+
+// 16-bit vectors (h16c fields with per-site norms) and 16-bit links: the
+// sloppy operator at sloppy_prec = HISQ_HALF.
+hisq_status launch_dslash_h16(hisq_gauge_s *g, int out_parity, const void *in, void *out,
+                              int nrhs, const void *aux, double ca, double cd, double *partials,
+                              hipStream_t s, const double *ca_rhs, const int *rhs_status) {
+    HISQ_TRY(ensure_links_q16(g, s));
+    const q16c *fat[2] = {g->fatq[0], g->fatq[1]};
+    const q16c *lng[2] = {g->lngq[0], g->lngq[1]};
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, true);
+    HISQ_TRY(dslash_check_shape(sh));
+    ProfileScope prof(aux ? "dslash_h16_aux" : "dslash_h16", s);
+    return dslash_impl::launch_dslash_t<float, h16c, q16c>(
+        g->geom, fat, lng, out_parity, static_cast<const h16c *>(in), static_cast<h16c *>(out),
+        nrhs, static_cast<const h16c *>(aux), ca, nullptr, 0.0, cd * g->q16_step, partials, sh, s,
+        ca_rhs, rhs_status);
+}
+
+}  // namespace hisq

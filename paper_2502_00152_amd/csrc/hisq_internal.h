@@ -256,6 +256,21 @@ hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 
                                   const int *rhs_status = nullptr);
 hisq_status apply_mdagm_q16(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out, int nrhs,
                             hipStream_t s);
+// 16-bit fixed-point vector fields (HISQ_HALF): [nrhs][3][Vh] int16 pairs, then
+// [nrhs][Vh] float norms (the largest |component| of the site); the stencil
+// with 16-bit links, and the CG updates on such p and A p
+int64_t half_field_bytes(int64_t vh, int nrhs);
+hisq_status launch_dslash_h16(hisq_gauge_s *g, int out_parity, const void *in, void *out,
+                              int nrhs, const void *aux, double ca, double cd, double *partials,
+                              hipStream_t s, const double *ca_rhs = nullptr,
+                              const int *rhs_status = nullptr);
+hisq_status half_update_r(int64_t vh, int nrhs, float2 *r, const void *ap, const double *pap,
+                          int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s);
+hisq_status half_update_xp(int64_t vh, int nrhs, float2 *x, const float2 *r, void *p,
+                           const CgDev &cg, hipStream_t s);
+// p = r + beta p (mode 1) or p = r (mode 2) per RHS; mode null: p = r for all
+hisq_status half_p_restart(int64_t vh, int nrhs, void *p, const float2 *r, const double *beta,
+                           const int *mode, hipStream_t s);
 
 // The CG drivers run on the handle's own non-blocking stream (created on first
 // use, default priority), ordered after the caller's stream on entry and

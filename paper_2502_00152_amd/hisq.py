@@ -34,7 +34,7 @@ HISQ_ERR_UNSUPPORTED = 7
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED", 5: "NAN",
                 6: "BREAKDOWN", 7: "UNSUPPORTED"}
 
-HISQ_FP64, HISQ_FP32, HISQ_BF16, HISQ_Q16 = 0, 1, 2, 3
+HISQ_FP64, HISQ_FP32, HISQ_BF16, HISQ_Q16, HISQ_HALF = 0, 1, 2, 3, 4
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
 ABI_VERSION = 8

@@ -311,3 +311,57 @@ def test_cg_with_q16_links_keeps_fp32_iterations(w8):
         tr = O.norm(pr.y[j] - O.apply_A(pr.F, pr.L, pr.two_m, full)) / O.norm(pr.y[j])
         assert tr <= tol
     assert max(res.iterations) <= 1.05 * max(r32.iterations) + 8, (res.iterations, r32.iterations)
+
+
+# ------------------------------------- 16-bit vectors in the CG (HISQ_HALF)
+def test_cg_with_half_vectors_meets_fp64_residual(w8):
+    """p, A p and the odd temporary in 16-bit fixed point with one norm per
+    site (~3e-5 relative), 16-bit links: the FP64 true residual decides, the
+    iteration count stays that of FP32 vectors, and the solution is within
+    ||A^-1|| (r_gpu + r_oracle) ||b|| of the oracle's."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = w8
+    tol = 1e-10
+    bs = to_parity(pr.y, pr.dims, 0)
+    b = dev(bs)
+    x = torch.zeros_like(b)
+    res = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=tol, sloppy_prec=hisq.HISQ_HALF)
+    assert all(res.converged)
+    r32 = hisq.hisq_cg_solve(pr.g, pr.two_m, b, torch.zeros_like(b), tol=tol,
+                             sloppy_prec=hisq.HISQ_FP32)
+    xs = host(x)
+    for j in range(3):
+        full = from_parity(xs[j:j + 1], pr.dims, 0)[0]
+        tr = O.norm(pr.y[j] - O.apply_A(pr.F, pr.L, pr.two_m, full)) / O.norm(pr.y[j])
+        assert tr <= tol
+        xo, _, _ = O.solve_even(pr.F, pr.L, pr.two_m, pr.y[j], tol=1e-13)
+        bound = (tr + 1e-13) * np.linalg.norm(bs[j]) / pr.two_m ** 2
+        assert np.linalg.norm(xs[j] - to_parity(xo, pr.dims, 0)[0]) <= bound
+    assert max(res.iterations) <= 1.05 * max(r32.iterations) + 8, (res.iterations, r32.iterations)
+
+
+def test_cg_half_batch_equals_single_solves(w8):
+    """Quantisation is per (RHS, site) and the <p, Ap> partials are summed in
+    one order for any launch shape, so a batch equals separate solves bitwise."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = w8
+    b = dev(to_parity(pr.y, pr.dims, 0))
+    x = torch.zeros_like(b)
+    rb = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=1e-10, sloppy_prec=hisq.HISQ_HALF)
+    for j in range(3):
+        xj = torch.zeros_like(b[j:j + 1])
+        rj = hisq.hisq_cg_solve(pr.g, pr.two_m, b[j:j + 1].clone(), xj, tol=1e-10,
+                                sloppy_prec=hisq.HISQ_HALF)
+        assert rj.iterations[0] == rb.iterations[j]
+        assert torch.equal(xj[0], x[j])
+
+
+def test_half_is_a_solver_precision_only(prob):
+    import torch
+    from paper_2502_00152_amd import hisq
+    a = torch.zeros((1, 3, prob.g.vh), dtype=torch.complex64, device="cuda")
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.hisq_dslash_eo(prob.g, 0, a, torch.empty_like(a), prec=hisq.HISQ_HALF)
+    assert e.value.status == hisq.HISQ_ERR_INVALID_ARG

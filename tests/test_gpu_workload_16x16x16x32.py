@@ -210,9 +210,11 @@ def test_q16_stencil_sampled_sites(wl):
     print(f"[16x16x16x32] q16 stencil: worst error / bound {worst:.3f}", flush=True)
 
 
-def test_timed_step_q16_links_multi_deflation(wl, eig):
+@pytest.mark.parametrize("sloppy", ["q16", "half"])
+def test_timed_step_16bit_multi_deflation(wl, eig, sloppy):
     """The timed step of the benchmark: FP32 eigenvectors, mixed CG whose
-    sloppy operator reads 16-bit links, re-deflation at delta_tr = 1e-3.
+    sloppy operator reads 16-bit links (and, for "half", whose p and A p are
+    held in 16 bits), re-deflation at delta_tr = 1e-3.
     Oracle-evaluated FP64 true residual <= 1e-10 on two sources, the solution
     within (||r|| + ||r'||) / lambda_1 of the FP64 path's, and the iteration
     count of the FP32-link path."""
@@ -233,9 +235,10 @@ def test_timed_step_q16_links_multi_deflation(wl, eig):
 
     x64, r64 = solve(ev)
     kw = dict(reliable_delta=0.1, evecs=ev32, evals=eps, tol_restart=1e-3)
-    xq, rq = solve(ev32, sloppy_prec=hisq.HISQ_Q16, **kw)
+    sp = hisq.HISQ_Q16 if sloppy == "q16" else hisq.HISQ_HALF
+    xq, rq = solve(ev32, sloppy_prec=sp, **kw)
     _, rf = solve(ev32, sloppy_prec=hisq.HISQ_FP32, **kw)
-    print(f"[16x16x16x32] timed step iterations: q16 {max(rq.iterations)}, "
+    print(f"[16x16x16x32] timed step iterations: {sloppy} {max(rq.iterations)}, "
           f"fp32 links {max(rf.iterations)}, fp64 {max(r64.iterations)}", flush=True)
     assert max(rq.iterations) <= max(rf.iterations) + 3
     xs, ys, x64s = host(xq), host(wl.y), host(x64)
