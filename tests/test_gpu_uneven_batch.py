@@ -52,11 +52,11 @@ def batch():
         d["g"].close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "half"])
 def test_uneven_batch_concurrent(batch, prec):
     import torch
     from paper_2502_00152_amd import hisq
-    sp = hisq.HISQ_FP64 if prec == "fp64" else hisq.HISQ_FP32
+    sp = {"fp64": hisq.HISQ_FP64, "fp32": hisq.HISQ_FP32, "half": hisq.HISQ_HALF}[prec]
     systems = [(d["g"], d["masses"], d["b"], torch.zeros_like(d["b"])) for d in batch]
     t0 = time.time()
     res = hisq.hisq_cg_solve_multi(systems, tol=1e-10, sloppy_prec=sp)

@@ -159,7 +159,8 @@ def test_eigenpairs_sampled_against_oracle(wl, eig):
     assert np.all(np.diff(lam) >= 0) and lam[0] > wl.two_m ** 2
 
 
-def test_mixed_multi_deflation_24rhs(wl, eig):
+@pytest.mark.parametrize("sloppy", ["fp32", "half"])
+def test_mixed_multi_deflation_24rhs(wl, eig, sloppy):
     """The 24-RHS mixed-precision solve with FP32 eigenvectors and re-deflation
     at delta_tr = 1e-3 against the FP64 path: both meet the FP64 true residual
     1e-10 (oracle-evaluated for two sources), the solutions agree within the
@@ -173,7 +174,8 @@ def test_mixed_multi_deflation_24rhs(wl, eig):
     t0 = time.time()
     x = torch.empty_like(wl.y)
     hisq.hisq_deflate(wl.g, ev32, eps, wl.two_m, wl.y, x)
-    rm = hisq.hisq_cg_solve(wl.g, wl.two_m, wl.y, x, tol=1e-10, sloppy_prec=hisq.HISQ_FP32,
+    sp = hisq.HISQ_FP32 if sloppy == "fp32" else hisq.HISQ_HALF
+    rm = hisq.hisq_cg_solve(wl.g, wl.two_m, wl.y, x, tol=1e-10, sloppy_prec=sp,
                             evecs=ev32, evals=eps, tol_restart=1e-3)
     torch.cuda.synchronize()
     t1 = time.time()
@@ -182,7 +184,7 @@ def test_mixed_multi_deflation_24rhs(wl, eig):
     r64 = hisq.hisq_cg_solve(wl.g, wl.two_m, wl.y, x64, tol=1e-10)
     torch.cuda.synchronize()
     t2 = time.time()
-    say(f"mixed {max(rm.iterations)} it {t1 - t0:.2f}s ({min(rm.redeflations)}-"
+    say(f"mixed ({sloppy}) {max(rm.iterations)} it {t1 - t0:.2f}s ({min(rm.redeflations)}-"
         f"{max(rm.redeflations)} re-deflations), FP64 {max(r64.iterations)} it {t2 - t1:.2f}s")
     assert all(rm.converged) and all(r64.converged)
     assert max(rm.iterations) <= 1.1 * max(r64.iterations) + 10
