@@ -12,7 +12,8 @@ One step solves the 12 sources end to end on the GPU, inputs already resident
 in HBM, with the paper's production method (sections 2 and 3): source
 preparation y_e = 2m eta_e - D_eo eta_o (FP64); deflation guess
 x0 = V diag(1/lambda) V^H y_e with single-precision eigenvectors; batched
-mixed-precision CG (FP32 stencil and vectors, FP64 dot products, FP64
+mixed-precision CG (16-bit fixed-point links, search direction and A p
+with a norm per site, FP32 residual and correction, FP64 dot products, FP64
 reliable updates at delta_rd = 0.1) with re-deflation whenever the true
 residual has fallen by delta_tr = 1e-3 since the last deflation, to
 ||y - A x|| <= 1e-10 ||y||; odd reconstruction psi_o = (eta_o - D_oe psi_e) / (2m)
@@ -25,8 +26,9 @@ Also reported: the same step in FP64 throughout (FP64 eigenvectors, single
 deflation, FP64 CG), plain FP64 even-odd CG (no deflation, one source at a
 time), the relative difference of the mixed solutions from the FP64 ones, the
 half-stencil bandwidth at 32^3 x 64 (beyond the 256 MB last-level cache) in
-both precisions, the FP32 half-stencil roofline measured live with HIP events
-inside the timed region, and the oracle timed on the host cores.
+FP64, FP32 and BF16, the roofline of the CG's 16-bit half stencil measured
+live with HIP events inside the timed region, and the oracle timed on the
+host cores.
 """
 from __future__ import annotations
 
@@ -47,6 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed instructions (disabled in every kernel here):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# two-way int16 dot products (two multiply-adds per lane and cycle), the form
+# the 16-bit stencil computes its products in: 157.3 T ops/s
+DOT2_VALU_PEAK_TOPS = 2 * FP32_VALU_PEAK_TFLOPS
 STENCIL_FLOPS_PER_SITE_RHS = 16 * 66 + 15 * 6  # 16 SU(3) x vector products and their sum
 PROFILE_PERIOD = 16
 LEARNED_PAIRS = 128   # training pairs the solver generates for the learned guess
@@ -475,7 +480,7 @@ def main():
     true_res = max(max(r.true_residual) for r in results)
     assert all(all(r.converged) for r in results), "a timed solve did not converge"
 
-    # live FP32 half-stencil roofline over the timed region (the CG's stencil)
+    # live roofline of the CG's 16-bit half stencil over the timed region
     n_plain, ms_plain = prof["dslash_h16"]
     n_aux, ms_aux = prof["dslash_h16_aux"]
     bytes_total = (n_plain * dslash_alg_bytes(g.vh, nrhs, 0, 4, 2, 16)
@@ -484,8 +489,9 @@ def main():
     avg_ms = (ms_plain + ms_aux) / max(launches, 1)
     # GB/s = (bytes per launch) / (ms per launch * 1e-3) / 1e9
     hbm_achieved = bytes_total / max(launches, 1) / avg_ms / 1e6 if launches else None
-    # the same launches in flops: at 16-bit storage the stencil does 13 flop per
-    # algorithmic byte, above the FP32 ridge (78.6 TFLOP/s / 8 TB/s = 9.8)
+    # the same launches in operations: 13 per algorithmic byte, below the ridge
+    # of the int16 dot-product rate (157.3 T ops/s / 8 TB/s = 19.7), so the
+    # bound is HBM bandwidth
     flops_launch = STENCIL_FLOPS_PER_SITE_RHS * nrhs * g.vh
     achieved = flops_launch / avg_ms / 1e9 if launches else None
     traffic = read_traffic()
@@ -613,22 +619,24 @@ def main():
                             "per site; FP32 residual and correction; FP64 reductions and "
                             "reliable updates, delta_rd 0.1), re-deflation at delta_tr "
                             "1e-3")},
-        "roofline": {"bound": "alu",
+        "roofline": {"bound": "hbm",
                      "kernel": "k_dslash<float, h16c, q16c> (half stencil, 16-bit vectors "
-                               "and links, FP32 arithmetic, 12 RHS)",
-                     "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VALU_PEAK_TFLOPS if achieved else None,
+                               "and links, int16 dot products, FP32 accumulation, 12 RHS)",
+                     "achieved": hbm_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hbm_achieved / HBM_PEAK_GBS if hbm_achieved else None,
                      "traffic": traffic, "launches_timed": launches, "timed_every": PROFILE_PERIOD,
                      "avg_launch_us": avg_ms * 1e3,
-                     "flops_per_launch": flops_launch,
                      "alg_bytes_per_launch": bytes_total / max(launches, 1),
-                     "arith_intensity_flop_per_byte": flops_launch / (bytes_total / max(launches, 1))
+                     "ops_per_launch": flops_launch,
+                     "arith_intensity_op_per_byte": flops_launch / (bytes_total / max(launches, 1))
                      if launches else None,
-                     "hbm_achieved_GB_s": hbm_achieved,
-                     "hbm_frac": hbm_achieved / HBM_PEAK_GBS if hbm_achieved else None,
-                     "peak_note": ("FP32 FMA rate without packed instructions (disabled in "
-                                   "every kernel); 157.3 TFLOP/s with them")},
+                     "alu_achieved_Tops": achieved,
+                     "alu_peak_Tops": DOT2_VALU_PEAK_TOPS,
+                     "alu_frac": achieved / DOT2_VALU_PEAK_TOPS if achieved else None,
+                     "peak_note": ("algorithmic bytes per launch / average launch time (HIP "
+                                   "events) against 8 TB/s; ops = the 1146 flops per site and "
+                                   "RHS of the FP32 stencil, here as int16 dot products "
+                                   "(157.3 T ops/s, ridge 19.7 op/B)")},
         "cpu_baseline": cpu,
         "iterations_per_source": last.iterations,
         "reliable_updates_per_source": last.reliable_updates,

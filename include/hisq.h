@@ -64,10 +64,12 @@ typedef enum hisq_status {
 /* HISQ_Q16: 16-bit fixed-point links (one scale per gauge handle: the largest
  * link component / 32767) with FP32 vectors and arithmetic, for the stencil,
  * M^H M and the CG's sloppy operator only.
- * HISQ_HALF: as HISQ_Q16, and the CG's search direction p, A p and the odd
- * temporary held in 16-bit fixed point with one scale per RHS and site (the
- * largest |component| of its three colours; relative accuracy ~3e-5); for
- * sloppy_prec only. */
+ * HISQ_HALF: the CG's search direction p, A p and the odd temporary held in
+ * 16-bit fixed point with one scale per RHS and site (the largest |component|
+ * of its three colours; relative accuracy ~3e-5), and links in 16-bit fixed
+ * point with components up to 10922 (scale: the largest link component /
+ * 10922, ~5e-5 absolute error), so that the stencil sums the integer products
+ * of a link row and a colour vector exactly in 32 bits; for sloppy_prec only. */
 typedef enum hisq_prec {
     HISQ_FP64 = 0,
     HISQ_FP32 = 1,

@@ -119,6 +119,8 @@ hisq_status hisq_gauge_destroy(hisq_gauge g) {
         if (g->lng16[p]) (void)hipFree(g->lng16[p]);
         if (g->fatq[p]) (void)hipFree(g->fatq[p]);
         if (g->lngq[p]) (void)hipFree(g->lngq[p]);
+        if (g->fatn[p]) (void)hipFree(g->fatn[p]);
+        if (g->lngn[p]) (void)hipFree(g->lngn[p]);
     }
     g->ws.release();
     if (g->cg_stream) (void)hipStreamDestroy(g->cg_stream);

@@ -102,6 +102,29 @@ using h16c = vec2<short>;
 template <typename VS>
 constexpr bool is_normed() { return std::is_same<VS, h16c>::value; }
 constexpr float kQ16 = 32767.0f;
+// Largest link component of the fixed-point links read with 16-bit vectors:
+// six products |link| <= 10922 times |vector| <= 32767 sum to at most
+// 2147287044 < 2^31, so the integer dot products of a link row and a colour
+// vector cannot overflow.
+constexpr int kQLinkNarrow = 10922;
+// hops whose loads are in flight while a hop's arithmetic runs (16-bit path)
+#ifndef HISQ_INT_LOOKAHEAD
+#define HISQ_INT_LOOKAHEAD 1
+#endif
+constexpr int kIntLookahead = HISQ_INT_LOOKAHEAD;
+// Lookahead that still fits the registers of a lane: a block of 256 LPS lanes
+// leaves 512 / LPS registers (at most 256) per lane; a hop's loads take
+// 9 + 4 NR, the accumulators 6 NR, the rearranged links and addresses ~48.
+constexpr int int_lookahead(int nr, int lps) {
+    const int cap = (512 / lps < 256 ? 512 / lps : 256) - 6 * nr - 48;
+    const int fit = cap / (9 + 4 * nr) - 1;
+    return fit < 0 ? 0 : (fit < kIntLookahead ? fit : kIntLookahead);
+}
+// 16-bit vectors with 16-bit links: the hops run on integer dot products
+template <typename VS, typename LS>
+constexpr bool int_hops() {
+    return std::is_same<VS, h16c>::value && std::is_same<LS, q16c>::value;
+}
 
 // Launch shape of the half stencil: NR RHS per lane, LPS lanes per site, the
 // XCD-contiguous block order and the order of site blocks and RHS groups.
@@ -213,6 +236,126 @@ __device__ __forceinline__ void hop_fence(V (&acc)[NR][3]) {
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) __asm__ __volatile__("" : "+v"(acc[r][c])::"memory");
+}
+
+// Hops with 16-bit vectors and links (forward: acc += U v; backward:
+// acc -= U^H v).  Each real or imaginary part of a row of U times the colour
+// vector is a sum of six int16 products, formed exactly by three two-way
+// integer dot products from the link entry rearranged once per hop: forward
+// Re uses (Ur, -Ui) and Im (Ui, Ur) against (vr, vi); backward, with
+// (U^H)_ab = conj(U_ba), Re uses (Ur, Ui) and Im (-Ui, Ur).  The sum is
+// converted to float and scaled by the neighbour's norm (the link step and
+// 1/32767 are in the coefficient cd).
+//
+// A hop is split into its loads (HopRaw) and its arithmetic, so that the
+// kernel issues the loads of the next hops before the arithmetic of the
+// current one: the neighbour gathers are served from the last-level cache
+// and their latency, not the ALU, bounds a wave that waits for each hop.
+template <int NR>
+struct HopRaw {
+    h16c u[9];
+    h16c v[NR][3];
+    float n[NR];
+};
+
+template <int NR, bool NT>
+__device__ __forceinline__ void hop_load(HopRaw<NR> &d, const q16c *__restrict__ U, int vh,
+                                         uint32_t uoff, const h16c *__restrict__ in,
+                                         uint32_t voff, const uint32_t (&roff)[NR],
+                                         const float *__restrict__ nrm) {
+    const gptr<const q16c> up = at(U, uoff);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d.u[k] = __builtin_bit_cast(h16c, ldlink<NT>(up + k * kLinkTile));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        d.v[r][0] = *at(in, roff[r] + voff);
+        d.v[r][1] = *at(in + vh, roff[r] + voff);
+        d.v[r][2] = *at(in + 2 * (int64_t)vh, roff[r] + voff);
+        // the norm plane: one float per (RHS, site), RHS offset roff / 3
+        d.n[r] = *at(nrm, roff[r] / 3 + voff);
+    }
+}
+
+template <int NR, bool FWD>
+__device__ __forceinline__ void hop_math(const HopRaw<NR> &d, vec2<float> (&acc)[NR][3]) {
+    h16c ure[9], uim[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        // one packed 16-bit multiply or one byte rotation each
+        const h16c u = d.u[k];
+        const h16c w = __builtin_shufflevector(u, u, 1, 0);
+        if constexpr (FWD) {
+            ure[k] = u * h16c{1, -1};
+            uim[k] = w;
+        } else {
+            ure[k] = u;
+            uim[k] = w * h16c{-1, 1};
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const float sc = FWD ? d.n[r] : -d.n[r];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // entry of (row a, column b): 3a + b forward, 3b + a (transposed) backward
+            constexpr int s0 = FWD ? 1 : 3;
+            const int k0 = FWD ? 3 * a : a;
+            // the first product of each sum in the three-operand form (zero as
+            // an inline constant; its clamp never acts, the sums fit int32)
+            int re = __builtin_amdgcn_sdot2(ure[k0], d.v[r][0], 0, true);
+            re = __builtin_amdgcn_sdot2(ure[k0 + s0], d.v[r][1], re, false);
+            re = __builtin_amdgcn_sdot2(ure[k0 + 2 * s0], d.v[r][2], re, false);
+            int im = __builtin_amdgcn_sdot2(uim[k0], d.v[r][0], 0, true);
+            im = __builtin_amdgcn_sdot2(uim[k0 + s0], d.v[r][1], im, false);
+            im = __builtin_amdgcn_sdot2(uim[k0 + 2 * s0], d.v[r][2], im, false);
+            acc[r][a].x = fmaf(sc, (float)re, acc[r][a].x);
+            acc[r][a].y = fmaf(sc, (float)im, acc[r][a].y);
+        }
+    }
+}
+
+// Checkerboard index of the neighbour of (x, y, z, t) at distance dist along mu.
+__device__ __forceinline__ int nbr_cb(const Geom &g, int x, int y, int z, int t, int mu, int dist) {
+    if (mu == 0) x = wrap(x + dist, g.X);
+    else if (mu == 1) y = wrap(y + dist, g.Y);
+    else if (mu == 2) z = wrap(z + dist, g.Z);
+    else t = wrap(t + dist, g.T);
+    return (((t * g.Z + z) * g.Y + y) * g.X + x) >> 1;
+}
+
+// The 16 hops of a site on 16-bit vectors and links, in the order of the
+// generic path (fat then long; x, y, z, t; forward then backward), with the
+// loads of hop i + LA issued before the arithmetic of hop i.
+template <int NR, int LA, bool NT>
+__device__ __forceinline__ void int_hops_all(const q16c *const (&Uo)[2], const q16c *const (&Ui)[2],
+                                             int64_t lstride, const Geom &g, int x, int y, int z,
+                                             int t, uint32_t own_l, const h16c *__restrict__ in,
+                                             const uint32_t (&roff)[NR],
+                                             const float *__restrict__ nrm,
+                                             vec2<float> (&acc)[NR][3]) {
+    HopRaw<NR> buf[LA + 1];
+    auto load = [&](int i, HopRaw<NR> &d) {
+        const int h = i >> 3, mu = (i >> 1) & 3;
+        const int dist = h == 0 ? 1 : 3;
+        if ((i & 1) == 0) {
+            const int f = nbr_cb(g, x, y, z, t, mu, dist);
+            hop_load<NR, NT>(d, Uo[h] + mu * lstride, g.vh, own_l, in,
+                             (uint32_t)f * (uint32_t)sizeof(h16c), roff, nrm);
+        } else {
+            const int b = nbr_cb(g, x, y, z, t, mu, -dist);
+            hop_load<NR, NT>(d, Ui[h] + mu * lstride, g.vh, link_off<q16c>(b), in,
+                             (uint32_t)b * (uint32_t)sizeof(h16c), roff, nrm);
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < LA; ++i) load(i, buf[i]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i + LA < 16) load(i + LA, buf[(i + LA) % (LA + 1)]);
+        if ((i & 1) == 0) hop_math<NR, true>(buf[i % (LA + 1)], acc);
+        else hop_math<NR, false>(buf[i % (LA + 1)], acc);
+        hop_fence<NR>(acc);
+    }
 }
 
 // roff[r]: byte offset of the lane's r-th RHS plane from the group's first
@@ -378,6 +521,12 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
         const uint32_t own = (uint32_t)cb * (uint32_t)sizeof(VS);
         const uint32_t own_l = link_off<LS>(cb);
 
+        if constexpr (int_hops<VS, LS>()) {
+            const q16c *const Uo[2] = {a.fat_out, a.lng_out};
+            const q16c *const Ui[2] = {a.fat_in, a.lng_in};
+            int_hops_all<NR, int_lookahead(NR, LPS), NT>(Uo, Ui, lstride, g, x, y, z, t, own_l, in,
+                                                         roff, nrm_in, acc);
+        } else {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int hop = h == 0 ? 1 : 3;
@@ -415,6 +564,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
                 hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
                 hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
             }
+        }
         }
 
         // epilogue

@@ -6,7 +6,9 @@
 // error <= step / 2 per component; vectors stay FP32 and the arithmetic is
 // FP32.  The kernel multiplies the integers as floats and the launcher folds
 // step into the stencil coefficient cd.  Half the link bytes of FP32, about
-// 4e-5 relative accuracy for unitary links (BF16: 2e-3).
+// 4e-5 relative accuracy for unitary links (BF16: 2e-3).  The stencil on
+// 16-bit vectors reads a second copy with step = largest / 10922 (about 1e-4),
+// so that six products of a link row and a colour vector sum exactly in int32.
 #include <algorithm>
 #include <vector>
 
@@ -39,25 +41,27 @@ __global__ __launch_bounds__(kBS) void k_absmax(const double2 *__restrict__ src,
     if (threadIdx.x == 0) partials[blockIdx.x] = m[0];
 }
 
-__device__ __forceinline__ uint32_t q16_of(double x, double inv_step) {
+__device__ __forceinline__ uint32_t q16_of(double x, double inv_step, int qmax) {
     const long long q = llrint(x * inv_step);
-    const int c = (int)(q > 32767 ? 32767 : (q < -32767 ? -32767 : q));
+    const int c = (int)(q > qmax ? qmax : (q < -qmax ? -qmax : q));
     return (uint32_t)c & 0xffffu;
 }
 
 __global__ __launch_bounds__(kBS) void k_links_to_q16(const double2 *__restrict__ src,
                                                       q16c *__restrict__ dst, int64_t n,
-                                                      double inv_step) {
+                                                      double inv_step, int qmax) {
     for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
         const double2 v = src[i];
-        dst[i] = (q16c)(q16_of(v.x, inv_step) | (q16_of(v.y, inv_step) << 16));
+        dst[i] = (q16c)(q16_of(v.x, inv_step, qmax) | (q16_of(v.y, inv_step, qmax) << 16));
     }
 }
 
-}  // namespace
-
-hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s) {
-    if (g->fatq[0]) return HISQ_OK;
+// largest |component| over the fat and long links (once per handle)
+hisq_status link_absmax(hisq_gauge_s *g, hipStream_t s, double *mx_out) {
+    if (g->link_absmax >= 0.0) {
+        *mx_out = g->link_absmax;
+        return HISQ_OK;
+    }
     const int64_t n = link_array_entries(g->geom.vh);
     const int nb = (int)std::min<int64_t>((n + kBS - 1) / kBS, kMaxBlocks);
     void *p = nullptr;
@@ -73,22 +77,45 @@ hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s) {
     double mx = 0.0;
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < nb; ++b) mx = std::max(mx, h[(size_t)a * kMaxBlocks + b]);
-    const double step = mx > 0.0 ? mx / 32767.0 : 1.0;
+    g->link_absmax = mx;
+    *mx_out = mx;
+    return HISQ_OK;
+}
+
+// fixed-point copies of both link fields, components in [-qmax, qmax]
+hisq_status make_q16_links(hisq_gauge_s *g, int qmax, int32_t *(&fat)[2], int32_t *(&lng)[2],
+                           double *step_out, hipStream_t s) {
+    double mx = 0.0;
+    HISQ_TRY(link_absmax(g, s, &mx));
+    const int64_t n = link_array_entries(g->geom.vh);
+    const double step = mx > 0.0 ? mx / qmax : 1.0;
     for (int q = 0; q < 2; ++q) {
-        if (hipMalloc(&g->fatq[q], sizeof(q16c) * n) != hipSuccess ||
-            hipMalloc(&g->lngq[q], sizeof(q16c) * n) != hipSuccess)
+        if (hipMalloc(&fat[q], sizeof(q16c) * n) != hipSuccess ||
+            hipMalloc(&lng[q], sizeof(q16c) * n) != hipSuccess)
             return fail(HISQ_ERR_OOM, "device allocation of the 16-bit links");
     }
     const int nc = (int)std::min<int64_t>((n + kBS - 1) / kBS, 8192);
     for (int q = 0; q < 2; ++q) {
-        hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->fat[q], g->fatq[q], n,
-                           1.0 / step);
-        hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->lng[q], g->lngq[q], n,
-                           1.0 / step);
+        hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->fat[q], fat[q], n,
+                           1.0 / step, qmax);
+        hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->lng[q], lng[q], n,
+                           1.0 / step, qmax);
     }
     HISQ_HIP(hipGetLastError());
-    g->q16_step = step;
+    *step_out = step;
     return HISQ_OK;
+}
+
+}  // namespace
+
+hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s) {
+    if (g->fatq[0]) return HISQ_OK;
+    return make_q16_links(g, 32767, g->fatq, g->lngq, &g->q16_step, s);
+}
+
+hisq_status ensure_links_q16n(hisq_gauge_s *g, hipStream_t s) {
+    if (g->fatn[0]) return HISQ_OK;
+    return make_q16_links(g, kQLinkNarrow, g->fatn, g->lngn, &g->qn_step, s);
 }
 
 hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
@@ -122,20 +149,22 @@ hisq_status apply_mdagm_q16(hisq_gauge_s *g, double two_m, const float2 *in, flo
 namespace hisq {
 
 // 16-bit vectors (h16c fields with per-site norms) and 16-bit links: the
-// sloppy operator at sloppy_prec = HISQ_HALF.
+// sloppy operator at sloppy_prec = HISQ_HALF.  The kernel sums the integer
+// products of a link row and a colour vector exactly in 32 bits and scales by
+// the neighbour's norm; the link step and 1/32767 of the vectors fold into cd.
 hisq_status launch_dslash_h16(hisq_gauge_s *g, int out_parity, const void *in, void *out,
                               int nrhs, const void *aux, double ca, double cd, double *partials,
                               hipStream_t s, const double *ca_rhs, const int *rhs_status) {
-    HISQ_TRY(ensure_links_q16(g, s));
-    const q16c *fat[2] = {g->fatq[0], g->fatq[1]};
-    const q16c *lng[2] = {g->lngq[0], g->lngq[1]};
+    HISQ_TRY(ensure_links_q16n(g, s));
+    const q16c *fat[2] = {g->fatn[0], g->fatn[1]};
+    const q16c *lng[2] = {g->lngn[0], g->lngn[1]};
     const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, true);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux ? "dslash_h16_aux" : "dslash_h16", s);
     return dslash_impl::launch_dslash_t<float, h16c, q16c>(
         g->geom, fat, lng, out_parity, static_cast<const h16c *>(in), static_cast<h16c *>(out),
-        nrhs, static_cast<const h16c *>(aux), ca, nullptr, 0.0, cd * g->q16_step, partials, sh, s,
-        ca_rhs, rhs_status);
+        nrhs, static_cast<const h16c *>(aux), ca, nullptr, 0.0, cd * g->qn_step / kQ16, partials,
+        sh, s, ca_rhs, rhs_status);
 }
 
 }  // namespace hisq

@@ -91,6 +91,10 @@ struct hisq_gauge_s {
     int32_t *fatq[2] = {nullptr, nullptr};   // 16-bit fixed-point copies (two int16
     int32_t *lngq[2] = {nullptr, nullptr};   //   per complex), made on first use,
     double q16_step = 0.0;                   //   value = integer * q16_step
+    int32_t *fatn[2] = {nullptr, nullptr};   // the same with components in
+    int32_t *lngn[2] = {nullptr, nullptr};   //   [-10922, 10922] (integer-dot
+    double qn_step = 0.0;                    //   stencil), value = integer * qn_step
+    double link_absmax = -1.0;               // largest |component| of fat and long
     hipStream_t cg_stream = nullptr;        // the solvers' own stream (capturable)
     hisq::Workspace ws;
 };
@@ -250,6 +254,9 @@ hisq_status launch_dslash_f32_bl(hisq_gauge_s *g, int out_parity, const float2 *
                                  const int *rhs_status = nullptr);
 // 16-bit fixed-point links (HISQ_Q16): FP32 vectors and arithmetic
 hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s);
+// the copy with components in [-kQLinkNarrow, kQLinkNarrow] read by the
+// stencil on 16-bit vectors
+hisq_status ensure_links_q16n(hisq_gauge_s *g, hipStream_t s);
 hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
                                   int nrhs, const float2 *aux, double ca, double cd,
                                   double *partials, hipStream_t s, const double *ca_rhs = nullptr,
