@@ -83,7 +83,8 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
 
     // the sloppy links are made here, not inside a captured iteration chunk
     if (bf16_links) HISQ_TRY(ensure_links_bf16(g, s));
-    else if (q16_links || half) HISQ_TRY(ensure_links_q16(g, s));
+    else if (half) HISQ_TRY(ensure_links_q16n(g, s));
+    else if (q16_links) HISQ_TRY(ensure_links_q16(g, s));
     else HISQ_TRY(ensure_links_f32(g, s));
 
     // ------------------------------------------------------------ buffers
@@ -110,26 +111,30 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     HISQ_TRY(g->ws.get("mx_scalars", (nd * sizeof(double) + ni * sizeof(int)) * nrhs + 64 * (nd + ni), &p));
     char *cp = static_cast<char *>(p);
     CgDev dev{};
+    // The host mirror below is carved in the same order, so that the state a
+    // poll reads (rho, status, iters, ru_flag) is one contiguous copy, and so
+    // is what a reliable update writes back (those, rho_ru, true_res2, the
+    // restart coefficients and modes).
     dev.rho = carve<double>(cp, nrhs);
+    dev.status = carve<int>(cp, nrhs);
+    dev.iters = carve<int>(cp, nrhs);
+    dev.ru_flag = carve<int>(cp, nrhs);
+    dev.rho_ru = carve<double>(cp, nrhs);
+    dev.true_res2 = carve<double>(cp, nrhs);
+    double *d_rbeta = carve<double>(cp, nrhs);
+    int *d_mode = carve<int>(cp, nrhs);
     dev.rho_pend = carve<double>(cp, nrhs);
     dev.alpha = carve<double>(cp, nrhs);
     dev.beta = carve<double>(cp, nrhs);
     dev.bnorm2 = carve<double>(cp, nrhs);
     dev.tol2b = carve<double>(cp, nrhs);
-    dev.true_res2 = carve<double>(cp, nrhs);
     dev.xp_alpha = carve<double>(cp, nrhs);
     dev.xp_beta = carve<double>(cp, nrhs);
-    dev.rho_ru = carve<double>(cp, nrhs);
     double *d_rho_t = carve<double>(cp, nrhs);
-    double *d_rbeta = carve<double>(cp, nrhs);
-    dev.status = carve<int>(cp, nrhs);
-    dev.iters = carve<int>(cp, nrhs);
     dev.checks = carve<int>(cp, nrhs);
     dev.xp_mode = carve<int>(cp, nrhs);
-    dev.ru_flag = carve<int>(cp, nrhs);
     int *d_mask = carve<int>(cp, nrhs);
     int *d_skip = carve<int>(cp, nrhs);
-    int *d_mode = carve<int>(cp, nrhs);
     dev.delta2 = delta * delta;
     // With BF16 links the sloppy operator is accurate to ~1e-3 only: a
     // recurrence run on past the delta trigger (until the next poll) can make
@@ -167,12 +172,16 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     HISQ_HIP(hipHostMalloc(&pin.ptr, (6 * sizeof(double) + 7 * sizeof(int)) * nrhs + 64 * 13,
                            hipHostMallocDefault));
     char *hp = static_cast<char *>(pin.ptr);
-    double *h_rho = carve<double>(hp, nrhs), *h_rho_ru = carve<double>(hp, nrhs);
-    double *h_rho_t = carve<double>(hp, nrhs), *h_b2 = carve<double>(hp, nrhs);
-    double *h_tr2 = carve<double>(hp, nrhs), *h_rbeta = carve<double>(hp, nrhs);
+    double *h_rho = carve<double>(hp, nrhs);
     int *h_status = carve<int>(hp, nrhs), *h_iters = carve<int>(hp, nrhs);
+    int *h_flag = carve<int>(hp, nrhs);
+    const size_t poll_bytes = (size_t)(hp - static_cast<char *>(pin.ptr));
+    double *h_rho_ru = carve<double>(hp, nrhs), *h_tr2 = carve<double>(hp, nrhs);
+    double *h_rbeta = carve<double>(hp, nrhs);
+    int *h_mode = carve<int>(hp, nrhs);
+    const size_t state_bytes = (size_t)(hp - static_cast<char *>(pin.ptr));
+    double *h_rho_t = carve<double>(hp, nrhs), *h_b2 = carve<double>(hp, nrhs);
     int *h_defl = carve<int>(hp, nrhs), *h_mask = carve<int>(hp, nrhs);
-    int *h_mode = carve<int>(hp, nrhs), *h_flag = carve<int>(hp, nrhs);
     int *h_skip = carve<int>(hp, nrhs);
     std::vector<int> ru_count(nrhs, 0), defl_count(nrhs, 0), iters_at_ru(nrhs, 0);
     std::vector<double> rho_defl(nrhs, 0.0);
@@ -269,12 +278,16 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     int64_t enqueued = 0;
     const bool graphs = cg_use_graphs(g, nrhs);
     GraphChunk chunk;
+    // Right after a reliable update no iteration has run since the host wrote
+    // the state back, so the host mirror is current and the poll is skipped.
+    bool mirror_current = false;
     for (;;) {
-        HISQ_TRY(d2h(h_status, dev.status, in_));
-        HISQ_TRY(d2h(h_iters, dev.iters, in_));
-        HISQ_TRY(d2h(h_rho, dev.rho, dn));
-        HISQ_TRY(d2h(h_flag, dev.ru_flag, in_));
-        HISQ_TRY(sync());
+        if (!mirror_current) {
+            // rho, status, iters, ru_flag in one copy
+            HISQ_TRY(d2h(h_rho, dev.rho, poll_bytes));
+            HISQ_TRY(sync());
+        }
+        mirror_current = false;
         int nactive = 0, nru = 0;
         for (int q = 0; q < nrhs; ++q) {
             const int st = h_status[q];
@@ -372,15 +385,12 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
                 }
             }
         }
-        HISQ_TRY(h2d(dev.status, h_status, in_));
-        HISQ_TRY(h2d(dev.rho, h_rho, dn));
-        HISQ_TRY(h2d(dev.rho_ru, h_rho_ru, dn));
-        HISQ_TRY(h2d(dev.true_res2, h_tr2, dn));
-        HISQ_TRY(h2d(d_rbeta, h_rbeta, dn));
-        HISQ_TRY(h2d(d_mode, h_mode, in_));
-        HISQ_TRY(h2d(dev.ru_flag, h_flag, in_));
+        // rho, status, iters (unchanged), ru_flag, rho_ru, true_res2, the
+        // restart coefficients and modes in one copy
+        HISQ_TRY(h2d(dev.rho, h_rho, state_bytes));
         if (half) HISQ_TRY(half_p_restart(vh, nrhs, ps, rs, d_rbeta, d_mode, s));
         else HISQ_TRY(mixed_p_restart(ps, rs, n, nrhs, d_rbeta, d_mode, s));
+        mirror_current = true;
     }
 
     // fold any remaining FP32 correction into x; b = 0 gives x = 0
