@@ -69,7 +69,8 @@ typedef enum hisq_status {
  * of its three colours; relative accuracy ~3e-5), and links in 16-bit fixed
  * point with components up to 10922 (scale: the largest link component /
  * 10922, ~5e-5 absolute error), so that the stencil sums the integer products
- * of a link row and a colour vector exactly in 32 bits; for sloppy_prec only. */
+ * of a link row and a colour vector exactly in 32 bits; for sloppy_prec and,
+ * with FP32 vectors at the boundary, for hisq_dslash_eo and hisq_mdagm. */
 typedef enum hisq_prec {
     HISQ_FP64 = 0,
     HISQ_FP32 = 1,
@@ -163,7 +164,12 @@ hisq_status hisq_convert_vectors(const void *src_dev, hisq_prec src_prec, void *
  * nearest even once; the BF16 links made from the FP64 ones on first use) or
  * HISQ_Q16 (vectors of complex float as for HISQ_FP32; links in 16-bit fixed
  * point, made from the FP64 ones on first use: absolute error <= step / 2 per
- * component, step = the largest link component of the handle / 32767).
+ * component, step = the largest link component of the handle / 32767) or
+ * HISQ_HALF (vectors of complex float at the boundary; inside, the input is
+ * rounded to 16-bit fixed point with one norm per RHS and site, the stencil of
+ * the CG at sloppy_prec = HISQ_HALF is applied, links with components up to
+ * 10922, and its 16-bit output is widened to FP32: each value is that of the
+ * stored 16-bit result).
  */
 hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
                            void *out_dev, int nrhs, hisq_prec prec, void *stream);

@@ -29,7 +29,8 @@ hisq_status check_nrhs(int nrhs) {
 }
 
 hisq_status check_prec(hisq_prec p) {
-    if (p == HISQ_FP64 || p == HISQ_FP32 || p == HISQ_BF16 || p == HISQ_Q16) return HISQ_OK;
+    if (p == HISQ_FP64 || p == HISQ_FP32 || p == HISQ_BF16 || p == HISQ_Q16 || p == HISQ_HALF)
+        return HISQ_OK;
     return fail(HISQ_ERR_INVALID_ARG, "unknown precision");
 }
 
@@ -189,6 +190,10 @@ hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev, voi
         return launch_dslash_f32(g, out_parity, static_cast<const float2 *>(in_dev),
                                  static_cast<float2 *>(out_dev), nrhs, nullptr, 0.0, nullptr, 0.0,
                                  1.0, nullptr, static_cast<hipStream_t>(stream));
+    if (prec == HISQ_HALF)
+        return apply_dslash_half(g, out_parity, static_cast<const float2 *>(in_dev),
+                                 static_cast<float2 *>(out_dev), nrhs,
+                                 static_cast<hipStream_t>(stream));
     if (prec == HISQ_Q16)
         return launch_dslash_f32_q16(g, out_parity, static_cast<const float2 *>(in_dev),
                                      static_cast<float2 *>(out_dev), nrhs, nullptr, 0.0, 1.0,
@@ -215,6 +220,10 @@ hisq_status hisq_mdagm(hisq_gauge g, double two_m, const void *in_e_dev, void *o
         return apply_mdagm_f32(g, two_m, static_cast<const float2 *>(in_e_dev),
                                static_cast<float2 *>(out_e_dev), nrhs, nullptr,
                                static_cast<hipStream_t>(stream));
+    if (prec == HISQ_HALF)
+        return apply_mdagm_half(g, two_m, static_cast<const float2 *>(in_e_dev),
+                                static_cast<float2 *>(out_e_dev), nrhs,
+                                static_cast<hipStream_t>(stream));
     if (prec == HISQ_Q16)
         return apply_mdagm_q16(g, two_m, static_cast<const float2 *>(in_e_dev),
                                static_cast<float2 *>(out_e_dev), nrhs,

@@ -132,6 +132,20 @@ __global__ __launch_bounds__(kBS) void k_p_restart_h(int64_t vh, h16c *__restric
     }
 }
 
+// out = the FP32 value of a 16-bit field
+__global__ __launch_bounds__(kBS) void k_h16_to_f32(int64_t vh, const h16c *__restrict__ h,
+                                                    const float *__restrict__ hn,
+                                                    fvec2 *__restrict__ out) {
+    const int j = blockIdx.y;
+    for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
+         cb += (int64_t)gridDim.x * kBS) {
+        fvec2 v[3];
+        load_site(h, hn, vh, j, cb, v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[((int64_t)j * 3 + c) * vh + cb] = v[c];
+    }
+}
+
 int site_blocks(int64_t vh) {
     const int64_t b = (vh + kBS - 1) / kBS;
     return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
@@ -172,6 +186,44 @@ hisq_status half_p_restart(int64_t vh, int nrhs, void *p, const float2 *r, const
                        reinterpret_cast<const fvec2 *>(r), beta, mode);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
+}
+
+hisq_status half_to_f32(int64_t vh, int nrhs, const void *h, float2 *out, hipStream_t s) {
+    const h16c *d = static_cast<const h16c *>(h);
+    const float *nrm = reinterpret_cast<const float *>(d + (int64_t)nrhs * 3 * vh);
+    hipLaunchKernelGGL(k_h16_to_f32, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh, d, nrm,
+                       reinterpret_cast<fvec2 *>(out));
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+// The operators at HISQ_HALF: FP32 vectors in and out, rounded to the 16-bit
+// format on entry, the 16-bit stencil (as in the CG's sloppy iteration), and
+// the result widened to FP32.
+hisq_status apply_dslash_half(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
+                              int nrhs, hipStream_t s) {
+    const int64_t vh = g->geom.vh;
+    const size_t hb = (size_t)half_field_bytes(vh, nrhs);
+    void *hin = nullptr, *hout = nullptr;
+    HISQ_TRY(g->ws.get("half_op_in", hb, &hin));
+    HISQ_TRY(g->ws.get("half_op_out", hb, &hout));
+    HISQ_TRY(half_p_restart(vh, nrhs, hin, in, nullptr, nullptr, s));
+    HISQ_TRY(launch_dslash_h16(g, out_parity, hin, hout, nrhs, nullptr, 0.0, 1.0, nullptr, s));
+    return half_to_f32(vh, nrhs, hout, out, s);
+}
+
+hisq_status apply_mdagm_half(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out,
+                             int nrhs, hipStream_t s) {
+    const int64_t vh = g->geom.vh;
+    const size_t hb = (size_t)half_field_bytes(vh, nrhs);
+    void *hin = nullptr, *hout = nullptr, *ht = nullptr;
+    HISQ_TRY(g->ws.get("half_op_in", hb, &hin));
+    HISQ_TRY(g->ws.get("half_op_out", hb, &hout));
+    HISQ_TRY(g->ws.get("half_op_t", hb, &ht));
+    HISQ_TRY(half_p_restart(vh, nrhs, hin, in, nullptr, nullptr, s));
+    HISQ_TRY(launch_dslash_h16(g, 1, hin, ht, nrhs, nullptr, 0.0, 1.0, nullptr, s));
+    HISQ_TRY(launch_dslash_h16(g, 0, ht, hout, nrhs, hin, two_m * two_m, -1.0, nullptr, s));
+    return half_to_f32(vh, nrhs, hout, out, s);
 }
 
 }  // namespace hisq

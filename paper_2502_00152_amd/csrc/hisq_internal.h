@@ -278,6 +278,12 @@ hisq_status half_update_xp(int64_t vh, int nrhs, float2 *x, const float2 *r, voi
 // p = r + beta p (mode 1) or p = r (mode 2) per RHS; mode null: p = r for all
 hisq_status half_p_restart(int64_t vh, int nrhs, void *p, const float2 *r, const double *beta,
                            const int *mode, hipStream_t s);
+hisq_status half_to_f32(int64_t vh, int nrhs, const void *h, float2 *out, hipStream_t s);
+// the operators at HISQ_HALF (FP32 vectors at the boundary, 16-bit inside)
+hisq_status apply_dslash_half(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
+                              int nrhs, hipStream_t s);
+hisq_status apply_mdagm_half(hisq_gauge_s *g, double two_m, const float2 *in, float2 *out,
+                             int nrhs, hipStream_t s);
 
 // The CG drivers run on the handle's own non-blocking stream (created on first
 // use, default priority), ordered after the caller's stream on entry and

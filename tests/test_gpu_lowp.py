@@ -1,7 +1,8 @@
 """GPU parity of the reduced-precision storage formats: BF16 (conversions,
-the half stencil and M^H M with BF16 vectors and links, FP32 arithmetic) and
-16-bit fixed-point links (HISQ_Q16: FP32 vectors and arithmetic), and the
-mixed-precision CG whose sloppy operator reads BF16 or 16-bit links (sections
+the half stencil and M^H M with BF16 vectors and links, FP32 arithmetic),
+16-bit fixed-point links (HISQ_Q16: FP32 vectors and arithmetic), the 16-bit
+stencil of the HISQ_HALF CG (16-bit vectors and links, integer products), and
+the mixed-precision CG whose sloppy operator reads BF16 or 16-bit links (sections
 2-3: the bulk of the operator in reduced precision, FP64 restored at
 reliable updates).
 
@@ -358,10 +359,115 @@ def test_cg_half_batch_equals_single_solves(w8):
         assert torch.equal(xj[0], x[j])
 
 
-def test_half_is_a_solver_precision_only(prob):
+# ------------------------------------- the 16-bit stencil itself (HISQ_HALF)
+# The operators at HISQ_HALF take FP32 vectors, round them to 16-bit fixed
+# point with one norm per site (|v - v'| <= m_y / 65534 per real component, m_y
+# = the site's largest |component|), apply the CG's 16-bit stencil (links with
+# step_n = largest folded link component / 10922, |dU| <= step_n / 2 per real;
+# integer products exact; FP32 accumulation) and store the result rounded to
+# its own site norm (<= m_o / 65534 per real).  Componentwise, per output
+# colour: |out - D v| <= (step_n / sqrt 2) T + |D| w + 200 u32 S + m_o / 65534,
+# with T the stencil of |v| through unit links, w = sqrt 2 m_y / 65534 the
+# per-site bound of |v - v'|, S = |D| |v|.
+def qn_step(pr):
+    return q16_step(pr) * 32767.0 / 10922.0
+
+
+def site_max(v):
+    """Largest |Re| or |Im| over the three colours of each site, [..., 1]."""
+    return np.maximum(np.abs(v.real), np.abs(v.imag)).max(axis=-1, keepdims=True)
+
+
+def half_bound(pr, full, mo_extra=None):
+    ones = np.ones_like(pr.F)
+    T = abs_stencil(ones, ones, full)
+    w = np.sqrt(2) * site_max(full) / 65534.0 * np.ones_like(np.abs(full))
+    S = abs_stencil(pr.F, pr.L, full)
+    return qn_step(pr) / np.sqrt(2) * T + 1.01 * abs_stencil(pr.F, pr.L, w) + 200 * U32 * S
+
+
+@pytest.mark.parametrize("nrhs", [1, 5, 12])
+@pytest.mark.parametrize("out_parity", [0, 1])
+def test_dslash_half_within_quantisation_bound(prob, nrhs, out_parity):
     import torch
     from paper_2502_00152_amd import hisq
-    a = torch.zeros((1, 3, prob.g.vh), dtype=torch.complex64, device="cuda")
-    with pytest.raises(hisq.HisqError) as e:
-        hisq.hisq_dslash_eo(prob.g, 0, a, torch.empty_like(a), prec=hisq.HISQ_HALF)
-    assert e.value.status == hisq.HISQ_ERR_INVALID_ARG
+    dims = prob.dims
+    in_par = 1 - out_parity
+    v32 = to_parity(sources(dims, nrhs, 480), dims, in_par).astype(np.complex64)
+    inp = torch.from_numpy(v32).cuda()
+    out = torch.empty_like(inp)
+    hisq.hisq_dslash_eo(prob.g, out_parity, inp, out, prec=hisq.HISQ_HALF)
+    got = host(out).astype(np.complex128)
+    worst = 0.0
+    for j in range(nrhs):
+        full = from_parity(v32[j:j + 1].astype(np.complex128), dims, in_par)[0]
+        ref_full = O.dslash(prob.F, prob.L, full, out_parity)
+        ref = to_parity(ref_full, dims, out_parity)[0]
+        B = half_bound(prob, full)
+        # the kernel's site norm is that of its own result, within B of ref
+        mo = 1.01 * (site_max(ref_full) + B.max(axis=-1, keepdims=True)) / 65534.0
+        bound = to_parity(B + mo, dims, out_parity)[0].real
+        err = np.abs(got[j] - ref)
+        assert (err <= bound + 1e-30).all(), (j, float((err / bound).max()))
+        worst = max(worst, float((err / bound).max()))
+    assert worst > 0.05  # the rounding is really there (an FP32 stencil: ~1e-3 of this)
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_mdagm_half_within_quantisation_bound(prob, nrhs):
+    """A = (2m)^2 - D_eo D_oe with the odd temporary stored in 16 bits too: the
+    first stencil's bound enters the second through |D_eo|, with the second's
+    own link, arithmetic and output-rounding terms and (2m)^2 |v - v'|."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = prob.dims
+    two_m = 0.07
+    v32 = to_parity(sources(dims, nrhs, 500), dims, 0).astype(np.complex64)
+    inp = torch.from_numpy(v32).cuda()
+    out = torch.empty_like(inp)
+    hisq.hisq_mdagm(prob.g, two_m, inp, out, prec=hisq.HISQ_HALF)
+    got = host(out).astype(np.complex128)
+    odd = (O.even_mask(dims)[..., None] == 0)
+    even = ~odd
+    for j in range(nrhs):
+        full = from_parity(v32[j:j + 1].astype(np.complex128), dims, 0)[0]
+        t = O.dslash(prob.F, prob.L, full, 1) * odd
+        B1 = half_bound(prob, full)
+        Bt = (B1 + 1.01 * (site_max(t) + B1.max(axis=-1, keepdims=True)) / 65534.0) * odd
+        ref_full = O.apply_A(prob.F, prob.L, two_m, full)
+        ref = to_parity(ref_full, dims, 0)[0]
+        # second stencil on t'' (|t''| <= |t| + Bt), (2m)^2 v' from the
+        # rounded input, FP32 epilogue, output rounding
+        ones = np.ones_like(prob.F)
+        B2 = half_bound(prob, t) + 1.01 * abs_stencil(prob.F, prob.L, Bt)
+        B2 = B2 + qn_step(prob) / np.sqrt(2) * abs_stencil(ones, ones, Bt)
+        B2 = B2 + two_m ** 2 * (1.01 * np.sqrt(2) * site_max(full) / 65534.0 + 200 * U32 * np.abs(full))
+        B2 = B2 + 1.01 * (site_max(ref_full) + B2.max(axis=-1, keepdims=True)) / 65534.0
+        bound = to_parity(B2 * even, dims, 0)[0].real
+        err = np.abs(got[j] - ref)
+        assert (err <= bound + 1e-30).all(), (j, float((err / bound).max()))
+
+
+def test_dslash_half_independent_of_launch_shape():
+    """Exact integer products and one FP32 accumulation order per site: every
+    launch shape gives the same bits."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (8, 8, 8, 12)
+    pr = Problem(dims, 0.5, 2111, 2112)
+    g = pr.gauge()
+    v = torch.from_numpy(to_parity(sources(dims, 12, 520), dims, 1).astype(np.complex64)).cuda()
+    ref = torch.empty_like(v)
+    hisq.hisq_dslash_eo(g, 0, v, ref, prec=hisq.HISQ_HALF)
+    shapes = [(nr, 1) for nr in (1, 2, 3, 4, 6, 12)] + [(nr, l) for l in (2, 4) for nr in (1, 3, 6)]
+    try:
+        for nr, lps in shapes:
+            hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
+            hisq.hisq_set_tuning("dslash_lanes_per_site", lps)
+            out = torch.empty_like(v)
+            hisq.hisq_dslash_eo(g, 0, v, out, prec=hisq.HISQ_HALF)
+            assert torch.equal(out, ref), (nr, lps)
+    finally:
+        hisq.hisq_set_tuning("dslash_rhs_per_thread", 0)
+        hisq.hisq_set_tuning("dslash_lanes_per_site", 0)
+        g.close()

@@ -210,6 +210,48 @@ def test_q16_stencil_sampled_sites(wl):
     print(f"[16x16x16x32] q16 stencil: worst error / bound {worst:.3f}", flush=True)
 
 
+def test_half_stencil_sampled_sites(wl):
+    """The timed sloppy stencil itself: 12 RHS rounded to 16-bit fixed point
+    with one norm per site, 16-bit links (step = largest link component /
+    10922), integer products, output rounded to its site norm, at 300 random
+    sites, within (step / sqrt 2) T + |D| w + 200 u32 S + m_o / 65534 (see
+    tests/test_gpu_lowp.py)."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    from tests.gpu_util import abs_stencil_site
+    dims = wl.dims
+    e32 = wl.eo.to(torch.complex64)
+    out = torch.empty_like(e32)
+    hisq.hisq_dslash_eo(wl.g, 0, e32, out, prec=hisq.HISQ_HALF)
+    got = host(out).astype(np.complex128)
+    eo32 = host(e32).astype(np.complex128)
+    step = max(np.abs(wl.F.real).max(), np.abs(wl.F.imag).max(),
+               np.abs(wl.L.real).max(), np.abs(wl.L.imag).max()) / 10922.0
+    ones = np.ones((4,) + wl.F.shape[1:], dtype=np.complex128)
+    rng = np.random.default_rng(7)
+    lex_even = np.nonzero(O.even_mask(dims).ravel())[0]
+    X, Y, Z, T = dims
+    worst = 0.0
+    for r in (0, 5, 11):
+        psi = from_parity(eo32[r:r + 1], dims, 1)[0]
+        m = np.maximum(np.abs(psi.real), np.abs(psi.imag)).max(axis=-1, keepdims=True)
+        w = np.sqrt(2) * m / 65534.0 * np.ones(psi.shape)
+        for lex in rng.choice(lex_even, 100, replace=False):
+            site = (lex % X, (lex // X) % Y, (lex // (X * Y)) % Z, lex // (X * Y * Z))
+            ref = O.dslash_site(wl.F, wl.L, psi, site)
+            S = abs_stencil_site(wl.F, wl.L, psi, site)
+            Tq = abs_stencil_site(ones, ones, psi, site)
+            Wq = abs_stencil_site(wl.F, wl.L, w, site)
+            B = step / np.sqrt(2) * Tq + 1.01 * Wq + 200 * 2.0 ** -24 * S
+            mo = 1.01 * (max(np.abs(ref.real).max(), np.abs(ref.imag).max()) + B.max()) / 65534.0
+            err = np.abs(got[r, :, lex >> 1] - ref)
+            bound = B + mo
+            assert (err <= bound).all(), (r, site)
+            worst = max(worst, float((err / bound).max()))
+    print(f"[16x16x16x32] 16-bit stencil: worst error / bound {worst:.3f}", flush=True)
+    assert worst > 0.05
+
+
 @pytest.mark.parametrize("sloppy", ["q16", "half"])
 def test_timed_step_16bit_multi_deflation(wl, eig, sloppy):
     """The timed step of the benchmark: FP32 eigenvectors, mixed CG whose
