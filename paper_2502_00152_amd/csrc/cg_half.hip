@@ -44,12 +44,23 @@ __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p
 
 // alpha = rho / <p, Ap> (the stencil's fixed-order partials), r -= alpha Ap,
 // per-block partials of ||r||^2.  Grid (blas_reduce_blocks(3 Vh), nrhs).
+// The first site's r and A p are loaded before the partials are summed, so
+// that the two memory latencies overlap.
 __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restrict__ r,
                                                     const h16c *__restrict__ ap,
                                                     const float *__restrict__ apn,
                                                     const double *__restrict__ pap, int nb_pap,
                                                     CgDev cg, Reduce red) {
     const int j = blockIdx.y;
+    const bool active = cg.status[j] == CG_ACTIVE;
+    const int64_t stride = (int64_t)gridDim.x * kBS;
+    int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    fvec2 q[3], rr[3];
+    if (active && cb < vh) {
+        load_site(ap, apn, vh, j, cb, q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
+    }
     __shared__ double pq_s;
     if (threadIdx.x < kWave) {
         const double v = wave_sum_partials(pap + (int64_t)j * nb_pap, nb_pap);
@@ -58,20 +69,23 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
     __syncthreads();
     const double pq = pq_s;
     double v[1] = {0.0};
-    if (cg.status[j] == CG_ACTIVE && isfinite(pq) && pq > 0.0) {
+    if (active && isfinite(pq) && pq > 0.0) {
         const float al = (float)(cg.rho[j] / pq);
-        for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
-             cb += (int64_t)gridDim.x * kBS) {
-            fvec2 q[3];
-            load_site(ap, apn, vh, j, cb, q);
+        while (cb < vh) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int64_t i = ((int64_t)j * 3 + c) * vh + cb;
-                fvec2 rr = r[i];
-                rr.x = fmaf(-al, q[c].x, rr.x);
-                rr.y = fmaf(-al, q[c].y, rr.y);
-                r[i] = rr;
-                v[0] = fma((double)rr.x, (double)rr.x, fma((double)rr.y, (double)rr.y, v[0]));
+                rr[c].x = fmaf(-al, q[c].x, rr[c].x);
+                rr[c].y = fmaf(-al, q[c].y, rr[c].y);
+                r[i] = rr[c];
+                v[0] = fma((double)rr[c].x, (double)rr[c].x,
+                           fma((double)rr[c].y, (double)rr[c].y, v[0]));
+            }
+            cb += stride;
+            if (cb < vh) {
+                load_site(ap, apn, vh, j, cb, q);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
             }
         }
     }
@@ -80,32 +94,47 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
     if (threadIdx.x == 0) red.partials[(int64_t)j * gridDim.x + blockIdx.x] = v[0];
 }
 
-// x += alpha p_old; p = r + beta p_old (mode 2), or only the x update (mode 1)
+// x += alpha p_old; p = r + beta p_old (mode 2), or only the x update (mode 1).
+// The first site's x, p and r are loaded before the RHS's mode and
+// coefficients are read.
 __global__ __launch_bounds__(kBS) void k_update_xp_h(int64_t vh, fvec2 *__restrict__ x,
                                                      const fvec2 *__restrict__ r,
                                                      h16c *__restrict__ p, float *__restrict__ pn,
                                                      CgDev cg) {
     const int j = blockIdx.y;
-    const int mode = cg.xp_mode[j];
-    if (mode == 0) return;
-    const float al = (float)cg.xp_alpha[j], be = (float)cg.xp_beta[j];
-    for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
-         cb += (int64_t)gridDim.x * kBS) {
-        fvec2 pp[3];
+    const int64_t stride = (int64_t)gridDim.x * kBS;
+    int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    fvec2 pp[3], xx[3], rr[3];
+    if (cb < vh) {
         load_site(p, pn, vh, j, cb, pp);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            xx[c] = x[((int64_t)j * 3 + c) * vh + cb];
+            rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
+        }
+    }
+    const int mode = cg.xp_mode[j];
+    if (mode == 0) return;
+    const float al = (float)cg.xp_alpha[j], be = (float)cg.xp_beta[j];
+    while (cb < vh) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
             const int64_t i = ((int64_t)j * 3 + c) * vh + cb;
-            fvec2 xx = x[i];
-            xx.x = fmaf(al, pp[c].x, xx.x);
-            xx.y = fmaf(al, pp[c].y, xx.y);
-            x[i] = xx;
-            if (mode == 2) {
-                const fvec2 rr = r[i];
-                pp[c] = fvec2{fmaf(be, pp[c].x, rr.x), fmaf(be, pp[c].y, rr.y)};
-            }
+            xx[c].x = fmaf(al, pp[c].x, xx[c].x);
+            xx[c].y = fmaf(al, pp[c].y, xx[c].y);
+            x[i] = xx[c];
+            if (mode == 2) pp[c] = fvec2{fmaf(be, pp[c].x, rr[c].x), fmaf(be, pp[c].y, rr[c].y)};
         }
         if (mode == 2) store_site(p, pn, vh, j, cb, pp);
+        cb += stride;
+        if (cb < vh) {
+            load_site(p, pn, vh, j, cb, pp);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xx[c] = x[((int64_t)j * 3 + c) * vh + cb];
+                rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
+            }
+        }
     }
 }
 

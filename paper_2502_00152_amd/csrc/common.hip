@@ -38,8 +38,12 @@ hisq_status Workspace::get(const char *name, size_t bytes, void **ptr) {
             return fail(HISQ_ERR_OOM, std::string("scratch '") + name + "' of " +
                                           std::to_string(bytes) + " bytes: " +
                                           hipGetErrorString(e));
-        // arrival counters and partial sums start from zero
+        // arrival counters and partial sums start from zero.  The clear goes
+        // to the null stream, which the solvers' non-blocking streams do not
+        // wait for, and reused device memory holds old values: the clear must
+        // be complete before the buffer is handed out.
         HISQ_HIP(hipMemset(p, 0, bytes));
+        HISQ_HIP(hipDeviceSynchronize());
         b.ptr = p;
         b.bytes = bytes;
     }

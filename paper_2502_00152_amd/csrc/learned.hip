@@ -721,6 +721,9 @@ hisq_status upload(hisq_nn n, const float *params_host) {
     }
     HISQ_HIP(hipMemset(n->m, 0, pb));
     HISQ_HIP(hipMemset(n->v, 0, pb));
+    // the clears go to the null stream: complete them before any caller's
+    // stream can read these arrays
+    HISQ_HIP(hipDeviceSynchronize());
     n->t = 0;
     n->have_grad = false;
     n->bf_stale = true;
