@@ -112,6 +112,24 @@ constexpr int kQLinkNarrow = 10922;
 #define HISQ_INT_LOOKAHEAD 1
 #endif
 constexpr int kIntLookahead = HISQ_INT_LOOKAHEAD;
+// the same for the other storage types, for lanes holding two or more RHS
+// (measured: 12-RHS FP32 and 16-bit-link stencils 5% faster; one RHS per lane
+// at 32^3 x 64 FP32 7% slower, FP64 and BF16 unchanged, so one RHS per lane
+// keeps one hop at a time)
+#ifndef HISQ_GEN_LOOKAHEAD
+#define HISQ_GEN_LOOKAHEAD 1
+#endif
+constexpr int kGenLookahead = HISQ_GEN_LOOKAHEAD;
+// Lookahead that fits a lane's registers for the other storage types: a hop's
+// loads take (9 link entries + 3 NR vector entries [+ NR norms]) words, the
+// accumulators and the widened links 6 NR + 18 reals, addresses ~40.
+constexpr int gen_lookahead(int nr, int lps, int rb, int vb, int lb, bool normed) {
+    if (nr < 2) return 0;
+    const int buf = (9 * lb + 3 * nr * vb + (normed ? 4 * nr : 0)) / 4;
+    const int cap = (512 / lps < 256 ? 512 / lps : 256) - (6 * nr + 18) * rb / 4 - 40;
+    const int fit = cap / buf - 1;
+    return fit < 0 ? 0 : (fit < kGenLookahead ? fit : kGenLookahead);
+}
 // Lookahead that still fits the registers of a lane: a block of 256 LPS lanes
 // leaves 512 / LPS registers (at most 256) per lane; a hop's loads take
 // 9 + 4 NR, the accumulators 6 NR, the rearranged links and addresses ~48.
@@ -440,6 +458,106 @@ __device__ __forceinline__ void hop_backward(const LS *__restrict__ U, int vh, u
     hop_fence<NR>(acc);
 }
 
+// The generic hops split into loads and arithmetic (the arithmetic of
+// hop_forward / hop_backward), for the pipelined loop below.
+template <int NR, typename VS, typename LS>
+struct HopRawG {
+    LS u[9];
+    VS v[NR][3];
+    float n[NR];
+};
+
+template <int NR, bool NT, typename VS, typename LS>
+__device__ __forceinline__ void hop_load_g(HopRawG<NR, VS, LS> &d, const LS *__restrict__ U,
+                                           int vh, uint32_t uoff, const VS *__restrict__ in,
+                                           uint32_t voff, const uint32_t (&roff)[NR],
+                                           const float *__restrict__ nrm) {
+    const gptr<const LS> up = at(U, uoff);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d.u[k] = ldlink<NT>(up + k * kLinkTile);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        d.v[r][0] = *at(in, roff[r] + voff);
+        d.v[r][1] = *at(in + vh, roff[r] + voff);
+        d.v[r][2] = *at(in + 2 * (int64_t)vh, roff[r] + voff);
+        if constexpr (is_normed<VS>()) d.n[r] = *at(nrm, roff[r] / 3 + voff);
+    }
+}
+
+template <int NR, bool FWD, typename R, typename VS, typename LS>
+__device__ __forceinline__ void hop_math_g(const HopRawG<NR, VS, LS> &d, vec2<R> (&acc)[NR][3]) {
+    using V = vec2<R>;
+    V u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = Conv<LS>::template ld<R>(d.u[k]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        V v0 = Conv<VS>::template ld<R>(d.v[r][0]);
+        V v1 = Conv<VS>::template ld<R>(d.v[r][1]);
+        V v2 = Conv<VS>::template ld<R>(d.v[r][2]);
+        if constexpr (is_normed<VS>()) {
+            const R sc = (R)(d.n[r] * (1.0f / kQ16));
+            v0 *= sc;
+            v1 *= sc;
+            v2 *= sc;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            V s = acc[r][a];
+            if constexpr (FWD) {
+                s.x = fma(u[3 * a].x, v0.x, s.x);  s.x = fma(-u[3 * a].y, v0.y, s.x);
+                s.y = fma(u[3 * a].x, v0.y, s.y);  s.y = fma(u[3 * a].y, v0.x, s.y);
+                s.x = fma(u[3 * a + 1].x, v1.x, s.x);  s.x = fma(-u[3 * a + 1].y, v1.y, s.x);
+                s.y = fma(u[3 * a + 1].x, v1.y, s.y);  s.y = fma(u[3 * a + 1].y, v1.x, s.y);
+                s.x = fma(u[3 * a + 2].x, v2.x, s.x);  s.x = fma(-u[3 * a + 2].y, v2.y, s.x);
+                s.y = fma(u[3 * a + 2].x, v2.y, s.y);  s.y = fma(u[3 * a + 2].y, v2.x, s.y);
+            } else {
+                s.x = fma(-u[a].x, v0.x, s.x);  s.x = fma(-u[a].y, v0.y, s.x);
+                s.y = fma(-u[a].x, v0.y, s.y);  s.y = fma(u[a].y, v0.x, s.y);
+                s.x = fma(-u[3 + a].x, v1.x, s.x);  s.x = fma(-u[3 + a].y, v1.y, s.x);
+                s.y = fma(-u[3 + a].x, v1.y, s.y);  s.y = fma(u[3 + a].y, v1.x, s.y);
+                s.x = fma(-u[6 + a].x, v2.x, s.x);  s.x = fma(-u[6 + a].y, v2.y, s.x);
+                s.y = fma(-u[6 + a].x, v2.y, s.y);  s.y = fma(u[6 + a].y, v2.x, s.y);
+            }
+            acc[r][a] = s;
+        }
+    }
+}
+
+// The 16 hops of a site in the order of the unpipelined loop, with the loads
+// of hop i + LA issued before the arithmetic of hop i.
+template <int NR, int LA, bool NT, typename R, typename VS, typename LS>
+__device__ __forceinline__ void gen_hops_all(const LS *const (&Uo)[2], const LS *const (&Ui)[2],
+                                             int64_t lstride, const Geom &g, int x, int y, int z,
+                                             int t, uint32_t own_l, const VS *__restrict__ in,
+                                             const uint32_t (&roff)[NR],
+                                             const float *__restrict__ nrm,
+                                             vec2<R> (&acc)[NR][3]) {
+    HopRawG<NR, VS, LS> buf[LA + 1];
+    auto load = [&](int i, HopRawG<NR, VS, LS> &d) {
+        const int h = i >> 3, mu = (i >> 1) & 3;
+        const int dist = h == 0 ? 1 : 3;
+        if ((i & 1) == 0) {
+            const int f = nbr_cb(g, x, y, z, t, mu, dist);
+            hop_load_g<NR, NT>(d, Uo[h] + mu * lstride, g.vh, own_l, in,
+                               (uint32_t)f * (uint32_t)sizeof(VS), roff, nrm);
+        } else {
+            const int b = nbr_cb(g, x, y, z, t, mu, -dist);
+            hop_load_g<NR, NT>(d, Ui[h] + mu * lstride, g.vh, link_off<LS>(b), in,
+                               (uint32_t)b * (uint32_t)sizeof(VS), roff, nrm);
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < LA; ++i) load(i, buf[i]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i + LA < 16) load(i + LA, buf[(i + LA) % (LA + 1)]);
+        if ((i & 1) == 0) hop_math_g<NR, true, R>(buf[i % (LA + 1)], acc);
+        else hop_math_g<NR, false, R>(buf[i % (LA + 1)], acc);
+        hop_fence<NR>(acc);
+    }
+}
+
 // Sum of x[0 .. kSites) in the canonical order, by one full wave (result in
 // every lane): lane l adds x[l], x[l+64], x[l+128], x[l+192] in that order,
 // then the fixed butterfly over the wave.
@@ -526,6 +644,13 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
             const q16c *const Ui[2] = {a.fat_in, a.lng_in};
             int_hops_all<NR, int_lookahead(NR, LPS), NT>(Uo, Ui, lstride, g, x, y, z, t, own_l, in,
                                                          roff, nrm_in, acc);
+        } else if constexpr (gen_lookahead(NR, LPS, sizeof(R), sizeof(VS), sizeof(LS),
+                                           is_normed<VS>()) > 0) {
+            const LS *const Uo[2] = {a.fat_out, a.lng_out};
+            const LS *const Ui[2] = {a.fat_in, a.lng_in};
+            gen_hops_all<NR,
+                         gen_lookahead(NR, LPS, sizeof(R), sizeof(VS), sizeof(LS), is_normed<VS>()),
+                         NT, R>(Uo, Ui, lstride, g, x, y, z, t, own_l, in, roff, nrm_in, acc);
         } else {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
