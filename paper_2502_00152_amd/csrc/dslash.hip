@@ -54,9 +54,11 @@ int nr_for(int nrhs, int lps) {
 // and 24 RHS: FP32 vectors with 16-bit links run best (or within 10%) with 3
 // RHS per lane at every volume; FP32 links with 3 per lane on small volumes
 // and up to 12 per lane on large ones (the (6 per lane, 4 lanes) shape chosen
-// earlier for 32^3 x 64 was up to 1.6x slower elsewhere); FP64 with 4 lanes
-// of 1 RHS on small volumes and 12 RHS per lane on large ones.  q16_links
-// selects the 16-bit-link defaults (FP32 vectors, real_bytes 4).
+// earlier for 32^3 x 64 was up to 1.6x slower elsewhere); FP64 with 2 lanes
+// of 3 RHS (M^H M with 12 RHS at 16^3 x 32: 139 us against 162-175 us with 4
+// lanes of 1 RHS; 24 RHS at 32^3 x 64: 5.3 ms against 5.8 ms with 12 RHS per
+// lane), the lanes loading the next hop before the current hop's arithmetic.
+// q16_links selects the 16-bit-link defaults (FP32 vectors, real_bytes 4).
 DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links) {
     const bool f32 = real_bytes <= 4, small = vh <= (1 << 18);  // FP32 and BF16
     DslashShape sh{};
@@ -69,8 +71,7 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
         if (small || q16_links) sh.nr = 3, sh.lps = 1;
         else sh.nr = nr_for(nrhs, 1), sh.lps = 1;
     } else {
-        if (small) sh.nr = 1, sh.lps = 4;
-        else sh.nr = 12, sh.lps = 1;
+        sh.nr = 3, sh.lps = 2;
     }
     int order = 0;
     // the autotuner's choice for this volume and batch, if any
