@@ -67,9 +67,11 @@ typedef enum hisq_status {
  * HISQ_HALF: the CG's search direction p, A p and the odd temporary held in
  * 16-bit fixed point with one scale per RHS and site (the largest |component|
  * of its three colours; relative accuracy ~3e-5), and links in 16-bit fixed
- * point with components up to 10922 (scale: the largest link component /
- * 10922, ~5e-5 absolute error), so that the stencil sums the integer products
- * of a link row and a colour vector exactly in 32 bits; for sloppy_prec and,
+ * point with components up to qmax (scale: the largest link component / qmax),
+ * qmax = min(32767, floor(65535 * largest component / largest row sum of
+ * |Re| + |Im|) - 1), at least 10922 (~26700 for near-unitary links), so that
+ * the stencil sums the integer products of a link row and a colour vector
+ * exactly in 32 bits for any vector; for sloppy_prec and,
  * with FP32 vectors at the boundary, for hisq_dslash_eo and hisq_mdagm. */
 typedef enum hisq_prec {
     HISQ_FP64 = 0,
@@ -167,9 +169,9 @@ hisq_status hisq_convert_vectors(const void *src_dev, hisq_prec src_prec, void *
  * component, step = the largest link component of the handle / 32767) or
  * HISQ_HALF (vectors of complex float at the boundary; inside, the input is
  * rounded to 16-bit fixed point with one norm per RHS and site, the stencil of
- * the CG at sloppy_prec = HISQ_HALF is applied, links with components up to
- * 10922, and its 16-bit output is widened to FP32: each value is that of the
- * stored 16-bit result).
+ * the CG at sloppy_prec = HISQ_HALF is applied, with its links, and its
+ * 16-bit output is widened to FP32: each value is that of the stored 16-bit
+ * result).
  */
 hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
                            void *out_dev, int nrhs, hisq_prec prec, void *stream);

@@ -102,10 +102,12 @@ using h16c = vec2<short>;
 template <typename VS>
 constexpr bool is_normed() { return std::is_same<VS, h16c>::value; }
 constexpr float kQ16 = 32767.0f;
-// Largest link component of the fixed-point links read with 16-bit vectors:
-// six products |link| <= 10922 times |vector| <= 32767 sum to at most
-// 2147287044 < 2^31, so the integer dot products of a link row and a colour
-// vector cannot overflow.
+// Fixed-point links read with 16-bit vectors: their largest integer
+// component qmax is chosen per gauge field so that a row's integer L1 norm
+// (sum of |Re| + |Im|) times 32767, the largest vector component, stays below
+// 2^31 and the integer dot products of a link row and a colour vector cannot
+// overflow.  10922 is safe for any field (6 * 10922 * 32767 < 2^31) and is the
+// floor of the choice.
 constexpr int kQLinkNarrow = 10922;
 // hops whose loads are in flight while a hop's arithmetic runs (16-bit path)
 #ifndef HISQ_INT_LOOKAHEAD

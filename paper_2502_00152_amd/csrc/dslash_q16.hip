@@ -7,9 +7,11 @@
 // FP32.  The kernel multiplies the integers as floats and the launcher folds
 // step into the stencil coefficient cd.  Half the link bytes of FP32, about
 // 4e-5 relative accuracy for unitary links (BF16: 2e-3).  The stencil on
-// 16-bit vectors reads a second copy with step = largest / 10922 (about 1e-4),
-// so that six products of a link row and a colour vector sum exactly in int32.
+// 16-bit vectors reads a second copy whose step is chosen per field so that
+// the integer products of a link row and a colour vector sum exactly in int32
+// (largest / ~26700 for near-unitary links, never coarser than / 10922).
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "dslash_kernel.h"
@@ -31,6 +33,33 @@ __global__ __launch_bounds__(kBS) void k_absmax(const double2 *__restrict__ src,
     for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
         const double2 a = src[i];
         v = fmax(v, fmax(fabs(a.x), fabs(a.y)));
+    }
+    m[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBS / 2; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = m[0];
+}
+
+// per-block max over link rows of sum_b (|Re U_ab| + |Im U_ab|), for nslots
+// site slots of the tiled layout [tile][9 entries][kLinkTile sites]
+__global__ __launch_bounds__(kBS) void k_rowl1max(const double2 *__restrict__ src, int64_t nslots,
+                                                  double *__restrict__ partials) {
+    __shared__ double m[kBS];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < nslots;
+         i += (int64_t)gridDim.x * kBS) {
+        const int64_t base = (i / kLinkTile) * 9 * kLinkTile + (i % kLinkTile);
+        for (int a = 0; a < 3; ++a) {
+            double r = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                const double2 u = src[base + (3 * a + b) * kLinkTile];
+                r += fabs(u.x) + fabs(u.y);
+            }
+            v = fmax(v, r);
+        }
     }
     m[threadIdx.x] = v;
     __syncthreads();
@@ -82,6 +111,28 @@ hisq_status link_absmax(hisq_gauge_s *g, hipStream_t s, double *mx_out) {
     return HISQ_OK;
 }
 
+// largest row sum of |Re| + |Im| over the fat and long links
+hisq_status link_rowl1max(hisq_gauge_s *g, hipStream_t s, double *out) {
+    const int64_t nslots = link_array_entries(g->geom.vh) / 9;
+    const int nb = (int)std::min<int64_t>((nslots + kBS - 1) / kBS, kMaxBlocks);
+    void *p = nullptr;
+    HISQ_TRY(g->ws.get("q16_absmax", sizeof(double) * 4 * kMaxBlocks, &p));
+    double *part = static_cast<double *>(p);
+    const double2 *arrays[4] = {g->fat[0], g->fat[1], g->lng[0], g->lng[1]};
+    for (int a = 0; a < 4; ++a)
+        hipLaunchKernelGGL(k_rowl1max, dim3(nb), dim3(kBS), 0, s, arrays[a], nslots,
+                           part + a * kMaxBlocks);
+    HISQ_HIP(hipGetLastError());
+    std::vector<double> h(4 * (size_t)kMaxBlocks);
+    HISQ_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HISQ_HIP(hipStreamSynchronize(s));
+    double mx = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < nb; ++b) mx = std::max(mx, h[(size_t)a * kMaxBlocks + b]);
+    *out = mx;
+    return HISQ_OK;
+}
+
 // fixed-point copies of both link fields, components in [-qmax, qmax]
 hisq_status make_q16_links(hisq_gauge_s *g, int qmax, int32_t *(&fat)[2], int32_t *(&lng)[2],
                            double *step_out, hipStream_t s) {
@@ -113,9 +164,26 @@ hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s) {
     return make_q16_links(g, 32767, g->fatq, g->lngq, &g->q16_step, s);
 }
 
+// The copy read by the stencil on 16-bit vectors, whose integer dot products
+// must not overflow for any vector with components up to 32767: Re and Im of
+// a row times a vector are bounded by 32767 times the row's integer L1 norm
+// (sum of |Re| + |Im|), which is at most rowl1 * qmax / absmax + 3 after
+// rounding; qmax <= 65535 absmax / rowl1 keeps that below 65538, and
+// 65538 * 32767 < 2^31.  Near-unitary links (row L1 <= sqrt 6 absmax) give
+// qmax ~ 26700; kQLinkNarrow covers any field.
+int q16n_qmax(double absmax, double rowl1) {
+    if (!(absmax > 0.0) || !(rowl1 > 0.0)) return kQLinkNarrow;
+    const double q = std::floor(65535.0 * absmax / rowl1) - 1.0;
+    return (int)std::max<double>(kQLinkNarrow, std::min<double>(32767.0, q));
+}
+
 hisq_status ensure_links_q16n(hisq_gauge_s *g, hipStream_t s) {
     if (g->fatn[0]) return HISQ_OK;
-    return make_q16_links(g, kQLinkNarrow, g->fatn, g->lngn, &g->qn_step, s);
+    double mx = 0.0, rl1 = 0.0;
+    HISQ_TRY(link_absmax(g, s, &mx));
+    HISQ_TRY(link_rowl1max(g, s, &rl1));
+    g->qn_max = q16n_qmax(mx, rl1);
+    return make_q16_links(g, g->qn_max, g->fatn, g->lngn, &g->qn_step, s);
 }
 
 hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,

@@ -92,8 +92,9 @@ struct hisq_gauge_s {
     int32_t *lngq[2] = {nullptr, nullptr};   //   per complex), made on first use,
     double q16_step = 0.0;                   //   value = integer * q16_step
     int32_t *fatn[2] = {nullptr, nullptr};   // the same with components in
-    int32_t *lngn[2] = {nullptr, nullptr};   //   [-10922, 10922] (integer-dot
+    int32_t *lngn[2] = {nullptr, nullptr};   //   [-qn_max, qn_max] (integer-dot
     double qn_step = 0.0;                    //   stencil), value = integer * qn_step
+    int qn_max = 0;                          //   largest integer component of that copy
     double link_absmax = -1.0;               // largest |component| of fat and long
     hipStream_t cg_stream = nullptr;        // the solvers' own stream (capturable)
     hisq::Workspace ws;

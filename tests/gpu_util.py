@@ -129,3 +129,19 @@ def abs_stencil_site(F, L, psi, site_xyzt):
             out += np.abs(U[mu][at(c)]) @ np.abs(psi[at(cf)])
             out += np.abs(U[mu][at(cb)]).T @ np.abs(psi[at(cb)])
     return out
+
+
+def half_link_step(F, L):
+    """Step of the fixed-point links the 16-bit stencil reads: largest folded
+    component / qmax, qmax = min(32767, floor(65535 * largest / largest row
+    sum of |Re| + |Im|) - 1), at least 10922 (the rule that keeps its integer
+    dot products below 2^31 for any vector with components up to 32767)."""
+    amax = max(np.abs(F.real).max(), np.abs(F.imag).max(), np.abs(L.real).max(),
+               np.abs(L.imag).max())
+    rowl1 = 0.0
+    for U in (F, L):
+        a = np.abs(U.real) + np.abs(U.imag)
+        rowl1 = max(rowl1, float(((a[..., 0] + a[..., 1]) + a[..., 2]).max()))
+    q = np.floor(65535.0 * amax / rowl1) - 1.0
+    qmax = int(max(10922.0, min(32767.0, q)))
+    return amax / qmax

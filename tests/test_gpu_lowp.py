@@ -34,7 +34,7 @@ import pytest
 
 from oracle import hisq_oracle as O
 from paper_2502_00152_amd import inputs as I
-from tests.gpu_util import Problem, abs_stencil, dev, from_parity, host, to_parity
+from tests.gpu_util import Problem, abs_stencil, dev, from_parity, half_link_step, host, to_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -363,14 +363,16 @@ def test_cg_half_batch_equals_single_solves(w8):
 # The operators at HISQ_HALF take FP32 vectors, round them to 16-bit fixed
 # point with one norm per site (|v - v'| <= m_y / 65534 per real component, m_y
 # = the site's largest |component|), apply the CG's 16-bit stencil (links with
-# step_n = largest folded link component / 10922, |dU| <= step_n / 2 per real;
+# step_n = largest folded link component / qmax, qmax chosen per field so that
+# the integer dot products cannot overflow (see tests/gpu_util.py; ~26700 for
+# these near-unitary links), |dU| <= step_n / 2 per real;
 # integer products exact; FP32 accumulation) and store the result rounded to
 # its own site norm (<= m_o / 65534 per real).  Componentwise, per output
 # colour: |out - D v| <= (step_n / sqrt 2) T + |D| w + 200 u32 S + m_o / 65534,
 # with T the stencil of |v| through unit links, w = sqrt 2 m_y / 65534 the
 # per-site bound of |v - v'|, S = |D| |v|.
 def qn_step(pr):
-    return q16_step(pr) * 32767.0 / 10922.0
+    return half_link_step(pr.F, pr.L)
 
 
 def site_max(v):

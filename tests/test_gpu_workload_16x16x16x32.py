@@ -213,20 +213,19 @@ def test_q16_stencil_sampled_sites(wl):
 def test_half_stencil_sampled_sites(wl):
     """The timed sloppy stencil itself: 12 RHS rounded to 16-bit fixed point
     with one norm per site, 16-bit links (step = largest link component /
-    10922), integer products, output rounded to its site norm, at 300 random
+    qmax, see tests/gpu_util.py), integer products, output rounded to its site norm, at 300 random
     sites, within (step / sqrt 2) T + |D| w + 200 u32 S + m_o / 65534 (see
     tests/test_gpu_lowp.py)."""
     import torch
     from paper_2502_00152_amd import hisq
-    from tests.gpu_util import abs_stencil_site
+    from tests.gpu_util import abs_stencil_site, half_link_step
     dims = wl.dims
     e32 = wl.eo.to(torch.complex64)
     out = torch.empty_like(e32)
     hisq.hisq_dslash_eo(wl.g, 0, e32, out, prec=hisq.HISQ_HALF)
     got = host(out).astype(np.complex128)
     eo32 = host(e32).astype(np.complex128)
-    step = max(np.abs(wl.F.real).max(), np.abs(wl.F.imag).max(),
-               np.abs(wl.L.real).max(), np.abs(wl.L.imag).max()) / 10922.0
+    step = half_link_step(wl.F, wl.L)
     ones = np.ones((4,) + wl.F.shape[1:], dtype=np.complex128)
     rng = np.random.default_rng(7)
     lex_even = np.nonzero(O.even_mask(dims).ravel())[0]
