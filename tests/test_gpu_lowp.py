@@ -473,3 +473,46 @@ def test_dslash_half_independent_of_launch_shape():
         hisq.hisq_set_tuning("dslash_rhs_per_thread", 0)
         hisq.hisq_set_tuning("dslash_lanes_per_site", 0)
         g.close()
+
+
+def test_dslash_half_integer_sums_at_their_bound(prob):
+    """The worst case of the integer dot products: the input at the neighbour
+    of the link row with the largest sum of |Re| + |Im| has every component at
+    +-1 (the site's norm, stored as +-32767) with the signs of that row, so the
+    real part of the row times it is the largest integer sum any vector can
+    give.  An int32 overflow would put that output off by ~2^32 steps; it must
+    stay within the quantisation bound."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = prob.dims
+    X, Y, Z, T = dims
+    a = np.abs(prob.F.real) + np.abs(prob.F.imag)
+    rowl1 = (a[..., 0] + a[..., 1]) + a[..., 2]           # [4][T][Z][Y][X][3]
+    mu, t, z, y, x, row = np.unravel_index(int(np.argmax(rowl1)), rowl1.shape)
+    site = [x, y, z, t]
+    nb = list(site)
+    nb[mu] = (nb[mu] + 1) % dims[mu]
+    U = prob.F[mu, t, z, y, x, row]                        # the row, 3 complex
+    psi = np.zeros((T, Z, Y, X, 3), dtype=np.complex128)
+    psi[nb[3], nb[2], nb[1], nb[0]] = np.sign(U.real) - 1j * np.sign(U.imag)
+    out_parity = int((x + y + z + t) % 2)
+    in_par = 1 - out_parity
+    v32 = to_parity(psi[None], dims, in_par).astype(np.complex64)
+    inp = torch.from_numpy(v32).cuda()
+    out = torch.empty_like(inp)
+    hisq.hisq_dslash_eo(prob.g, out_parity, inp, out, prec=hisq.HISQ_HALF)
+    got = host(out).astype(np.complex128)[0]
+    ref_full = O.dslash(prob.F, prob.L, psi, out_parity)
+    ref = to_parity(ref_full[None], dims, out_parity)[0]
+    B = half_bound(prob, psi)
+    mo = 1.01 * (site_max(ref_full) + B.max(axis=-1, keepdims=True)) / 65534.0
+    bound = to_parity((B + mo)[None], dims, out_parity)[0].real
+    err = np.abs(got - ref)
+    assert (err <= bound + 1e-30).all(), float((err / bound).max())
+    # the chosen output really is the extreme sum (real part = row L1 norm),
+    # where no other hop of the site reaches the same neighbour
+    if dims[mu] in (2, 4):
+        return
+    lex = ((t * Z + z) * Y + y) * X + x
+    assert abs(ref[row, lex >> 1].real - rowl1[mu, t, z, y, x, row]) < 1e-12
+    assert abs(got[row, lex >> 1].real - ref[row, lex >> 1].real) <= bound[row, lex >> 1]
