@@ -12,8 +12,11 @@
 // chip and costs more than the update itself): the r update re-sums the
 // <p, Ap> partials of its own RHS in every block, a small kernel (one wave
 // per RHS) advances the per-RHS state, and x and p are updated together
-// afterwards (x += alpha p with the old p, then p = r + beta p).  The rare kernels (initial and true
-// residuals, restarts) finish their reduction in the last block to arrive.
+// afterwards (x += alpha p with the old p, then p = r + beta p).  The rare
+// steps (initial and true residuals, restarts) work the same way: a pass
+// that stores per-block partials, then a small kernel (one wave per RHS)
+// that adds them in block order and takes the decision.  No kernel depends
+// on a counter or on scratch memory being zero when it starts.
 #include "device_util.h"
 #include "hisq_internal.h"
 
@@ -44,11 +47,12 @@ BlasGrid make_grid(int64_t n) {
 
 __device__ __forceinline__ double norm2(dvec2 v) { return fma(v.x, v.x, v.y * v.y); }
 
-// r = b - Ax; p = r; partials: ||b||^2 and ||r||^2 per RHS.
+// r = b - Ax; p = r; partials of ||b||^2 and ||r||^2 per RHS, stored as
+// [2][nrhs][gridDim.x] (k_cg_init_state adds them).
 __global__ __launch_bounds__(kBS) void k_cg_init(int64_t n, int nrhs, const dvec2 *__restrict__ b,
                                                  const dvec2 *__restrict__ Ax,
                                                  dvec2 *__restrict__ r, dvec2 *__restrict__ p,
-                                                 double tol, CgDev cg, Reduce red) {
+                                                 double *__restrict__ partials) {
     const int rhs = blockIdx.y;
     const int64_t off = rhs * n;
     double v[2] = {0.0, 0.0};
@@ -64,32 +68,8 @@ __global__ __launch_bounds__(kBS) void k_cg_init(int64_t n, int nrhs, const dvec
     block_sum<2, kBS>(v, lds);
     const int nbx = gridDim.x;
     if (threadIdx.x == 0) {
-        red.partials[(int64_t)rhs * nbx + blockIdx.x] = v[0];
-        red.partials[(int64_t)(nrhs + rhs) * nbx + blockIdx.x] = v[1];
-    }
-    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
-        __shared__ double w[kBS / kWave];
-        for (int q = 0; q < nrhs; ++q) {
-            const double bn = sum_partials<kBS>(red.partials + (int64_t)q * nbx, nbx, w);
-            const double rn = sum_partials<kBS>(red.partials + (int64_t)(nrhs + q) * nbx, nbx, w);
-            if (threadIdx.x == 0) {
-                cg.bnorm2[q] = bn;
-                cg.tol2b[q] = tol * tol * bn;
-                cg.rho[q] = rn;
-                cg.true_res2[q] = rn;
-                cg.iters[q] = 0;
-                cg.checks[q] = 0;
-                cg.alpha[q] = 0.0;
-                cg.beta[q] = 0.0;
-                if (!isfinite(bn) || !isfinite(rn))
-                    cg.status[q] = CG_NAN;
-                else if (bn == 0.0 || rn <= tol * tol * bn)
-                    cg.status[q] = CG_CONVERGED;
-                else
-                    cg.status[q] = CG_ACTIVE;
-            }
-        }
-        last_block_done(red.counter);
+        partials[(int64_t)rhs * nbx + blockIdx.x] = v[0];
+        partials[(int64_t)(nrhs + rhs) * nbx + blockIdx.x] = v[1];
     }
 }
 
@@ -100,6 +80,35 @@ __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p
     double v = 0.0;
     for (int i = lane; i < nb; i += kWave) v += p[i];
     return wave_sum(v);
+}
+
+// One wave per RHS: ||b||^2 and ||r||^2 from k_cg_init's partials, and the
+// initial per-RHS state (every field the iteration reads is written here).
+__global__ __launch_bounds__(kBS) void k_cg_init_state(int nrhs, const double *__restrict__ partials,
+                                                       int nbx, double tol, CgDev cg) {
+    const int q = blockIdx.x * (kBS / kWave) + threadIdx.x / kWave;
+    if (q >= nrhs) return;
+    const double bn = wave_sum_partials(partials + (int64_t)q * nbx, nbx);
+    const double rn = wave_sum_partials(partials + (int64_t)(nrhs + q) * nbx, nbx);
+    if ((threadIdx.x & (kWave - 1)) != 0) return;
+    cg.bnorm2[q] = bn;
+    cg.tol2b[q] = tol * tol * bn;
+    cg.rho[q] = rn;
+    cg.rho_pend[q] = rn;
+    cg.true_res2[q] = rn;
+    cg.iters[q] = 0;
+    cg.checks[q] = 0;
+    cg.alpha[q] = 0.0;
+    cg.beta[q] = 0.0;
+    cg.xp_alpha[q] = 0.0;
+    cg.xp_beta[q] = 0.0;
+    cg.xp_mode[q] = 0;
+    if (!isfinite(bn) || !isfinite(rn))
+        cg.status[q] = CG_NAN;
+    else if (bn == 0.0 || rn <= tol * tol * bn)
+        cg.status[q] = CG_CONVERGED;
+    else
+        cg.status[q] = CG_ACTIVE;
 }
 
 // alpha = rho / <p, Ap>, with <p, Ap> summed from the stencil kernel's
@@ -217,18 +226,18 @@ __global__ __launch_bounds__(kBS) void k_cg_update_xp(int64_t n, V *__restrict__
     }
 }
 
-// For pending RHS (or all, with final_only): r = b - Ax and ||r||^2; then
-// decide convergence of each pending RHS.
-__global__ __launch_bounds__(kBS) void k_cg_true_residual(int64_t n, int nrhs,
-                                                          const dvec2 *__restrict__ b,
+// For pending RHS (or all, with final_only): r = b - Ax (stored unless
+// final_only) and per-block partials of ||r||^2 (0 for the other RHS);
+// k_cg_true_state takes the decisions.
+__global__ __launch_bounds__(kBS) void k_cg_true_residual(int64_t n, const dvec2 *__restrict__ b,
                                                           const dvec2 *__restrict__ Ax,
                                                           dvec2 *__restrict__ r, CgDev cg,
-                                                          Reduce red, int final_only) {
+                                                          double *__restrict__ partials,
+                                                          int final_only) {
     const int rhs = blockIdx.y;
     const int64_t off = rhs * n;
     double v[1] = {0.0};
-    const int st = cg.status[rhs];
-    if (final_only || st == CG_PENDING) {
+    if (final_only || cg.status[rhs] == CG_PENDING) {
         for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
              i += (int64_t)gridDim.x * kBS) {
             const dvec2 rr = b[off + i] - Ax[off + i];
@@ -238,61 +247,58 @@ __global__ __launch_bounds__(kBS) void k_cg_true_residual(int64_t n, int nrhs,
     }
     __shared__ double lds[kBS / kWave];
     block_sum<1, kBS>(v, lds);
-    const int nbx = gridDim.x;
-    if (threadIdx.x == 0) red.partials[(int64_t)rhs * nbx + blockIdx.x] = v[0];
-    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
-        __shared__ double w[kBS / kWave];
-        for (int q = 0; q < nrhs; ++q) {
-            const double tr = sum_partials<kBS>(red.partials + (int64_t)q * nbx, nbx, w);
-            if (threadIdx.x == 0) {
-                if (final_only) {
-                    cg.true_res2[q] = tr;
-                } else if (cg.status[q] == CG_PENDING) {
-                    cg.checks[q] += 1;
-                    cg.true_res2[q] = tr;
-                    if (!isfinite(tr)) {
-                        cg.status[q] = CG_NAN;
-                    } else if (tr <= cg.tol2b[q]) {
-                        cg.status[q] = CG_CONVERGED;
-                    } else if (cg.iters[q] >= cg.max_iter) {
-                        cg.status[q] = CG_MAXITER;
-                    } else {
-                        cg.beta[q] = tr / cg.rho[q];
-                        cg.rho[q] = tr;
-                        cg.status[q] = CG_RESTART;
-                    }
-                }
-            }
-        }
-        last_block_done(red.counter);
+    if (threadIdx.x == 0) partials[(int64_t)rhs * gridDim.x + blockIdx.x] = v[0];
+}
+
+// One wave per RHS: the true ||r||^2 in block order; for a pending RHS the
+// convergence decision (converged, out of iterations, or a restart of the
+// recurrence from the true residual with beta = rho_true / rho).
+__global__ __launch_bounds__(kBS) void k_cg_true_state(int nrhs, const double *__restrict__ partials,
+                                                       int nbx, CgDev cg, int final_only) {
+    const int q = blockIdx.x * (kBS / kWave) + threadIdx.x / kWave;
+    if (q >= nrhs) return;
+    const double tr = wave_sum_partials(partials + (int64_t)q * nbx, nbx);
+    if ((threadIdx.x & (kWave - 1)) != 0) return;
+    if (final_only) {
+        cg.true_res2[q] = tr;
+        return;
+    }
+    if (cg.status[q] != CG_PENDING) return;
+    cg.checks[q] += 1;
+    cg.true_res2[q] = tr;
+    if (!isfinite(tr)) {
+        cg.status[q] = CG_NAN;
+    } else if (tr <= cg.tol2b[q]) {
+        cg.status[q] = CG_CONVERGED;
+    } else if (cg.iters[q] >= cg.max_iter) {
+        cg.status[q] = CG_MAXITER;
+    } else {
+        cg.beta[q] = tr / cg.rho[q];
+        cg.rho[q] = tr;
+        cg.status[q] = CG_RESTART;
     }
 }
 
-// p = r + beta p for RHS restarting from a true residual; then mark them active.
-__global__ __launch_bounds__(kBS) void k_cg_restart_p(int64_t n, int nrhs,
-                                                      const dvec2 *__restrict__ r,
-                                                      dvec2 *__restrict__ p, CgDev cg,
-                                                      Reduce red) {
+// p = r + beta p for RHS restarting from a true residual.
+__global__ __launch_bounds__(kBS) void k_cg_restart_p(int64_t n, const dvec2 *__restrict__ r,
+                                                      dvec2 *__restrict__ p, CgDev cg) {
     const int rhs = blockIdx.y;
-    if (cg.status[rhs] == CG_RESTART) {
-        const int64_t off = rhs * n;
-        const double be = cg.beta[rhs];
-        for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * kBS) {
-            const dvec2 rr = r[off + i];
-            dvec2 pp = p[off + i];
-            pp.x = fma(be, pp.x, rr.x);
-            pp.y = fma(be, pp.y, rr.y);
-            p[off + i] = pp;
-        }
+    if (cg.status[rhs] != CG_RESTART) return;
+    const int64_t off = rhs * n;
+    const double be = cg.beta[rhs];
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+        const dvec2 rr = r[off + i];
+        dvec2 pp = p[off + i];
+        pp.x = fma(be, pp.x, rr.x);
+        pp.y = fma(be, pp.y, rr.y);
+        p[off + i] = pp;
     }
-    __syncthreads();
-    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
-        if (threadIdx.x == 0)
-            for (int q = 0; q < nrhs; ++q)
-                if (cg.status[q] == CG_RESTART) cg.status[q] = CG_ACTIVE;
-        last_block_done(red.counter);
-    }
+}
+
+// Restarted RHS become active again (after k_cg_restart_p has read their state).
+__global__ __launch_bounds__(kBS) void k_cg_activate(int nrhs, CgDev cg) {
+    const int q = blockIdx.x * kBS + threadIdx.x;
+    if (q < nrhs && cg.status[q] == CG_RESTART) cg.status[q] = CG_ACTIVE;
 }
 
 }  // namespace
@@ -308,7 +314,11 @@ hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, do
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
     hipLaunchKernelGGL(k_cg_init, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs, AS_CV(b),
-                       AS_CV(Ax), AS_V(r), AS_V(p), tol, cg, red);
+                       AS_CV(Ax), AS_V(r), AS_V(p), red.partials);
+    HISQ_HIP(hipGetLastError());
+    const int per = kBS / kWave;
+    hipLaunchKernelGGL(k_cg_init_state, dim3((nrhs + per - 1) / per), dim3(kBS), 0, s, nrhs,
+                       red.partials, gr.nbx, tol, cg);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
@@ -372,18 +382,24 @@ hisq_status cg_true_residual(int64_t n, int nrhs, const double2 *b, const double
                              hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_true_residual, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs,
-                       AS_CV(b), AS_CV(Ax), AS_V(r), cg, red, final_only ? 1 : 0);
+    hipLaunchKernelGGL(k_cg_true_residual, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_CV(b),
+                       AS_CV(Ax), AS_V(r), cg, red.partials, final_only ? 1 : 0);
+    HISQ_HIP(hipGetLastError());
+    const int per = kBS / kWave;
+    hipLaunchKernelGGL(k_cg_true_state, dim3((nrhs + per - 1) / per), dim3(kBS), 0, s, nrhs,
+                       red.partials, gr.nbx, cg, final_only ? 1 : 0);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
 hisq_status cg_restart_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
-                         const Reduce &red, hipStream_t s) {
+                         hipStream_t s) {
     const BlasGrid gr = make_grid(n);
     ProfileScope prof("blas", s);
-    hipLaunchKernelGGL(k_cg_restart_p, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, nrhs,
-                       AS_CV(r), AS_V(p), cg, red);
+    hipLaunchKernelGGL(k_cg_restart_p, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_CV(r), AS_V(p),
+                       cg);
+    HISQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cg_activate, dim3((nrhs + kBS - 1) / kBS), dim3(kBS), 0, s, nrhs, cg);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }

@@ -80,12 +80,9 @@ hisq_status alloc_cg(hisq_gauge_s *g, int nrhs, CgBuffers &B) {
                                            (size_t)2 * nrhs * blas_reduce_blocks(n));
     HISQ_TRY(g->ws.get("reduce_partials", sizeof(double) * nparts, &p));
     B.red.partials = static_cast<double *>(p);
-    HISQ_TRY(g->ws.get("reduce_counter", 256, &p));
-    B.red.counter = static_cast<unsigned *>(p);
     HISQ_TRY(g->ws.get("cg_pap_partials",
                        sizeof(double) * (size_t)nrhs * dslash_reduce_blocks(g, nrhs), &p));
     B.pap.partials = static_cast<double *>(p);
-    B.pap.counter = nullptr;
     return HISQ_OK;
 }
 
@@ -225,7 +222,7 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
                                     hipMemcpyHostToDevice, s));
             HISQ_TRY(apply_mdagm(g, two_m, x, B.Ap, nrhs, s, par, m2_rhs, B.dev_skip));
             HISQ_TRY(cg_true_residual(n, nrhs, b, B.Ap, B.r, B.dev, B.red, false, s));
-            HISQ_TRY(cg_restart_p(n, nrhs, B.r, B.p, B.dev, B.red, s));
+            HISQ_TRY(cg_restart_p(n, nrhs, B.r, B.p, B.dev, s));
             HISQ_TRY(fetch_state());
             continue;
         }

@@ -151,8 +151,6 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
                            std::max<int>(std::max(2 * nb_blas, nb_pap), mixed_resid_blocks(n)),
                        &p));
     red.partials = static_cast<double *>(p);
-    HISQ_TRY(g->ws.get("reduce_counter", 256, &p));
-    red.counter = static_cast<unsigned *>(p);
     HISQ_TRY(g->ws.get("cg_pap_partials", sizeof(double) * (size_t)nrhs * nb_pap, &p));
     pap.partials = static_cast<double *>(p);
 

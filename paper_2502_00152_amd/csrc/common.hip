@@ -38,10 +38,13 @@ hisq_status Workspace::get(const char *name, size_t bytes, void **ptr) {
             return fail(HISQ_ERR_OOM, std::string("scratch '") + name + "' of " +
                                           std::to_string(bytes) + " bytes: " +
                                           hipGetErrorString(e));
-        // arrival counters and partial sums start from zero.  The clear goes
-        // to the null stream, which the solvers' non-blocking streams do not
-        // wait for, and reused device memory holds old values: the clear must
-        // be complete before the buffer is handed out.
+        // No kernel reads scratch it has not written in the same solve (the
+        // reductions store every partial before a later kernel sums them, and
+        // the CG state is set by its init kernel), so the contents of a new
+        // buffer do not matter.  It is still cleared, and the clear completed
+        // before the buffer is handed out (the solvers' non-blocking streams
+        // do not wait for the null stream), so that a stray read of it is
+        // reproducible.
         HISQ_HIP(hipMemset(p, 0, bytes));
         HISQ_HIP(hipDeviceSynchronize());
         b.ptr = p;

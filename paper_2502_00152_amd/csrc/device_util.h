@@ -1,5 +1,4 @@
-// Device helpers: complex arithmetic on double2, fixed-order block reductions,
-// the last-block arrival used to finish a global reduction inside a kernel,
+// Device helpers: complex arithmetic on double2, fixed-order block reductions
 // and the XCD-aware block order.
 #pragma once
 
@@ -72,41 +71,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
         }
     }
     __syncthreads();
-}
-
-// Every block calls this once after thread 0 has stored its partial sums.
-// Returns true in exactly one block - the last to arrive - after making the
-// other blocks' stores visible to it.  The counter is reset by that block
-// through last_block_done().
-__device__ __forceinline__ bool last_block_arrive(unsigned *counter, unsigned total) {
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == total - 1u);
-    }
-    __syncthreads();
-    const bool last = is_last != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-__device__ __forceinline__ void last_block_done(unsigned *counter) {
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-}
-
-// Fixed-order sum of partials[0..nb) by one block (all threads call it).
-template <int BS>
-__device__ __forceinline__ double sum_partials(const double *partials, int nb, double *lds) {
-    double v[1] = {0.0};
-    for (int i = threadIdx.x; i < nb; i += BS) v[0] += partials[i];
-    block_sum<1, BS>(v, lds);
-    __shared__ double result;
-    if (threadIdx.x == 0) result = v[0];
-    __syncthreads();
-    const double r = result;
-    __syncthreads();
-    return r;
 }
 
 }  // namespace hisq

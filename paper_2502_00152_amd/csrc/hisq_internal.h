@@ -150,10 +150,10 @@ struct CgDev {
     int max_iter;
 };
 
-// Reduction bookkeeping for kernels that end with a fixed-order global sum.
+// Per-block partial sums of a reduction, [nvals][nblocks]; every launch writes
+// all of its entries before a later kernel adds them in block order.
 struct Reduce {
-    double *partials;   // [nvals][nblocks]
-    unsigned *counter;  // arrival counter, zero between launches
+    double *partials;
 };
 
 // ------------------------------------------------------- kernel launchers
@@ -203,7 +203,7 @@ hisq_status cg_true_residual(int64_t n, int nrhs, const double2 *b, const double
                              double2 *r, const CgDev &cg, const Reduce &red, bool final_only,
                              hipStream_t s);
 hisq_status cg_restart_p(int64_t n, int nrhs, const double2 *r, double2 *p, const CgDev &cg,
-                         const Reduce &red, hipStream_t s);
+                         hipStream_t s);
 
 // Layout conversion.
 hisq_status launch_split(const hisq_gauge_s *g, const double2 *full, double2 *even,

@@ -1,5 +1,5 @@
 // Vector kernels of the eigensolver: a counter-based random start vector,
-// FP64 dot products with fixed-order reductions, scaled sums, and per-column
+// FP64 dot products with fixed-order reductions (partials, then a sum in block order), scaled sums, and per-column
 // residual norms ||w_i - lambda_i u_i||.
 #include "device_util.h"
 #include "hisq_internal.h"
@@ -39,9 +39,10 @@ __global__ __launch_bounds__(kBS) void k_random(dvec2 *__restrict__ x, int64_t n
     }
 }
 
-// out[0] + i out[1] = <x, y> = sum conj(x) y
+// Per-block partials of <x, y> = sum conj(x) y: real parts at [block],
+// imaginary parts at [nb + block]; k_sum_rows adds them in block order.
 __global__ __launch_bounds__(kBS) void k_dot(const dvec2 *__restrict__ x, const dvec2 *__restrict__ y,
-                                             int64_t n, double *out, Reduce red) {
+                                             int64_t n, double *__restrict__ partials) {
     double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
         const dvec2 a = x[i], b = y[i];
@@ -52,19 +53,21 @@ __global__ __launch_bounds__(kBS) void k_dot(const dvec2 *__restrict__ x, const 
     block_sum<2, kBS>(v, lds);
     const int nb = gridDim.x;
     if (threadIdx.x == 0) {
-        red.partials[blockIdx.x] = v[0];
-        red.partials[nb + blockIdx.x] = v[1];
+        partials[blockIdx.x] = v[0];
+        partials[nb + blockIdx.x] = v[1];
     }
-    if (last_block_arrive(red.counter, nb)) {
-        __shared__ double w[kBS / kWave];
-        const double re = sum_partials<kBS>(red.partials, nb, w);
-        const double im = sum_partials<kBS>(red.partials + nb, nb, w);
-        if (threadIdx.x == 0) {
-            out[0] = re;
-            out[1] = im;
-        }
-        last_block_done(red.counter);
-    }
+}
+
+// out[q] = sum of row q of partials ([rows][nb]) in block order; one wave per row.
+__global__ __launch_bounds__(kBS) void k_sum_rows(const double *__restrict__ partials, int nb,
+                                                  int rows, double *__restrict__ out) {
+    const int q = blockIdx.x * (kBS / kWave) + threadIdx.x / kWave;
+    if (q >= rows) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    double v = 0.0;
+    for (int i = lane; i < nb; i += kWave) v += partials[(int64_t)q * nb + i];
+    v = wave_sum(v);
+    if (lane == 0) out[q] = v;
 }
 
 // y = a y + b1 x1 + b2 x2 (x1, x2 optional)
@@ -88,10 +91,11 @@ __global__ __launch_bounds__(kBS) void k_axpby2(dvec2 *__restrict__ y, double a,
     }
 }
 
-// out[i] = ||W_i - lam_i U_i||^2 over k columns of n complex (grid.y = column)
+// Per-block partials of ||W_i - lam_i U_i||^2 over k columns of n complex
+// (grid.y = column), stored as [k][gridDim.x].
 __global__ __launch_bounds__(kBS) void k_colres(const dvec2 *__restrict__ W, const dvec2 *__restrict__ U,
-                                                const double *__restrict__ lam, int64_t n, int k,
-                                                double *out, Reduce red) {
+                                                const double *__restrict__ lam, int64_t n,
+                                                double *__restrict__ partials) {
     const int col = blockIdx.y;
     const double l = lam[col];
     double v[1] = {0.0};
@@ -103,24 +107,20 @@ __global__ __launch_bounds__(kBS) void k_colres(const dvec2 *__restrict__ W, con
     }
     __shared__ double lds[kBS / kWave];
     block_sum<1, kBS>(v, lds);
-    const int nb = gridDim.x;
-    if (threadIdx.x == 0) red.partials[(int64_t)col * nb + blockIdx.x] = v[0];
-    if (last_block_arrive(red.counter, gridDim.x * gridDim.y)) {
-        __shared__ double w2[kBS / kWave];
-        for (int c = 0; c < k; ++c) {
-            const double s = sum_partials<kBS>(red.partials + (int64_t)c * nb, nb, w2);
-            if (threadIdx.x == 0) out[c] = s;
-        }
-        last_block_done(red.counter);
-    }
+    if (threadIdx.x == 0) partials[(int64_t)col * gridDim.x + blockIdx.x] = v[0];
 }
 
-hisq_status reduce_buffers(hisq_gauge_s *g, size_t nvals, Reduce &red) {
+double *reduce_buffer(hisq_gauge_s *g, size_t nvals, hisq_status *st) {
     void *p = nullptr;
-    HISQ_TRY(g->ws.get("vec_partials", sizeof(double) * nvals, &p));
-    red.partials = static_cast<double *>(p);
-    HISQ_TRY(g->ws.get("vec_counter", 256, &p));
-    red.counter = static_cast<unsigned *>(p);
+    *st = g->ws.get("vec_partials", sizeof(double) * nvals, &p);
+    return static_cast<double *>(p);
+}
+
+hisq_status sum_rows(const double *partials, int nb, int rows, double *out, hipStream_t s) {
+    const int per = kBS / kWave;
+    hipLaunchKernelGGL(k_sum_rows, dim3((rows + per - 1) / per), dim3(kBS), 0, s, partials, nb,
+                       rows, out);
+    HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
@@ -135,14 +135,15 @@ hisq_status vec_random(double2 *x, int64_t n, uint64_t seed, hipStream_t s) {
 
 hisq_status vec_dot(hisq_gauge_s *g, const double2 *x, const double2 *y, int64_t n, double *out,
                     hipStream_t s) {
-    Reduce red{};
     const int nb = grid_for(n);
-    HISQ_TRY(reduce_buffers(g, 2 * (size_t)nb, red));
+    hisq_status st = HISQ_OK;
+    double *partials = reduce_buffer(g, 2 * (size_t)nb, &st);
+    HISQ_TRY(st);
     ProfileScope prof("blas", s);
     hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBS), 0, s, reinterpret_cast<const dvec2 *>(x),
-                       reinterpret_cast<const dvec2 *>(y), n, out, red);
+                       reinterpret_cast<const dvec2 *>(y), n, partials);
     HISQ_HIP(hipGetLastError());
-    return HISQ_OK;
+    return sum_rows(partials, nb, 2, out, s);
 }
 
 hisq_status vec_axpby2(double2 *y, double a, const double2 *x1, double b1, const double2 *x2,
@@ -158,14 +159,15 @@ hisq_status vec_axpby2(double2 *y, double a, const double2 *x1, double b1, const
 hisq_status vec_col_residuals(hisq_gauge_s *g, const double2 *W, const double2 *U,
                               const double *lam_dev, int64_t n, int k, double *out_dev,
                               hipStream_t s) {
-    Reduce red{};
     const int nb = std::max(1, grid_for(n) / 4);
-    HISQ_TRY(reduce_buffers(g, (size_t)nb * k, red));
+    hisq_status st = HISQ_OK;
+    double *partials = reduce_buffer(g, (size_t)nb * k, &st);
+    HISQ_TRY(st);
     ProfileScope prof("blas", s);
     hipLaunchKernelGGL(k_colres, dim3(nb, k), dim3(kBS), 0, s, reinterpret_cast<const dvec2 *>(W),
-                       reinterpret_cast<const dvec2 *>(U), lam_dev, n, k, out_dev, red);
+                       reinterpret_cast<const dvec2 *>(U), lam_dev, n, partials);
     HISQ_HIP(hipGetLastError());
-    return HISQ_OK;
+    return sum_rows(partials, nb, k, out_dev, s);
 }
 
 }  // namespace hisq

@@ -223,3 +223,55 @@ def test_several_masses_in_one_batch(w8, prec):
     assert O.norm(pr.y - O.apply_A(pr.F, pr.L, 0.05, xe)) / O.norm(pr.y) <= 1e-10
     with pytest.raises(hisq.HisqError):
         hisq.hisq_cg_solve(pr.g, [0.1, -0.1, 0.2], b, torch.zeros_like(b))
+
+
+def residual_agreement_bound(pr, two_m, x_soa, b_soa, j):
+    """Allowed gap between the library's reported FP64 true residual and the
+    oracle's for RHS j: 5% of the residual plus the rounding of b - A x, whose
+    terms are of size lambda_max ||x|| with lambda_max <= (2m)^2 + 69.4 for
+    unitary links (the bound pinned on the oracle), i.e. 64 u lambda_max
+    ||x|| / ||b|| relative, u = 2^-53."""
+    lam_max = two_m ** 2 + 69.4
+    xn = np.linalg.norm(x_soa[j])
+    bn = np.linalg.norm(b_soa[j])
+    return lambda tr: 0.05 * tr + 64 * 2.0 ** -53 * lam_max * xn / bn
+
+
+def test_many_solves_on_one_handle_report_true_residuals():
+    """Solves in a row on one handle with different RHS counts (the scratch
+    buffers grow and are reused, the reduction grids change), FP64 and mixed,
+    interleaved with solves on a second handle of another shape: every RHS's
+    reported FP64 true residual must agree with the oracle's and meet tol.
+    (Guards against a convergence decision taken on stale reduction state.)"""
+    import torch
+    from paper_2502_00152_amd import hisq
+    shapes = [((4, 4, 4, 8), 0.3, 3101, 3102, 0.1), ((8, 4, 6, 4), 0.5, 3201, 3202, 0.05)]
+    probs = []
+    for dims, eps, sf, sl, two_m in shapes:
+        pr = Problem(dims, eps, sf, sl)
+        pr.g = pr.gauge()
+        pr.two_m = two_m
+        probs.append(pr)
+    plan = [(0, 1, "fp64"), (1, 3, "fp64"), (0, 12, "fp32"), (0, 5, "fp64"), (1, 24, "half"),
+            (0, 2, "fp64"), (1, 7, "fp64"), (0, 24, "fp64"), (0, 3, "half"), (1, 1, "fp32")]
+    sp = {"fp64": hisq.HISQ_FP64, "fp32": hisq.HISQ_FP32, "half": hisq.HISQ_HALF}
+    try:
+        for step, (which, nrhs, prec) in enumerate(plan):
+            pr = probs[which]
+            etas = [I.gaussian_source(pr.dims, 5000 + 97 * step + j) for j in range(nrhs)]
+            ys = np.concatenate([to_parity(O.source_even(pr.F, pr.L, pr.two_m, e), pr.dims, 0)
+                                 for e in etas])
+            b = dev(ys)
+            x = torch.zeros_like(b)
+            res = hisq.hisq_cg_solve(pr.g, pr.two_m, b, x, tol=1e-10, sloppy_prec=sp[prec])
+            assert all(res.converged), (step, prec)
+            xs = host(x)
+            tr = oracle_true_residual(pr, pr.two_m, xs, ys)
+            for j in range(nrhs):
+                assert tr[j] <= 1e-10, (step, prec, j, tr[j])
+                bound = residual_agreement_bound(pr, pr.two_m, xs, ys, j)
+                assert abs(res.true_residual[j] - tr[j]) <= bound(tr[j]), \
+                    (step, prec, j, res.true_residual[j], tr[j])
+    finally:
+        for pr in probs:
+            pr.g.close()

@@ -6,9 +6,10 @@ RHS, shared link loads); the four systems run concurrently.
 
 Links are drawn on the device and copied to the host for the oracle (the
 host draw of 24^3 x 48 takes about a minute).  Checks: every RHS converges;
-the oracle's true residual of one RHS per (lattice, mass) meets tol; the
-concurrent batched solve equals separate single-mass solves bitwise for the
-smallest lattice.
+the oracle's FP64 true residual of every RHS meets tol, and the library's
+reported true residual of every RHS agrees with the oracle's (5% plus the
+rounding of b - A x); the concurrent batched solve equals separate
+single-mass solves bitwise for the smallest lattice.
 """
 from __future__ import annotations
 
@@ -64,16 +65,22 @@ def test_uneven_batch_concurrent(batch, prec):
     n = sum(d["b"].shape[0] for d in batch)
     print(f"[uneven] {prec}: {n} solves in {time.time() - t0:.2f}s, iterations "
           f"{[max(r.iterations) for r in res]}", flush=True)
+    worst = 0.0
     for d, (g, ms, b, x), r in zip(batch, systems, res):
         assert all(r.converged)
         xs, bs = host(x), host(b)
-        nr = d["nrhs"]
-        for k in range(3):
-            j = k * nr + (k % nr)
+        for j in range(bs.shape[0]):
             xe = from_parity(xs[j:j + 1], d["dims"], 0)[0]
             be = from_parity(bs[j:j + 1], d["dims"], 0)[0]
             tr = O.norm(be - O.apply_A(d["F"], d["L"], ms[j], xe)) / O.norm(be)
-            assert tr <= 1e-10, (d["dims"], ms[j], tr)
+            assert tr <= 1e-10, (d["dims"], j, ms[j], tr)
+            # rounding of b - A x: terms of size lambda_max ||x||, lambda_max
+            # <= (2m)^2 + 69.4 for unitary links
+            slack = 64 * 2.0 ** -53 * (ms[j] ** 2 + 69.4) * O.norm(xe) / O.norm(be)
+            gap = abs(r.true_residual[j] - tr)
+            assert gap <= 0.05 * tr + slack, (d["dims"], j, ms[j], r.true_residual[j], tr)
+            worst = max(worst, tr)
+    print(f"[uneven] {prec}: largest oracle true residual {worst:.3e}", flush=True)
     # the smallest lattice: equal to separate single-mass solves
     d = batch[0]
     x = systems[0][3]

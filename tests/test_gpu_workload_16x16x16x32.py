@@ -17,6 +17,8 @@ from tests.gpu_util import Problem, dev, from_parity, host, to_parity
 pytestmark = pytest.mark.gpu
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_16x16x16x32.json")))
+SOLUTIONS = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                        "oracle_solutions_16x16x16x32.json")))
 
 
 @pytest.fixture(scope="module")
@@ -79,6 +81,11 @@ def test_eigenpairs_match_oracle(wl, eig):
     ref = np.array(GOLDEN["eigenvalues"])
     lmax = stats.lambda_max
     assert np.abs(lam - ref).max() <= 1e-10 * lmax
+    # relative to each eigenvalue: a residual r <= tol lambda_max moves a
+    # Rayleigh quotient by at most r^2 / gap, far below 1e-10 lambda_i here
+    print(f"[16x16x16x32] largest relative eigenvalue difference "
+          f"{(np.abs(lam - ref) / ref).max():.3e}", flush=True)
+    assert (np.abs(lam - ref) <= 1e-10 * ref).all()
     V = host(ev)
     G = V.reshape(64, -1).conj() @ V.reshape(64, -1).T
     assert np.abs(G - np.eye(64)).max() <= 1e-12
@@ -292,3 +299,41 @@ def test_timed_step_16bit_multi_deflation(wl, eig, sloppy):
     for r in range(12):
         bound = (rq.true_residual[r] + r64.true_residual[r]) * np.linalg.norm(ys[r]) / lam1
         assert np.linalg.norm(xs[r] - x64s[r]) <= bound * 1.01, r
+
+
+def test_fp64_solution_matches_oracle_reference(wl, eig):
+    """FP64 solution parity at the full size: sources 0 and 1, deflated FP64
+    CG stopped at a true residual of 1e-13 (min(1e-10, 1e-9 / kappa) with
+    kappa = lambda_max / lambda_1 ~ 7e3, floored at 1e-13), against the
+    oracle's plain CG solution to 1e-14 stored by
+    tests/golden/make_solutions_16x16x16x32_golden.py: the solution at 128
+    seeded sites and its inner products with 8 seeded Gaussian vectors, each
+    within 1e-9 relative."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    ev, lam, stats = eig
+    two_m = wl.cfg["two_m"]
+    sites = np.array(SOLUTIONS["sites_lex"])
+    probes = np.stack([to_parity(np.where(O.even_mask(wl.dims)[..., None],
+                                          I.gaussian_source(wl.dims, sd), 0), wl.dims, 0)[0]
+                       for sd in SOLUTIONS["probe_seeds"]])
+    y = wl.y[:2].clone()
+    x = torch.empty_like(y)
+    hisq.hisq_deflate(wl.g, ev, lam - two_m ** 2, two_m, y, x)
+    res = hisq.hisq_cg_solve(wl.g, two_m, y, x, tol=1e-13)
+    assert all(res.converged)
+    xs = host(x)
+    for k, ref in enumerate(SOLUTIONS["solutions"]):
+        assert ref["source"] == k and ref["true_residual"] <= 1e-14
+        got = xs[k][:, sites >> 1].T                        # [site][colour]
+        want = np.array(ref["site_values_re"]) + 1j * np.array(ref["site_values_im"])
+        e_sites = np.linalg.norm(got - want) / np.linalg.norm(want)
+        pr_got = probes.reshape(len(probes), -1).conj() @ xs[k].reshape(-1)
+        pr_want = np.array(ref["probe_re"]) + 1j * np.array(ref["probe_im"])
+        scale = np.linalg.norm(probes.reshape(len(probes), -1), axis=1) * ref["norm"]
+        e_probe = (np.abs(pr_got - pr_want) / scale).max()
+        e_norm = abs(np.linalg.norm(xs[k]) - ref["norm"]) / ref["norm"]
+        print(f"[16x16x16x32] source {k}: {res.iterations[k]} iterations, reported residual "
+              f"{res.true_residual[k]:.2e}; relative error at sites {e_sites:.2e}, "
+              f"probes {e_probe:.2e}, norm {e_norm:.2e}", flush=True)
+        assert e_sites <= 1e-9 and e_probe <= 1e-9 and e_norm <= 1e-9

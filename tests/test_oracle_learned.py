@@ -122,3 +122,36 @@ def test_first_adam_step_is_signed_learning_rate():
     assert np.allclose(th[:2], [-0.01, 0.01], rtol=1e-4)
     assert th[2] == 0.0
     assert abs(th[3]) < 0.01   # |g| comparable to eps: a damped step
+
+
+def test_gates_hand_computed_at_one_site():
+    """A hand-worked value with non-zero gate slopes a.  The weights keep only
+    the identity hop and channel 0, and the input is zero except at one site
+    where r = (3+4i, 12i, 0), so |r| = sqrt(9 + 16 + 144) = 13 (the norm of the
+    colour vector, not of a single colour, not squared):
+      gate 1, a = 0.1, b = -1.3:  sigmoid(0.1 * 13 - 1.3) = sigmoid(0) = 1/2,
+          z = (1.5+2i, 6i, 0), |z| = sqrt(2.25 + 4 + 36) = 6.5;
+      gate 2, a = 0.2, b = -0.3:  sigmoid(0.2 * 6.5 - 0.3) = sigmoid(1) = e/(1+e)
+          = 0.7310585786300049,
+      N(r) = z e/(1+e) = (1.0965878679450074 + 1.4621171572600098i,
+                          4.3863514717800295i, 0) at that site, 0 elsewhere.
+    A gate on |r|^2, on each colour separately, or with the sign of a or b
+    flipped gives another value."""
+    dims = (4, 4, 4, 4)
+    F = links(dims)
+    p = {k: np.zeros(s) for k, s in N.SHAPES}
+    p["W1"][0, 0, 0] = 1.0
+    p["W2"][0, 0, 0] = 1.0
+    p["W3"][0, 0, 0] = 1.0
+    p["g1"][0] = (0.1, -1.3)
+    p["g2"][0] = (0.2, -0.3)
+    theta = np.concatenate([p[k].ravel() for k, _ in N.SHAPES])
+    r = np.zeros((4, 4, 4, 4, 3), dtype=np.complex128)
+    site = (2, 1, 3, 0)  # [t][z][y][x], an even site
+    assert sum(site) % 2 == 0
+    r[site] = (3 + 4j, 12j, 0)
+    out = N.apply(theta, F, r, O.even_mask(dims))
+    want = np.array([1.0965878679450074 + 1.4621171572600098j, 4.3863514717800295j, 0])
+    assert np.allclose(out[site], want, rtol=1e-15, atol=1e-15)
+    out[site] = 0
+    assert np.abs(out).max() == 0.0
