@@ -96,7 +96,7 @@ const char *hisq_last_error(void);
 
 /* ABI revision of this header; bumped on any incompatible change. */
 int hisq_abi_version(void);
-#define HISQ_ABI_VERSION 8
+#define HISQ_ABI_VERSION 9
 
 /* ------------------------------------------------------------------ gauge */
 
@@ -386,7 +386,10 @@ typedef struct hisq_eig_params {
     double cheb_b;
     double tol;            /* accept when ||A v - lambda v|| <= tol * lambda_max(A) */
     int max_restarts;      /* 0 = default 200 */
-    int reserved0;
+    int evec_prec;         /* storage of evecs_dev: HISQ_FP64 (0) or HISQ_FP32 (the
+                              solve itself is FP64 throughout; FP32 output is the
+                              FP64 result rounded, section 3's single-precision
+                              eigenvectors) */
     uint64_t seed;         /* seed of the counter-based start vector */
     hisq_eig_progress_fn progress; /* optional progress report (NULL: none) */
     void *progress_user;   /* passed to progress */
@@ -410,7 +413,13 @@ typedef struct hisq_eig_stats {
  * step on A itself (section 2: eigenvectors of the squared operator from
  * thick-restart Lanczos, used for deflation; the vectors are single parity,
  * section 3).
- *   evecs_dev   caller-allocated [n_ev][3][Vh] complex double (orthonormal on exit)
+ *   evecs_dev   caller-allocated [n_ev][3][Vh] complex double, or complex float
+ *               with evec_prec = HISQ_FP32 (orthonormal on exit)
+ * Device memory: one FP64 basis of n_kr + 1 vectors, a block of
+ * min(n_ev, 32) vectors (twice: the block and M^H M's odd temporary) and
+ * four more vectors (48 Vh bytes each), all freed before the call returns;
+ * e.g. n_ev = 512, n_kr = 640 at 48^3 x 96 (Vh = 5308416) takes 173 GB
+ * besides the caller's 65 GB of FP32 eigenvectors and the links.
  *   evals_host  n_ev doubles, ascending: eigenvalues of A at this two_m
  *   stats_host  may be NULL.
  * Returns NOT_CONVERGED if max_restarts passes without n_ev accepted pairs
@@ -454,7 +463,8 @@ typedef struct hisq_tune_result {
     double us_best;        /* average launch time of the chosen shape */
     double us_default;     /* and of the shape in use before the call */
     int shapes_timed;
-    int reserved[3];
+    int march;             /* time segments of the time-marching kernel (0: not used) */
+    int reserved[2];
 } hisq_tune_result;
 
 /*
@@ -463,6 +473,13 @@ typedef struct hisq_tune_result {
  * volume, nrhs right-hand sides and precision prec (HISQ_FP64 or HISQ_FP32),
  * `reps` launches each (0 = 20) on scratch vectors, with HIP events on
  * `stream`; remember the fastest for (volume, nrhs, prec) for the rest of the
+ *   "dslash_march"           -1: automatic (off); 0: off; n > 0: for two or
+ *                            more RHS when X Y Z / 2 is a multiple of 256, the
+ *                            kernel that marches along time with n time
+ *                            segments: each workgroup takes 256 sites of a
+ *                            slice and keeps their time neighbours in
+ *                            registers (FP64, FP32 and 16-bit storage; never
+ *                            BF16); bitwise the same results
  * process (every later stencil, M^H M, CG and eigensolver launch of that size
  * uses it, unless a "dslash_*" knob is set).  Results do not change, only
  * speed.  Leaves the "dslash_*" knobs at automatic.  Not safe to run

@@ -3,7 +3,9 @@
     python -m paper_2502_00152_amd.build [-v]
 
 Every .hip (device + host) and .cpp (host-only) file under csrc/ is compiled to an object in _build/ and linked into
-paper_2502_00152_amd/libhisq.so.  Always rebuilds.
+paper_2502_00152_amd/libhisq.so.  Always rebuilds, unless called with --incremental (or
+incremental=True), which recompiles only sources newer than their object or than any header in
+csrc/ and include/.
 """
 from __future__ import annotations
 
@@ -13,6 +15,7 @@ import os
 import shutil
 import subprocess
 import sys
+import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -40,8 +43,32 @@ COMMON = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _deps(src: str) -> list:
+    """src and the project headers it includes, followed recursively."""
+    seen, todo = [], [src]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.append(f)
+        for line in open(f):
+            line = line.strip()
+            if line.startswith("#include") and '"' in line:
+                name = line.split('"')[1]
+                for d in (os.path.dirname(f), CSRC, INCLUDE):
+                    cand = os.path.join(d, name)
+                    if os.path.exists(cand):
+                        todo.append(cand)
+                        break
+    return seen
+
+
+def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        if max(os.path.getmtime(d) for d in _deps(src)) <= os.path.getmtime(obj):
+            return obj
+    t0 = time.time()
     if src.endswith(".cpp"):  # host-only C++
         cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC,
                "-c", src, "-o", obj]
@@ -56,14 +83,16 @@ def _compile(src: str, verbose: bool) -> str:
         lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l]
         if lines:
             print("\n".join(lines), flush=True)
+    if verbose:
+        print(f"{os.path.basename(src)}: {time.time() - t0:.0f} s", flush=True)
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
@@ -74,4 +103,4 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)

@@ -31,6 +31,7 @@ struct KnobGuard {
         (void)dslash_set_tuning("dslash_lanes_per_site", 0);
         (void)dslash_set_tuning("dslash_group_order", -1);
         (void)dslash_set_tuning("dslash_xcd_remap", -1);
+        (void)dslash_set_tuning("dslash_march", -1);
     }
 };
 
@@ -78,13 +79,16 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
     };
 
     // the shape in use before tuning (built-in default or an earlier choice)
-    DslashShape def = dslash_pick_shape(nrhs, vh, rb);
+    DslashShape def = dslash_pick_shape(nrhs, vh, rb, false, g->geom);
     double us_def = 0.0;
     HISQ_TRY(dslash_set_tuning("dslash_rhs_per_thread", def.nr));
     HISQ_TRY(dslash_set_tuning("dslash_lanes_per_site", def.lps));
     HISQ_TRY(dslash_set_tuning("dslash_group_order", def.group_outer));
     HISQ_TRY(dslash_set_tuning("dslash_xcd_remap", def.xcd_remap));
+    HISQ_TRY(dslash_set_tuning("dslash_march", def.march));
     HISQ_TRY(time_current(&us_def));
+    const int kind = rb == 8 ? 0 : 1;
+    const bool march_geom = (int64_t)g->geom.Xh * g->geom.Y * g->geom.Z % 256 == 0;
 
     const int nr1[] = {1, 2, 3, 4, 6, 12}, nrn[] = {1, 3, 6};
     DslashShape best = def;
@@ -105,6 +109,7 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
                     HISQ_TRY(dslash_set_tuning("dslash_lanes_per_site", lps));
                     HISQ_TRY(dslash_set_tuning("dslash_group_order", order));
                     HISQ_TRY(dslash_set_tuning("dslash_xcd_remap", xcd));
+                    HISQ_TRY(dslash_set_tuning("dslash_march", 0));
                     double us = 0.0;
                     HISQ_TRY(time_current(&us));
                     ++timed;
@@ -112,6 +117,29 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
                         us_best = us;
                         best = DslashShape{nr, lps, xcd, order};
                     }
+                }
+            }
+            // the time-marching kernel with this shape (time segments chosen
+            // automatically, XCD-contiguous chunks)
+            if (march_geom && nrhs >= 2 && dslash_impl::march_shape_supported(kind, nr, lps)) {
+                HISQ_TRY(dslash_set_tuning("dslash_rhs_per_thread", nr));
+                HISQ_TRY(dslash_set_tuning("dslash_lanes_per_site", lps));
+                HISQ_TRY(dslash_set_tuning("dslash_group_order", 0));
+                HISQ_TRY(dslash_set_tuning("dslash_xcd_remap", 1));
+                HISQ_TRY(dslash_set_tuning("dslash_march", 0));
+                const DslashShape auto_m = [&] {
+                    (void)dslash_set_tuning("dslash_march", -1);
+                    return dslash_pick_shape(nrhs, vh, rb, false, g->geom);
+                }();
+                const int nseg = auto_m.march > 0 ? auto_m.march : 4;
+                HISQ_TRY(dslash_set_tuning("dslash_march", nseg));
+                double us = 0.0;
+                HISQ_TRY(time_current(&us));
+                ++timed;
+                if (us < us_best) {
+                    us_best = us;
+                    best = DslashShape{nr, lps, 1, 0};
+                    best.march = nseg;
                 }
             }
         }
@@ -126,6 +154,7 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
         result_host->us_best = us_best;
         result_host->us_default = us_def;
         result_host->shapes_timed = timed;
+        result_host->march = best.march;
     }
     return HISQ_OK;
 }

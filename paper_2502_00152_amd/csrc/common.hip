@@ -23,6 +23,13 @@ void Workspace::release() {
     bufs_.clear();
 }
 
+void Workspace::release_one(const char *name) {
+    auto it = bufs_.find(name);
+    if (it == bufs_.end()) return;
+    if (it->second.ptr) (void)hipFree(it->second.ptr);
+    bufs_.erase(it);
+}
+
 hisq_status Workspace::get(const char *name, size_t bytes, void **ptr) {
     Buf &b = bufs_[name];
     if (b.bytes < bytes) {

@@ -71,7 +71,7 @@ hisq_status launch_dslash_bf16(hisq_gauge_s *g, int out_parity, const bf16c *in,
     HISQ_TRY(ensure_links_bf16(g, s));
     const bf16c *fat[2] = {g->fat16[0], g->fat16[1]};
     const bf16c *lng[2] = {g->lng16[0], g->lng16[1]};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2);
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, false, g->geom);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux2 ? "dslash_bf16_aux2" : aux ? "dslash_bf16_aux" : "dslash_bf16", s);
     return dslash_impl::launch_dslash_t<float, bf16c, bf16c>(g->geom, fat, lng, out_parity, in, out,
@@ -87,7 +87,7 @@ hisq_status launch_dslash_f32_bl(hisq_gauge_s *g, int out_parity, const float2 *
     using V = vec2<float>;
     const bf16c *fat[2] = {g->fat16[0], g->fat16[1]};
     const bf16c *lng[2] = {g->lng16[0], g->lng16[1]};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 4);
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 4, false, g->geom);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux ? "dslash_f32bl_aux" : "dslash_f32bl", s);
     return dslash_impl::launch_dslash_t<float, V, bf16c>(

@@ -50,7 +50,7 @@ hisq_status launch_dslash_f32(hisq_gauge_s *g, int out_parity, const float2 *in,
                        reinterpret_cast<const V *>(g->fat32[1])};
     const V *lng[2] = {reinterpret_cast<const V *>(g->lng32[0]),
                        reinterpret_cast<const V *>(g->lng32[1])};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, sizeof(float));
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, sizeof(float), false, g->geom);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux2 ? "dslash_f32_aux2" : aux ? "dslash_f32_aux" : "dslash_f32", s);
     return dslash_impl::launch_dslash_t<float>(

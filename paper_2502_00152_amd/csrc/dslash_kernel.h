@@ -147,18 +147,22 @@ constexpr bool int_hops() {
 }
 
 // Launch shape of the half stencil: NR RHS per lane, LPS lanes per site, the
-// XCD-contiguous block order and the order of site blocks and RHS groups.
+// XCD-contiguous block order and the order of site blocks and RHS groups;
+// march > 0 selects the kernel that marches along time (dslash_march.h) with
+// that many time segments.
 struct DslashShape {
     int nr;
     int lps;
     int xcd_remap;
     int group_outer;
+    int march = 0;
 };
 
 // Launch shape of the half stencil (tuned or default) for nrhs RHS at half
 // volume vh, real_bytes per stored vector real (8, 4 or 2); q16_links: FP32
 // vectors with 16-bit links.
-DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links = false);
+DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links,
+                              const Geom &geom);
 
 namespace dslash_impl {
 
@@ -813,6 +817,33 @@ inline bool shape_fits(int nr, int lps, int vh, size_t real_bytes) {
     return span < (1ull << 32);
 }
 
+// Storage kinds of the marching kernel: 0 FP64 vectors and links, 1 FP32
+// vectors (FP32 or 16-bit links), 2 16-bit vectors and links; -1 none (BF16).
+template <typename R, typename VS, typename LS>
+constexpr int march_kind() {
+    if constexpr (int_hops<VS, LS>()) return 2;
+    else if constexpr (std::is_same<VS, vec2<double>>::value && std::is_same<LS, vec2<double>>::value)
+        return 0;
+    else if constexpr (std::is_same<VS, vec2<float>>::value &&
+                       (std::is_same<LS, q16c>::value || std::is_same<LS, vec2<float>>::value))
+        return 1;
+    else return -1;
+}
+
+// (NR, LPS) shapes the marching kernel is built for, per storage kind.
+__host__ __device__ constexpr bool march_shape_supported(int kind, int nr, int lps) {
+    return kind == 2   ? (lps == 2 && (nr == 6 || nr == 3)) || (lps == 4 && nr == 3)
+           : kind == 1 ? (lps == 2 && (nr == 6 || nr == 3)) || (lps == 4 && nr == 3)
+           : kind == 0 ? lps == 2 && (nr == 1 || nr == 2 || nr == 3)
+                       : false;
+}
+
+// The marching kernel (dslash_march.h), instantiated in dslash_march_*.hip
+// for the storage kinds and shapes march_shape_supported() lists.
+template <typename R, typename VS, typename LS>
+hisq_status launch_march(const DslashArgs<R, VS, LS> &a, const DslashShape &sh, bool aux,
+                         bool aux2, bool dot, hipStream_t s);
+
 // Fill the argument block and launch with the given shape.
 template <typename R, typename VS = vec2<R>, typename LS = vec2<R>>
 hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *const lng[2],
@@ -857,6 +888,8 @@ hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *
     const bool dot = partials != nullptr;
     const int nblocks = a.nsb * a.ngroups;
     const bool x = aux != nullptr, x2 = aux2 != nullptr;
+    if constexpr (march_kind<R, VS, LS>() >= 0)
+        if (sh.march > 0) return launch_march<R, VS, LS>(a, sh, x, x2, dot, s);
 #define HISQ_SHAPE(NR_, LPS_)                                                            \
     if (sh.nr == NR_ && sh.lps == LPS_)                                                  \
     return launch_shape<R, VS, LS, NR_, LPS_>(a, nblocks, x, x2, dot, s)

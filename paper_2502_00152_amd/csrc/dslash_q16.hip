@@ -194,7 +194,7 @@ hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 
     using V = vec2<float>;
     const q16c *fat[2] = {g->fatq[0], g->fatq[1]};
     const q16c *lng[2] = {g->lngq[0], g->lngq[1]};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 4, true);
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 4, true, g->geom);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux ? "dslash_q16_aux" : "dslash_q16", s);
     return dslash_impl::launch_dslash_t<float, V, q16c>(
@@ -226,7 +226,7 @@ hisq_status launch_dslash_h16(hisq_gauge_s *g, int out_parity, const void *in, v
     HISQ_TRY(ensure_links_q16n(g, s));
     const q16c *fat[2] = {g->fatn[0], g->fatn[1]};
     const q16c *lng[2] = {g->lngn[0], g->lngn[1]};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, true);
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, true, g->geom);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux ? "dslash_h16_aux" : "dslash_h16", s);
     return dslash_impl::launch_dslash_t<float, h16c, q16c>(

@@ -268,9 +268,9 @@ __global__ __launch_bounds__(kBS) void k_gemv_reduce(const double *__restrict__ 
 
 //   gemv_nn: X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i], one thread per site
 template <typename TV, int NB>
-__global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int k,
+__global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int64_t ldv, int k,
                                                  const dvec2 *__restrict__ C, int64_t N,
-                                                 double beta, dvec2 *__restrict__ X) {
+                                                 double beta, dvec2 *__restrict__ X, int64_t ldx) {
     extern __shared__ dvec2 cs[];  // [NB][k]
     for (int e = threadIdx.x; e < NB * k; e += kBS) cs[e] = C[e];
     __syncthreads();
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int k
         for (; i + 4 <= k; i += 4) {
             dvec2 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = load2(V + 2 * ((int64_t)(i + u) * N + s));
+            for (int u = 0; u < 4; ++u) v[u] = load2(V + 2 * ((int64_t)(i + u) * ldv + s));
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int k
                 }
         }
         for (; i < k; ++i) {
-            const dvec2 v = load2(V + 2 * ((int64_t)i * N + s));
+            const dvec2 v = load2(V + 2 * ((int64_t)i * ldv + s));
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const dvec2 c = cs[j * k + i];
@@ -305,11 +305,11 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int k
         for (int j = 0; j < NB; ++j) {
             dvec2 o = dvec2{acc[j][0], acc[j][1]};
             if (beta != 0.0) {
-                const dvec2 x = X[(int64_t)j * N + s];
+                const dvec2 x = X[(int64_t)j * ldx + s];
                 o.x = fma(beta, x.x, o.x);
                 o.y = fma(beta, x.y, o.y);
             }
-            X[(int64_t)j * N + s] = o;
+            X[(int64_t)j * ldx + s] = o;
         }
     }
 }
@@ -324,13 +324,13 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int k
 // Grid: x = column tiles (grid-stride), y = groups of 16*MT right-hand sides.
 template <typename TV>
 struct NnArgs {
-    const TV *V;          // k columns of 2N reals
+    const TV *V;          // k columns, column i at V + i * ldv (reals)
     const dvec2 *C;       // [n][k] complex coefficients
-    double *X;            // n columns of 2N reals
-    int64_t twoN;
+    double *X;            // n columns, column j at X + j * ldx (reals)
+    int64_t ldv, ldx;     // reals between consecutive columns
     int k, n;
     double beta;
-    int64_t tiles;        // twoN / 16
+    int64_t tiles;        // (2 * rows) / 16
 };
 
 template <typename TV, int MT>
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs<TV> a) {
             const int i = i0 + (q >> 1);
             double bval = 0.0;
             if (i < a.k) {
-                const dvec2 v = load2(a.V + (int64_t)i * a.twoN + 2 * site);
+                const dvec2 v = load2(a.V + (int64_t)i * a.ldv + 2 * site);
                 // V_big[2s+c][2i+d]
                 bval = c == 0 ? (dsel == 0 ? v.x : -v.y) : (dsel == 0 ? v.y : v.x);
             }
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs<TV> a) {
             for (int r = 0; r < 4; ++r) {
                 const int j = jbase + 16 * m + 4 * r + q;
                 if (j < a.n) {
-                    double *dst = a.X + (int64_t)j * a.twoN + tile * 16 + lr;
+                    double *dst = a.X + (int64_t)j * a.ldx + tile * 16 + lr;
                     double v = acc[m][r];
                     if (a.beta != 0.0) v = fma(a.beta, *dst, v);
                     *dst = v;
@@ -458,34 +458,36 @@ hisq_status gemm_tn_t(hisq_gauge_s *g, const TV *V, int k, const double2 *B, int
     return HISQ_OK;
 }
 
-// X = beta X + V C   (C complex [n][k] on the device)
+// X = beta X + V C   (C complex [n][k] on the device) over `rows` rows of
+// columns ldv (V) and ldx (X) complex numbers apart
 template <typename TV>
-hisq_status gemm_nn_t(const TV *V, int k, const double2 *C, int n, int64_t N, double beta,
-                      double2 *X, hipStream_t s) {
+hisq_status gemm_nn_t(const TV *V, int64_t ldv, int k, const double2 *C, int n, int64_t rows,
+                      double beta, double2 *X, int64_t ldx, hipStream_t s) {
     NnArgs<TV> a{};
     a.V = V;
     a.C = reinterpret_cast<const dvec2 *>(C);
     a.X = reinterpret_cast<double *>(X);
-    a.twoN = 2 * N;
+    a.ldv = 2 * ldv;
+    a.ldx = 2 * ldx;
     a.k = k;
     a.n = n;
     a.beta = beta;
-    if (a.twoN % 16) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: 2N must be a multiple of 16");
-    a.tiles = a.twoN / 16;
+    if ((2 * rows) % 16) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: rows must be a multiple of 8");
+    a.tiles = 2 * rows / 16;
     ProfileScope prof("gemm", s);
     if (n <= 2) {
-        int64_t nb = (N + 4 * kBS - 1) / (4 * kBS);
+        int64_t nb = (rows + 4 * kBS - 1) / (4 * kBS);
         nb = std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
         const size_t lds = sizeof(dvec2) * n * k;
         if (lds > 64 * 1024) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: too many columns");
         const dvec2 *Cv = reinterpret_cast<const dvec2 *>(C);
         dvec2 *Xv = reinterpret_cast<dvec2 *>(X);
         if (n == 1)
-            hipLaunchKernelGGL((k_gemv_nn<TV, 1>), dim3((unsigned)nb), dim3(kBS), lds, s, V, k, Cv,
-                               N, beta, Xv);
+            hipLaunchKernelGGL((k_gemv_nn<TV, 1>), dim3((unsigned)nb), dim3(kBS), lds, s, V, ldv, k,
+                               Cv, rows, beta, Xv, ldx);
         else
-            hipLaunchKernelGGL((k_gemv_nn<TV, 2>), dim3((unsigned)nb), dim3(kBS), lds, s, V, k, Cv,
-                               N, beta, Xv);
+            hipLaunchKernelGGL((k_gemv_nn<TV, 2>), dim3((unsigned)nb), dim3(kBS), lds, s, V, ldv, k,
+                               Cv, rows, beta, Xv, ldx);
         HISQ_HIP(hipGetLastError());
         return HISQ_OK;
     }
@@ -515,11 +517,16 @@ hisq_status gemm_tn(hisq_gauge_s *g, const float2 *V, int k, const double2 *B, i
 }
 hisq_status gemm_nn(const double2 *V, int k, const double2 *C, int n, int64_t N, double beta,
                     double2 *X, hipStream_t s) {
-    return gemm_nn_t<double>(reinterpret_cast<const double *>(V), k, C, n, N, beta, X, s);
+    return gemm_nn_t<double>(reinterpret_cast<const double *>(V), N, k, C, n, N, beta, X, N, s);
 }
 hisq_status gemm_nn(const float2 *V, int k, const double2 *C, int n, int64_t N, double beta,
                     double2 *X, hipStream_t s) {
-    return gemm_nn_t<float>(reinterpret_cast<const float *>(V), k, C, n, N, beta, X, s);
+    return gemm_nn_t<float>(reinterpret_cast<const float *>(V), N, k, C, n, N, beta, X, N, s);
+}
+hisq_status gemm_nn_ld(const double2 *V, int64_t ldv, int k, const double2 *C, int n,
+                       int64_t rows, double beta, double2 *X, int64_t ldx, hipStream_t s) {
+    return gemm_nn_t<double>(reinterpret_cast<const double *>(V), ldv, k, C, n, rows, beta, X, ldx,
+                             s);
 }
 
 }  // namespace hisq

@@ -51,6 +51,8 @@ public:
     ~Workspace();
     hisq_status get(const char *name, size_t bytes, void **ptr);
     void release();
+    // free one named buffer (after its last use has completed)
+    void release_one(const char *name);
 
 private:
     struct Buf {
@@ -238,6 +240,10 @@ hisq_status apply_mdagm_f32(hisq_gauge_s *g, double two_m, const float2 *in, flo
                             double *partials, hipStream_t s);
 
 // BF16 storage (uint32_t = two bfloat16: real part low, imaginary part high).
+// The same over `rows` rows (a multiple of 8) of columns ldv and ldx complex
+// numbers apart (a block of rows of larger matrices).
+hisq_status gemm_nn_ld(const double2 *V, int64_t ldv, int k, const double2 *C, int n,
+                       int64_t rows, double beta, double2 *X, int64_t ldx, hipStream_t s);
 hisq_status ensure_links_bf16(hisq_gauge_s *g, hipStream_t s);
 // FP64 -> BF16, rounded to nearest even (n complex numbers)
 hisq_status convert_double_to_bf16(const double2 *src, uint32_t *dst, int64_t n, hipStream_t s);

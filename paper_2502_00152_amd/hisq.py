@@ -37,7 +37,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED
 HISQ_FP64, HISQ_FP32, HISQ_BF16, HISQ_Q16, HISQ_HALF = 0, 1, 2, 3, 4
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
-ABI_VERSION = 8
+ABI_VERSION = 9
 HISQ_NN_CHANNELS = 8
 HISQ_NN_PARAMS = 752
 HISQ_NN_NORMALIZE, HISQ_NN_BF16 = 1, 2
@@ -98,7 +98,8 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("rhs_per_thread", ctypes.c_int), ("lanes_per_site", ctypes.c_int),
                 ("group_order", ctypes.c_int), ("xcd_remap", ctypes.c_int),
                 ("us_best", ctypes.c_double), ("us_default", ctypes.c_double),
-                ("shapes_timed", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("shapes_timed", ctypes.c_int), ("march", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 EIG_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -109,7 +110,7 @@ class EigParams(ctypes.Structure):
     _fields_ = [("n_kr", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("cheb_a", ctypes.c_double), ("cheb_b", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
-                ("reserved0", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("evec_prec", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("progress", EIG_PROGRESS), ("progress_user", ctypes.c_void_p),
                 ("reserved", ctypes.c_int * 8)]
 
@@ -535,12 +536,13 @@ def hisq_eigensolve(g, two_m, n_ev, evecs, n_kr=0, cheb_degree=0, cheb_a=0.0, ch
                     tol=1e-10, max_restarts=0, seed=0, stream=None, raise_on_fail=True,
                     progress=None):
     """progress: optional callable(restart, step, matvecs, seconds), called after
-    every Lanczos step (restart -1 = pilot)."""
+    every Lanczos step (restart -1 = pilot).  evecs complex128, or complex64 for
+    single-precision eigenvectors (the solve is FP64 either way)."""
     if _nrhs(evecs, g.vh, "evecs") != n_ev:
         raise ValueError("evecs must hold n_ev vectors")
     p = EigParams(n_kr=int(n_kr), cheb_degree=int(cheb_degree), cheb_a=float(cheb_a),
                   cheb_b=float(cheb_b), tol=float(tol), max_restarts=int(max_restarts),
-                  seed=int(seed))
+                  seed=int(seed), evec_prec=_prec_of(evecs, "evecs"))
     cb = None
     if progress is not None:
         cb = EIG_PROGRESS(lambda _u, r, j, mv, sec: progress(r, j, mv, sec))
@@ -548,7 +550,7 @@ def hisq_eigensolve(g, two_m, n_ev, evecs, n_kr=0, cheb_degree=0, cheb_a=0.0, ch
     evals = np.zeros(n_ev, dtype=np.float64)
     stats = EigStats()
     st = lib().hisq_eigensolve(_h(g), float(two_m), int(n_ev), ctypes.byref(p),
-                               _ptr(evecs, "evecs"),
+                               _ptr(evecs, "evecs", ("complex128", "complex64")),
                                evals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                ctypes.byref(stats), _stream(stream))
     del cb  # kept alive across the call above

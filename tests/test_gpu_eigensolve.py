@@ -105,3 +105,30 @@ def test_eigensolve_rejects_bad_sizes():
     st, _, _ = hisq.hisq_eigensolve(g, 0.1, 8, ev, n_kr=8, raise_on_fail=False)
     assert st == hisq.HISQ_ERR_INVALID_ARG
     g.close()
+
+
+def test_fp32_output_is_the_rounded_fp64_result_and_memory_is_returned():
+    """evec_prec = HISQ_FP32 gives the FP64 eigenvectors rounded to nearest
+    (the solve is the same), the eigenvalues are identical, and the basis and
+    scratch the solve allocates are freed before it returns (the device's free
+    memory is back to its value before the first call, within 64 MiB)."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = Problem((8, 8, 8, 8), 0.3, 4101, 4102)
+    g = pr.gauge()
+    try:
+        n_ev = 24
+        e64 = torch.empty((n_ev, 3, g.vh), dtype=torch.complex128, device="cuda")
+        e32 = torch.empty((n_ev, 3, g.vh), dtype=torch.complex64, device="cuda")
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        _, lam64, _ = hisq.hisq_eigensolve(g, 0.1, n_ev, e64, tol=TOL, seed=5)
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+        _, lam32, _ = hisq.hisq_eigensolve(g, 0.1, n_ev, e32, tol=TOL, seed=5)
+        torch.cuda.synchronize()
+        assert np.array_equal(lam64, lam32)
+        assert torch.equal(e32, e64.to(torch.complex64))
+        assert abs(free1 - free0) <= 64 << 20, (free0, free1)
+    finally:
+        g.close()

@@ -260,3 +260,58 @@ def test_autotuner_picks_a_valid_shape_and_keeps_results(prec):
     finally:
         hisq.hisq_set_tuning("dslash_autotune_clear", 1)
         g.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 8, 8, 6)])
+def test_time_marching_kernel_is_bitwise_the_standard_kernel(dims):
+    """The stencil that marches along time (hisq_set_tuning "dslash_march") on
+    lattices with whole 256-site chunks per time slice: the half stencil in
+    FP64, FP32 and 16-bit storage, M^H M, and a CG solve (whose <p, A p>
+    partials it forms) are bitwise those of the standard kernel."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    pr = Problem(dims, 0.4, 5101, 5102)
+    g = pr.gauge()
+    try:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(3)
+        x64 = torch.randn((10, 3, g.vh), dtype=torch.complex128, device="cuda", generator=gen)
+        x32 = x64.to(torch.complex64)
+        cases = [(x64, hisq.HISQ_FP64, (1, 2)), (x64, hisq.HISQ_FP64, (2, 2)),
+                 (x64, hisq.HISQ_FP64, (3, 2)), (x32, hisq.HISQ_FP32, (3, 2)),
+                 (x32, hisq.HISQ_Q16, (6, 2)), (x32, hisq.HISQ_Q16, (3, 4)),
+                 (x32, hisq.HISQ_HALF, (3, 2)), (x32, hisq.HISQ_HALF, (6, 2))]
+
+        def knobs(nr, lps, march):
+            hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
+            hisq.hisq_set_tuning("dslash_lanes_per_site", lps)
+            hisq.hisq_set_tuning("dslash_march", march)
+
+        for x, prec, (nr, lps) in cases:
+            outs = []
+            for march in (0, 1, 3):
+                knobs(nr, lps, march) if march else knobs(0, 0, 0)
+                d = torch.empty_like(x)
+                m = torch.empty_like(x)
+                hisq.hisq_dslash_eo(g, 1, x, d, prec=prec)
+                hisq.hisq_mdagm(g, 0.05, x, m, prec=prec)
+                torch.cuda.synchronize()
+                outs.append((d, m))
+            for d, m in outs[1:]:
+                assert torch.equal(d, outs[0][0]), (prec, nr, lps)
+                assert torch.equal(m, outs[0][1]), (prec, nr, lps)
+        # CG: iterates and iteration counts
+        b = x64[:6].clone()
+        res = []
+        for march in (0, 2):
+            knobs(1, 2, march) if march else knobs(0, 0, 0)
+            xs = torch.zeros_like(b)
+            r = hisq.hisq_cg_solve(g, 0.05, b, xs, tol=1e-10)
+            res.append((r.iterations, xs))
+        assert res[0][0] == res[1][0]
+        assert torch.equal(res[0][1], res[1][1])
+    finally:
+        hisq.hisq_set_tuning("dslash_rhs_per_thread", 0)
+        hisq.hisq_set_tuning("dslash_lanes_per_site", 0)
+        hisq.hisq_set_tuning("dslash_march", -1)
+        g.close()
