@@ -185,6 +185,33 @@ hisq_status hisq_dslash_eo(hisq_gauge g, int out_parity, const void *in_dev,
 hisq_status hisq_mdagm(hisq_gauge g, double two_m, const void *in_e_dev, void *out_e_dev,
                        int nrhs, hisq_prec prec, void *stream);
 
+/* Bytes of the device array that hisq_mdagm_noalloc uses as its scratch. */
+#define HISQ_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * hisq_mdagm for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid allocation.  Same operator, kernels and launch shapes as hisq_mdagm
+ * (the same results bit for bit), but its odd-parity temporary lives in one
+ * file-scope device array of HISQ_NOALLOC_SCRATCH_BYTES per GPU (held until
+ * the process ends) instead of the handle's scratch, and the call makes no
+ * allocation of any kind (no hipMalloc, hipFree, event or library buffer;
+ * kernel timing by hisq_profile_enable is skipped for it).  The caller owns
+ * in_e and out_e as for hisq_mdagm; the device current on the calling thread
+ * must be the handle's.
+ * prec: HISQ_FP64, or HISQ_FP32 once the handle's FP32 links exist (a first
+ * hisq_mdagm or hisq_dslash_eo call with HISQ_FP32 makes them; otherwise
+ * HISQ_ERR_INVALID_ARG).  The temporary takes 3 * Vh * nrhs complex numbers
+ * of prec (48 or 24 bytes per site and RHS); a call that needs more than
+ * HISQ_NOALLOC_SCRATCH_BYTES returns HISQ_ERR_INVALID_ARG and launches
+ * nothing.  Every call on one GPU shares that GPU's array: calls that overlap
+ * in time on one GPU (two streams, two threads) race and give wrong results;
+ * the array keeps the last call's contents, which no later call reads before
+ * writing it.
+ */
+hisq_status hisq_mdagm_noalloc(hisq_gauge g, double two_m, const void *in_e_dev,
+                               void *out_e_dev, int nrhs, hisq_prec prec, void *stream);
+
 /*
  * Even-site source of the preconditioned system: y_e = 2m eta_e - D_eo eta_o,
  * the even half of M^H eta (section 2, the Schur step before the CG).
@@ -445,6 +472,13 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            next to each other; 1: all sites of one group first
  *   "dslash_xcd_remap"       -1: automatic; 1: give each XCD a contiguous range
  *                            of sites; 0: off
+ *   "dslash_march"           -1: automatic (off); 0: off; n > 0: for two or
+ *                            more RHS when X Y Z / 2 is a multiple of 256, the
+ *                            kernel that marches along time with n time
+ *                            segments: each workgroup takes 256 sites of a
+ *                            slice and keeps their time neighbours in
+ *                            registers (FP64, FP32 and 16-bit storage; never
+ *                            BF16); bitwise the same results
  *   "dslash_autotune_clear"  any value: forget the autotuner's choices
  *   "cg_graphs"              -1 automatic (off), 0 off, 1: replay the CG's
  *                            chunks of iterations from a captured HIP graph
@@ -473,13 +507,6 @@ typedef struct hisq_tune_result {
  * volume, nrhs right-hand sides and precision prec (HISQ_FP64 or HISQ_FP32),
  * `reps` launches each (0 = 20) on scratch vectors, with HIP events on
  * `stream`; remember the fastest for (volume, nrhs, prec) for the rest of the
- *   "dslash_march"           -1: automatic (off); 0: off; n > 0: for two or
- *                            more RHS when X Y Z / 2 is a multiple of 256, the
- *                            kernel that marches along time with n time
- *                            segments: each workgroup takes 256 sites of a
- *                            slice and keeps their time neighbours in
- *                            registers (FP64, FP32 and 16-bit storage; never
- *                            BF16); bitwise the same results
  * process (every later stencil, M^H M, CG and eigensolver launch of that size
  * uses it, unless a "dslash_*" knob is set).  Results do not change, only
  * speed.  Leaves the "dslash_*" knobs at automatic.  Not safe to run

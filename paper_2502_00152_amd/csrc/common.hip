@@ -113,7 +113,12 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool profile_enabled() { return g_prof_on; }
+thread_local bool t_prof_suppressed = false;
+
+bool profile_enabled() { return g_prof_on && !t_prof_suppressed; }
+
+ProfileSuppress::ProfileSuppress() : prev_(t_prof_suppressed) { t_prof_suppressed = true; }
+ProfileSuppress::~ProfileSuppress() { t_prof_suppressed = prev_; }
 
 // "cg_graphs": -1 automatic, 0 off, 1 on (never while kernel timing is on:
 // its events would be captured into the graph).
@@ -130,7 +135,7 @@ bool cg_use_graphs(const hisq_gauge_s *g, int nrhs) {
 }
 
 ProfileScope::ProfileScope(const char *cls, hipStream_t s) : s_(s), cls_(cls) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || t_prof_suppressed) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     auto &rec = g_prof[cls];
     if (rec.seen++ % g_prof_period != 0) return;

@@ -105,6 +105,17 @@ struct hisq_gauge_s {
 namespace hisq {
 
 // ------------------------------------------------------------ profiling
+// While an object of this class lives, ProfileScope records nothing on the
+// calling thread (the allocation-free entry points create no events).
+class ProfileSuppress {
+public:
+    ProfileSuppress();
+    ~ProfileSuppress();
+
+private:
+    bool prev_;
+};
+
 // Event-timed launches, per kernel class.
 class ProfileScope {
 public:
@@ -229,6 +240,10 @@ hisq_status gemm_tn(hisq_gauge_s *g, const float2 *V, int k, const double2 *B, i
                     hipStream_t s);
 hisq_status gemm_nn(const float2 *V, int k, const double2 *C, int n, int64_t N, double beta,
                     double2 *X, hipStream_t s);
+// The same over `rows` rows (a multiple of 8) of columns ldv and ldx complex
+// numbers apart (a block of rows of larger matrices).
+hisq_status gemm_nn_ld(const double2 *V, int64_t ldv, int k, const double2 *C, int n,
+                       int64_t rows, double beta, double2 *X, int64_t ldx, hipStream_t s);
 
 // FP32 (sloppy) half stencil; partials (optional) as for FIN_CG_ALPHA.
 hisq_status ensure_links_f32(hisq_gauge_s *g, hipStream_t s);
@@ -240,10 +255,6 @@ hisq_status apply_mdagm_f32(hisq_gauge_s *g, double two_m, const float2 *in, flo
                             double *partials, hipStream_t s);
 
 // BF16 storage (uint32_t = two bfloat16: real part low, imaginary part high).
-// The same over `rows` rows (a multiple of 8) of columns ldv and ldx complex
-// numbers apart (a block of rows of larger matrices).
-hisq_status gemm_nn_ld(const double2 *V, int64_t ldv, int k, const double2 *C, int n,
-                       int64_t rows, double beta, double2 *X, int64_t ldx, hipStream_t s);
 hisq_status ensure_links_bf16(hisq_gauge_s *g, hipStream_t s);
 // FP64 -> BF16, rounded to nearest even (n complex numbers)
 hisq_status convert_double_to_bf16(const double2 *src, uint32_t *dst, int64_t n, hipStream_t s);

@@ -38,6 +38,7 @@ HISQ_FP64, HISQ_FP32, HISQ_BF16, HISQ_Q16, HISQ_HALF = 0, 1, 2, 3, 4
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
 ABI_VERSION = 9
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HISQ_NOALLOC_SCRATCH_BYTES
 HISQ_NN_CHANNELS = 8
 HISQ_NN_PARAMS = 752
 HISQ_NN_NORMALIZE, HISQ_NN_BF16 = 1, 2
@@ -51,7 +52,7 @@ EXPORTS = (
     "hisq_profile_read", "hisq_convert_vectors", "hisq_propagator_solve",
     "hisq_autotune_dslash", "hisq_cg_solve_multi", "hisq_nn_create", "hisq_nn_destroy",
     "hisq_nn_set_params", "hisq_nn_get_params", "hisq_nn_apply", "hisq_nn_loss_grad",
-    "hisq_nn_adam_step", "hisq_nn_train", "hisq_nn_guess",
+    "hisq_nn_adam_step", "hisq_nn_train", "hisq_nn_guess", "hisq_mdagm_noalloc",
 )
 
 
@@ -146,6 +147,7 @@ def lib():
         "hisq_spinor_merge": ([P, P, P, P, I, P], I),
         "hisq_dslash_eo": ([P, I, P, P, I, I, P], I),
         "hisq_mdagm": ([P, D, P, P, I, I, P], I),
+        "hisq_mdagm_noalloc": ([P, D, P, P, I, I, P], I),
         "hisq_prepare_source": ([P, D, P, P, P, I, P], I),
         "hisq_reconstruct_odd": ([P, D, P, P, P, I, P], I),
         "hisq_cg_solve": ([P, D, P, P, I, ctypes.POINTER(CgParams), ctypes.POINTER(CgStats),
@@ -340,6 +342,15 @@ def hisq_mdagm(g, two_m, inp, out, prec=None, stream=None):
     _check(lib().hisq_mdagm(_h(g), float(two_m), _ptr(inp, "in", _VEC_DTYPES),
                             _ptr(out, "out", _VEC_DTYPES), nrhs, prec, _stream(stream)),
            "hisq_mdagm")
+
+
+def hisq_mdagm_noalloc(g, two_m, inp, out, prec=None, stream=None):
+    """hisq_mdagm with its temporary in the library's fixed device array (no
+    allocation); FP64 or FP32 vectors, at most NOALLOC_SCRATCH_BYTES of temporary."""
+    nrhs, prec = _vec_pair(g, inp, out, prec)
+    _check(lib().hisq_mdagm_noalloc(_h(g), float(two_m), _ptr(inp, "in", _VEC_DTYPES),
+                                    _ptr(out, "out", _VEC_DTYPES), nrhs, prec, _stream(stream)),
+           "hisq_mdagm_noalloc")
 
 
 def hisq_prepare_source(g, two_m, eta_e, eta_o, y_e, stream=None):
