@@ -461,7 +461,8 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
 
 /*
  * Launch-shape knobs of the kernels, process-wide (for the autotuner and for
- * measurements); results do not depend on them, only speed.  Keys:
+ * measurements); results do not depend on them, only speed, except where a
+ * key says otherwise.  Keys:
  *   "dslash_rhs_per_thread"  right-hand sides one lane carries: 0 = automatic,
  *                            or one of 1, 2, 3, 4, 6, 12
  *   "dslash_lanes_per_site"  lanes that share one site's link loads, each with
@@ -471,7 +472,8 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *   "dslash_group_order"     -1: automatic; 0: RHS groups of one site block run
  *                            next to each other; 1: all sites of one group first
  *   "dslash_xcd_remap"       -1: automatic; 1: give each XCD a contiguous range
- *                            of sites; 0: off
+ *                            of sites; 0: off; n >= 2: deal chunks of n site
+ *                            blocks (x RHS groups) round-robin to the XCDs
  *   "dslash_march"           -1: automatic (off); 0: off; n > 0: for two or
  *                            more RHS when X Y Z / 2 is a multiple of 256, the
  *                            kernel that marches along time with n time
@@ -480,6 +482,14 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            registers (FP64, FP32 and 16-bit storage; never
  *                            BF16); bitwise the same results
  *   "dslash_autotune_clear"  any value: forget the autotuner's choices
+ *   "gemm_fp32_mfma"         -1: automatic; 0: never; 1: always: the projection
+ *                            with FP32 eigenvectors (V^H B and V C) on the FP32
+ *                            matrix cores (products in FP32, each wave's part of
+ *                            a sum in FP32, the parts summed in FP64) instead of
+ *                            widening to FP64; automatic: where the FP64 form
+ *                            would be bound by the FP64 matrix rate (4 k n /
+ *                            (4 k + 8 n) > 10 flop/B, e.g. 256 vectors x 24 RHS).
+ *                            This knob changes results at the FP32 rounding level.
  *   "cg_graphs"              -1 automatic (off), 0 off, 1: replay the CG's
  *                            chunks of iterations from a captured HIP graph
  *                            (measured: no gain on MI355X, kept as an option)

@@ -42,10 +42,63 @@ __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p
     return wave_sum(v);
 }
 
+// Two consecutive sites per lane (Vh is even): one 8-byte load per colour of
+// a 16-bit field, one 16-byte load per colour of an FP32 field, one 8-byte
+// load of the two norms.
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef short svec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load_pair(const h16c *__restrict__ d, const float *__restrict__ nrm,
+                                          int64_t vh, int j, int64_t cb, fvec2 (&v)[2][3]) {
+    const fvec2 sc = *reinterpret_cast<const fvec2 *>(nrm + (int64_t)j * vh + cb) * (1.0f / kQ16);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const svec4 h = *reinterpret_cast<const svec4 *>(d + ((int64_t)j * 3 + c) * vh + cb);
+        v[0][c] = fvec2{(float)h.x * sc.x, (float)h.y * sc.x};
+        v[1][c] = fvec2{(float)h.z * sc.y, (float)h.w * sc.y};
+    }
+}
+
+__device__ __forceinline__ void store_pair(h16c *__restrict__ d, float *__restrict__ nrm, int64_t vh,
+                                           int j, int64_t cb, const fvec2 (&v)[2][3]) {
+    fvec2 m = fvec2{0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        m.x = fmaxf(m.x, fmaxf(fabsf(v[0][c].x), fabsf(v[0][c].y)));
+        m.y = fmaxf(m.y, fmaxf(fabsf(v[1][c].x), fabsf(v[1][c].y)));
+    }
+    const float q0 = m.x > 0.0f ? kQ16 / m.x : 0.0f, q1 = m.y > 0.0f ? kQ16 / m.y : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        *reinterpret_cast<svec4 *>(d + ((int64_t)j * 3 + c) * vh + cb) =
+            svec4{(short)rintf(v[0][c].x * q0), (short)rintf(v[0][c].y * q0),
+                  (short)rintf(v[1][c].x * q1), (short)rintf(v[1][c].y * q1)};
+    *reinterpret_cast<fvec2 *>(nrm + (int64_t)j * vh + cb) = m;
+}
+
+__device__ __forceinline__ void load_pair_f32(const fvec2 *__restrict__ f, int64_t vh, int j,
+                                              int64_t cb, fvec2 (&v)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const fvec4 q = *reinterpret_cast<const fvec4 *>(f + ((int64_t)j * 3 + c) * vh + cb);
+        v[0][c] = fvec2{q.x, q.y};
+        v[1][c] = fvec2{q.z, q.w};
+    }
+}
+
+__device__ __forceinline__ void store_pair_f32(fvec2 *__restrict__ f, int64_t vh, int j, int64_t cb,
+                                               const fvec2 (&v)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        *reinterpret_cast<fvec4 *>(f + ((int64_t)j * 3 + c) * vh + cb) =
+            fvec4{v[0][c].x, v[0][c].y, v[1][c].x, v[1][c].y};
+}
+
 // alpha = rho / <p, Ap> (the stencil's fixed-order partials), r -= alpha Ap,
-// per-block partials of ||r||^2.  Grid (blas_reduce_blocks(3 Vh), nrhs).
-// The first site's r and A p are loaded before the partials are summed, so
-// that the two memory latencies overlap.
+// per-block partials of ||r||^2.  Grid (blas_reduce_blocks(3 Vh), nrhs); a
+// lane takes two consecutive sites at a time.  The first pair's r and A p are
+// loaded before the partials are summed, so that the two memory latencies
+// overlap.
 __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restrict__ r,
                                                     const h16c *__restrict__ ap,
                                                     const float *__restrict__ apn,
@@ -53,13 +106,13 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
                                                     CgDev cg, Reduce red) {
     const int j = blockIdx.y;
     const bool active = cg.status[j] == CG_ACTIVE;
+    const int64_t npair = vh / 2;
     const int64_t stride = (int64_t)gridDim.x * kBS;
-    int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    fvec2 q[3], rr[3];
-    if (active && cb < vh) {
-        load_site(ap, apn, vh, j, cb, q);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
+    int64_t pi = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    fvec2 q[2][3], rr[2][3];
+    if (active && pi < npair) {
+        load_pair(ap, apn, vh, j, 2 * pi, q);
+        load_pair_f32(r, vh, j, 2 * pi, rr);
     }
     __shared__ double pq_s;
     if (threadIdx.x < kWave) {
@@ -71,21 +124,21 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
     double v[1] = {0.0};
     if (active && isfinite(pq) && pq > 0.0) {
         const float al = (float)(cg.rho[j] / pq);
-        while (cb < vh) {
+        while (pi < npair) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int64_t i = ((int64_t)j * 3 + c) * vh + cb;
-                rr[c].x = fmaf(-al, q[c].x, rr[c].x);
-                rr[c].y = fmaf(-al, q[c].y, rr[c].y);
-                r[i] = rr[c];
-                v[0] = fma((double)rr[c].x, (double)rr[c].x,
-                           fma((double)rr[c].y, (double)rr[c].y, v[0]));
-            }
-            cb += stride;
-            if (cb < vh) {
-                load_site(ap, apn, vh, j, cb, q);
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
+                for (int c = 0; c < 3; ++c) {
+                    rr[h][c].x = fmaf(-al, q[h][c].x, rr[h][c].x);
+                    rr[h][c].y = fmaf(-al, q[h][c].y, rr[h][c].y);
+                    v[0] = fma((double)rr[h][c].x, (double)rr[h][c].x,
+                               fma((double)rr[h][c].y, (double)rr[h][c].y, v[0]));
+                }
+            store_pair_f32(r, vh, j, 2 * pi, rr);
+            pi += stride;
+            if (pi < npair) {
+                load_pair(ap, apn, vh, j, 2 * pi, q);
+                load_pair_f32(r, vh, j, 2 * pi, rr);
             }
         }
     }
@@ -95,45 +148,42 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
 }
 
 // x += alpha p_old; p = r + beta p_old (mode 2), or only the x update (mode 1).
-// The first site's x, p and r are loaded before the RHS's mode and
-// coefficients are read.
+// Two consecutive sites per lane; the first pair's x, p and r are loaded
+// before the RHS's mode and coefficients are read.
 __global__ __launch_bounds__(kBS) void k_update_xp_h(int64_t vh, fvec2 *__restrict__ x,
                                                      const fvec2 *__restrict__ r,
                                                      h16c *__restrict__ p, float *__restrict__ pn,
                                                      CgDev cg) {
     const int j = blockIdx.y;
+    const int64_t npair = vh / 2;
     const int64_t stride = (int64_t)gridDim.x * kBS;
-    int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    fvec2 pp[3], xx[3], rr[3];
-    if (cb < vh) {
-        load_site(p, pn, vh, j, cb, pp);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            xx[c] = x[((int64_t)j * 3 + c) * vh + cb];
-            rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
-        }
+    int64_t pi = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    fvec2 pp[2][3], xx[2][3], rr[2][3];
+    if (pi < npair) {
+        load_pair(p, pn, vh, j, 2 * pi, pp);
+        load_pair_f32(x, vh, j, 2 * pi, xx);
+        load_pair_f32(r, vh, j, 2 * pi, rr);
     }
     const int mode = cg.xp_mode[j];
     if (mode == 0) return;
     const float al = (float)cg.xp_alpha[j], be = (float)cg.xp_beta[j];
-    while (cb < vh) {
+    while (pi < npair) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t i = ((int64_t)j * 3 + c) * vh + cb;
-            xx[c].x = fmaf(al, pp[c].x, xx[c].x);
-            xx[c].y = fmaf(al, pp[c].y, xx[c].y);
-            x[i] = xx[c];
-            if (mode == 2) pp[c] = fvec2{fmaf(be, pp[c].x, rr[c].x), fmaf(be, pp[c].y, rr[c].y)};
-        }
-        if (mode == 2) store_site(p, pn, vh, j, cb, pp);
-        cb += stride;
-        if (cb < vh) {
-            load_site(p, pn, vh, j, cb, pp);
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                xx[c] = x[((int64_t)j * 3 + c) * vh + cb];
-                rr[c] = r[((int64_t)j * 3 + c) * vh + cb];
+                xx[h][c].x = fmaf(al, pp[h][c].x, xx[h][c].x);
+                xx[h][c].y = fmaf(al, pp[h][c].y, xx[h][c].y);
+                if (mode == 2)
+                    pp[h][c] = fvec2{fmaf(be, pp[h][c].x, rr[h][c].x), fmaf(be, pp[h][c].y, rr[h][c].y)};
             }
+        store_pair_f32(x, vh, j, 2 * pi, xx);
+        if (mode == 2) store_pair(p, pn, vh, j, 2 * pi, pp);
+        pi += stride;
+        if (pi < npair) {
+            load_pair(p, pn, vh, j, 2 * pi, pp);
+            load_pair_f32(x, vh, j, 2 * pi, xx);
+            load_pair_f32(r, vh, j, 2 * pi, rr);
         }
     }
 }

@@ -120,6 +120,8 @@ bool profile_enabled() { return g_prof_on && !t_prof_suppressed; }
 ProfileSuppress::ProfileSuppress() : prev_(t_prof_suppressed) { t_prof_suppressed = true; }
 ProfileSuppress::~ProfileSuppress() { t_prof_suppressed = prev_; }
 
+extern int64_t g_gemm_f32;  // gemm.hip
+
 // "cg_graphs": -1 automatic, 0 off, 1 on (never while kernel timing is on:
 // its events would be captured into the graph).
 int64_t g_cg_graphs = -1;
@@ -164,6 +166,12 @@ int hisq_abi_version(void) { return HISQ_ABI_VERSION; }
 
 hisq_status hisq_set_tuning(const char *key, int64_t value) {
     if (!key) return fail(HISQ_ERR_INVALID_ARG, "hisq_set_tuning: null key");
+    if (std::string(key) == "gemm_fp32_mfma") {
+        if (value != -1 && value != 0 && value != 1)
+            return fail(HISQ_ERR_INVALID_ARG, "gemm_fp32_mfma must be -1, 0 or 1");
+        g_gemm_f32 = value;
+        return HISQ_OK;
+    }
     if (std::string(key) == "cg_graphs") {
         if (value != -1 && value != 0 && value != 1)
             return fail(HISQ_ERR_INVALID_ARG, "cg_graphs must be -1, 0 or 1");

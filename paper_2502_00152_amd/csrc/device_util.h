@@ -41,6 +41,24 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
     return x * q + (x < r ? x : r) + j;
 }
 
+// Chunks of n logical blocks dealt round-robin to the XCDs: XCD x takes the
+// chunks x, x + 8, x + 16, ...  All XCDs then work on the same stretch of 8 n
+// blocks at the same time, so the data around it is shared in the
+// last-level cache, while the n consecutive blocks of a chunk share the
+// XCD's L2.  The tail that does not fill a whole round keeps dispatch order.
+__device__ __forceinline__ int xcd_block_chunked(int b, int nblocks, int n) {
+    const int x = b % kNumXcd, j = b / kNumXcd;
+    const int rounds = nblocks / (kNumXcd * n);
+    if (j >= rounds * n) return b;
+    return ((j / n) * kNumXcd + x) * n + j % n;
+}
+
+// Logical block of workgroup b for a remap mode: 0 dispatch order, 1 one
+// contiguous range per XCD, n >= 2 chunks of n blocks round-robin.
+__device__ __forceinline__ int remap_block(int mode, int b, int nblocks) {
+    return mode == 1 ? xcd_block(b, nblocks) : mode > 1 ? xcd_block_chunked(b, nblocks, mode) : b;
+}
+
 // ---------------------------------------------------------- reductions
 // Sum over the 64 lanes of a wave, in a fixed order; result in every lane.
 __device__ __forceinline__ double wave_sum(double v) {

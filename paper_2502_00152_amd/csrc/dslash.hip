@@ -173,8 +173,8 @@ hisq_status dslash_set_tuning(const std::string &key, int64_t v) {
         if (v < -1) return fail(HISQ_ERR_INVALID_ARG, "dslash_march must be -1, 0 or a segment count");
         g_tune.march = v;
     } else if (key == "dslash_xcd_remap") {
-        if (v != -1 && v != 0 && v != 1)
-            return fail(HISQ_ERR_INVALID_ARG, "dslash_xcd_remap must be -1, 0 or 1");
+        if (v < -1 || v > (1 << 20))
+            return fail(HISQ_ERR_INVALID_ARG, "dslash_xcd_remap must be -1, 0, 1 or a chunk size");
         g_tune.xcd_remap = v;
     } else {
         return fail(HISQ_ERR_INVALID_ARG, "unknown tuning key '" + key + "'");

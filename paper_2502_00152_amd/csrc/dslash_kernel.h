@@ -188,7 +188,7 @@ struct DslashArgs {
                            // are all inactive (converged, frozen) does nothing
     Geom geom;
     int out_parity;
-    int xcd_remap;         // 1: contiguous site ranges per XCD
+    int xcd_remap;         // 0 off, 1 contiguous site ranges per XCD, n > 1 chunks
     int group_outer;       // 1: block index = group * nsb + site block
     int nrhs;
     int ngroups;           // ceil(nrhs / (LPS * NR))
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
     constexpr int RG = LPS * NR;      // RHS per group
     const Geom g = a.geom;
     const int vh = g.vh;
-    const int lb = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int lb = remap_block(a.xcd_remap, (int)blockIdx.x, (int)gridDim.x);
     int sb, grp;
     if (a.group_outer) {
         grp = lb / a.nsb;

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash_march(DslashArgs<R, VS, 
     constexpr int RG = LPS * NR;      // RHS per group
     const Geom g = a.geom;
     const int vh = g.vh;
-    const int lb = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int lb = remap_block(a.xcd_remap, (int)blockIdx.x, (int)gridDim.x);
     const int s = lb & 1;
     int rest = lb >> 1;
     const int grp = rest % a.ngroups;

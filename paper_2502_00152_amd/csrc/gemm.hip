@@ -23,6 +23,8 @@
 // Output layout of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l,
 // accumulator register r holds C[4r + l/16][l%16]; lane l supplies
 // A[l%16][l/16] and B[l/16][l%16].
+#include <type_traits>
+
 #include "device_util.h"
 #include "hisq_internal.h"
 
@@ -30,6 +32,18 @@ namespace hisq {
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+// FP32 eigenvectors on the FP32 matrix cores: -1 automatic, 0 never, 1 always
+// (hisq_set_tuning "gemm_fp32_mfma").
+int64_t g_gemm_f32 = -1;
+
+// The FP32 form is chosen automatically where the FP64 one would be bound by
+// the FP64 matrix rate: 4 k n flops per reduction real against 4 k + 8 n
+// bytes (FP32 V, FP64 B) exceed the FP64 ridge of about 10 flop/B.
+bool use_f32_mfma(int k, int n) {
+    if (g_gemm_f32 >= 0) return g_gemm_f32 == 1;
+    return 4.0 * k * n > 10.0 * (4.0 * k + 8.0 * n);
+}
 
 namespace {
 
@@ -157,6 +171,97 @@ __global__ __launch_bounds__(kBS) void k_gemm_tn(TnArgs<TV> a) {
         const double v = ((lds[0][slot][ln] + lds[1][slot][ln]) + lds[2][slot][ln]) + lds[3][slot][ln];
         const int mt = slot / (NT * 4), t = (slot / 4) % NT, r = slot % 4;
         const int i = i0 + 16 * mt + 4 * r + (ln >> 4);
+        const int j = j0 + 16 * t + (ln & 15);
+        if (i < a.kpad && j < a.ncpad) P[(int64_t)i * a.ncpad + j] = v;
+    }
+}
+
+// The same contraction for FP32 V on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32, B rounded to FP32 on load): each wave accumulates
+// its part of the reduction index in FP32, the four waves and the blocks are
+// summed in FP64.  Lane layout of this instruction (checked on gfx950): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] as the FP64 form does, and
+// accumulator register r holds C[4 (l/16) + r][l%16].
+template <int MT, int NT>
+__global__ __launch_bounds__(kBS) void k_gemm_tn_f32(TnArgs<float> a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, q = lane >> 4;
+    const int i0 = blockIdx.y * (16 * MT);
+    const int j0 = blockIdx.z * (16 * NT);
+    fvec4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = fvec4{0, 0, 0, 0};
+    const float *vcol[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int i = i0 + 16 * m + lr;
+        vcol[m] = i < a.k ? a.V + (int64_t)i * a.twoN : nullptr;
+    }
+    const double *bcol[NT];
+    bool imag_part[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int j = j0 + 16 * t + lr;
+        imag_part[t] = j >= a.n;
+        const int jj = imag_part[t] ? j - a.n : j;
+        bcol[t] = j < 2 * a.n ? a.B + (int64_t)jj * a.twoN : nullptr;
+    }
+    const int64_t per = (a.steps + gridDim.x - 1) / gridDim.x;
+    const int64_t s0 = blockIdx.x * per;
+    const int64_t s1 = min(a.steps, s0 + per);
+    for (int64_t s = s0 + wave; s < s1; s += 4) {
+        const int64_t off = s * kStep + 4 * q;
+        float av[MT][4], bv[NT][4];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (vcol[m]) {
+                const fvec4 x = *reinterpret_cast<const fvec4 *>(vcol[m] + off);
+                av[m][0] = x.x; av[m][1] = x.y; av[m][2] = x.z; av[m][3] = x.w;
+            } else {
+                av[m][0] = av[m][1] = av[m][2] = av[m][3] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (bcol[t]) {
+                const dvec2 y0 = *reinterpret_cast<const dvec2 *>(bcol[t] + off);
+                const dvec2 y1 = *reinterpret_cast<const dvec2 *>(bcol[t] + off + 2);
+                if (imag_part[t]) {
+                    bv[t][0] = (float)y0.y; bv[t][1] = (float)-y0.x;
+                    bv[t][2] = (float)y1.y; bv[t][3] = (float)-y1.x;
+                } else {
+                    bv[t][0] = (float)y0.x; bv[t][1] = (float)y0.y;
+                    bv[t][2] = (float)y1.x; bv[t][3] = (float)y1.y;
+                }
+            } else {
+                bv[t][0] = bv[t][1] = bv[t][2] = bv[t][3] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m][u], bv[t][u], acc[m][t],
+                                                                     0, 0, 0);
+    }
+    __shared__ double lds[4][MT * NT * 4][64];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds[wave][(m * NT + t) * 4 + r][lane] = (double)acc[m][t][r];
+    __syncthreads();
+    double *P = a.partials + (int64_t)blockIdx.x * a.kpad * a.ncpad;
+    for (int e = threadIdx.x; e < MT * NT * 4 * 64; e += kBS) {
+        const int slot = e / 64, ln = e % 64;
+        const double v = ((lds[0][slot][ln] + lds[1][slot][ln]) + lds[2][slot][ln]) + lds[3][slot][ln];
+        const int mt = slot / (NT * 4), t = (slot / 4) % NT, r = slot % 4;
+        const int i = i0 + 16 * mt + 4 * (ln >> 4) + r;
         const int j = j0 + 16 * t + (ln & 15);
         if (i < a.kpad && j < a.ncpad) P[(int64_t)i * a.ncpad + j] = v;
     }
@@ -383,6 +488,57 @@ __global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs<TV> a) {
     }
 }
 
+// X = beta X + V C for FP32 V on the FP32 matrix cores: the coefficients
+// rounded to FP32, the k products of an output summed in FP32, beta X added
+// in FP64.  Layout as k_gemm_nn, with the FP32 accumulator rows of
+// v_mfma_f32_16x16x4f32 (register r of lane l: row 4 (l/16) + r).
+template <int MT>
+__global__ __launch_bounds__(kBS) void k_gemm_nn_f32(NnArgs<float> a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, q = lane >> 4;
+    const int jbase = blockIdx.y * (16 * MT);
+    const int c = lr & 1;
+    const int dsel = q & 1;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < a.tiles;
+         tile += (int64_t)gridDim.x * 4) {
+        const int64_t col = tile * 16 + lr;
+        const int64_t site = col >> 1;
+        fvec4 acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = fvec4{0, 0, 0, 0};
+        for (int i0 = 0; i0 < a.k; i0 += 2) {
+            const int i = i0 + (q >> 1);
+            float bval = 0.0f;
+            if (i < a.k) {
+                const fvec2 v = *reinterpret_cast<const fvec2 *>(a.V + (int64_t)i * a.ldv + 2 * site);
+                bval = c == 0 ? (dsel == 0 ? v.x : -v.y) : (dsel == 0 ? v.y : v.x);
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int j = jbase + 16 * m + lr;
+                float aval = 0.0f;
+                if (j < a.n && i < a.k) {
+                    const dvec2 cc = a.C[(int64_t)j * a.k + i];
+                    aval = (float)(dsel == 0 ? cc.x : cc.y);
+                }
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[m], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jbase + 16 * m + 4 * q + r;
+                if (j < a.n) {
+                    double *dst = a.X + (int64_t)j * a.ldx + tile * 16 + lr;
+                    double v = (double)acc[m][r];
+                    if (a.beta != 0.0) v = fma(a.beta, *dst, v);
+                    *dst = v;
+                }
+            }
+    }
+}
+
 int round16(int v) { return (v + 15) / 16 * 16; }
 
 }  // namespace
@@ -441,6 +597,25 @@ hisq_status gemm_tn_t(hisq_gauge_s *g, const TV *V, int k, const double2 *B, int
     void *p = nullptr;
     HISQ_TRY(g->ws.get("gemm_partials", sizeof(double) * nbx * a.kpad * a.ncpad, &p));
     a.partials = static_cast<double *>(p);
+    if constexpr (std::is_same<TV, float>::value) {
+        if (use_f32_mfma(k, n)) {
+            ProfileScope prof("gemm", s);
+            const dim3 grid((unsigned)nbx, mtiles, ntiles);
+            if (mt == 4 && NT == 2) hipLaunchKernelGGL((k_gemm_tn_f32<4, 2>), grid, dim3(kBS), 0, s, a);
+            else if (mt == 4) hipLaunchKernelGGL((k_gemm_tn_f32<4, 1>), grid, dim3(kBS), 0, s, a);
+            else if (mt == 2 && NT == 2) hipLaunchKernelGGL((k_gemm_tn_f32<2, 2>), grid, dim3(kBS), 0, s, a);
+            else if (mt == 2) hipLaunchKernelGGL((k_gemm_tn_f32<2, 1>), grid, dim3(kBS), 0, s, a);
+            else if (NT == 2) hipLaunchKernelGGL((k_gemm_tn_f32<1, 2>), grid, dim3(kBS), 0, s, a);
+            else hipLaunchKernelGGL((k_gemm_tn_f32<1, 1>), grid, dim3(kBS), 0, s, a);
+            HISQ_HIP(hipGetLastError());
+            const int waves = k * n;
+            hipLaunchKernelGGL(k_tn_reduce, dim3((waves + 3) / 4), dim3(kBS), 0, s, a.partials,
+                               (int)nbx, k, n, a.kpad, a.ncpad, row_scale_dev, out_scale,
+                               reinterpret_cast<dvec2 *>(C));
+            HISQ_HIP(hipGetLastError());
+            return HISQ_OK;
+        }
+    }
     {
         ProfileScope prof("gemm", s);
         if (mt == 4 && NT == 2) launch_tn<TV, 4, 2>(a, (int)nbx, mtiles, ntiles, s);
@@ -493,6 +668,19 @@ hisq_status gemm_nn_t(const TV *V, int64_t ldv, int k, const double2 *C, int n, 
     }
     int64_t nbx = (a.tiles + 3) / 4;
     nbx = std::max<int64_t>(1, std::min<int64_t>(nbx, 2048));
+    if constexpr (std::is_same<TV, float>::value) {
+        if (use_f32_mfma(k, n)) {
+            if (n <= 16) {
+                hipLaunchKernelGGL((k_gemm_nn_f32<1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
+            } else {
+                const int groups = (n + 63) / 64;
+                hipLaunchKernelGGL((k_gemm_nn_f32<4>), dim3((unsigned)nbx, groups), dim3(kBS), 0, s,
+                                   a);
+            }
+            HISQ_HIP(hipGetLastError());
+            return HISQ_OK;
+        }
+    }
     if (n <= 16) {
         hipLaunchKernelGGL((k_gemm_nn<TV, 1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
     } else {

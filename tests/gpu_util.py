@@ -145,3 +145,33 @@ def half_link_step(F, L):
     q = np.floor(65535.0 * amax / rowl1) - 1.0
     qmax = int(max(10922.0, min(32767.0, q)))
     return amax / qmax
+
+
+U32 = 2.0 ** -24
+
+
+def gamma32(n):
+    """Higham's gamma_n = n u / (1 - n u) for FP32 (u = 2^-24): the relative
+    bound on a length-n chain of FP32 products and sums."""
+    return n * U32 / (1.0 - n * U32)
+
+
+def fp32_projection_bound(V, B, w, C):
+    """Componentwise bound on the error of the real and of the imaginary part
+    of x0 = V diag(w) V^H B (Eq. (4)) when both products run on the FP32
+    matrix cores (FP32 eigenvectors, gemm_fp32_mfma on).
+
+    V [k][N] are the FP32 vectors exactly widened, B [n][N], w [k], and
+    C [k][n] = diag(w) V^H B in FP64.  V^H B: B rounded to FP32, each wave's
+    part of a sum accumulated in FP32 over at most 256 + 2N/4096 reals, the
+    parts summed in FP64 (error not counted: below 1e-13 relative), so each
+    of Re, Im of (V^H B)_ij is off by at most gamma(K+1) sum_s |V_is||B_js|.
+    V C: coefficients rounded to FP32, 2k real products summed in FP32.
+    Returns [n][N] (same bound for Re and Im)."""
+    k, N = V.shape
+    kw = 256 + 2 * N / 4096
+    aV = np.abs(V)
+    cb = gamma32(kw + 1) * (aV @ np.abs(B).T)                     # [k][n]
+    first = np.sqrt(2.0) * (aV.T @ (np.asarray(w)[:, None] * cb))   # [N][n]
+    second = gamma32(2 * k + 1) * (aV.T @ np.abs(C))
+    return (first + second).T

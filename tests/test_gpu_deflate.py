@@ -1,5 +1,7 @@
 """GPU parity of hisq_deflate (Eq. (4): x0 = V diag(1/(eps + (2m)^2)) V^H b)
-against the oracle's dense FP64 formula, <= 1e-13 relative per RHS."""
+against the oracle's dense FP64 formula: <= 1e-13 relative per RHS with FP64
+arithmetic (FP64 vectors, or FP32 vectors widened exactly); with FP32 vectors
+on the FP32 matrix cores, within the componentwise FP32 rounding bound."""
 from __future__ import annotations
 
 import numpy as np
@@ -7,7 +9,8 @@ import pytest
 
 from oracle import hisq_oracle as O
 from paper_2502_00152_amd import inputs as I
-from tests.gpu_util import Problem, dev, from_parity, host, rel_per_rhs, to_parity
+from tests.gpu_util import (Problem, dev, fp32_projection_bound, from_parity, host,
+                            rel_per_rhs, to_parity)
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +41,47 @@ def test_deflate_matches_dense_formula(dims, k, nrhs):
     hisq.hisq_deflate(g, dev(evecs), eps, two_m, dev(B), x0)
     ref = O.deflation_guess(Q, eps + two_m ** 2, B.reshape(nrhs, N).T).T.reshape(nrhs, 3, vh)
     assert max(rel_per_rhs(host(x0), ref)) <= 1e-13
+    g.close()
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 6, 8, 10), (8, 8, 8, 8)])
+@pytest.mark.parametrize("k,nrhs", [(3, 3), (7, 5), (16, 12), (37, 17), (64, 3), (130, 40)])
+@pytest.mark.parametrize("mfma32", [0, 1])
+def test_deflate_fp32_vectors(dims, k, nrhs, mfma32):
+    """FP32 eigenvectors: gemm_fp32_mfma 0 widens them and keeps FP64
+    arithmetic (1e-13 of the oracle's formula on the rounded vectors); 1 runs
+    both products on the FP32 matrix cores (ragged vector and RHS tiles,
+    n > 16 column groups) and stays inside the FP32 rounding bound."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    vh = int(np.prod(dims)) // 2
+    N = 3 * vh
+    if k > N:
+        pytest.skip("more vectors than the space holds")
+    pr = Problem(dims, 0.5, 13, 14)
+    g = pr.gauge()
+    Q = orthonormal(N, k, 6).astype(np.complex64).astype(np.complex128)
+    evecs = np.ascontiguousarray(Q.T.reshape(k, 3, vh)).astype(np.complex64)
+    eps = np.linspace(0.01, 2.0, k) ** 2
+    two_m = 0.05
+    w = 1.0 / (eps + two_m ** 2)
+    B = I.gaussian_even_vectors(nrhs, N, 19).reshape(nrhs, 3, vh)
+    x0 = torch.empty((nrhs, 3, vh), dtype=torch.complex128, device="cuda")
+    hisq.hisq_set_tuning("gemm_fp32_mfma", mfma32)
+    try:
+        hisq.hisq_deflate(g, dev(evecs), eps, two_m, dev(B), x0)
+    finally:
+        hisq.hisq_set_tuning("gemm_fp32_mfma", -1)
+    Bm = B.reshape(nrhs, N)
+    ref = O.deflation_guess(Q, eps + two_m ** 2, Bm.T).T
+    got = host(x0).reshape(nrhs, N)
+    if mfma32 == 0:
+        assert max(rel_per_rhs(got, ref)) <= 1e-13
+    else:
+        C = w[:, None] * (Q.conj().T @ Bm.T)
+        bound = fp32_projection_bound(Q.T, Bm, w, C) + 1e-13 * np.abs(ref).max()
+        assert (np.abs(got.real - ref.real) <= bound).all()
+        assert (np.abs(got.imag - ref.imag) <= bound).all()
     g.close()
 
 

@@ -147,8 +147,9 @@ def test_invalid_arguments_are_rejected():
 
 def test_launch_shape_knobs_do_not_change_results():
     """hisq_set_tuning changes only the launch shape: every choice of RHS per
-    thread, group order and XCD remap gives bitwise the same half stencil on
-    12 RHS."""
+    thread, group order and XCD remap (off, contiguous, chunks of 2, 3 and 5
+    blocks: whole rounds and a tail in dispatch order) gives bitwise the same
+    half stencil on 12 RHS."""
     import torch
     from paper_2502_00152_amd import hisq
     dims = (4, 6, 8, 10)
@@ -161,7 +162,7 @@ def test_launch_shape_knobs_do_not_change_results():
     try:
         for nr, lps in shapes:
             for order in (0, 1):
-                for xcd in (0, 1):
+                for xcd in (0, 1, 2, 3, 5):
                     hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
                     hisq.hisq_set_tuning("dslash_lanes_per_site", lps)
                     hisq.hisq_set_tuning("dslash_group_order", order)

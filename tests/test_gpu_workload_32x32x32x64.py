@@ -23,7 +23,7 @@ import pytest
 
 from oracle import hisq_oracle as O
 from paper_2502_00152_amd import inputs as I
-from tests.gpu_util import abs_stencil_site, dev, from_parity, host, to_parity
+from tests.gpu_util import abs_stencil_site, dev, from_parity, gamma32, host, to_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -96,9 +96,13 @@ def test_dslash_fp32_24rhs_sampled_sites(wl):
     say(f"FP32 stencil worst error {worst / U32:.1f} u of |D||psi|")
 
 
-def test_deflate_fp32_256_vectors_24rhs_sampled(wl):
+@pytest.mark.parametrize("mfma32", [0, 1])
+def test_deflate_fp32_256_vectors_24rhs_sampled(wl, mfma32):
     """Eq. (4) with 256 FP32 vectors x 24 RHS at full size: sampled entries of
-    x0 = V diag(w) V^H b against FP64 sums of the same (exactly widened) values."""
+    x0 = V diag(w) V^H b against FP64 sums of the same (exactly widened)
+    values; FP64 arithmetic (gemm_fp32_mfma 0) to 1e-11, the FP32 matrix
+    cores (1, the automatic choice at this shape) within the componentwise
+    FP32 rounding bound."""
     import torch
     from paper_2502_00152_amd import hisq
     n_ev, vh = 256, wl.g.vh
@@ -107,14 +111,20 @@ def test_deflate_fp32_256_vectors_24rhs_sampled(wl):
     V = torch.randn((n_ev, 3, vh), dtype=torch.complex64, device="cuda", generator=gen)
     eps = np.linspace(1e-3, 0.2, n_ev)
     x0 = torch.empty_like(wl.y)
-    hisq.hisq_deflate(wl.g, V, eps, wl.two_m, wl.y, x0)
+    hisq.hisq_set_tuning("gemm_fp32_mfma", mfma32)
+    try:
+        hisq.hisq_deflate(wl.g, V, eps, wl.two_m, wl.y, x0)
+    finally:
+        hisq.hisq_set_tuning("gemm_fp32_mfma", -1)
     w8 = 1.0 / (eps + wl.two_m ** 2)
     cols = (0, 11, 23)
     B = host(wl.y[list(cols)]).reshape(len(cols), -1)             # [3][N]
     C = np.zeros((n_ev, len(cols)), dtype=np.complex128)
+    S = np.zeros((n_ev, len(cols)))                                # sum |V||B|
     for i0 in range(0, n_ev, 32):
         Vc = host(V[i0:i0 + 32]).reshape(32, -1).astype(np.complex128)
         C[i0:i0 + 32] = Vc.conj() @ B.T
+        S[i0:i0 + 32] = np.abs(Vc) @ np.abs(B).T
     C *= w8[:, None]
     rng = np.random.default_rng(12)
     ent = rng.choice(3 * vh, 400, replace=False)
@@ -123,8 +133,21 @@ def test_deflate_fp32_256_vectors_24rhs_sampled(wl):
     ref = (Vs.T @ C).T                                             # [3][400]
     got = host(x0[list(cols)]).reshape(len(cols), -1)[:, ent]
     scale = np.abs(ref).max()
-    assert np.abs(got - ref).max() <= 1e-11 * scale
-    say(f"projection max rel error {np.abs(got - ref).max() / scale:.2e}")
+    err = np.abs(got - ref).max()
+    if mfma32 == 0:
+        assert err <= 1e-11 * scale
+    else:
+        # the bound of tests/gpu_util.fp32_projection_bound at the sampled entries
+        N = 3 * vh
+        aVs = np.abs(Vs)
+        cb = gamma32(256 + 2 * N / 4096 + 1) * S
+        bound = (np.sqrt(2.0) * (aVs.T @ (w8[:, None] * cb))
+                 + gamma32(2 * n_ev + 1) * (aVs.T @ np.abs(C))).T + 1e-13 * scale
+        assert (np.abs(got.real - ref.real) <= bound).all()
+        assert (np.abs(got.imag - ref.imag) <= bound).all()
+        say(f"FP32 matrix cores: worst error {float((np.abs(got - ref) / bound).max()):.2e} "
+            f"of the bound")
+    say(f"projection (gemm_fp32_mfma={mfma32}) max rel error {err / scale:.2e}")
 
 
 @pytest.fixture(scope="module")
