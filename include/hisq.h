@@ -490,6 +490,11 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            would be bound by the FP64 matrix rate (4 k n /
  *                            (4 k + 8 n) > 10 flop/B, e.g. 256 vectors x 24 RHS).
  *                            This knob changes results at the FP32 rounding level.
+ *   "cg_reliable_freeze"     mixed CG: -1 automatic; 1: a right-hand side whose
+ *                            iterated residual has fallen by reliable_delta
+ *                            stops iterating until its reliable update at the
+ *                            next host poll; 0: it iterates on until then.
+ *                            Changes iterates and iteration counts.
  *   "cg_graphs"              -1 automatic (off), 0 off, 1: replay the CG's
  *                            chunks of iterations from a captured HIP graph
  *                            (measured: no gain on MI355X, kept as an option)

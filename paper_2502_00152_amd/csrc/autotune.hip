@@ -101,7 +101,7 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
             const int nr = opts[i];
             // groups much wider than the batch only add idle lanes
             if (nr * lps > 2 * nrhs && !(nr == 1 && lps == 1)) continue;
-            if (!dslash_impl::shape_fits(nr, lps, vh, rb)) continue;
+            if (!dslash_impl::shape_fits(nr, lps, vh, 6 * rb)) continue;
             const int ngroups = (nrhs + nr * lps - 1) / (nr * lps);
             for (int order = 0; order < (ngroups > 1 ? 2 : 1); ++order) {
                 for (int xcd = 0; xcd < 2; ++xcd) {

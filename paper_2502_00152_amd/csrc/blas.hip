@@ -147,6 +147,21 @@ __global__ __launch_bounds__(kBS) void k_cg_update_r(int64_t n, V *__restrict__ 
     if (threadIdx.x == 0) red.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = v[0];
 }
 
+// pq[j] = RHS j's nb <p, A p> partials in one fixed order: one block of
+// kSumBS threads per RHS, thread i adding entries i, i + kSumBS, ... in
+// turn, then the block sum (waves in order).
+constexpr int kSumBS = 1024;
+__global__ __launch_bounds__(kSumBS) void k_sum_pap(const double *__restrict__ pap, int nb,
+                                                    double *__restrict__ pq) {
+    const int j = blockIdx.x;
+    const double *p = pap + (int64_t)j * nb;
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < nb; i += kSumBS) v[0] += p[i];
+    __shared__ double lds[kSumBS / kWave];
+    block_sum<1, kSumBS>(v, lds);
+    if (threadIdx.x == 0) pq[j] = v[0];
+}
+
 // One wave per RHS: the per-RHS state machine after an r update.  x and p are
 // updated afterwards by k_cg_update_xp with the alpha and beta written here.
 __global__ __launch_bounds__(kBS) void k_cg_finalize(int nrhs, const double *__restrict__ pap,
@@ -329,6 +344,12 @@ hisq_status cg_update_r(int64_t n, int nrhs, double2 *r, const double2 *Ap, cons
     ProfileScope prof("blas", s);
     hipLaunchKernelGGL(k_cg_update_r<dvec2>, dim3(gr.nbx, nrhs), dim3(kBS), 0, s, n, AS_V(r),
                        AS_CV(Ap), pap, nb_pap, cg, red);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+hisq_status cg_sum_pap(int nrhs, const double *pap, int nb_pap, double *pq, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_pap, dim3(nrhs), dim3(kSumBS), 0, s, pap, nb_pap, pq);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }

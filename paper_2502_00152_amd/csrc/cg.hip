@@ -195,14 +195,27 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     double2 *t = static_cast<double2 *>(tmpv);
     const double m2 = two_m * two_m;
     const int nb_pap = dslash_reduce_blocks(g, nrhs);
+    double *pq_sum = nullptr;
+    if (nb_pap >= kPapPresum) {
+        void *pp = nullptr;
+        HISQ_TRY(g->ws.get("cg_pq", sizeof(double) * nrhs, &pp));
+        pq_sum = static_cast<double *>(pp);
+    }
 
     auto iterate = [&]() -> hisq_status {
         HISQ_TRY(launch_dslash(g, 1 - par, B.p, t, nrhs, nullptr, 0.0, nullptr, 0.0, 1.0, FIN_NONE,
                                &B.dev, nullptr, s));
         HISQ_TRY(launch_dslash(g, par, t, B.Ap, nrhs, B.p, m2, nullptr, 0.0, -1.0, FIN_CG_ALPHA,
                                &B.dev, &B.pap, s, m2_rhs));
-        HISQ_TRY(cg_update_r(n, nrhs, B.r, B.Ap, B.pap.partials, nb_pap, B.dev, B.red, s));
-        HISQ_TRY(cg_finalize(n, nrhs, B.pap.partials, nb_pap, B.dev, B.red, s));
+        const double *pq = B.pap.partials;
+        int nbq = nb_pap;
+        if (pq_sum) {
+            HISQ_TRY(cg_sum_pap(nrhs, B.pap.partials, nb_pap, pq_sum, s));
+            pq = pq_sum;
+            nbq = 1;
+        }
+        HISQ_TRY(cg_update_r(n, nrhs, B.r, B.Ap, pq, nbq, B.dev, B.red, s));
+        HISQ_TRY(cg_finalize(n, nrhs, pq, nbq, B.dev, B.red, s));
         HISQ_TRY(cg_update_xp(n, nrhs, x, B.r, B.p, B.dev, s));
         return HISQ_OK;
     };

@@ -1,5 +1,5 @@
-// CG vector updates on 16-bit fixed-point fields (h16c with one norm per RHS
-// and site; see dslash_kernel.h) for the mixed-precision CG at sloppy_prec =
+// CG vector updates on 16-bit fixed-point fields (h16p: a site's three
+// colours and their norm in 16 bytes; see dslash_kernel.h) for the mixed-precision CG at sloppy_prec =
 // HISQ_HALF: the search direction p and A p are stored in 16 bits, the
 // residual and the solution correction stay FP32, scalars and partial sums
 // FP64 (the same fixed-order reductions as the FP32 and FP64 updates).
@@ -12,27 +12,29 @@ constexpr int kBS = 256;
 typedef float fvec2 __attribute__((ext_vector_type(2)));
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void load_site(const h16c *__restrict__ d, const float *__restrict__ nrm,
-                                          int64_t vh, int j, int64_t cb, fvec2 (&v)[3]) {
-    const float sc = nrm[(int64_t)j * vh + cb] * (1.0f / kQ16);
+// A 16-bit field is [nrhs][Vh] of h16p: three colours as int16 pairs and
+// the site's norm, value = integer * norm / 32767.
+__device__ __forceinline__ void load_site(const h16p *__restrict__ d, int64_t vh, int j,
+                                          int64_t cb, fvec2 (&v)[3]) {
+    h16c c[3];
+    float n;
+    h16_unpack(d[(int64_t)j * vh + cb], c, n);
+    const float sc = n * (1.0f / kQ16);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const h16c h = d[((int64_t)j * 3 + c) * vh + cb];
-        v[c] = fvec2{(float)h.x * sc, (float)h.y * sc};
-    }
+    for (int k = 0; k < 3; ++k) v[k] = fvec2{(float)c[k].x * sc, (float)c[k].y * sc};
 }
 
-__device__ __forceinline__ void store_site(h16c *__restrict__ d, float *__restrict__ nrm, int64_t vh,
-                                           int j, int64_t cb, const fvec2 (&v)[3]) {
+__device__ __forceinline__ void store_site(h16p *__restrict__ d, int64_t vh, int j, int64_t cb,
+                                           const fvec2 (&v)[3]) {
     float m = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].x), fabsf(v[c].y)));
+    for (int k = 0; k < 3; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
     const float qs = m > 0.0f ? kQ16 / m : 0.0f;
+    h16c q[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        d[((int64_t)j * 3 + c) * vh + cb] =
-            h16c{(short)rintf(v[c].x * qs), (short)rintf(v[c].y * qs)};
-    nrm[(int64_t)j * vh + cb] = m;
+    for (int k = 0; k < 3; ++k) q[k] = h16c{(short)rintf(v[k].x * qs), (short)rintf(v[k].y * qs)};
+    d[(int64_t)j * vh + cb] = h16p{__builtin_bit_cast(int, q[0]), __builtin_bit_cast(int, q[1]),
+                                   __builtin_bit_cast(int, q[2]), __float_as_int(m)};
 }
 
 __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p, int nb) {
@@ -42,38 +44,20 @@ __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p
     return wave_sum(v);
 }
 
-// Two consecutive sites per lane (Vh is even): one 8-byte load per colour of
-// a 16-bit field, one 16-byte load per colour of an FP32 field, one 8-byte
-// load of the two norms.
+// Two consecutive sites per lane (Vh is even): one 16-byte load per site of a
+// 16-bit field, one 16-byte load per colour of an FP32 field.
 typedef float fvec4 __attribute__((ext_vector_type(4)));
-typedef short svec4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void load_pair(const h16c *__restrict__ d, const float *__restrict__ nrm,
-                                          int64_t vh, int j, int64_t cb, fvec2 (&v)[2][3]) {
-    const fvec2 sc = *reinterpret_cast<const fvec2 *>(nrm + (int64_t)j * vh + cb) * (1.0f / kQ16);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const svec4 h = *reinterpret_cast<const svec4 *>(d + ((int64_t)j * 3 + c) * vh + cb);
-        v[0][c] = fvec2{(float)h.x * sc.x, (float)h.y * sc.x};
-        v[1][c] = fvec2{(float)h.z * sc.y, (float)h.w * sc.y};
-    }
+__device__ __forceinline__ void load_pair(const h16p *__restrict__ d, int64_t vh, int j,
+                                          int64_t cb, fvec2 (&v)[2][3]) {
+    load_site(d, vh, j, cb, v[0]);
+    load_site(d, vh, j, cb + 1, v[1]);
 }
 
-__device__ __forceinline__ void store_pair(h16c *__restrict__ d, float *__restrict__ nrm, int64_t vh,
-                                           int j, int64_t cb, const fvec2 (&v)[2][3]) {
-    fvec2 m = fvec2{0.0f, 0.0f};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        m.x = fmaxf(m.x, fmaxf(fabsf(v[0][c].x), fabsf(v[0][c].y)));
-        m.y = fmaxf(m.y, fmaxf(fabsf(v[1][c].x), fabsf(v[1][c].y)));
-    }
-    const float q0 = m.x > 0.0f ? kQ16 / m.x : 0.0f, q1 = m.y > 0.0f ? kQ16 / m.y : 0.0f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        *reinterpret_cast<svec4 *>(d + ((int64_t)j * 3 + c) * vh + cb) =
-            svec4{(short)rintf(v[0][c].x * q0), (short)rintf(v[0][c].y * q0),
-                  (short)rintf(v[1][c].x * q1), (short)rintf(v[1][c].y * q1)};
-    *reinterpret_cast<fvec2 *>(nrm + (int64_t)j * vh + cb) = m;
+__device__ __forceinline__ void store_pair(h16p *__restrict__ d, int64_t vh, int j, int64_t cb,
+                                           const fvec2 (&v)[2][3]) {
+    store_site(d, vh, j, cb, v[0]);
+    store_site(d, vh, j, cb + 1, v[1]);
 }
 
 __device__ __forceinline__ void load_pair_f32(const fvec2 *__restrict__ f, int64_t vh, int j,
@@ -100,8 +84,7 @@ __device__ __forceinline__ void store_pair_f32(fvec2 *__restrict__ f, int64_t vh
 // loaded before the partials are summed, so that the two memory latencies
 // overlap.
 __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restrict__ r,
-                                                    const h16c *__restrict__ ap,
-                                                    const float *__restrict__ apn,
+                                                    const h16p *__restrict__ ap,
                                                     const double *__restrict__ pap, int nb_pap,
                                                     CgDev cg, Reduce red) {
     const int j = blockIdx.y;
@@ -111,7 +94,7 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
     int64_t pi = (int64_t)blockIdx.x * kBS + threadIdx.x;
     fvec2 q[2][3], rr[2][3];
     if (active && pi < npair) {
-        load_pair(ap, apn, vh, j, 2 * pi, q);
+        load_pair(ap, vh, j, 2 * pi, q);
         load_pair_f32(r, vh, j, 2 * pi, rr);
     }
     __shared__ double pq_s;
@@ -137,7 +120,7 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
             store_pair_f32(r, vh, j, 2 * pi, rr);
             pi += stride;
             if (pi < npair) {
-                load_pair(ap, apn, vh, j, 2 * pi, q);
+                load_pair(ap, vh, j, 2 * pi, q);
                 load_pair_f32(r, vh, j, 2 * pi, rr);
             }
         }
@@ -152,15 +135,14 @@ __global__ __launch_bounds__(kBS) void k_update_r_h(int64_t vh, fvec2 *__restric
 // before the RHS's mode and coefficients are read.
 __global__ __launch_bounds__(kBS) void k_update_xp_h(int64_t vh, fvec2 *__restrict__ x,
                                                      const fvec2 *__restrict__ r,
-                                                     h16c *__restrict__ p, float *__restrict__ pn,
-                                                     CgDev cg) {
+                                                     h16p *__restrict__ p, CgDev cg) {
     const int j = blockIdx.y;
     const int64_t npair = vh / 2;
     const int64_t stride = (int64_t)gridDim.x * kBS;
     int64_t pi = (int64_t)blockIdx.x * kBS + threadIdx.x;
     fvec2 pp[2][3], xx[2][3], rr[2][3];
     if (pi < npair) {
-        load_pair(p, pn, vh, j, 2 * pi, pp);
+        load_pair(p, vh, j, 2 * pi, pp);
         load_pair_f32(x, vh, j, 2 * pi, xx);
         load_pair_f32(r, vh, j, 2 * pi, rr);
     }
@@ -178,10 +160,10 @@ __global__ __launch_bounds__(kBS) void k_update_xp_h(int64_t vh, fvec2 *__restri
                     pp[h][c] = fvec2{fmaf(be, pp[h][c].x, rr[h][c].x), fmaf(be, pp[h][c].y, rr[h][c].y)};
             }
         store_pair_f32(x, vh, j, 2 * pi, xx);
-        if (mode == 2) store_pair(p, pn, vh, j, 2 * pi, pp);
+        if (mode == 2) store_pair(p, vh, j, 2 * pi, pp);
         pi += stride;
         if (pi < npair) {
-            load_pair(p, pn, vh, j, 2 * pi, pp);
+            load_pair(p, vh, j, 2 * pi, pp);
             load_pair_f32(x, vh, j, 2 * pi, xx);
             load_pair_f32(r, vh, j, 2 * pi, rr);
         }
@@ -189,8 +171,7 @@ __global__ __launch_bounds__(kBS) void k_update_xp_h(int64_t vh, fvec2 *__restri
 }
 
 // p = r + beta p (mode 1) or p = r (mode 2) per RHS; mode == null: p = r for all
-__global__ __launch_bounds__(kBS) void k_p_restart_h(int64_t vh, h16c *__restrict__ p,
-                                                     float *__restrict__ pn,
+__global__ __launch_bounds__(kBS) void k_p_restart_h(int64_t vh, h16p *__restrict__ p,
                                                      const fvec2 *__restrict__ r,
                                                      const double *__restrict__ beta,
                                                      const int *__restrict__ mode) {
@@ -201,25 +182,24 @@ __global__ __launch_bounds__(kBS) void k_p_restart_h(int64_t vh, h16c *__restric
     for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
          cb += (int64_t)gridDim.x * kBS) {
         fvec2 pp[3];
-        if (m == 1) load_site(p, pn, vh, j, cb, pp);
+        if (m == 1) load_site(p, vh, j, cb, pp);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const fvec2 rr = r[((int64_t)j * 3 + c) * vh + cb];
             pp[c] = m == 1 ? fvec2{fmaf(be, pp[c].x, rr.x), fmaf(be, pp[c].y, rr.y)} : rr;
         }
-        store_site(p, pn, vh, j, cb, pp);
+        store_site(p, vh, j, cb, pp);
     }
 }
 
 // out = the FP32 value of a 16-bit field
-__global__ __launch_bounds__(kBS) void k_h16_to_f32(int64_t vh, const h16c *__restrict__ h,
-                                                    const float *__restrict__ hn,
+__global__ __launch_bounds__(kBS) void k_h16_to_f32(int64_t vh, const h16p *__restrict__ h,
                                                     fvec2 *__restrict__ out) {
     const int j = blockIdx.y;
     for (int64_t cb = (int64_t)blockIdx.x * kBS + threadIdx.x; cb < vh;
          cb += (int64_t)gridDim.x * kBS) {
         fvec2 v[3];
-        load_site(h, hn, vh, j, cb, v);
+        load_site(h, vh, j, cb, v);
 #pragma unroll
         for (int c = 0; c < 3; ++c) out[((int64_t)j * 3 + c) * vh + cb] = v[c];
     }
@@ -236,41 +216,36 @@ int64_t half_field_bytes(int64_t vh, int nrhs) { return (int64_t)nrhs * vh * (3 
 
 hisq_status half_update_r(int64_t vh, int nrhs, float2 *r, const void *ap, const double *pap,
                           int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s) {
-    const h16c *d = static_cast<const h16c *>(ap);
-    const float *nrm = reinterpret_cast<const float *>(d + (int64_t)nrhs * 3 * vh);
+    const h16p *d = static_cast<const h16p *>(ap);
     ProfileScope prof("blas", s);
     hipLaunchKernelGGL(k_update_r_h, dim3(blas_reduce_blocks(3 * vh), nrhs), dim3(kBS), 0, s, vh,
-                       reinterpret_cast<fvec2 *>(r), d, nrm, pap, nb_pap, cg, red);
+                       reinterpret_cast<fvec2 *>(r), d, pap, nb_pap, cg, red);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
 hisq_status half_update_xp(int64_t vh, int nrhs, float2 *x, const float2 *r, void *p,
                            const CgDev &cg, hipStream_t s) {
-    h16c *d = static_cast<h16c *>(p);
-    float *nrm = reinterpret_cast<float *>(d + (int64_t)nrhs * 3 * vh);
+    h16p *d = static_cast<h16p *>(p);
     ProfileScope prof("blas", s);
     hipLaunchKernelGGL(k_update_xp_h, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh,
-                       reinterpret_cast<fvec2 *>(x), reinterpret_cast<const fvec2 *>(r), d, nrm,
-                       cg);
+                       reinterpret_cast<fvec2 *>(x), reinterpret_cast<const fvec2 *>(r), d, cg);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
 hisq_status half_p_restart(int64_t vh, int nrhs, void *p, const float2 *r, const double *beta,
                            const int *mode, hipStream_t s) {
-    h16c *d = static_cast<h16c *>(p);
-    float *nrm = reinterpret_cast<float *>(d + (int64_t)nrhs * 3 * vh);
-    hipLaunchKernelGGL(k_p_restart_h, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh, d, nrm,
+    h16p *d = static_cast<h16p *>(p);
+    hipLaunchKernelGGL(k_p_restart_h, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh, d,
                        reinterpret_cast<const fvec2 *>(r), beta, mode);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
 }
 
 hisq_status half_to_f32(int64_t vh, int nrhs, const void *h, float2 *out, hipStream_t s) {
-    const h16c *d = static_cast<const h16c *>(h);
-    const float *nrm = reinterpret_cast<const float *>(d + (int64_t)nrhs * 3 * vh);
-    hipLaunchKernelGGL(k_h16_to_f32, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh, d, nrm,
+    const h16p *d = static_cast<const h16p *>(h);
+    hipLaunchKernelGGL(k_h16_to_f32, dim3(site_blocks(vh), nrhs), dim3(kBS), 0, s, vh, d,
                        reinterpret_cast<fvec2 *>(out));
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;

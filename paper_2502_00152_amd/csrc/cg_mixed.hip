@@ -140,7 +140,7 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     // recurrence run on past the delta trigger (until the next poll) can make
     // the FP64 correction diverge on ill-conditioned systems, so the RHS stops
     // at the trigger, as in the paper's reliable update.  FP32 goes on.
-    dev.ru_freeze = bf16_links ? 1 : 0;
+    dev.ru_freeze = g_ru_freeze >= 0 ? (int)g_ru_freeze : (bf16_links ? 1 : 0);
     dev.max_iter = P->max_iter;
 
     const int nb_pap = dslash_reduce_blocks(g, nrhs);
@@ -223,14 +223,28 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     const double tol2 = P->tol * P->tol;
     const double m2 = two_m * two_m;
 
+    // the <p, A p> partials as the r update and the state kernel read them
+    double *pq_sum = nullptr;
+    if (nb_pap >= kPapPresum) {
+        HISQ_TRY(g->ws.get("cg_pq", sizeof(double) * nrhs, &p));
+        pq_sum = static_cast<double *>(p);
+    }
+    struct PapView {
+        const double *p;
+        int nb;
+    };
+    auto pap_view = [&]() { return pq_sum ? PapView{pq_sum, 1} : PapView{pap.partials, nb_pap}; };
+
     auto iterate = [&]() -> hisq_status {
         if (half) {
             HISQ_TRY(launch_dslash_h16(g, 1 - par, ps, t32, nrhs, nullptr, 0.0, 1.0, nullptr, s,
                                        nullptr, dev.status));
             HISQ_TRY(launch_dslash_h16(g, par, t32, Aps, nrhs, ps, m2, -1.0, pap.partials, s,
                                        m2_rhs, dev.status));
-            HISQ_TRY(half_update_r(vh, nrhs, rs, Aps, pap.partials, nb_pap, dev, red, s));
-            HISQ_TRY(cg_finalize(n, nrhs, pap.partials, nb_pap, dev, red, s));
+            const PapView pv = pap_view();
+            if (pq_sum) HISQ_TRY(cg_sum_pap(nrhs, pap.partials, nb_pap, pq_sum, s));
+            HISQ_TRY(half_update_r(vh, nrhs, rs, Aps, pv.p, pv.nb, dev, red, s));
+            HISQ_TRY(cg_finalize(n, nrhs, pv.p, pv.nb, dev, red, s));
             HISQ_TRY(half_update_xp(vh, nrhs, xs, rs, ps, dev, s));
             return HISQ_OK;
         }
@@ -250,8 +264,10 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
             HISQ_TRY(launch_dslash_f32(g, par, t32, Aps, nrhs, ps, m2, nullptr, 0.0, -1.0,
                                        pap.partials, s, m2_rhs, dev.status));
         }
-        HISQ_TRY(cg_update_r(n, nrhs, rs, Aps, pap.partials, nb_pap, dev, red, s));
-        HISQ_TRY(cg_finalize(n, nrhs, pap.partials, nb_pap, dev, red, s));
+        const PapView pv = pap_view();
+        if (pq_sum) HISQ_TRY(cg_sum_pap(nrhs, pap.partials, nb_pap, pq_sum, s));
+        HISQ_TRY(cg_update_r(n, nrhs, rs, Aps, pv.p, pv.nb, dev, red, s));
+        HISQ_TRY(cg_finalize(n, nrhs, pv.p, pv.nb, dev, red, s));
         HISQ_TRY(cg_update_xp(n, nrhs, xs, rs, ps, dev, s));
         return HISQ_OK;
     };

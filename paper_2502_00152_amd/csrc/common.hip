@@ -122,6 +122,9 @@ ProfileSuppress::~ProfileSuppress() { t_prof_suppressed = prev_; }
 
 extern int64_t g_gemm_f32;  // gemm.hip
 
+// "cg_reliable_freeze": -1 automatic, 0 off, 1 on (see ru_freeze in CgDev).
+int64_t g_ru_freeze = -1;
+
 // "cg_graphs": -1 automatic, 0 off, 1 on (never while kernel timing is on:
 // its events would be captured into the graph).
 int64_t g_cg_graphs = -1;
@@ -170,6 +173,12 @@ hisq_status hisq_set_tuning(const char *key, int64_t value) {
         if (value != -1 && value != 0 && value != 1)
             return fail(HISQ_ERR_INVALID_ARG, "gemm_fp32_mfma must be -1, 0 or 1");
         g_gemm_f32 = value;
+        return HISQ_OK;
+    }
+    if (std::string(key) == "cg_reliable_freeze") {
+        if (value != -1 && value != 0 && value != 1)
+            return fail(HISQ_ERR_INVALID_ARG, "cg_reliable_freeze must be -1, 0 or 1");
+        g_ru_freeze = value;
         return HISQ_OK;
     }
     if (std::string(key) == "cg_graphs") {

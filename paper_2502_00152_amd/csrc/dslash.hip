@@ -137,7 +137,9 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
         }
     }
     // the per-lane 32-bit offsets must cover the group: shrink it if not
-    while (!dslash_impl::shape_fits(sh.nr, sh.lps, vh, real_bytes) && (sh.lps > 1 || sh.nr > 1)) {
+    // (one RHS's colour vector at one site: 6 reals, or 16 bytes packed 16-bit)
+    const size_t site_bytes = q16_links && real_bytes == 2 ? 16 : 6 * real_bytes;
+    while (!dslash_impl::shape_fits(sh.nr, sh.lps, vh, site_bytes) && (sh.lps > 1 || sh.nr > 1)) {
         if (sh.lps > 1) sh.lps /= 2;
         else sh.nr = sh.nr == 12 ? 6 : sh.nr == 6 ? 3 : 1;
     }

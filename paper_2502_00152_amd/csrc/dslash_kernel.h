@@ -94,14 +94,43 @@ struct Conv<bf16c> {
     }
 };
 
-// A colour vector field in 16-bit fixed point: each complex as two int16
-// (vec2<short>), and after the [nrhs][3][Vh] entries one float per (RHS, site),
-// [nrhs][Vh]: the largest |component| of the site's three colours.  Value =
-// integer * norm / 32767 (relative accuracy ~3e-5 per site, any magnitude).
+// One complex number in 16-bit fixed point: two int16 (real part first).
 using h16c = vec2<short>;
+// The colour vector of one site and RHS in 16-bit fixed point, packed in 16
+// bytes: the three complex entries as int16 pairs (x, y, z) and the bits of
+// a float norm (w), the largest |component| of the three.  Value = integer *
+// norm / 32767 (relative accuracy ~3e-5 per site, any magnitude).  A field is
+// [nrhs][Vh] of these, so one 16-byte load brings a neighbour's whole colour
+// vector (three 4-byte gathers and a norm gather in a colour-plane layout).
+using h16p = int __attribute__((ext_vector_type(4)));
 template <typename VS>
-constexpr bool is_normed() { return std::is_same<VS, h16c>::value; }
+constexpr bool is_normed() { return std::is_same<VS, h16p>::value; }
+// colour planes per RHS in a field of VS: 3 ([nrhs][3][Vh]) or 1 (packed sites)
+template <typename VS>
+constexpr int planes() { return is_normed<VS>() ? 1 : 3; }
 constexpr float kQ16 = 32767.0f;
+
+// The int16 pair held in a 32-bit word.  The word is taken by value: a
+// __builtin_bit_cast applied directly to a vector element (v.y) reads the
+// vector's element 0 with this compiler.
+__device__ __forceinline__ h16c as_h16c(int w) { return __builtin_bit_cast(h16c, w); }
+
+__device__ __forceinline__ void h16_unpack(h16p v, h16c (&c)[3], float &n) {
+    c[0] = as_h16c(v.x);
+    c[1] = as_h16c(v.y);
+    c[2] = as_h16c(v.z);
+    n = __int_as_float(v.w);
+}
+
+// 16-bit fixed-point links laid out for 16-byte loads (the copy read with
+// 16-bit vectors).  Per direction: entries 0-3 of every site's matrix
+// ([Vhp] x 16 bytes), then entries 4-7 (the same), then entry 8 ([Vhp] x 4
+// bytes), Vhp = Vh rounded up to kLinkTile; one direction takes 9 Vhp words,
+// as the tiled layout does.  A link is three loads (16, 16, 4 bytes per
+// lane), each contiguous over consecutive sites.
+struct q16s {
+    int32_t w;
+};
 // Fixed-point links read with 16-bit vectors: their largest integer
 // component qmax is chosen per gauge field so that a row's integer L1 norm
 // (sum of |Re| + |Im|) times 32767, the largest vector component, stays below
@@ -143,7 +172,7 @@ constexpr int int_lookahead(int nr, int lps) {
 // 16-bit vectors with 16-bit links: the hops run on integer dot products
 template <typename VS, typename LS>
 constexpr bool int_hops() {
-    return std::is_same<VS, h16c>::value && std::is_same<LS, q16c>::value;
+    return std::is_same<VS, h16p>::value && std::is_same<LS, q16s>::value;
 }
 
 // Launch shape of the half stencil: NR RHS per lane, LPS lanes per site, the
@@ -179,9 +208,6 @@ struct DslashArgs {
     VS *out;                 // [nrhs][3][Vh], parity p
     const VS *aux;           // [nrhs][3][Vh], parity p (optional)
     const VS *aux2;          // [nrhs][3][Vh], parity p (optional; may alias out)
-    const float *in_norm;    // per-site norms of in, aux and out (h16c fields only)
-    const float *aux_norm;
-    float *out_norm;
     R ca, cb, cd;
     const double *ca_rhs;  // per-RHS ca (device, indexed by RHS), or null for ca
     const int *rhs_status; // CG state per RHS (device) or null: a block whose RHS
@@ -241,9 +267,12 @@ __device__ __forceinline__ V ldlink(gptr<const V> p) {
 }
 
 // Byte offset of entry 0 of the link of checkerboard site cb within one
-// direction's tiled array (entry k follows at k * kLinkTile entries).
+// direction's tiled array (entry k follows at k * kLinkTile entries); for the
+// q16s layout, the offset of the site's 16 bytes in the first two parts (a
+// quarter of it in the third).
 template <typename V>
 __device__ __forceinline__ uint32_t link_off(int cb) {
+    if constexpr (std::is_same<V, q16s>::value) return (uint32_t)cb * 16u;
     return ((uint32_t)(cb / kLinkTile) * (9 * kLinkTile) + (uint32_t)(cb % kLinkTile)) *
            (uint32_t)sizeof(V);
 }
@@ -282,22 +311,32 @@ struct HopRaw {
     float n[NR];
 };
 
+// The link of one direction (q16s layout, vhp sites per part) at byte offset
+// uoff (link_off), as its nine int16 pairs.
+template <bool NT>
+__device__ __forceinline__ void load_link_q16s(h16c (&u)[9], const q16s *__restrict__ U,
+                                               int64_t vhp, uint32_t uoff) {
+    const h16p a = ldlink<NT>(at(reinterpret_cast<const h16p *>(U), uoff));
+    const h16p b = ldlink<NT>(at(reinterpret_cast<const h16p *>(U + 4 * vhp), uoff));
+    const int32_t c = ldlink<NT>(at(reinterpret_cast<const int32_t *>(U + 8 * vhp), uoff >> 2));
+    u[0] = as_h16c(a.x);
+    u[1] = as_h16c(a.y);
+    u[2] = as_h16c(a.z);
+    u[3] = as_h16c(a.w);
+    u[4] = as_h16c(b.x);
+    u[5] = as_h16c(b.y);
+    u[6] = as_h16c(b.z);
+    u[7] = as_h16c(b.w);
+    u[8] = as_h16c(c);
+}
+
 template <int NR, bool NT>
-__device__ __forceinline__ void hop_load(HopRaw<NR> &d, const q16c *__restrict__ U, int vh,
-                                         uint32_t uoff, const h16c *__restrict__ in,
-                                         uint32_t voff, const uint32_t (&roff)[NR],
-                                         const float *__restrict__ nrm) {
-    const gptr<const q16c> up = at(U, uoff);
+__device__ __forceinline__ void hop_load(HopRaw<NR> &d, const q16s *__restrict__ U, int64_t vhp,
+                                         uint32_t uoff, const h16p *__restrict__ in,
+                                         uint32_t voff, const uint32_t (&roff)[NR]) {
+    load_link_q16s<NT>(d.u, U, vhp, uoff);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d.u[k] = __builtin_bit_cast(h16c, ldlink<NT>(up + k * kLinkTile));
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        d.v[r][0] = *at(in, roff[r] + voff);
-        d.v[r][1] = *at(in + vh, roff[r] + voff);
-        d.v[r][2] = *at(in + 2 * (int64_t)vh, roff[r] + voff);
-        // the norm plane: one float per (RHS, site), RHS offset roff / 3
-        d.n[r] = *at(nrm, roff[r] / 3 + voff);
-    }
+    for (int r = 0; r < NR; ++r) h16_unpack(*at(in, roff[r] + voff), d.v[r], d.n[r]);
 }
 
 template <int NR, bool FWD>
@@ -351,24 +390,24 @@ __device__ __forceinline__ int nbr_cb(const Geom &g, int x, int y, int z, int t,
 // generic path (fat then long; x, y, z, t; forward then backward), with the
 // loads of hop i + LA issued before the arithmetic of hop i.
 template <int NR, int LA, bool NT>
-__device__ __forceinline__ void int_hops_all(const q16c *const (&Uo)[2], const q16c *const (&Ui)[2],
+__device__ __forceinline__ void int_hops_all(const q16s *const (&Uo)[2], const q16s *const (&Ui)[2],
                                              int64_t lstride, const Geom &g, int x, int y, int z,
-                                             int t, uint32_t own_l, const h16c *__restrict__ in,
+                                             int t, uint32_t own_l, const h16p *__restrict__ in,
                                              const uint32_t (&roff)[NR],
-                                             const float *__restrict__ nrm,
                                              vec2<float> (&acc)[NR][3]) {
     HopRaw<NR> buf[LA + 1];
+    const int64_t vhp = lstride / 9;
     auto load = [&](int i, HopRaw<NR> &d) {
         const int h = i >> 3, mu = (i >> 1) & 3;
         const int dist = h == 0 ? 1 : 3;
         if ((i & 1) == 0) {
             const int f = nbr_cb(g, x, y, z, t, mu, dist);
-            hop_load<NR, NT>(d, Uo[h] + mu * lstride, g.vh, own_l, in,
-                             (uint32_t)f * (uint32_t)sizeof(h16c), roff, nrm);
+            hop_load<NR, NT>(d, Uo[h] + mu * lstride, vhp, own_l, in,
+                             (uint32_t)f * (uint32_t)sizeof(h16p), roff);
         } else {
             const int b = nbr_cb(g, x, y, z, t, mu, -dist);
-            hop_load<NR, NT>(d, Ui[h] + mu * lstride, g.vh, link_off<q16c>(b), in,
-                             (uint32_t)b * (uint32_t)sizeof(h16c), roff, nrm);
+            hop_load<NR, NT>(d, Ui[h] + mu * lstride, vhp, link_off<q16s>(b), in,
+                             (uint32_t)b * (uint32_t)sizeof(h16p), roff);
         }
     };
 #pragma unroll
@@ -387,8 +426,7 @@ __device__ __forceinline__ void int_hops_all(const q16c *const (&Uo)[2], const q
 template <int NR, bool NT, typename R, typename VS, typename LS>
 __device__ __forceinline__ void hop_forward(const LS *__restrict__ U, int vh, uint32_t uoff,
                                             const VS *__restrict__ in, uint32_t voff,
-                                            const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3],
-                                            const float *__restrict__ nrm) {
+                                            const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
     using V = vec2<R>;
     V u[9];
     const gptr<const LS> up = at(U, uoff);
@@ -397,16 +435,9 @@ __device__ __forceinline__ void hop_forward(const LS *__restrict__ U, int vh, ui
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         {
-            V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
-            V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
-            V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
-            if constexpr (is_normed<VS>()) {
-                // the norm plane: one float per (RHS, site), RHS offset roff / 3
-                const R sc = (R)(*at(nrm, roff[r] / 3 + voff) * (1.0f / kQ16));
-                v0 *= sc;
-                v1 *= sc;
-                v2 *= sc;
-            }
+            const V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
+            const V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
+            const V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 V s = acc[r][a];
@@ -427,8 +458,7 @@ __device__ __forceinline__ void hop_forward(const LS *__restrict__ U, int vh, ui
 template <int NR, bool NT, typename R, typename VS, typename LS>
 __device__ __forceinline__ void hop_backward(const LS *__restrict__ U, int vh, uint32_t uoff,
                                              const VS *__restrict__ in, uint32_t voff,
-                                             const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3],
-                                             const float *__restrict__ nrm) {
+                                             const uint32_t (&roff)[NR], vec2<R> (&acc)[NR][3]) {
     using V = vec2<R>;
     V u[9];
     const gptr<const LS> up = at(U, uoff);
@@ -437,16 +467,9 @@ __device__ __forceinline__ void hop_backward(const LS *__restrict__ U, int vh, u
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         {
-            V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
-            V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
-            V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
-            if constexpr (is_normed<VS>()) {
-                // the norm plane: one float per (RHS, site), RHS offset roff / 3
-                const R sc = (R)(*at(nrm, roff[r] / 3 + voff) * (1.0f / kQ16));
-                v0 *= sc;
-                v1 *= sc;
-                v2 *= sc;
-            }
+            const V v0 = Conv<VS>::template ld<R>(*at(in, roff[r] + voff));
+            const V v1 = Conv<VS>::template ld<R>(*at(in + vh, roff[r] + voff));
+            const V v2 = Conv<VS>::template ld<R>(*at(in + 2 * (int64_t)vh, roff[r] + voff));
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 // (U^H)_{ab} = conj(U_{ba})
@@ -470,14 +493,12 @@ template <int NR, typename VS, typename LS>
 struct HopRawG {
     LS u[9];
     VS v[NR][3];
-    float n[NR];
 };
 
 template <int NR, bool NT, typename VS, typename LS>
 __device__ __forceinline__ void hop_load_g(HopRawG<NR, VS, LS> &d, const LS *__restrict__ U,
                                            int vh, uint32_t uoff, const VS *__restrict__ in,
-                                           uint32_t voff, const uint32_t (&roff)[NR],
-                                           const float *__restrict__ nrm) {
+                                           uint32_t voff, const uint32_t (&roff)[NR]) {
     const gptr<const LS> up = at(U, uoff);
 #pragma unroll
     for (int k = 0; k < 9; ++k) d.u[k] = ldlink<NT>(up + k * kLinkTile);
@@ -486,7 +507,6 @@ __device__ __forceinline__ void hop_load_g(HopRawG<NR, VS, LS> &d, const LS *__r
         d.v[r][0] = *at(in, roff[r] + voff);
         d.v[r][1] = *at(in + vh, roff[r] + voff);
         d.v[r][2] = *at(in + 2 * (int64_t)vh, roff[r] + voff);
-        if constexpr (is_normed<VS>()) d.n[r] = *at(nrm, roff[r] / 3 + voff);
     }
 }
 
@@ -498,15 +518,9 @@ __device__ __forceinline__ void hop_math_g(const HopRawG<NR, VS, LS> &d, vec2<R>
     for (int k = 0; k < 9; ++k) u[k] = Conv<LS>::template ld<R>(d.u[k]);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        V v0 = Conv<VS>::template ld<R>(d.v[r][0]);
-        V v1 = Conv<VS>::template ld<R>(d.v[r][1]);
-        V v2 = Conv<VS>::template ld<R>(d.v[r][2]);
-        if constexpr (is_normed<VS>()) {
-            const R sc = (R)(d.n[r] * (1.0f / kQ16));
-            v0 *= sc;
-            v1 *= sc;
-            v2 *= sc;
-        }
+        const V v0 = Conv<VS>::template ld<R>(d.v[r][0]);
+        const V v1 = Conv<VS>::template ld<R>(d.v[r][1]);
+        const V v2 = Conv<VS>::template ld<R>(d.v[r][2]);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             V s = acc[r][a];
@@ -537,7 +551,6 @@ __device__ __forceinline__ void gen_hops_all(const LS *const (&Uo)[2], const LS 
                                              int64_t lstride, const Geom &g, int x, int y, int z,
                                              int t, uint32_t own_l, const VS *__restrict__ in,
                                              const uint32_t (&roff)[NR],
-                                             const float *__restrict__ nrm,
                                              vec2<R> (&acc)[NR][3]) {
     HopRawG<NR, VS, LS> buf[LA + 1];
     auto load = [&](int i, HopRawG<NR, VS, LS> &d) {
@@ -546,11 +559,11 @@ __device__ __forceinline__ void gen_hops_all(const LS *const (&Uo)[2], const LS 
         if ((i & 1) == 0) {
             const int f = nbr_cb(g, x, y, z, t, mu, dist);
             hop_load_g<NR, NT>(d, Uo[h] + mu * lstride, g.vh, own_l, in,
-                               (uint32_t)f * (uint32_t)sizeof(VS), roff, nrm);
+                               (uint32_t)f * (uint32_t)sizeof(VS), roff);
         } else {
             const int b = nbr_cb(g, x, y, z, t, mu, -dist);
             hop_load_g<NR, NT>(d, Ui[h] + mu * lstride, g.vh, link_off<LS>(b), in,
-                               (uint32_t)b * (uint32_t)sizeof(VS), roff, nrm);
+                               (uint32_t)b * (uint32_t)sizeof(VS), roff);
         }
     };
 #pragma unroll
@@ -562,6 +575,46 @@ __device__ __forceinline__ void gen_hops_all(const LS *const (&Uo)[2], const LS 
         else hop_math_g<NR, false, R>(buf[i % (LA + 1)], acc);
         hop_fence<NR>(acc);
     }
+}
+
+// Epilogue of one RHS at one site for packed 16-bit vectors: o = cd acc
+// (+ ca aux), rounded to 16 bits against the largest |component| of the
+// three colours, stored with that norm; with DOT, dot += Re<aux, o> of the
+// stored (rounded) o.  aux/out: the RHS's field, off: the site's byte offset.
+template <bool AUX, bool DOT>
+__device__ __forceinline__ void h16_epilogue(const vec2<float> (&acc)[3], float cd, float ca,
+                                             const h16p *aux, h16p *out, uint32_t off,
+                                             double &dot) {
+    vec2<float> o[3], ax[3];
+    if constexpr (AUX) {
+        h16c c[3];
+        float n;
+        h16_unpack(*at(aux, off), c, n);
+        const float sc = n * (1.0f / kQ16);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ax[k] = vec2<float>{(float)c[k].x * sc, (float)c[k].y * sc};
+    }
+    float m = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o[k] = acc[k] * cd;
+        if constexpr (AUX) {
+            o[k].x = fmaf(ca, ax[k].x, o[k].x);
+            o[k].y = fmaf(ca, ax[k].y, o[k].y);
+        }
+        m = fmaxf(m, fmaxf(fabsf(o[k].x), fabsf(o[k].y)));
+    }
+    const float qs = m > 0.0f ? kQ16 / m : 0.0f, ds = m * (1.0f / kQ16);
+    h16c qv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        qv[k] = h16c{(short)rintf(o[k].x * qs), (short)rintf(o[k].y * qs)};
+        if constexpr (AUX && DOT)  // the partial of the stored (rounded) output
+            dot = fma((double)ax[k].x, (double)(qv[k].x * ds),
+                      fma((double)ax[k].y, (double)(qv[k].y * ds), dot));
+    }
+    *at(out, off) = h16p{__builtin_bit_cast(int, qv[0]), __builtin_bit_cast(int, qv[1]),
+                         __builtin_bit_cast(int, qv[2]), __float_as_int(m)};
 }
 
 // Sum of x[0 .. kSites) in the canonical order, by one full wave (result in
@@ -601,7 +654,8 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
     const int rg0 = grp * RG;                 // first RHS of the group
     const int nr = min(NR, a.nrhs - rg0 - q * NR);
     // byte offset of this lane's first RHS plane within the group
-    const uint32_t qoff = (uint32_t)(q * NR * 3) * (uint32_t)vh * (uint32_t)sizeof(VS);
+    constexpr int CP = planes<VS>();
+    const uint32_t qoff = (uint32_t)(q * NR * CP) * (uint32_t)vh * (uint32_t)sizeof(VS);
 
     double dotv[NR];
 #pragma unroll
@@ -635,28 +689,27 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[r][c] = V{R(0), R(0)};
 
-        const VS *in = a.in + (int64_t)rg0 * 3 * vh;
-        const float *nrm_in = is_normed<VS>() ? a.in_norm + (int64_t)rg0 * vh : nullptr;
+        const VS *in = a.in + (int64_t)rg0 * CP * vh;
         uint32_t roff[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            roff[r] = qoff + (uint32_t)(3 * min(r, nr - 1)) * (uint32_t)vh * (uint32_t)sizeof(VS);
+            roff[r] = qoff + (uint32_t)(CP * min(r, nr - 1)) * (uint32_t)vh * (uint32_t)sizeof(VS);
         const int64_t lstride = 9 * kLinkTile * link_tiles(vh);  // one direction
         const uint32_t own = (uint32_t)cb * (uint32_t)sizeof(VS);
         const uint32_t own_l = link_off<LS>(cb);
 
+        static_assert(!is_normed<VS>() || int_hops<VS, LS>(),
+                      "packed 16-bit vectors are read with q16s links only");
         if constexpr (int_hops<VS, LS>()) {
-            const q16c *const Uo[2] = {a.fat_out, a.lng_out};
-            const q16c *const Ui[2] = {a.fat_in, a.lng_in};
+            const q16s *const Uo[2] = {a.fat_out, a.lng_out};
+            const q16s *const Ui[2] = {a.fat_in, a.lng_in};
             int_hops_all<NR, int_lookahead(NR, LPS), NT>(Uo, Ui, lstride, g, x, y, z, t, own_l, in,
-                                                         roff, nrm_in, acc);
-        } else if constexpr (gen_lookahead(NR, LPS, sizeof(R), sizeof(VS), sizeof(LS),
-                                           is_normed<VS>()) > 0) {
+                                                         roff, acc);
+        } else if constexpr (gen_lookahead(NR, LPS, sizeof(R), sizeof(VS), sizeof(LS), false) > 0) {
             const LS *const Uo[2] = {a.fat_out, a.lng_out};
             const LS *const Ui[2] = {a.fat_in, a.lng_in};
-            gen_hops_all<NR,
-                         gen_lookahead(NR, LPS, sizeof(R), sizeof(VS), sizeof(LS), is_normed<VS>()),
-                         NT, R>(Uo, Ui, lstride, g, x, y, z, t, own_l, in, roff, nrm_in, acc);
+            gen_hops_all<NR, gen_lookahead(NR, LPS, sizeof(R), sizeof(VS), sizeof(LS), false), NT,
+                         R>(Uo, Ui, lstride, g, x, y, z, t, own_l, in, roff, acc);
         } else {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -668,71 +721,44 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
                 const int f = (rowYZT * g.X + wrap(x + hop, g.X)) >> 1;
                 const int b = (rowYZT * g.X + wrap(x - hop, g.X)) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
-                hop_backward<NR, NT, R>(Ui, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
+                hop_forward<NR, NT, R>(Uo, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui, vh, link_off<LS>(b), in, bo, roff, acc);
             }
             // mu = 1 (y)
             {
                 const int f = ((((t * g.Z + z) * g.Y + wrap(y + hop, g.Y)) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + z) * g.Y + wrap(y - hop, g.Y)) * g.X) + x) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo + lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
-                hop_backward<NR, NT, R>(Ui + lstride, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
+                hop_forward<NR, NT, R>(Uo + lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui + lstride, vh, link_off<LS>(b), in, bo, roff, acc);
             }
             // mu = 2 (z)
             {
                 const int f = ((((t * g.Z + wrap(z + hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((t * g.Z + wrap(z - hop, g.Z)) * g.Y + y) * g.X) + x) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
-                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
+                hop_forward<NR, NT, R>(Uo + 2 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui + 2 * lstride, vh, link_off<LS>(b), in, bo, roff, acc);
             }
             // mu = 3 (t)
             {
                 const int f = ((((wrap(t + hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
                 const int b = ((((wrap(t - hop, g.T) * g.Z + z) * g.Y + y) * g.X) + x) >> 1;
                 const uint32_t bo = (uint32_t)b * (uint32_t)sizeof(VS);
-                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc, nrm_in);
-                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<LS>(b), in, bo, roff, acc, nrm_in);
+                hop_forward<NR, NT, R>(Uo + 3 * lstride, vh, own_l, in, (uint32_t)f * (uint32_t)sizeof(VS), roff, acc);
+                hop_backward<NR, NT, R>(Ui + 3 * lstride, vh, link_off<LS>(b), in, bo, roff, acc);
             }
         }
         }
 
         // epilogue
         if constexpr (is_normed<VS>()) {
-            // a site's three colours share one norm: form them all, then round
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (r < nr) {
-                    const uint32_t off = qoff + own, noff = qoff / 3 + own;
-                    V o[3], ax[3];
-                    R asc = 0;
-                    if (AUX) asc = (R)(*at(a.aux_norm + (int64_t)(rg0 + r) * vh, noff) * (1.0f / kQ16));
-                    R m = 0;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const int64_t plane = (int64_t)(rg0 * 3 + 3 * r + c) * vh;
-                        o[c] = acc[r][c] * a.cd;
-                        if (AUX) {
-                            ax[c] = Conv<VS>::template ld<R>(*at(a.aux + plane, off)) * asc;
-                            const R ca = a.ca_rhs ? (R)a.ca_rhs[rg0 + q * NR + r] : a.ca;
-                            o[c].x = fma(ca, ax[c].x, o[c].x);
-                            o[c].y = fma(ca, ax[c].y, o[c].y);
-                        }
-                        m = fmax(m, fmax(fabs(o[c].x), fabs(o[c].y)));
-                    }
-                    const R qs = m > 0 ? (R)kQ16 / m : (R)0, ds = m * (R)(1.0f / kQ16);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const int64_t plane = (int64_t)(rg0 * 3 + 3 * r + c) * vh;
-                        const short qx = (short)rintf((float)(o[c].x * qs));
-                        const short qy = (short)rintf((float)(o[c].y * qs));
-                        *at(a.out + plane, off) = VS{qx, qy};
-                        if (AUX && DOT)  // the partial of the stored (rounded) output
-                            dotv[r] = fma((double)ax[c].x, (double)(qx * ds),
-                                          fma((double)ax[c].y, (double)(qy * ds), dotv[r]));
-                    }
-                    *at(a.out_norm + (int64_t)(rg0 + r) * vh, noff) = (float)m;
+                    const R ca = AUX ? (a.ca_rhs ? (R)a.ca_rhs[rg0 + q * NR + r] : a.ca) : R(0);
+                    h16_epilogue<AUX, DOT>(acc[r], a.cd, ca, a.aux + (int64_t)(rg0 + r) * vh,
+                                           a.out + (int64_t)(rg0 + r) * vh, qoff + own, dotv[r]);
                 }
             }
         } else {
@@ -811,9 +837,10 @@ hisq_status launch_shape(const DslashArgs<R, VS, LS> &args, int nblocks, bool au
 }
 
 // True if the per-lane 32-bit byte offsets of the shape fit for this volume
-// (real_bytes: bytes of one stored real, 8, 4 or 2).
-inline bool shape_fits(int nr, int lps, int vh, size_t real_bytes) {
-    const uint64_t span = (uint64_t)(lps * nr * 3) * (uint64_t)vh * 2 * real_bytes;
+// (site_bytes: bytes of one RHS's colour vector at one site: 48 FP64, 24
+// FP32, 12 BF16, 16 packed 16-bit).
+inline bool shape_fits(int nr, int lps, int vh, size_t site_bytes) {
+    const uint64_t span = (uint64_t)(lps * nr) * (uint64_t)vh * site_bytes;
     return span < (1ull << 32);
 }
 
@@ -854,7 +881,7 @@ hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *
     if (aux2 && !aux) return fail(HISQ_ERR_INVALID_ARG, "dslash: aux2 needs aux");
     if (is_normed<VS>() && aux2)
         return fail(HISQ_ERR_INVALID_ARG, "dslash: no second epilogue field for 16-bit vectors");
-    if (!shape_fits(sh.nr, sh.lps, geom.vh, sizeof(VS) / 2))
+    if (!shape_fits(sh.nr, sh.lps, geom.vh, planes<VS>() * sizeof(VS)))
         return fail(HISQ_ERR_INVALID_ARG, "dslash: RHS group too large for this volume");
     DslashArgs<R, VS, LS> a{};
     const int p = out_parity;
@@ -866,12 +893,6 @@ hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *
     a.out = out;
     a.aux = aux;
     a.aux2 = aux2;
-    if (is_normed<VS>()) {  // norm planes follow the nrhs x 3 x Vh entries
-        const int64_t ne = (int64_t)nrhs * 3 * geom.vh;
-        a.in_norm = reinterpret_cast<const float *>(in + ne);
-        a.aux_norm = aux ? reinterpret_cast<const float *>(aux + ne) : nullptr;
-        a.out_norm = reinterpret_cast<float *>(out + ne);
-    }
     a.ca = (R)ca;
     a.cb = (R)cb;
     a.cd = (R)cd;

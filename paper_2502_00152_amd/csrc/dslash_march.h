@@ -42,22 +42,28 @@ struct MarchGeo {
     int nsteps;  // T / 2
 };
 
+// The neighbour vectors of one lattice column slice: the stored values (for
+// packed 16-bit vectors, the three colours and the norm of each RHS).
 template <int NR, typename VS>
 struct RingSlot {
-    VS v[NR][3];
+    using E = typename std::conditional<is_normed<VS>(), h16c, VS>::type;
+    E v[NR][3];
     float n[NR];
 };
 
 template <int NR, typename VS>
 __device__ __forceinline__ void march_load_vec(RingSlot<NR, VS> &d, const VS *__restrict__ in,
-                                               int vh, uint32_t voff, const uint32_t (&roff)[NR],
-                                               const float *__restrict__ nrm) {
+                                               int vh, uint32_t voff,
+                                               const uint32_t (&roff)[NR]) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        d.v[r][0] = *at(in, roff[r] + voff);
-        d.v[r][1] = *at(in + vh, roff[r] + voff);
-        d.v[r][2] = *at(in + 2 * (int64_t)vh, roff[r] + voff);
-        if constexpr (is_normed<VS>()) d.n[r] = *at(nrm, roff[r] / 3 + voff);
+        if constexpr (is_normed<VS>()) {
+            h16_unpack(*at(in, roff[r] + voff), d.v[r], d.n[r]);
+        } else {
+            d.v[r][0] = *at(in, roff[r] + voff);
+            d.v[r][1] = *at(in + vh, roff[r] + voff);
+            d.v[r][2] = *at(in + 2 * (int64_t)vh, roff[r] + voff);
+        }
     }
 }
 
@@ -66,15 +72,19 @@ template <typename R, typename VS, typename LS, int NR>
 struct MarchRaw {
     static constexpr bool kInt = int_hops<VS, LS>();
     using Raw = typename std::conditional<kInt, HopRaw<NR>, HopRawG<NR, VS, LS>>::type;
-    using U = typename std::conditional<kInt, h16c, LS>::type;
 };
 
+// The link at byte offset uoff of one direction (lstride words per direction).
 template <bool NT, typename LS, typename UT>
 __device__ __forceinline__ void march_load_links(UT (&u)[9], const LS *__restrict__ U,
-                                                 uint32_t uoff) {
-    const gptr<const LS> up = at(U, uoff);
+                                                 int64_t lstride, uint32_t uoff) {
+    if constexpr (std::is_same<LS, q16s>::value) {
+        load_link_q16s<NT>(u, U, lstride / 9, uoff);
+    } else {
+        const gptr<const LS> up = at(U, uoff);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = __builtin_bit_cast(UT, ldlink<NT>(up + k * kLinkTile));
+        for (int k = 0; k < 9; ++k) u[k] = ldlink<NT>(up + k * kLinkTile);
+    }
 }
 
 template <typename R, typename VS, typename LS, int NR, bool FWD, typename Raw>
@@ -112,7 +122,8 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash_march(DslashArgs<R, VS, 
     const int j = c * kSites + sl;           // index within a time slice
     const int rg0 = grp * RG;
     const int nr = min(NR, a.nrhs - rg0 - q * NR);
-    const uint32_t qoff = (uint32_t)(q * NR * 3) * (uint32_t)vh * (uint32_t)sizeof(VS);
+    constexpr int CP = planes<VS>();
+    const uint32_t qoff = (uint32_t)(q * NR * CP) * (uint32_t)vh * (uint32_t)sizeof(VS);
     const int cps = mg.S / kSites;  // chunks per slice
 
     if (a.rhs_status) {
@@ -137,12 +148,11 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash_march(DslashArgs<R, VS, 
 
     // the group's first RHS exists (rg0 < nrhs); a lane past the last RHS of
     // a ragged group reads that first RHS's planes and stores nothing
-    const VS *in = a.in + (int64_t)rg0 * 3 * vh;
-    const float *nrm_in = is_normed<VS>() ? a.in_norm + (int64_t)rg0 * vh : nullptr;
+    const VS *in = a.in + (int64_t)rg0 * CP * vh;
     uint32_t roff[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        roff[r] = live ? qoff + (uint32_t)(3 * min(r, nr - 1)) * (uint32_t)vh * (uint32_t)sizeof(VS)
+        roff[r] = live ? qoff + (uint32_t)(CP * min(r, nr - 1)) * (uint32_t)vh * (uint32_t)sizeof(VS)
                        : 0u;
     const int64_t lstride = 9 * kLinkTile * link_tiles(vh);
     const VS *const in_l = in;
@@ -158,9 +168,9 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash_march(DslashArgs<R, VS, 
     RingSlot<NR, VS> ring[4];
     {
         const int t0 = 2 * k0 + s;
-        march_load_vec<NR>(ring[0], in_l, vh, vcol(t0 - 3), roff, nrm_in);
-        march_load_vec<NR>(ring[1], in_l, vh, vcol(t0 - 1), roff, nrm_in);
-        march_load_vec<NR>(ring[2], in_l, vh, vcol(t0 + 1), roff, nrm_in);
+        march_load_vec<NR>(ring[0], in_l, vh, vcol(t0 - 3), roff);
+        march_load_vec<NR>(ring[1], in_l, vh, vcol(t0 - 1), roff);
+        march_load_vec<NR>(ring[2], in_l, vh, vcol(t0 + 1), roff);
     }
 
     const LS *const Uo[2] = {a.fat_out, a.lng_out};
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash_march(DslashArgs<R, VS, 
 
     for (int k = k0; k < k1; ++k) {
         const int t = 2 * k + s;
-        march_load_vec<NR>(ring[3], in_l, vh, vcol(t + 3), roff, nrm_in);
+        march_load_vec<NR>(ring[3], in_l, vh, vcol(t + 3), roff);
         const int cb = slice(t) * mg.S + j;
         const uint32_t own_l = link_off<LS>(cb);
 
@@ -187,26 +197,26 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash_march(DslashArgs<R, VS, 
             const bool fwd = (i & 1) == 0;
             if (mu == 3) {
                 const int b = slice(t - dist) * mg.S + j;
-                if (fwd) march_load_links<NT, LS>(d.u, Uo[h] + mu * lstride, own_l);
-                else march_load_links<NT, LS>(d.u, Ui[h] + mu * lstride, link_off<LS>(b));
+                if (fwd) march_load_links<NT, LS>(d.u, Uo[h] + mu * lstride, lstride, own_l);
+                else march_load_links<NT, LS>(d.u, Ui[h] + mu * lstride, lstride, link_off<LS>(b));
                 const RingSlot<NR, VS> &rs = ring[fwd ? (h == 0 ? 2 : 3) : (h == 0 ? 1 : 0)];
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) d.v[r][cc] = rs.v[r][cc];
-                    d.n[r] = rs.n[r];
+                    if constexpr (is_normed<VS>()) d.n[r] = rs.n[r];
                 }
             } else {
                 const int nb = nbr_cb(g, x, y, z, slice(t), mu, fwd ? dist : -dist);
-                if (fwd) march_load_links<NT, LS>(d.u, Uo[h] + mu * lstride, own_l);
-                else march_load_links<NT, LS>(d.u, Ui[h] + mu * lstride, link_off<LS>(nb));
+                if (fwd) march_load_links<NT, LS>(d.u, Uo[h] + mu * lstride, lstride, own_l);
+                else march_load_links<NT, LS>(d.u, Ui[h] + mu * lstride, lstride, link_off<LS>(nb));
                 RingSlot<NR, VS> tmp;
-                march_load_vec<NR>(tmp, in_l, vh, (uint32_t)nb * (uint32_t)sizeof(VS), roff, nrm_in);
+                march_load_vec<NR>(tmp, in_l, vh, (uint32_t)nb * (uint32_t)sizeof(VS), roff);
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) d.v[r][cc] = tmp.v[r][cc];
-                    d.n[r] = tmp.n[r];
+                    if constexpr (is_normed<VS>()) d.n[r] = tmp.n[r];
                 }
             }
         };
@@ -234,36 +244,9 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash_march(DslashArgs<R, VS, 
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     if (r < nr) {
-                        const uint32_t off = qoff + own, noff = qoff / 3 + own;
-                        V o[3], ax[3];
-                        R asc = 0;
-                        if (AUX)
-                            asc = (R)(*at(a.aux_norm + (int64_t)(rg0 + r) * vh, noff) * (1.0f / kQ16));
-                        R m = 0;
-#pragma unroll
-                        for (int cc = 0; cc < 3; ++cc) {
-                            const int64_t plane = (int64_t)(rg0 * 3 + 3 * r + cc) * vh;
-                            o[cc] = acc[r][cc] * a.cd;
-                            if (AUX) {
-                                ax[cc] = Conv<VS>::template ld<R>(*at(a.aux + plane, off)) * asc;
-                                const R ca = a.ca_rhs ? (R)a.ca_rhs[rg0 + q * NR + r] : a.ca;
-                                o[cc].x = fma(ca, ax[cc].x, o[cc].x);
-                                o[cc].y = fma(ca, ax[cc].y, o[cc].y);
-                            }
-                            m = fmax(m, fmax(fabs(o[cc].x), fabs(o[cc].y)));
-                        }
-                        const R qs = m > 0 ? (R)kQ16 / m : (R)0, ds = m * (R)(1.0f / kQ16);
-#pragma unroll
-                        for (int cc = 0; cc < 3; ++cc) {
-                            const int64_t plane = (int64_t)(rg0 * 3 + 3 * r + cc) * vh;
-                            const short qx = (short)rintf((float)(o[cc].x * qs));
-                            const short qy = (short)rintf((float)(o[cc].y * qs));
-                            *at(a.out + plane, off) = VS{qx, qy};
-                            if (AUX && DOT)
-                                dotv[r] = fma((double)ax[cc].x, (double)(qx * ds),
-                                              fma((double)ax[cc].y, (double)(qy * ds), dotv[r]));
-                        }
-                        *at(a.out_norm + (int64_t)(rg0 + r) * vh, noff) = (float)m;
+                        const R ca = AUX ? (a.ca_rhs ? (R)a.ca_rhs[rg0 + q * NR + r] : a.ca) : R(0);
+                        h16_epilogue<AUX, DOT>(acc[r], a.cd, ca, a.aux + (int64_t)(rg0 + r) * vh,
+                                               a.out + (int64_t)(rg0 + r) * vh, qoff + own, dotv[r]);
                     }
                 }
             } else {

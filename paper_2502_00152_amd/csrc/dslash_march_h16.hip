@@ -3,7 +3,8 @@
 
 namespace hisq {
 namespace dslash_impl {
-template hisq_status launch_march<float, h16c, q16c>(const DslashArgs<float, h16c, q16c> &, const DslashShape &, bool, bool,
-                                      bool, hipStream_t);
+template hisq_status launch_march<float, h16p, q16s>(const DslashArgs<float, h16p, q16s> &,
+                                                     const DslashShape &, bool, bool, bool,
+                                                     hipStream_t);
 }  // namespace dslash_impl
 }  // namespace hisq

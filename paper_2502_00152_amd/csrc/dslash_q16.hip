@@ -76,12 +76,26 @@ __device__ __forceinline__ uint32_t q16_of(double x, double inv_step, int qmax) 
     return (uint32_t)c & 0xffffu;
 }
 
+// Entry i of the tiled layout [4 mu][tile][9 k][kLinkTile] rounded to 16
+// bits; split: stored at its place in the q16s layout instead (per direction
+// entries 0-3 of each site, then 4-7, then 8; vhp = tiles * kLinkTile sites).
 __global__ __launch_bounds__(kBS) void k_links_to_q16(const double2 *__restrict__ src,
                                                       q16c *__restrict__ dst, int64_t n,
-                                                      double inv_step, int qmax) {
+                                                      double inv_step, int qmax, bool split,
+                                                      int64_t tiles) {
+    const int64_t vhp = tiles * kLinkTile;
     for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
         const double2 v = src[i];
-        dst[i] = (q16c)(q16_of(v.x, inv_step, qmax) | (q16_of(v.y, inv_step, qmax) << 16));
+        int64_t o = i;
+        if (split) {
+            const int64_t lane = i % kLinkTile, r = i / kLinkTile;
+            const int k = (int)(r % 9);
+            const int64_t rt = r / 9, tile = rt % tiles, mu = rt / tiles;
+            const int64_t cb = tile * kLinkTile + lane;
+            const int part = k < 4 ? 0 : (k < 8 ? 1 : 2);
+            o = mu * 9 * vhp + part * 4 * vhp + (part < 2 ? cb * 4 + (k - 4 * part) : cb);
+        }
+        dst[o] = (q16c)(q16_of(v.x, inv_step, qmax) | (q16_of(v.y, inv_step, qmax) << 16));
     }
 }
 
@@ -133,9 +147,10 @@ hisq_status link_rowl1max(hisq_gauge_s *g, hipStream_t s, double *out) {
     return HISQ_OK;
 }
 
-// fixed-point copies of both link fields, components in [-qmax, qmax]
-hisq_status make_q16_links(hisq_gauge_s *g, int qmax, int32_t *(&fat)[2], int32_t *(&lng)[2],
-                           double *step_out, hipStream_t s) {
+// fixed-point copies of both link fields, components in [-qmax, qmax], in
+// the tiled layout or (split) the q16s layout
+hisq_status make_q16_links(hisq_gauge_s *g, int qmax, bool split, int32_t *(&fat)[2],
+                           int32_t *(&lng)[2], double *step_out, hipStream_t s) {
     double mx = 0.0;
     HISQ_TRY(link_absmax(g, s, &mx));
     const int64_t n = link_array_entries(g->geom.vh);
@@ -148,9 +163,9 @@ hisq_status make_q16_links(hisq_gauge_s *g, int qmax, int32_t *(&fat)[2], int32_
     const int nc = (int)std::min<int64_t>((n + kBS - 1) / kBS, 8192);
     for (int q = 0; q < 2; ++q) {
         hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->fat[q], fat[q], n,
-                           1.0 / step, qmax);
+                           1.0 / step, qmax, split, link_tiles(g->geom.vh));
         hipLaunchKernelGGL(k_links_to_q16, dim3(nc), dim3(kBS), 0, s, g->lng[q], lng[q], n,
-                           1.0 / step, qmax);
+                           1.0 / step, qmax, split, link_tiles(g->geom.vh));
     }
     HISQ_HIP(hipGetLastError());
     *step_out = step;
@@ -161,7 +176,7 @@ hisq_status make_q16_links(hisq_gauge_s *g, int qmax, int32_t *(&fat)[2], int32_
 
 hisq_status ensure_links_q16(hisq_gauge_s *g, hipStream_t s) {
     if (g->fatq[0]) return HISQ_OK;
-    return make_q16_links(g, 32767, g->fatq, g->lngq, &g->q16_step, s);
+    return make_q16_links(g, 32767, false, g->fatq, g->lngq, &g->q16_step, s);
 }
 
 // The copy read by the stencil on 16-bit vectors, whose integer dot products
@@ -183,7 +198,7 @@ hisq_status ensure_links_q16n(hisq_gauge_s *g, hipStream_t s) {
     HISQ_TRY(link_absmax(g, s, &mx));
     HISQ_TRY(link_rowl1max(g, s, &rl1));
     g->qn_max = q16n_qmax(mx, rl1);
-    return make_q16_links(g, g->qn_max, g->fatn, g->lngn, &g->qn_step, s);
+    return make_q16_links(g, g->qn_max, true, g->fatn, g->lngn, &g->qn_step, s);
 }
 
 hisq_status launch_dslash_f32_q16(hisq_gauge_s *g, int out_parity, const float2 *in, float2 *out,
@@ -216,7 +231,7 @@ hisq_status apply_mdagm_q16(hisq_gauge_s *g, double two_m, const float2 *in, flo
 
 namespace hisq {
 
-// 16-bit vectors (h16c fields with per-site norms) and 16-bit links: the
+// 16-bit vectors (packed h16p fields) and 16-bit links (q16s layout): the
 // sloppy operator at sloppy_prec = HISQ_HALF.  The kernel sums the integer
 // products of a link row and a colour vector exactly in 32 bits and scales by
 // the neighbour's norm; the link step and 1/32767 of the vectors fold into cd.
@@ -224,14 +239,16 @@ hisq_status launch_dslash_h16(hisq_gauge_s *g, int out_parity, const void *in, v
                               int nrhs, const void *aux, double ca, double cd, double *partials,
                               hipStream_t s, const double *ca_rhs, const int *rhs_status) {
     HISQ_TRY(ensure_links_q16n(g, s));
-    const q16c *fat[2] = {g->fatn[0], g->fatn[1]};
-    const q16c *lng[2] = {g->lngn[0], g->lngn[1]};
+    const q16s *fat[2] = {reinterpret_cast<const q16s *>(g->fatn[0]),
+                          reinterpret_cast<const q16s *>(g->fatn[1])};
+    const q16s *lng[2] = {reinterpret_cast<const q16s *>(g->lngn[0]),
+                          reinterpret_cast<const q16s *>(g->lngn[1])};
     const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, true, g->geom);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux ? "dslash_h16_aux" : "dslash_h16", s);
-    return dslash_impl::launch_dslash_t<float, h16c, q16c>(
-        g->geom, fat, lng, out_parity, static_cast<const h16c *>(in), static_cast<h16c *>(out),
-        nrhs, static_cast<const h16c *>(aux), ca, nullptr, 0.0, cd * g->qn_step / kQ16, partials,
+    return dslash_impl::launch_dslash_t<float, h16p, q16s>(
+        g->geom, fat, lng, out_parity, static_cast<const h16p *>(in), static_cast<h16p *>(out),
+        nrhs, static_cast<const h16p *>(aux), ca, nullptr, 0.0, cd * g->qn_step / kQ16, partials,
         sh, s, ca_rhs, rhs_status);
 }
 

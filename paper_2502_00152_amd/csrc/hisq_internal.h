@@ -95,7 +95,8 @@ struct hisq_gauge_s {
     double q16_step = 0.0;                   //   value = integer * q16_step
     int32_t *fatn[2] = {nullptr, nullptr};   // the same with components in
     int32_t *lngn[2] = {nullptr, nullptr};   //   [-qn_max, qn_max] (integer-dot
-    double qn_step = 0.0;                    //   stencil), value = integer * qn_step
+    double qn_step = 0.0;                    //   stencil; q16s layout of
+                                             //   dslash_kernel.h), value = integer * qn_step
     int qn_max = 0;                          //   largest integer component of that copy
     double link_absmax = -1.0;               // largest |component| of fat and long
     hipStream_t cg_stream = nullptr;        // the solvers' own stream (capturable)
@@ -165,6 +166,9 @@ struct CgDev {
 
 // Per-block partial sums of a reduction, [nvals][nblocks]; every launch writes
 // all of its entries before a later kernel adds them in block order.
+// hisq_set_tuning "cg_reliable_freeze" (-1 automatic, 0, 1)
+extern int64_t g_ru_freeze;
+
 struct Reduce {
     double *partials;
 };
@@ -203,6 +207,13 @@ hisq_status cg_init(int64_t n, int nrhs, const double2 *b, const double2 *Ax, do
 // cg_update_xp then does x += alpha p and p = r + beta p (old p in both).
 hisq_status cg_update_r(int64_t n, int nrhs, double2 *r, const double2 *Ap, const double *pap,
                         int nb_pap, const CgDev &cg, const Reduce &red, hipStream_t s);
+// From kPapPresum stencil blocks per RHS up, the CG sums the <p, A p>
+// partials once per iteration (cg_sum_pap: pq[j], a block per RHS, in one
+// fixed order) and the r update and the state kernel read that one value per
+// RHS, instead of every r-update block re-reading all partials (at 48^3 x 96,
+// 20736 per RHS); below it they sum the partials themselves.
+constexpr int kPapPresum = 1024;
+hisq_status cg_sum_pap(int nrhs, const double *pap, int nb_pap, double *pq, hipStream_t s);
 hisq_status cg_finalize(int64_t n, int nrhs, const double *pap, int nb_pap, const CgDev &cg,
                         const Reduce &red, hipStream_t s);
 hisq_status cg_update_xp(int64_t n, int nrhs, double2 *x, const double2 *r, double2 *p,
