@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S]
                     [--no-cpu-baseline] [--no-secondary] [--no-uneven]
-                    [--no-dslash-scan] [--pmc-probe 48|16]
+                    [--no-dslash-scan] [--no-ru-variants] [--pmc-probe 48|16]
 
 Headline workload (the learned-guess configuration, synthetic): one GPU's
 share of a large lattice, 48^3 x 96, random SU(3) fat and long links (eps 0.5,
@@ -28,7 +28,10 @@ all are timed and reported.  value = solves per second = 12 K / (K steps).
 Also reported: the same step without the learned guess; the same sources in
 FP64 throughout (FP64 eigenvectors, single deflation, FP64 CG) and each mixed
 solution's difference from it; the oracle-evaluated FP64 residual of two
-sources; plain FP64 even-odd CG (no deflation, one source); the live roofline
+sources; the solve with the reliable update taken at three points (stopped
+at the delta_rd trigger until the next host poll, run on to the poll, a poll
+after every iteration); plain FP64 even-odd CG (no deflation, one source);
+the live roofline
 of the CG's 16-bit half stencil (HIP events inside the timed region); the
 oracle timed on the host cores; and secondary legs: the 16^3 x 32 deflated
 workload, the uneven batch (four lattices x three masses) and a half-stencil
@@ -395,6 +398,34 @@ def headline(args, out):
         f"{np.mean(rn.iterations):.1f} (with: {np.mean(last.iterations):.1f})")
     net.close()
 
+    # when the reliable update is taken (paper section 3: at the delta_rd
+    # trigger): the RHS stops at its trigger until the next host poll (the
+    # default for 16-bit vectors), goes on iterating until the poll, or the
+    # host polls after every iteration
+    ru_variants = {}
+    if not args.no_ru_variants:
+        for name, freeze, interval in (("stop_at_trigger_poll_16", 1, 16),
+                                       ("run_on_to_poll_16", 0, 16),
+                                       ("poll_every_iteration", 0, 1)):
+            hisq.hisq_set_tuning("cg_reliable_freeze", freeze)
+            try:
+                hisq.hisq_prepare_source(g, two_m, ee, eo, y)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                hisq.hisq_deflate(g, ev32, eps, two_m, y, x)
+                rv = hisq.hisq_cg_solve(g, two_m, y, x, tol=tol, check_interval=interval, **kw)
+                hisq.hisq_reconstruct_odd(g, two_m, x, eo, po)
+                torch.cuda.synchronize()
+                tv = time.perf_counter() - t0
+            finally:
+                hisq.hisq_set_tuning("cg_reliable_freeze", -1)
+            ru_variants[name] = {"solves_per_s": nrhs / tv,
+                                 "mean_iterations": float(np.mean(rv.iterations)),
+                                 "mean_reliable_updates": float(np.mean(rv.reliable_updates)),
+                                 "max_true_residual": max(rv.true_residual)}
+            say(f"reliable updates, {name}: {nrhs / tv:.2f} solves/s, mean iterations "
+                f"{np.mean(rv.iterations):.1f}, {np.mean(rv.reliable_updates):.1f} updates")
+
     # FP64 throughout (FP64 eigenvectors, single deflation, FP64 CG), once
     hisq.hisq_prepare_source(g, two_m, ee, eo, y)
     x64 = torch.empty_like(y)
@@ -489,6 +520,7 @@ def headline(args, out):
         "max_true_residual": max(max(r.true_residual) for r in results),
         "per_solve_error": per_solve,
         "learned_guess": dict(learn, kept=list(kept), without_guess=without),
+        "reliable_update_timing": ru_variants,
         "deflated_fp64_cg": fp64,
         "plain_fp64_cg": plain,
         "speedup_vs_plain_fp64_cg": value / plain["solves_per_s"],
@@ -588,24 +620,33 @@ def uneven_leg():
         del Wd, Nd
         lat.append(dict(dims=dims, g=g, b=torch.cat(bs), masses=np.repeat(B["masses"], nrhs)))
     out = {}
-    for name, sp in (("fp64", hisq.HISQ_FP64), ("half", hisq.HISQ_HALF)):
-        systems = [(d["g"], d["masses"], d["b"], torch.zeros_like(d["b"])) for d in lat]
-        hisq.hisq_cg_solve_multi(systems, tol=B["tol"], sloppy_prec=sp)  # warm
-        systems = [(d["g"], d["masses"], d["b"], torch.zeros_like(d["b"])) for d in lat]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = hisq.hisq_cg_solve_multi(systems, tol=B["tol"], sloppy_prec=sp)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        n = sum(d["b"].shape[0] for d in lat)
-        out[name] = {"solves_per_s": n / dt, "solves": n, "seconds": dt,
-                     "max_iterations_per_system": [max(r.iterations) for r in res]}
-        out[name]["max_true_residual_per_system"] = [max(r.true_residual) for r in res]
-        out[name]["all_converged"] = all(all(r.converged) for r in res)
+    # one stream per system, or every chunk of iterations of the four systems
+    # as one captured graph (bitwise the same solutions)
+    for mode, tag in ((0, ""), (1, "_one_graph")):
+        hisq.hisq_set_tuning("cg_multi_graph", mode)
+        try:
+            for name, sp in (("fp64", hisq.HISQ_FP64), ("half", hisq.HISQ_HALF)):
+                systems = [(d["g"], d["masses"], d["b"], torch.zeros_like(d["b"])) for d in lat]
+                hisq.hisq_cg_solve_multi(systems, tol=B["tol"], sloppy_prec=sp)  # warm
+                systems = [(d["g"], d["masses"], d["b"], torch.zeros_like(d["b"])) for d in lat]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = hisq.hisq_cg_solve_multi(systems, tol=B["tol"], sloppy_prec=sp)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                n = sum(d["b"].shape[0] for d in lat)
+                o = {"solves_per_s": n / dt, "solves": n, "seconds": dt,
+                     "max_iterations_per_system": [max(r.iterations) for r in res],
+                     "max_true_residual_per_system": [max(r.true_residual) for r in res],
+                     "all_converged": all(all(r.converged) for r in res)}
+                out[name + tag] = o
+        finally:
+            hisq.hisq_set_tuning("cg_multi_graph", -1)
     for d in lat:
         d["g"].close()
     say(f"uneven batch: {out['half']['solves_per_s']:.0f} solves/s (16-bit sloppy), "
-        f"{out['fp64']['solves_per_s']:.0f} (FP64)")
+        f"{out['fp64']['solves_per_s']:.0f} (FP64); one graph per chunk: "
+        f"{out['half_one_graph']['solves_per_s']:.0f}, {out['fp64_one_graph']['solves_per_s']:.0f}")
     return out
 
 
@@ -698,6 +739,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-dslash-scan", action="store_true")
+    ap.add_argument("--no-ru-variants", action="store_true",
+                    help="skip the reliable-update timing variants of the headline solve")
     ap.add_argument("--pmc-probe", choices=("48", "16"))
     args = ap.parse_args()
     if args.gpus != 1:

@@ -471,9 +471,13 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            stencil calls return INVALID_ARG)
  *   "dslash_group_order"     -1: automatic; 0: RHS groups of one site block run
  *                            next to each other; 1: all sites of one group first
- *   "dslash_xcd_remap"       -1: automatic; 1: give each XCD a contiguous range
- *                            of sites; 0: off; n >= 2: deal chunks of n site
- *                            blocks (x RHS groups) round-robin to the XCDs
+ *   "dslash_xcd_remap"       -1: automatic (3 or more RHS above 2^18 sites
+ *                            per parity: chunks of an eighth of a time slice;
+ *                            otherwise contiguous ranges, or dispatch order
+ *                            for 1-2 RHS in FP32); 1: give each XCD a
+ *                            contiguous range of sites; 0: dispatch order;
+ *                            n >= 2: deal chunks of n launched blocks (site
+ *                            blocks x RHS groups) round-robin to the XCDs
  *   "dslash_march"           -1: automatic (off); 0: off; n > 0: for two or
  *                            more RHS when X Y Z / 2 is a multiple of 256, the
  *                            kernel that marches along time with n time
@@ -490,11 +494,18 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            would be bound by the FP64 matrix rate (4 k n /
  *                            (4 k + 8 n) > 10 flop/B, e.g. 256 vectors x 24 RHS).
  *                            This knob changes results at the FP32 rounding level.
- *   "cg_reliable_freeze"     mixed CG: -1 automatic; 1: a right-hand side whose
- *                            iterated residual has fallen by reliable_delta
- *                            stops iterating until its reliable update at the
- *                            next host poll; 0: it iterates on until then.
- *                            Changes iterates and iteration counts.
+ *   "cg_reliable_freeze"     mixed CG: -1 automatic (on for sloppy_prec
+ *                            HISQ_BF16 only); 1: a right-hand side
+ *                            whose iterated residual has fallen by
+ *                            reliable_delta stops iterating until its
+ *                            reliable update at the next host poll; 0: it
+ *                            iterates on until then.  Changes iterates and
+ *                            iteration counts.
+ *   "cg_multi_graph"         -1 automatic (off), 0 off, 1: hisq_cg_solve_multi
+ *                            launches each chunk of iterations of all systems
+ *                            (on distinct gauge handles) as one captured HIP
+ *                            graph, the systems' kernels on parallel branches
+ *                            (bitwise the same results as separate streams)
  *   "cg_graphs"              -1 automatic (off), 0 off, 1: replay the CG's
  *                            chunks of iterations from a captured HIP graph
  *                            (measured: no gain on MI355X, kept as an option)

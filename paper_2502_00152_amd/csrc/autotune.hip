@@ -104,7 +104,11 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
             if (!dslash_impl::shape_fits(nr, lps, vh, 6 * rb)) continue;
             const int ngroups = (nrhs + nr * lps - 1) / (nr * lps);
             for (int order = 0; order < (ngroups > 1 ? 2 : 1); ++order) {
-                for (int xcd = 0; xcd < 2; ++xcd) {
+                // dispatch order, contiguous ranges, or chunks of an eighth
+                // of a time slice per XCD
+                const int chunk = xcd_chunk_blocks(g->geom, ngroups);
+                for (int xi = 0; xi < 3; ++xi) {
+                    const int xcd = xi < 2 ? xi : chunk;
                     HISQ_TRY(dslash_set_tuning("dslash_rhs_per_thread", nr));
                     HISQ_TRY(dslash_set_tuning("dslash_lanes_per_site", lps));
                     HISQ_TRY(dslash_set_tuning("dslash_group_order", order));

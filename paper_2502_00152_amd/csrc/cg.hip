@@ -227,6 +227,10 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
     int64_t enqueued = 0;
     const bool graphs = cg_use_graphs(g, nrhs);
     GraphChunk chunk;
+    const std::function<hisq_status()> chunk_body = [&]() -> hisq_status {
+        for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+        return HISQ_OK;
+    };
     for (;;) {
         if (count(CG_PENDING) > 0) {
             // A x for the groups holding a pending RHS only
@@ -241,13 +245,14 @@ extern "C" hisq_status hisq_cg_solve(hisq_gauge g, double two_m, const void *b_e
         }
         if (count(CG_ACTIVE) + count(CG_RESTART) == 0) break;
         if (params->max_iter == 0 || enqueued >= cap) break;
-        if (graphs) {
-            HISQ_TRY(chunk.run(s, [&]() -> hisq_status {
-                for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
-                return HISQ_OK;
-            }));
+        if (t_chunk_group && enqueued > 0) {
+            // with the other systems' chunks in one graph (the first chunk runs
+            // eagerly, so that lazily made copies exist before any capture)
+            HISQ_TRY(t_chunk_group->run(s, t_chunk_sys, chunk_body));
+        } else if (graphs) {
+            HISQ_TRY(chunk.run(s, chunk_body));
         } else {
-            for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+            HISQ_TRY(chunk_body());
         }
         enqueued += interval;
         HISQ_TRY(fetch_state());

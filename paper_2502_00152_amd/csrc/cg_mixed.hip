@@ -139,7 +139,13 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     // With BF16 links the sloppy operator is accurate to ~1e-3 only: a
     // recurrence run on past the delta trigger (until the next poll) can make
     // the FP64 correction diverge on ill-conditioned systems, so the RHS stops
-    // at the trigger, as in the paper's reliable update.  FP32 goes on.
+    // at the trigger, as in the paper's reliable update.  FP32 and 16-bit
+    // vectors go on: stopping lets the RHS of a batch trigger in separate
+    // rounds of FP64 updates (measured on the 48^3 x 96 deflated solve, 12
+    // RHS: 3.29 solves/s running on against 2.92 stopped, 566 and 571
+    // iterations), though an undeflated ill-conditioned solve gains from it
+    // (32^3 x 64, 2m = 0.005, 16-bit vectors: 1204 iterations stopped against
+    // 1475, 1.69 against 2.18 s); "cg_reliable_freeze" chooses.
     dev.ru_freeze = g_ru_freeze >= 0 ? (int)g_ru_freeze : (bf16_links ? 1 : 0);
     dev.max_iter = P->max_iter;
 
@@ -292,6 +298,10 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
     int64_t enqueued = 0;
     const bool graphs = cg_use_graphs(g, nrhs);
     GraphChunk chunk;
+    const std::function<hisq_status()> chunk_body = [&]() -> hisq_status {
+        for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+        return HISQ_OK;
+    };
     // Right after a reliable update no iteration has run since the host wrote
     // the state back, so the host mirror is current and the poll is skipped.
     bool mirror_current = false;
@@ -315,13 +325,14 @@ hisq_status solve_mixed(hisq_gauge_s *g, double two_m, const double2 *b, double2
         }
         if (nru == 0) {
             if (nactive == 0 || P->max_iter == 0 || enqueued >= cap) break;
-            if (graphs) {
-                HISQ_TRY(chunk.run(s, [&]() -> hisq_status {
-                    for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
-                    return HISQ_OK;
-                }));
+            if (t_chunk_group && enqueued > 0) {
+                // with the other systems' chunks in one graph (the first chunk
+                // runs eagerly, so that lazily made copies exist before any capture)
+                HISQ_TRY(t_chunk_group->run(s, t_chunk_sys, chunk_body));
+            } else if (graphs) {
+                HISQ_TRY(chunk.run(s, chunk_body));
             } else {
-                for (int k = 0; k < interval; ++k) HISQ_TRY(iterate());
+                HISQ_TRY(chunk_body());
             }
             enqueued += interval;
             continue;

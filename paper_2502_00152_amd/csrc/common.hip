@@ -1,6 +1,8 @@
 // Error reporting, device scratch and launch timing for libhisq.
 #include <mutex>
 
+#include <algorithm>
+
 #include "hisq_internal.h"
 
 namespace hisq {
@@ -67,6 +69,105 @@ GraphChunk::~GraphChunk() {
     if (graph_) (void)hipGraphDestroy(graph_);
 }
 
+// ------------------------------------------------------ combined chunks
+thread_local ChunkGroup *t_chunk_group = nullptr;
+thread_local int t_chunk_sys = -1;
+
+ChunkGroup::~ChunkGroup() {
+    if (exec_) (void)hipGraphExecDestroy(exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+    if (origin_) (void)hipStreamDestroy(origin_);
+}
+
+hisq_status ChunkGroup::run(hipStream_t s, int sys, const std::function<hisq_status()> &body) {
+    std::unique_lock<std::mutex> lk(mu_);
+    if (round_status_ != HISQ_OK) return fail(round_status_, round_error_);
+    const uint64_t mine = round_;
+    pending_.push_back(Pending{s, sys, &body});
+    if ((int)pending_.size() == active_) launch_locked();
+    else cv_.wait(lk, [&] { return round_ != mine; });
+    if (round_status_ != HISQ_OK) return fail(round_status_, round_error_);
+    return HISQ_OK;
+}
+
+void ChunkGroup::leave() {
+    std::lock_guard<std::mutex> lk(mu_);
+    --active_;
+    if (active_ > 0 && (int)pending_.size() == active_) launch_locked();
+}
+
+// Capture the pending chunks into graph_/exec_ (members in system order).
+hisq_status ChunkGroup::capture_locked() {
+    if (exec_) (void)hipGraphExecDestroy(exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    exec_ = nullptr;
+    graph_ = nullptr;
+    const size_t n = pending_.size();
+    while (events_.size() < n + 1) {
+        hipEvent_t e = nullptr;
+        HISQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        events_.push_back(e);
+    }
+    HISQ_HIP(hipStreamBeginCapture(origin_, hipStreamCaptureModeRelaxed));
+    hisq_status st = HISQ_OK;
+    hipError_t e = hipEventRecord(events_[n], origin_);  // the fork
+    for (size_t i = 0; i < n && e == hipSuccess && st == HISQ_OK; ++i) {
+        e = hipStreamWaitEvent(pending_[i].s, events_[n], 0);
+        if (e != hipSuccess) break;
+        st = (*pending_[i].body)();
+        if (st != HISQ_OK) break;
+        e = hipEventRecord(events_[i], pending_[i].s);  // the join
+        if (e == hipSuccess) e = hipStreamWaitEvent(origin_, events_[i], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(origin_, &graph);
+    if (st != HISQ_OK || e != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st != HISQ_OK) return st;
+        HISQ_HIP(e != hipSuccess ? e : ee);
+    }
+    graph_ = graph;
+    HISQ_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+    return HISQ_OK;
+}
+
+void ChunkGroup::launch_locked() {
+    std::sort(pending_.begin(), pending_.end(),
+              [](const Pending &a, const Pending &b) { return a.sys < b.sys; });
+    std::vector<std::pair<hipStream_t, int>> key;
+    for (const Pending &p : pending_) key.emplace_back(p.s, p.sys);
+    hisq_status st = HISQ_OK;
+    auto check = [&](hipError_t e, const char *what) {
+        if (st == HISQ_OK && e != hipSuccess)
+            st = fail(HISQ_ERR_HIP, std::string("chunk group: ") + what + ": " +
+                                        hipGetErrorString(e));
+    };
+    if (!origin_) check(hipStreamCreateWithFlags(&origin_, hipStreamNonBlocking), "stream");
+    if (st == HISQ_OK && (key != key_ || !exec_)) {
+        st = capture_locked();
+        key_ = st == HISQ_OK ? key : std::vector<std::pair<hipStream_t, int>>();
+    }
+    // the graph runs after every member's earlier work, and every member's
+    // later work after the graph
+    const size_t n = pending_.size();
+    for (size_t i = 0; i < n && st == HISQ_OK; ++i) {
+        check(hipEventRecord(events_[i], pending_[i].s), "record");
+        check(hipStreamWaitEvent(origin_, events_[i], 0), "wait");
+    }
+    if (st == HISQ_OK) check(hipGraphLaunch(exec_, origin_), "graph launch");
+    if (st == HISQ_OK) check(hipEventRecord(events_[n], origin_), "record");
+    for (size_t i = 0; i < n && st == HISQ_OK; ++i)
+        check(hipStreamWaitEvent(pending_[i].s, events_[n], 0), "wait");
+    if (st != HISQ_OK) {
+        round_status_ = st;
+        round_error_ = hisq_last_error();
+    }
+    pending_.clear();
+    ++round_;
+    cv_.notify_all();
+}
+
 hisq_status solver_stream(hisq_gauge_s *g, hipStream_t caller, hipStream_t *out) {
     if (!g->cg_stream) HISQ_HIP(hipStreamCreateWithFlags(&g->cg_stream, hipStreamNonBlocking));
     hipEvent_t e = nullptr;
@@ -122,6 +223,11 @@ ProfileSuppress::~ProfileSuppress() { t_prof_suppressed = prev_; }
 
 extern int64_t g_gemm_f32;  // gemm.hip
 
+// "cg_multi_graph": -1 automatic (off), 0 off, 1: hisq_cg_solve_multi
+// launches the chunks of all systems as one graph (ChunkGroup).
+int64_t g_multi_graph = -1;
+bool cg_multi_graph() { return g_multi_graph == 1 && !g_prof_on; }
+
 // "cg_reliable_freeze": -1 automatic, 0 off, 1 on (see ru_freeze in CgDev).
 int64_t g_ru_freeze = -1;
 
@@ -173,6 +279,12 @@ hisq_status hisq_set_tuning(const char *key, int64_t value) {
         if (value != -1 && value != 0 && value != 1)
             return fail(HISQ_ERR_INVALID_ARG, "gemm_fp32_mfma must be -1, 0 or 1");
         g_gemm_f32 = value;
+        return HISQ_OK;
+    }
+    if (std::string(key) == "cg_multi_graph") {
+        if (value != -1 && value != 0 && value != 1)
+            return fail(HISQ_ERR_INVALID_ARG, "cg_multi_graph must be -1, 0 or 1");
+        g_multi_graph = value;
         return HISQ_OK;
     }
     if (std::string(key) == "cg_reliable_freeze") {

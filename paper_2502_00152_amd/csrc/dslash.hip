@@ -65,11 +65,30 @@ bool geom_march_ok(const Geom &g) {
     return g.T >= 2 && (int64_t)g.Xh * g.Y * g.Z % dslash_impl::kSites == 0;
 }
 
+// XCD remap value meaning "chunks of one eighth of a time slice" (resolved
+// once the RHS groups are known).
+constexpr int kXcdChunkAuto = -2;
+
+// Chunks of site blocks dealt round-robin to the XCDs, one eighth of a time
+// slice each (times the RHS groups of a site block), so that the eight XCDs
+// sweep one time slice per round together: the time and z neighbours of the
+// sites in flight are then shared in the last-level cache.  Measured with 12
+// RHS (HIP events, including the 16-bit format conversions): 16-bit vectors
+// 0.600 -> 0.537 ms at 32^3 x 64 and 3.11 -> 2.74 ms at 48^3 x 96, FP32 0.743
+// -> 0.661 and 3.83 -> 3.59 ms, FP64 1.475 -> 1.233 and 7.16 -> 6.50 ms
+// against one contiguous range per XCD; one RHS is unchanged or slower, so
+// it keeps the contiguous ranges.
+int xcd_chunk_blocks(const Geom &geom, int ngroups) {
+    const int64_t S = (int64_t)geom.Xh * geom.Y * geom.Z;
+    const int64_t c = (S + 8 * dslash_impl::kSites - 1) / (8 * dslash_impl::kSites);
+    return (int)std::max<int64_t>(2, std::min<int64_t>(c * ngroups, 1 << 20));
+}
+
 DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links,
                               const Geom &geom) {
     const bool f32 = real_bytes <= 4, small = vh <= (1 << 18);  // FP32 and BF16
     DslashShape sh{};
-    int xcd = 1;
+    int xcd = nrhs >= 3 && !small ? kXcdChunkAuto : 1;
     if (nrhs <= 2) {
         sh.nr = nrhs, sh.lps = 1, xcd = f32 ? 0 : 1;
     } else if (nrhs <= 4) {
@@ -143,6 +162,8 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
         if (sh.lps > 1) sh.lps /= 2;
         else sh.nr = sh.nr == 12 ? 6 : sh.nr == 6 ? 3 : 1;
     }
+    if (sh.xcd_remap == kXcdChunkAuto)
+        sh.xcd_remap = xcd_chunk_blocks(geom, (nrhs + sh.nr * sh.lps - 1) / (sh.nr * sh.lps));
     return sh;
 }
 

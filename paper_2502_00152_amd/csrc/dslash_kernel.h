@@ -192,6 +192,9 @@ struct DslashShape {
 // vectors with 16-bit links.
 DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links,
                               const Geom &geom);
+// XCD remap chunk (in launched blocks) of an eighth of a time slice for
+// ngroups RHS groups per site block
+int xcd_chunk_blocks(const Geom &geom, int ngroups);
 
 namespace dslash_impl {
 

@@ -3,8 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
 #include <cstdint>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -352,6 +355,53 @@ private:
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t exec_ = nullptr;
 };
+
+// Chunks of CG iterations of several systems, one host thread each,
+// launched as one HIP graph (hisq_cg_solve_multi with "cg_multi_graph").
+// Each solver hands its chunk (stream-ordered launches on its own stream) to
+// the group and waits; the last member to arrive captures every member's
+// chunk on the members' streams, forked from and joined to one origin
+// stream, into one graph, launches it, and orders every member stream after
+// it.  The instantiated graph is replayed while the members and their
+// systems stay the same.  A member leaves when its thread has no system
+// left.  Launch arguments of a chunk must not change between chunks of one
+// system (the CG iteration kernels read all scalars from device memory).
+class ChunkGroup {
+public:
+    explicit ChunkGroup(int members) : active_(members) {}
+    ~ChunkGroup();
+    // member `sys` (a system index) runs `body` on stream s as part of the
+    // next combined launch
+    hisq_status run(hipStream_t s, int sys, const std::function<hisq_status()> &body);
+    void leave();
+
+private:
+    struct Pending {
+        hipStream_t s;
+        int sys;
+        const std::function<hisq_status()> *body;
+    };
+    void launch_locked();
+    hisq_status capture_locked();
+    std::mutex mu_;
+    std::condition_variable cv_;
+    int active_;
+    uint64_t round_ = 0;
+    hisq_status round_status_ = HISQ_OK;
+    std::string round_error_;
+    std::vector<Pending> pending_;
+    std::vector<std::pair<hipStream_t, int>> key_;  // members of the cached graph
+    hipStream_t origin_ = nullptr;
+    std::vector<hipEvent_t> events_;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+};
+// hisq_set_tuning "cg_multi_graph" is 1 (and kernel timing is off)
+bool cg_multi_graph();
+// the group this thread's CG solves hand their chunks to (null: none), and
+// the index of the system being solved
+extern thread_local ChunkGroup *t_chunk_group;
+extern thread_local int t_chunk_sys;
 
 // Mixed-precision CG helpers; mask (nrhs ints, device) selects RHS, null = all.
 hisq_status mixed_to_f32(const double2 *src, float2 *dst, int64_t n, int nrhs, const int *mask,

@@ -37,12 +37,28 @@ extern "C" hisq_status hisq_cg_solve_multi(int n_systems, const hisq_system *sys
         std::string msg;
     };
     std::vector<Outcome> out(n_systems);
+    // one graph per chunk for all systems, if asked for (one device, no
+    // kernel timing: its events would be captured)
+    bool one_device = true;
+    for (hisq_gauge g : order) one_device = one_device && g->device == order[0]->device;
+    const bool combined = order.size() > 1 && one_device && cg_multi_graph();
+    ChunkGroup group((int)order.size());
     auto run_group = [&](hisq_gauge g) {
+        struct Member {  // leaves the group when the thread has no system left
+            ChunkGroup *grp;
+            ~Member() {
+                if (grp) grp->leave();
+                t_chunk_group = nullptr;
+                t_chunk_sys = -1;
+            }
+        } member{combined ? &group : nullptr};
+        t_chunk_group = member.grp;
         if (hipSetDevice(g->device) != hipSuccess) {
             for (int i : by_handle[g]) out[i] = {HISQ_ERR_HIP, "hipSetDevice failed"};
             return;
         }
         for (int i : by_handle[g]) {
+            t_chunk_sys = i;
             const hisq_system &S = systems[i];
             const hisq_status st =
                 hisq_cg_solve(S.g, S.two_m, S.b_dev, S.x_dev, S.nrhs, &params[i],

@@ -9,7 +9,9 @@ host draw of 24^3 x 48 takes about a minute).  Checks: every RHS converges;
 the oracle's FP64 true residual of every RHS meets tol, and the library's
 reported true residual of every RHS agrees with the oracle's (5% plus the
 rounding of b - A x); the concurrent batched solve equals separate
-single-mass solves bitwise for the smallest lattice.
+single-mass solves bitwise for the smallest lattice; launching every chunk
+of iterations of the four systems as one captured graph gives bitwise the
+same solutions and iteration counts as one stream per system.
 """
 from __future__ import annotations
 
@@ -91,3 +93,27 @@ def test_uneven_batch_concurrent(batch, prec):
                                 sloppy_prec=sp)
         assert rk.iterations == res[0].iterations[k * nr:(k + 1) * nr]
         assert torch.equal(xk, x[k * nr:(k + 1) * nr])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "half"])
+def test_uneven_batch_one_graph_per_chunk(batch, prec):
+    import torch
+    from paper_2502_00152_amd import hisq
+    sp = {"fp64": hisq.HISQ_FP64, "half": hisq.HISQ_HALF}[prec]
+    out = {}
+    try:
+        for mode in (0, 1):
+            hisq.hisq_set_tuning("cg_multi_graph", mode)
+            systems = [(d["g"], d["masses"], d["b"], torch.zeros_like(d["b"])) for d in batch]
+            t0 = time.time()
+            res = hisq.hisq_cg_solve_multi(systems, tol=1e-10, sloppy_prec=sp)
+            torch.cuda.synchronize()
+            out[mode] = (res, [x for (_, _, _, x) in systems], time.time() - t0)
+    finally:
+        hisq.hisq_set_tuning("cg_multi_graph", -1)
+    print(f"[uneven] {prec}: streams {out[0][2]:.3f}s, one graph per chunk {out[1][2]:.3f}s",
+          flush=True)
+    for r0, r1, x0, x1 in zip(out[0][0], out[1][0], out[0][1], out[1][1]):
+        assert all(r1.converged)
+        assert r0.iterations == r1.iterations
+        assert torch.equal(x0, x1)
