@@ -2,7 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S]
                     [--no-cpu-baseline] [--no-secondary] [--no-uneven]
-                    [--no-dslash-scan] [--no-ru-variants] [--pmc-probe 48|16]
+                    [--no-dslash-scan] [--no-ru-variants] [--pmc-probe 48|16|32]
+                    [--gemm-probe]
 
 Headline workload (the learned-guess configuration, synthetic): one GPU's
 share of a large lattice, 48^3 x 96, random SU(3) fat and long links (eps 0.5,
@@ -331,6 +332,8 @@ def headline(args, out):
     from paper_2502_00152_amd import hisq, inputs as I
     cfg = I.workload(4)
     dims, two_m, tol, n_ev, nrhs = cfg["dims"], cfg["two_m"], cfg["tol"], cfg["n_ev"], cfg["nrhs"]
+    if args.n_ev:
+        n_ev = args.n_ev
     say(f"setup {cfg['name']}")
     g, W, N, t_pack = device_gauge(cfg)
     ee, eo = device_sources(g, nrhs, cfg["seed_src"][0], two_m)
@@ -701,19 +704,32 @@ def dslash_scan(reps=10):
 
 def pmc_probe(which):
     """Short run for hardware-counter passes: a few launches of the CG's
-    16-bit half stencil with 12 RHS at the workload's volume, and a plain
-    1 GiB copy whose counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    16-bit half stencil with 12 RHS at the workload's volume (48: 48^3 x 96,
+    16: 16^3 x 32), or (32) the half stencil with 24 RHS at 32^3 x 64 in
+    16-bit, FP32 and FP64 storage; then a plain 1 GiB copy whose counter
+    readings calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2502_00152_amd import hisq, inputs as I
-    cfg = I.workload({"48": 4, "16": 1}[which])
+    cfg = I.workload({"48": 4, "16": 1, "32": 2}[which])
     g, W, N, _ = device_gauge(cfg)
     del W, N
     torch.cuda.empty_cache()
-    x = torch.randn((12, 3, g.vh), dtype=torch.complex64, device="cuda")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        hisq.hisq_dslash_eo(g, 0, x, y, prec=hisq.HISQ_HALF)
-        hisq.hisq_mdagm(g, cfg["two_m"], x, y, prec=hisq.HISQ_HALF)
+    if which == "32":
+        for prec, dt in ((hisq.HISQ_HALF, torch.complex64), (hisq.HISQ_FP32, torch.complex64),
+                         (hisq.HISQ_FP64, torch.complex128)):
+            x = torch.randn((24, 3, g.vh), dtype=dt, device="cuda")
+            y = torch.empty_like(x)
+            for _ in range(3):
+                hisq.hisq_dslash_eo(g, 0, x, y, prec=prec)
+            del x, y
+            torch.cuda.empty_cache()
+    else:
+        x = torch.randn((12, 3, g.vh), dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            hisq.hisq_dslash_eo(g, 0, x, y, prec=hisq.HISQ_HALF)
+            hisq.hisq_mdagm(g, cfg["two_m"], x, y, prec=hisq.HISQ_HALF)
+        del x, y
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
     a.fill_(1.0)
     b = torch.empty_like(a)
@@ -725,6 +741,41 @@ def pmc_probe(which):
                       "kernel_source_hash": kernel_source_hash()}), flush=True)
 
 
+def gemm_probe():
+    """The deflation projection (Eq. (4)) at 32^3 x 64 with FP32 eigenvectors:
+    64 vectors x 12 RHS and 256 x 24, with FP64 arithmetic and on the FP32
+    matrix cores, five calls each (for kernel traces and MFMA counters)."""
+    import torch
+    from paper_2502_00152_amd import hisq, inputs as I
+    cfg = I.workload(2)
+    g, W, N, _ = device_gauge(cfg)
+    del W, N
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    out = {}
+    for k, n in ((64, 12), (256, 24)):
+        V = torch.randn((k, 3, g.vh), dtype=torch.complex64, device="cuda", generator=gen)
+        B = torch.randn((n, 3, g.vh), dtype=torch.complex128, device="cuda", generator=gen)
+        x = torch.empty_like(B)
+        eps = np.linspace(1e-3, 0.2, k)
+        for mode in (0, 1):
+            hisq.hisq_set_tuning("gemm_fp32_mfma", mode)
+            try:
+                hisq.hisq_deflate(g, V, eps, cfg["two_m"], B, x)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    hisq.hisq_deflate(g, V, eps, cfg["two_m"], B, x)
+                torch.cuda.synchronize()
+                out[f"{k}x{n}_fp32_mfma_{mode}_ms"] = (time.perf_counter() - t0) / 5 * 1e3
+            finally:
+                hisq.hisq_set_tuning("gemm_fp32_mfma", -1)
+        del V, B, x
+        torch.cuda.empty_cache()
+    g.close()
+    print(json.dumps({"gemm_probe": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -734,6 +785,8 @@ def main():
                     help="skip the legs after the headline once the run has used this long")
     ap.add_argument("--eig-tol", type=float, default=1e-10)
     ap.add_argument("--pairs", type=int, default=48, help="training pairs for the learned guess")
+    ap.add_argument("--n-ev", type=int, default=0,
+                    help="eigenpairs of the headline workload (0: its recipe's 64)")
     ap.add_argument("--train-steps-per-batch", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
@@ -741,7 +794,9 @@ def main():
     ap.add_argument("--no-dslash-scan", action="store_true")
     ap.add_argument("--no-ru-variants", action="store_true",
                     help="skip the reliable-update timing variants of the headline solve")
-    ap.add_argument("--pmc-probe", choices=("48", "16"))
+    ap.add_argument("--pmc-probe", choices=("48", "16", "32"))
+    ap.add_argument("--gemm-probe", action="store_true",
+                    help="time the deflation projection at 32^3 x 64 (for profiles) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -754,6 +809,9 @@ def main():
         sys.exit(1)
     if args.pmc_probe:
         pmc_probe(args.pmc_probe)
+        return
+    if args.gemm_probe:
+        gemm_probe()
         return
     out = {}
     headline(args, out)
