@@ -306,8 +306,8 @@ def stencil_roofline(prof, vh, nrhs):
     achieved = bpl / avg_ms / 1e6  # GB/s
     ops = STENCIL_FLOPS_PER_SITE_RHS * nrhs * vh
     return {"bound": "hbm",
-            "kernel": f"k_dslash<float, h16c, q16c> (half stencil, 16-bit vectors and links, "
-                      f"int16 dot products, FP32 accumulation, {nrhs} RHS)",
+            "kernel": f"k_dslash<float, h16p, q16s> (half stencil, packed 16-bit vectors "
+                      f"and links, int16 dot products, FP32 accumulation, {nrhs} RHS)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "launches_timed": launches, "timed_every": PROFILE_PERIOD,
