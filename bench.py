@@ -326,6 +326,21 @@ PROFILE_CLASSES = ("dslash", "dslash_aux", "dslash_aux2", "dslash_f32", "dslash_
                    "dslash_h16_aux", "blas", "gemm", "nn_layer")
 
 
+def projection_rate(sample, k, n, N):
+    """MFMA rate of the deflation projection launches in the timed steps
+    (V^H B and V C: 8 k n N flops each, FP32 vectors widened onto the FP64
+    matrix cores at this shape), from the sampled HIP-event times."""
+    if not sample or not sample[0]:
+        return None
+    avg_ms = sample[1] / sample[0]
+    tflops = 8.0 * k * n * N / (avg_ms * 1e-3) / 1e12
+    return {"k": k, "n": n, "launches_timed": sample[0], "avg_us": avg_ms * 1e3,
+            "mfma_tflops": tflops, "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
+            "frac_of_fp64_mfma_peak": tflops / FP64_MFMA_PEAK_TFLOPS,
+            "note": ("V^H B and V C launches timed by HIP events; hardware MFMA counters "
+                     "of the same kernels: profiles/gemm_projection_32x32x32x64.md")}
+
+
 def headline(args, out):
     """The 48^3 x 96 learned + mixed + batched step."""
     import torch
@@ -483,6 +498,7 @@ def headline(args, out):
             f"{cpu['cpu_model']}); oracle residuals of sources 0, 1: "
             f"{cpu['oracle_true_residual_of_gpu_solutions']}")
     del W, N
+    g_vh = g.vh
     g.close()
 
     out.update({
@@ -532,6 +548,7 @@ def headline(args, out):
         "kernel_sample": {k: {"launches_timed": v[0],
                               "avg_us": v[1] / v[0] * 1e3 if v[0] else None}
                           for k, v in prof.items()},
+        "projection": projection_rate(prof.get("gemm"), n_ev, nrhs, 3 * g_vh),
     })
 
 
