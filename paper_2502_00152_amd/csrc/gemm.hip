@@ -420,13 +420,16 @@ __global__ __launch_bounds__(kBS) void k_gemv_nn(const TV *__restrict__ V, int64
 }
 
 // ------------------------------------------------------------------- nn
-// X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i].  Transposed real form:
-// X~^T (n x 2N) = C_big^T (n x 2k) * V_big^T (2k x 2N) with
-// V_big[2s+c][2i+d] = (c,d) = (0,0): vr, (0,1): -vi, (1,0): vi, (1,1): vr and
-// C_big[2i][j] = Re C[j][i], C_big[2i+1][j] = Im C[j][i].
-// Output rows are right-hand sides (16 per tile), output columns 16 reals of
-// X (8 sites): each store instruction writes 128 contiguous bytes per RHS.
-// Grid: x = column tiles (grid-stride), y = groups of 16*MT right-hand sides.
+// X[j][s] = beta X[j][s] + sum_i V[i][s] C[j][i], as four real products on
+// the matrix cores: with A = V (rows: 16 sites, K: 4 eigenvectors) and
+// B = C^T (K: the same 4 eigenvectors, columns: 16 RHS),
+//   Re X += Re V Re C - Im V Im C,   Im X += Re V Im C + Im V Re C.
+// Lane l supplies A[l%16][l/16] and B[l/16][l%16]: one complex V entry (site
+// l%16 of the tile, eigenvector l/16 of the step) and one complex
+// coefficient per lane and step, each used by two instructions; no entry is
+// loaded twice.  Grid: x = 16-site tiles (grid-stride, a wave per tile),
+// y = groups of 16 MT right-hand sides.  Per output, the sum over the
+// eigenvectors runs in the same order for any MT and batch size.
 template <typename TV>
 struct NnArgs {
     const TV *V;          // k columns, column i at V + i * ldv (reals)
@@ -435,107 +438,79 @@ struct NnArgs {
     int64_t ldv, ldx;     // reals between consecutive columns
     int k, n;
     double beta;
-    int64_t tiles;        // (2 * rows) / 16
+    int64_t rows;         // complex entries per column
+    int64_t tiles;        // ceil(rows / 16)
 };
 
-template <typename TV, int MT>
-__global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs<TV> a) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lr = lane & 15, q = lane >> 4;
-    const int jbase = blockIdx.y * (16 * MT);
-    const int c = lr & 1;   // 0: real row, 1: imaginary row of this lane's output column
-    const int dsel = q & 1; // K slot parity: 0 -> Re part of C / (vr | vi), 1 -> Im part
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < a.tiles;
-         tile += (int64_t)gridDim.x * 4) {
-        const int64_t col = tile * 16 + lr;     // real index in a column of X
-        const int64_t site = col >> 1;          // complex index
-        dvec4 acc[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = dvec4{0, 0, 0, 0};
-        // each MFMA consumes two eigenvectors: slot q <-> (i0 + (q >> 1), d = q & 1)
-        for (int i0 = 0; i0 < a.k; i0 += 2) {
-            const int i = i0 + (q >> 1);
-            double bval = 0.0;
-            if (i < a.k) {
-                const dvec2 v = load2(a.V + (int64_t)i * a.ldv + 2 * site);
-                // V_big[2s+c][2i+d]
-                bval = c == 0 ? (dsel == 0 ? v.x : -v.y) : (dsel == 0 ? v.y : v.x);
-            }
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                const int j = jbase + 16 * m + lr;  // A operand row = right-hand side
-                double aval = 0.0;
-                if (j < a.n && i < a.k) {
-                    const dvec2 cc = a.C[(int64_t)j * a.k + i];
-                    aval = dsel == 0 ? cc.x : cc.y;
-                }
-                acc[m] = mfma(aval, bval, acc[m]);
-            }
-        }
-        // acc[m][r] = X~^T[jbase + 16m + 4r + q][tile*16 + lr]
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = jbase + 16 * m + 4 * r + q;
-                if (j < a.n) {
-                    double *dst = a.X + (int64_t)j * a.ldx + tile * 16 + lr;
-                    double v = acc[m][r];
-                    if (a.beta != 0.0) v = fma(a.beta, *dst, v);
-                    *dst = v;
-                }
-            }
-    }
+__device__ __forceinline__ fvec4 mfma_any(float a, float b, fvec4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ dvec4 mfma_any(double a, double b, dvec4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// X = beta X + V C for FP32 V on the FP32 matrix cores: the coefficients
-// rounded to FP32, the k products of an output summed in FP32, beta X added
-// in FP64.  Layout as k_gemm_nn, with the FP32 accumulator rows of
-// v_mfma_f32_16x16x4f32 (register r of lane l: row 4 (l/16) + r).
-template <int MT>
-__global__ __launch_bounds__(kBS) void k_gemm_nn_f32(NnArgs<float> a) {
+// accumulator row (site of the tile) of register r for lane quarter q
+template <bool F32>
+__device__ __forceinline__ int acc_row(int r, int q) { return F32 ? 4 * q + r : 4 * r + q; }
+
+// E: arithmetic (double: FP64 matrix cores; float: FP32, the coefficients
+// and, for FP64 V, the vectors rounded to float)
+template <typename TV, typename E, int MT>
+__global__ __launch_bounds__(kBS) void k_gemm_nn(NnArgs<TV> a) {
+    using Acc = typename std::conditional<std::is_same<E, float>::value, fvec4, dvec4>::type;
+    constexpr bool F32 = std::is_same<E, float>::value;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, q = lane >> 4;
     const int jbase = blockIdx.y * (16 * MT);
-    const int c = lr & 1;
-    const int dsel = q & 1;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < a.tiles;
          tile += (int64_t)gridDim.x * 4) {
-        const int64_t col = tile * 16 + lr;
-        const int64_t site = col >> 1;
-        fvec4 acc[MT];
+        const int64_t site = tile * 16 + lr;  // A row of this lane
+        const bool site_ok = site < a.rows;
+        Acc re[MT], im[MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = fvec4{0, 0, 0, 0};
-        for (int i0 = 0; i0 < a.k; i0 += 2) {
-            const int i = i0 + (q >> 1);
-            float bval = 0.0f;
-            if (i < a.k) {
-                const fvec2 v = *reinterpret_cast<const fvec2 *>(a.V + (int64_t)i * a.ldv + 2 * site);
-                bval = c == 0 ? (dsel == 0 ? v.x : -v.y) : (dsel == 0 ? v.y : v.x);
+        for (int m = 0; m < MT; ++m) re[m] = im[m] = Acc{0, 0, 0, 0};
+        for (int i0 = 0; i0 < a.k; i0 += 4) {
+            const int i = i0 + q;  // K slot of this lane
+            E vr = 0, vi = 0;
+            if (site_ok && i < a.k) {
+                const dvec2 v = load2(a.V + (int64_t)i * a.ldv + 2 * site);
+                vr = (E)v.x;
+                vi = (E)v.y;
             }
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                const int j = jbase + 16 * m + lr;
-                float aval = 0.0f;
+                const int j = jbase + 16 * m + lr;  // B column of this lane
+                E cr = 0, ci = 0;
                 if (j < a.n && i < a.k) {
-                    const dvec2 cc = a.C[(int64_t)j * a.k + i];
-                    aval = (float)(dsel == 0 ? cc.x : cc.y);
+                    const dvec2 c = a.C[(int64_t)j * a.k + i];
+                    cr = (E)c.x;
+                    ci = (E)c.y;
                 }
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[m], 0, 0, 0);
+                re[m] = mfma_any(vr, cr, re[m]);
+                re[m] = mfma_any(-vi, ci, re[m]);
+                im[m] = mfma_any(vr, ci, im[m]);
+                im[m] = mfma_any(vi, cr, im[m]);
             }
         }
+        // register r of lane (lr, q): site tile*16 + acc_row(r, q), RHS jbase + 16m + lr
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+        for (int m = 0; m < MT; ++m) {
+            const int j = jbase + 16 * m + lr;
+            if (j >= a.n) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int j = jbase + 16 * m + 4 * q + r;
-                if (j < a.n) {
-                    double *dst = a.X + (int64_t)j * a.ldx + tile * 16 + lr;
-                    double v = (double)acc[m][r];
-                    if (a.beta != 0.0) v = fma(a.beta, *dst, v);
-                    *dst = v;
+                const int64_t st = tile * 16 + acc_row<F32>(r, q);
+                if (st >= a.rows) continue;
+                dvec2 *dst = reinterpret_cast<dvec2 *>(a.X + (int64_t)j * a.ldx + 2 * st);
+                dvec2 o = dvec2{(double)re[m][r], (double)im[m][r]};
+                if (a.beta != 0.0) {
+                    const dvec2 x = *dst;
+                    o.x = fma(a.beta, x.x, o.x);
+                    o.y = fma(a.beta, x.y, o.y);
                 }
+                *dst = o;
             }
+        }
     }
 }
 
@@ -647,8 +622,8 @@ hisq_status gemm_nn_t(const TV *V, int64_t ldv, int k, const double2 *C, int n, 
     a.k = k;
     a.n = n;
     a.beta = beta;
-    if ((2 * rows) % 16) return fail(HISQ_ERR_INVALID_ARG, "gemm_nn: rows must be a multiple of 8");
-    a.tiles = 2 * rows / 16;
+    a.rows = rows;
+    a.tiles = (rows + 15) / 16;
     ProfileScope prof("gemm", s);
     if (n <= 2) {
         int64_t nb = (rows + 4 * kBS - 1) / (4 * kBS);
@@ -668,24 +643,15 @@ hisq_status gemm_nn_t(const TV *V, int64_t ldv, int k, const double2 *C, int n, 
     }
     int64_t nbx = (a.tiles + 3) / 4;
     nbx = std::max<int64_t>(1, std::min<int64_t>(nbx, 2048));
-    if constexpr (std::is_same<TV, float>::value) {
-        if (use_f32_mfma(k, n)) {
-            if (n <= 16) {
-                hipLaunchKernelGGL((k_gemm_nn_f32<1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
-            } else {
-                const int groups = (n + 63) / 64;
-                hipLaunchKernelGGL((k_gemm_nn_f32<4>), dim3((unsigned)nbx, groups), dim3(kBS), 0, s,
-                                   a);
-            }
-            HISQ_HIP(hipGetLastError());
-            return HISQ_OK;
-        }
-    }
-    if (n <= 16) {
-        hipLaunchKernelGGL((k_gemm_nn<TV, 1>), dim3((unsigned)nbx, 1), dim3(kBS), 0, s, a);
+    const bool f32 = std::is_same<TV, float>::value && use_f32_mfma(k, n);
+    const int groups = n <= 16 ? 1 : (n + 63) / 64;
+    const dim3 grid((unsigned)nbx, groups);
+    if (f32) {
+        if (n <= 16) hipLaunchKernelGGL((k_gemm_nn<TV, float, 1>), grid, dim3(kBS), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm_nn<TV, float, 4>), grid, dim3(kBS), 0, s, a);
     } else {
-        const int groups = (n + 63) / 64;
-        hipLaunchKernelGGL((k_gemm_nn<TV, 4>), dim3((unsigned)nbx, groups), dim3(kBS), 0, s, a);
+        if (n <= 16) hipLaunchKernelGGL((k_gemm_nn<TV, double, 1>), grid, dim3(kBS), 0, s, a);
+        else hipLaunchKernelGGL((k_gemm_nn<TV, double, 4>), grid, dim3(kBS), 0, s, a);
     }
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
