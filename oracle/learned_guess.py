@@ -4,7 +4,7 @@ maps the residual left by deflation to a correction of the solution.
 TEST INFRASTRUCTURE ONLY (like the rest of oracle/).  Plain PyTorch CPU ops in
 float64; gradients by autograd.  This is an extension beyond the paper (which
 solves with deflated CG only): the guess is x0 = x_defl + N(r0) with
-r0 = b - A x_defl, and deflated CG stays the solver and the judge.
+r0 = b - A x_defl, and deflated CG stays the solver and decides what is kept.
 
 Network N (8 channels, each channel a colour-vector field on the full lattice):
   layer(W, psi)^o = sum_d sum_c W[d, o, c] T_d psi^c
