@@ -98,12 +98,7 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
         // (M^H M with 24 RHS at 32^3 x 64: 16-bit vectors 2.13 against 2.39
         // ms with 3 per lane, FP32 with 16-bit links 2.46 against 2.63, FP32
         // 2.83 against 2.94 with 12 per lane); BF16 keeps up to 12 per lane
-        // 16-bit vectors with 9-12 RHS: one lane holds the whole batch (one
-        // group: the links are read once; at 48^3 x 96 with 12 RHS, chunked
-        // XCD order, 2.65 against 2.81 ms with 6 per lane and 2.74 with 6 x 2
-        // lanes, conversions included; at 32^3 x 64 0.566 against 0.578)
         if (small) sh.nr = 3, sh.lps = 1;
-        else if (q16_links && real_bytes == 2 && nrhs >= 9 && nrhs <= 12) sh.nr = 12, sh.lps = 1;
         else if (q16_links || real_bytes == 4) sh.nr = nrhs >= 6 ? 6 : 3, sh.lps = 1;
         else sh.nr = nr_for(nrhs, 1), sh.lps = 1;
     } else {
