@@ -168,10 +168,15 @@ def test_graph_captured_chunks_give_identical_iterates(w8, prec):
     assert torch.equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("graph", [0, 1])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_multi_system_solve_equals_separate_solves(prec):
-    """Three systems on two lattices and two masses solved concurrently give
-    bitwise the solutions of separate hisq_cg_solve calls."""
+def test_multi_system_solve_equals_separate_solves(prec, graph):
+    """Three systems on two lattices and two masses solved concurrently (one
+    stream per system, or graph = 1: every chunk of iterations of both
+    lattices' threads captured and launched as one graph) give bitwise the
+    solutions of separate hisq_cg_solve calls; a system rejected before it
+    starts, and systems that stop at max_iter, end the call without waiting
+    on each other."""
     import torch
     from paper_2502_00152_amd import hisq
     pa = Problem((8, 8, 8, 8), 0.3, 301, 302)
@@ -183,6 +188,7 @@ def test_multi_system_solve_equals_separate_solves(prec):
         b = dev(to_parity(np.stack([I.gaussian_source(pr.dims, seed + j) for j in range(n)]),
                           pr.dims, 0))
         systems.append((g, two_m, b, torch.zeros_like(b)))
+    hisq.hisq_set_tuning("cg_multi_graph", graph)
     try:
         res = hisq.hisq_cg_solve_multi(systems, tol=1e-10, sloppy_prec=sp)
         for (g, two_m, b, x), r in zip(systems, res):
@@ -195,7 +201,14 @@ def test_multi_system_solve_equals_separate_solves(prec):
             bad = [(ga, 0.1, systems[0][2], systems[0][3]), (gb, -1.0, systems[2][2], systems[2][3])]
             hisq.hisq_cg_solve_multi(bad)
         assert "system 1" in str(e.value)
+        # every system stops at max_iter, in its second chunk of 16 iterations
+        capped = [(g, two_m, b, torch.zeros_like(b)) for (g, two_m, b, _) in systems]
+        rc = hisq.hisq_cg_solve_multi(capped, tol=1e-10, max_iter=20, sloppy_prec=sp,
+                                      raise_on_fail=False)
+        for r in rc:
+            assert not any(r.converged) and r.iterations == [20] * len(r.iterations)
     finally:
+        hisq.hisq_set_tuning("cg_multi_graph", -1)
         ga.close()
         gb.close()
 
