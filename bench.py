@@ -147,7 +147,7 @@ def device_sources(g, n, seed, two_m):
     return ee, eo
 
 
-def eigensolve(g, two_m, n_ev, tol, seed, tag):
+def eigensolve(g, two_m, n_ev, tol, seed, tag, block=0):
     import torch
     from paper_2502_00152_amd import hisq
     evecs = torch.empty((n_ev, 3, g.vh), dtype=torch.complex128, device="cuda")
@@ -160,12 +160,14 @@ def eigensolve(g, two_m, n_ev, tol, seed, tag):
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, lam, est = hisq.hisq_eigensolve(g, two_m, n_ev, evecs, tol=tol, seed=seed, progress=prog)
+    _, lam, est = hisq.hisq_eigensolve(g, two_m, n_ev, evecs, tol=tol, seed=seed, progress=prog,
+                                       block=block)
     torch.cuda.synchronize()
     t_eig = time.perf_counter() - t0
     say(f"{tag} eigensolve {t_eig:.1f} s, {est.matvecs} matvecs, {est.restarts} restarts, "
-        f"max residual {est.max_residual:.2e}, lambda_1 {lam[0]:.4e}")
-    info = {"seconds": t_eig, "n_ev": n_ev, "tol": tol, "matvecs": est.matvecs,
+        f"block {max(block, 1)}, max residual {est.max_residual:.2e}, lambda_1 {lam[0]:.4e}")
+    info = {"seconds": t_eig, "n_ev": n_ev, "tol": tol, "block": max(block, 1),
+            "matvecs": est.matvecs,
             "restarts": est.restarts, "cheb_degree": est.cheb_degree,
             "max_residual": est.max_residual, "lambda_max": est.lambda_max,
             "lambda_1": float(lam[0]), f"lambda_{n_ev}": float(lam[-1])}
@@ -352,7 +354,8 @@ def headline(args, out):
     say(f"setup {cfg['name']}")
     g, W, N, t_pack = device_gauge(cfg)
     ee, eo = device_sources(g, nrhs, cfg["seed_src"][0], two_m)
-    evecs, lam, eig = eigensolve(g, two_m, n_ev, args.eig_tol, cfg["seed_eig"], "48^3x96")
+    evecs, lam, eig = eigensolve(g, two_m, n_ev, args.eig_tol, cfg["seed_eig"], "48^3x96",
+                                 args.eig_block)
     eps = lam - two_m * two_m
     ev32 = torch.empty(evecs.shape, dtype=torch.complex64, device="cuda")
     hisq.hisq_convert_vectors(evecs, ev32)  # single-precision eigenvectors (section 3)
@@ -801,6 +804,8 @@ def main():
     ap.add_argument("--budget-s", type=float, default=420.0,
                     help="skip the legs after the headline once the run has used this long")
     ap.add_argument("--eig-tol", type=float, default=1e-10)
+    ap.add_argument("--eig-block", type=int, default=0,
+                    help="Lanczos block size of the 48^3 x 96 eigensolve (0: one vector per step)")
     ap.add_argument("--pairs", type=int, default=48, help="training pairs for the learned guess")
     ap.add_argument("--n-ev", type=int, default=0,
                     help="eigenpairs of the headline workload (0: its recipe's 64)")

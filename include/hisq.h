@@ -407,7 +407,8 @@ typedef void (*hisq_eig_progress_fn)(void *user, int restart, int step, int matv
                                      double seconds);
 
 typedef struct hisq_eig_params {
-    int n_kr;              /* Krylov basis size (0 = auto: max(2*n_ev, n_ev + 32)) */
+    int n_kr;              /* Krylov basis size (0 = auto: max(2*n_ev, n_ev + 32),
+                              rounded up to a multiple of the block size) */
     int cheb_degree;       /* Chebyshev filter degree (0 = auto) */
     double cheb_a;         /* filter interval [a, b] of A to suppress (0 = auto) */
     double cheb_b;
@@ -420,7 +421,13 @@ typedef struct hisq_eig_params {
     uint64_t seed;         /* seed of the counter-based start vector */
     hisq_eig_progress_fn progress; /* optional progress report (NULL: none) */
     void *progress_user;   /* passed to progress */
-    int reserved[8];       /* must be zero */
+    int block;             /* Lanczos block size nb (0 or 1: one vector per step;
+                              at most 32): each step filters nb vectors in one
+                              multi-RHS stencil launch per half stencil (block
+                              thick-restart Lanczos, the block variant named in
+                              the conclusions); needs
+                              n_ev + 2 nb - 1 <= n_kr <= 3 Vh - nb */
+    int reserved[7];       /* must be zero */
 } hisq_eig_params;
 
 typedef struct hisq_eig_stats {
@@ -442,16 +449,18 @@ typedef struct hisq_eig_stats {
  * section 3).
  *   evecs_dev   caller-allocated [n_ev][3][Vh] complex double, or complex float
  *               with evec_prec = HISQ_FP32 (orthonormal on exit)
- * Device memory: one FP64 basis of n_kr + 1 vectors, a block of
- * min(n_ev, 32) vectors (twice: the block and M^H M's odd temporary) and
- * four more vectors (48 Vh bytes each), all freed before the call returns;
- * e.g. n_ev = 512, n_kr = 640 at 48^3 x 96 (Vh = 5308416) takes 173 GB
+ * Device memory: one FP64 basis of n_kr + nb vectors, a block of
+ * max(min(n_ev, 32), nb) vectors (twice: the block and M^H M's odd
+ * temporary) and four blocks of nb vectors (48 Vh bytes each), freed before
+ * the call returns (M^H M's temporary stays with the gauge's scratch); e.g.
+ * n_ev = 512, n_kr = 640, nb = 1 at 48^3 x 96 (Vh = 5308416) takes 173 GB
  * besides the caller's 65 GB of FP32 eigenvectors and the links.
  *   evals_host  n_ev doubles, ascending: eigenvalues of A at this two_m
  *   stats_host  may be NULL.
  * Returns NOT_CONVERGED if max_restarts passes without n_ev accepted pairs
  * (the best Ritz pairs are still written), BREAKDOWN, INVALID_ARG
- * (n_ev < 1, n_kr <= n_ev, n_kr >= 3*Vh), OOM.  Synchronises `stream`.
+ * (n_ev < 1, block outside [0, 32], n_kr outside the range above), OOM.
+ * Synchronises `stream`.
  */
 hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
                             const hisq_eig_params *params, void *evecs_dev,

@@ -1,13 +1,14 @@
-// Host-side dense Hermitian eigensolver (cyclic Jacobi) for the small
-// projected matrices of the eigensolver: the Lanczos arrowhead/tridiagonal
-// matrix of a thick-restart cycle and the Rayleigh-Ritz Gram matrix.
-// Jacobi is slow for large n but accurate for graded matrices, which the
-// Chebyshev-filtered Lanczos matrices are.
+// Host-side dense Hermitian eigensolvers for the small projected matrices of
+// the eigensolver: cyclic Jacobi (the Rayleigh-Ritz Gram matrix; slow for
+// large n but accurate for graded matrices) and Householder + implicit QR (the
+// Lanczos matrices of a thick-restart cycle, real for one vector per step,
+// complex Hermitian for a block).
 #include <algorithm>
 #include <cmath>
 #include <complex>
 #include <limits>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 namespace hisq {
@@ -97,64 +98,99 @@ int heev_jacobi(int n, cd *A, double *w, cd *Z, int max_sweeps) {
     return sweep < max_sweeps ? sweep : -1;
 }
 
-// Real symmetric eigensolver for the Lanczos matrices (arrowhead plus
-// tridiagonal, real): Householder reduction to tridiagonal form, then the
-// implicit symmetric QR iteration with Wilkinson shifts (bulge chasing with
-// Givens rotations), eigenvectors accumulated throughout.  O(n^3) with a small
-// constant, against the O(sweeps n^3) complex cyclic Jacobi; backward stable
-// (errors of order eps ||A||, enough for the large filtered Ritz values the
-// eigensolver keeps).
-// A: n x n symmetric, row-major, overwritten.  On return w holds the
-// eigenvalues ascending and Z (row-major) the eigenvectors as columns.
-// Returns the number of QR steps, or -1 if an eigenvalue needed more than 60.
-int syev_qr(int n, double *A, double *w, double *Z) {
-    auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
-    auto z = [&](int i, int j) -> double & { return Z[(size_t)i * n + j]; };
+// Householder tridiagonalisation followed by the implicit symmetric QR
+// iteration with Wilkinson shifts (bulge chasing with Givens rotations),
+// eigenvectors accumulated throughout: for the Lanczos matrices, real
+// symmetric (T = double: arrowhead plus tridiagonal) or complex Hermitian
+// (T = complex: arrowhead plus block tridiagonal, from the block Lanczos).
+// O(n^3) with a small constant, against the O(sweeps n^3) cyclic Jacobi;
+// backward stable (errors of order eps ||A||, enough for the large filtered
+// Ritz values the eigensolver keeps).
+// A: n x n, row-major, overwritten.  On return w holds the eigenvalues
+// ascending and Z (row-major) the eigenvectors as columns.  Returns the
+// number of QR steps, or -1 if an eigenvalue needed more than 60.
+namespace {
+inline double conj_(double x) { return x; }
+inline cd conj_(cd x) { return std::conj(x); }
+inline double abs_(double x) { return std::fabs(x); }
+inline double abs_(cd x) { return std::abs(x); }
+inline double real_(double x) { return x; }
+inline double real_(cd x) { return x.real(); }
+
+template <typename T>
+int tridiag_qr(int n, T *A, double *w, T *Z) {
+    constexpr bool cplx = !std::is_same<T, double>::value;
+    auto a = [&](int i, int j) -> T & { return A[(size_t)i * n + j]; };
+    auto z = [&](int i, int j) -> T & { return Z[(size_t)i * n + j]; };
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) z(i, j) = i == j ? 1.0 : 0.0;
     // 1. Householder: for each column k, reflect rows/columns k+1.. so that
-    //    column k has a single nonzero below the diagonal.  Z accumulates the
+    //    column k has a single nonzero below the diagonal.  H = I - 2 v v^H
+    //    with alpha = -phase(x0) ||x|| maps x to alpha e_1.  Z accumulates the
     //    product of the reflections (Z <- Z H).
-    std::vector<double> v(n), p(n), q(n);
+    std::vector<T> v(n), p(n), q(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;  // length of the reflected part
         double xn = 0.0;
-        for (int i = 0; i < m; ++i) xn = std::hypot(xn, a(k + 1 + i, k));
+        for (int i = 0; i < m; ++i) xn = std::hypot(xn, abs_(a(k + 1 + i, k)));
         if (xn == 0.0) continue;
-        const double x0 = a(k + 1, k);
-        const double alpha = x0 >= 0.0 ? -xn : xn;
+        const T x0 = a(k + 1, k);
+        T ph = 1.0;
+        if (cplx) {
+            if (abs_(x0) > 0.0) ph = x0 / abs_(x0);
+        } else if (real_(x0) < 0.0) {
+            ph = -1.0;
+        }
+        const T alpha = -xn * ph;
         for (int i = 0; i < m; ++i) v[i] = a(k + 1 + i, k);
         v[0] -= alpha;
         double vn = 0.0;
-        for (int i = 0; i < m; ++i) vn = std::hypot(vn, v[i]);
+        for (int i = 0; i < m; ++i) vn = std::hypot(vn, abs_(v[i]));
         if (vn == 0.0) continue;
         for (int i = 0; i < m; ++i) v[i] /= vn;
-        // H = I - 2 v v^T on the trailing block B: B <- B - 2 v q^T - 2 q v^T,
-        // p = B v, q = p - (v^T p) v
+        // on the trailing block B: B <- H B H = B - 2 v q^H - 2 q v^H with
+        // p = B v, q = p - (v^H p) v (v^H p is real for Hermitian B)
         for (int i = 0; i < m; ++i) {
-            double t = 0.0;
+            T t = 0.0;
             for (int j = 0; j < m; ++j) t += a(k + 1 + i, k + 1 + j) * v[j];
             p[i] = t;
         }
         double vp = 0.0;
-        for (int i = 0; i < m; ++i) vp += v[i] * p[i];
+        for (int i = 0; i < m; ++i) vp += real_(conj_(v[i]) * p[i]);
         for (int i = 0; i < m; ++i) q[i] = p[i] - vp * v[i];
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j)
-                a(k + 1 + i, k + 1 + j) -= 2.0 * (v[i] * q[j] + q[i] * v[j]);
-        a(k + 1, k) = a(k, k + 1) = alpha;
+                a(k + 1 + i, k + 1 + j) -= 2.0 * (v[i] * conj_(q[j]) + q[i] * conj_(v[j]));
+        a(k + 1, k) = alpha;
+        a(k, k + 1) = conj_(alpha);
         for (int i = 1; i < m; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
         // Z <- Z H on columns k+1..
         for (int r = 0; r < n; ++r) {
-            double t = 0.0;
+            T t = 0.0;
             for (int j = 0; j < m; ++j) t += z(r, k + 1 + j) * v[j];
             t *= 2.0;
-            for (int j = 0; j < m; ++j) z(r, k + 1 + j) -= t * v[j];
+            for (int j = 0; j < m; ++j) z(r, k + 1 + j) -= t * conj_(v[j]);
         }
     }
     std::vector<double> d(n), e(n, 0.0);
-    for (int i = 0; i < n; ++i) d[i] = a(i, i);
-    for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
+    for (int i = 0; i < n; ++i) d[i] = real_(a(i, i));
+    if (cplx) {
+        // T = D T' D^H with D = diag(delta), delta_{k+1} = delta_k phase(e_k),
+        // makes the subdiagonal of T' real (|e_k|); the eigenvectors of T are
+        // D times those of T', so Z <- Z D.
+        T delta = 1.0;
+        for (int k = 0; k < n; ++k) {
+            if (k > 0) {
+                const T ek = a(k, k - 1);
+                const double ae = abs_(ek);
+                e[k - 1] = ae;
+                if (ae > 0.0) delta *= ek / ae;
+                for (int r = 0; r < n; ++r) z(r, k) *= delta;
+            }
+        }
+    } else {
+        for (int i = 0; i + 1 < n; ++i) e[i] = real_(a(i + 1, i));
+    }
     // 2. Implicit QR on the unreduced blocks, from the bottom up.
     const double eps = std::numeric_limits<double>::epsilon();
     int steps = 0, m = n - 1, iters = 0;
@@ -194,7 +230,7 @@ int syev_qr(int n, double *A, double *w, double *Z) {
                 e[k + 1] *= c;
             }
             for (int r2 = 0; r2 < n; ++r2) {
-                const double zk = z(r2, k), zk1 = z(r2, k + 1);
+                const T zk = z(r2, k), zk1 = z(r2, k + 1);
                 z(r2, k) = c * zk + s * zk1;
                 z(r2, k + 1) = -s * zk + c * zk1;
             }
@@ -204,7 +240,7 @@ int syev_qr(int n, double *A, double *w, double *Z) {
     std::vector<int> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int x1, int y1) { return d[x1] < d[y1]; });
-    std::vector<double> Zs((size_t)n * n);
+    std::vector<T> Zs((size_t)n * n);
     for (int c2 = 0; c2 < n; ++c2) {
         w[c2] = d[idx[c2]];
         for (int r = 0; r < n; ++r) Zs[(size_t)r * n + c2] = z(r, idx[c2]);
@@ -212,5 +248,9 @@ int syev_qr(int n, double *A, double *w, double *Z) {
     std::copy(Zs.begin(), Zs.end(), Z);
     return steps;
 }
+}  // namespace
+
+int syev_qr(int n, double *A, double *w, double *Z) { return tridiag_qr<double>(n, A, w, Z); }
+int heev_qr(int n, cd *A, double *w, cd *Z) { return tridiag_qr<cd>(n, A, w, Z); }
 
 }  // namespace hisq

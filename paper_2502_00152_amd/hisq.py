@@ -113,7 +113,7 @@ class EigParams(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
                 ("evec_prec", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("progress", EIG_PROGRESS), ("progress_user", ctypes.c_void_p),
-                ("reserved", ctypes.c_int * 8)]
+                ("block", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
 
 
 class EigStats(ctypes.Structure):
@@ -545,15 +545,16 @@ def hisq_deflate(g, evecs, evals, two_m, b, x0, stream=None):
 
 def hisq_eigensolve(g, two_m, n_ev, evecs, n_kr=0, cheb_degree=0, cheb_a=0.0, cheb_b=0.0,
                     tol=1e-10, max_restarts=0, seed=0, stream=None, raise_on_fail=True,
-                    progress=None):
+                    progress=None, block=0):
     """progress: optional callable(restart, step, matvecs, seconds), called after
     every Lanczos step (restart -1 = pilot).  evecs complex128, or complex64 for
-    single-precision eigenvectors (the solve is FP64 either way)."""
+    single-precision eigenvectors (the solve is FP64 either way).  block: the
+    Lanczos block size (0 or 1: one vector per step)."""
     if _nrhs(evecs, g.vh, "evecs") != n_ev:
         raise ValueError("evecs must hold n_ev vectors")
     p = EigParams(n_kr=int(n_kr), cheb_degree=int(cheb_degree), cheb_a=float(cheb_a),
                   cheb_b=float(cheb_b), tol=float(tol), max_restarts=int(max_restarts),
-                  seed=int(seed), evec_prec=_prec_of(evecs, "evecs"))
+                  seed=int(seed), evec_prec=_prec_of(evecs, "evecs"), block=int(block))
     cb = None
     if progress is not None:
         cb = EIG_PROGRESS(lambda _u, r, j, mv, sec: progress(r, j, mv, sec))

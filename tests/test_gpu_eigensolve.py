@@ -4,7 +4,9 @@ against the oracle's dense / ARPACK eigenpairs of A = (2m)^2 - D_eo D_oe.
 The Lanczos path itself is parity unpinned; its results are pinned:
 eigenvalues to 1e-10 * lambda_max, oracle-evaluated residuals
 ||A v - lambda v|| <= 1e-10 * lambda_max, orthonormality, and the spanned
-subspace (projectors) where the spectrum has a gap at n_ev.
+subspace (projectors) where the spectrum has a gap at n_ev.  Each check runs
+with one vector per Lanczos step and with blocks (block thick-restart
+Lanczos, including block sizes that do not divide the basis size).
 """
 from __future__ import annotations
 
@@ -47,10 +49,11 @@ def check_against(pr, two_m, lam, V, ref_w, ref_V=None):
     return np.array(res), lmax
 
 
+@pytest.mark.parametrize("block", [0, 4, 5])
 @pytest.mark.parametrize("dims,n_ev,two_m", [((4, 4, 4, 6), 16, 0.1), ((4, 6, 4, 8), 24, 0.0)])
-def test_eigensolve_small_vs_dense(dims, n_ev, two_m):
+def test_eigensolve_small_vs_dense(dims, n_ev, two_m, block):
     pr = Problem(dims, 0.5, 3001, 3002)
-    lam, V, stats = gpu_eigs(pr, two_m, n_ev)
+    lam, V, stats = gpu_eigs(pr, two_m, n_ev, block=block)
     w, Vc = O.lowest_eigenpairs(pr.F, pr.L, two_m, n_ev + 1, method="dense")
     res, _ = check_against(pr, two_m, lam, V, w)
     lmax = stats.lambda_max
@@ -68,12 +71,13 @@ def test_eigensolve_small_vs_dense(dims, n_ev, two_m):
     assert np.abs(Pg - Po).max() <= 1e-8
 
 
-def test_eigensolve_8to4_vs_arpack():
+@pytest.mark.parametrize("block", [0, 8])
+def test_eigensolve_8to4_vs_arpack(block):
     """The 8^4 workload (eps 0.3), 32 lowest pairs, against ARPACK."""
     cfg = I.workload(0)
     pr = Problem.from_workload(0)
     two_m = cfg["two_m"]
-    lam, V, stats = gpu_eigs(pr, two_m, 32)
+    lam, V, stats = gpu_eigs(pr, two_m, 32, block=block)
     w, _ = O.lowest_eigenpairs(pr.F, pr.L, two_m, 32, method="arpack",
                                v0=np.ones(3 * 2048, dtype=np.complex128))
     res, _ = check_against(pr, two_m, lam, V, w)
@@ -81,7 +85,8 @@ def test_eigensolve_8to4_vs_arpack():
     assert res.max() <= TOL * stats.lambda_max
 
 
-def test_eigensolve_free_field_degenerate():
+@pytest.mark.parametrize("block", [0, 4])
+def test_eigensolve_free_field_degenerate(block):
     """Unit links: large exact degeneracies; the eigenvalues must still be the
     closed-form lowest ones (n_ev chosen at a gap of the free spectrum)."""
     dims = (4, 4, 4, 8)
@@ -90,7 +95,7 @@ def test_eigensolve_free_field_degenerate():
     spec = pins.free_even_spectrum(dims, I.C_FAT, I.C_LONG, two_m)
     gaps = np.nonzero(np.diff(spec) > 1e-6)[0]
     n_ev = int(gaps[gaps + 1 >= 20][0] + 1)
-    lam, V, stats = gpu_eigs(pr, two_m, n_ev, max_restarts=400)
+    lam, V, stats = gpu_eigs(pr, two_m, n_ev, max_restarts=400, block=block)
     assert np.abs(lam - spec[:n_ev]).max() <= TOL * stats.lambda_max
     res, _ = check_against(pr, two_m, lam, V, spec)
     assert res.max() <= TOL * stats.lambda_max
@@ -102,9 +107,29 @@ def test_eigensolve_rejects_bad_sizes():
     pr = Problem((4, 4, 4, 4), 0.3, 1, 2)
     g = pr.gauge()
     ev = torch.empty((8, 3, g.vh), dtype=torch.complex128, device="cuda")
-    st, _, _ = hisq.hisq_eigensolve(g, 0.1, 8, ev, n_kr=8, raise_on_fail=False)
-    assert st == hisq.HISQ_ERR_INVALID_ARG
+    for kw in (dict(n_kr=8), dict(block=33), dict(block=-1), dict(block=4, n_kr=14),
+               dict(block=8, n_kr=3 * g.vh - 4)):
+        st, _, _ = hisq.hisq_eigensolve(g, 0.1, 8, ev, raise_on_fail=False, **kw)
+        assert st == hisq.HISQ_ERR_INVALID_ARG, kw
     g.close()
+
+
+@pytest.mark.parametrize("block", [1, 4, 6])
+def test_block_lanczos_when_the_basis_nearly_fills_the_space(block):
+    """2^3 x 4 (3 Vh = 48 unknowns) with a basis of 40 + block vectors: the
+    blocks lose rank, the Cholesky QR falls back to Gram-Schmidt with random
+    replacements, and the pairs still match the dense eigendecomposition."""
+    pr = Problem((2, 2, 2, 4), 0.5, 3101, 3102)
+    two_m = 0.05
+    n_ev = 8
+    n_kr = 48 - block if block > 1 else 40
+    lam, V, stats = gpu_eigs(pr, two_m, n_ev, block=block, n_kr=n_kr)
+    w, _ = O.lowest_eigenpairs(pr.F, pr.L, two_m, n_ev, method="dense")
+    res, _ = check_against(pr, two_m, lam, V, w)
+    assert np.abs(lam - w).max() <= TOL * stats.lambda_max
+    assert res.max() <= TOL * stats.lambda_max
+    G = V.reshape(n_ev, -1).conj() @ V.reshape(n_ev, -1).T
+    assert np.abs(G - np.eye(n_ev)).max() <= 1e-12
 
 
 def test_fp32_output_is_the_rounded_fp64_result_and_memory_is_returned():
