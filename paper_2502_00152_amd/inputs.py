@@ -125,12 +125,12 @@ WORKLOADS = {
             nrhs=12, n_ev=64, tol=1e-10),
     2: dict(name="mixed-precision-32^3x64", dims=(32, 32, 32, 64), eps=0.5,
             two_m=0.005, nrhs=24, n_ev=256, tol=1e-10),
-    # one GPU's share of a large-lattice solve with the learned guess; 64
+    # one GPU's share of a large-lattice solve with the learned guess; 128
     # eigenpairs and 48 streamed training pairs keep a run within minutes
     # (512 pairs fit one GPU's memory with one FP64 Lanczos basis, about 180
     # GB, but their eigensolve takes far longer than a benchmark run)
     4: dict(name="learned-guess-48^3x96", dims=(48, 48, 48, 96), eps=0.5, two_m=0.002,
-            nrhs=12, n_ev=64, tol=1e-10, n_pairs=48),
+            nrhs=12, n_ev=128, tol=1e-10, n_pairs=48),
 }
 C_FAT = 1.0
 C_LONG = -1.0 / 24.0
