@@ -532,10 +532,11 @@ def headline(args, out):
                             "it lowers the FP64 residual), batched mixed-precision CG (16-bit "
                             "sloppy operator and search direction, FP64 reliable updates at "
                             "delta_rd 0.1), re-deflation at delta_tr 1e-3"),
-                   "reduced": ("64 eigenpairs and a streamed few dozen training pairs instead "
-                               "of 512 and 2000, to keep the run within minutes (a 512-pair "
-                               "eigensolve at this volume takes far longer than the run; its "
-                               "memory fits: one FP64 basis of n_kr + 1 vectors)")},
+                   "reduced": (f"{n_ev} eigenpairs and {learn['training_pairs']} streamed "
+                               "training pairs instead of 512 and 2000, to keep the run within "
+                               "minutes (a 512-pair eigensolve at this volume takes far longer "
+                               "than the run; its memory fits: one FP64 basis of n_kr + block "
+                               "vectors)")},
         "roofline": roof,
         "cpu_baseline": cpu,
         "iterations_per_source": last.iterations,

@@ -15,3 +15,11 @@ int syev_qr(int n, double *A, double *w, double *Z);
 extern "C" int test_syev(int n, double *A, double *w, double *Z) {
     return hisq::syev_qr(n, A, w, Z);
 }
+
+namespace hisq {
+int heev_qr(int n, std::complex<double> *A, double *w, std::complex<double> *Z);
+}
+extern "C" int test_heev_qr(int n, double *A, double *w, double *Z) {
+    return hisq::heev_qr(n, reinterpret_cast<std::complex<double> *>(A), w,
+                         reinterpret_cast<std::complex<double> *>(Z));
+}
