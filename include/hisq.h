@@ -494,6 +494,13 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            slice and keeps their time neighbours in
  *                            registers (FP64, FP32 and 16-bit storage; never
  *                            BF16); bitwise the same results
+ *   "dslash_blocks_per_cu"   -1: automatic (no cap, or the autotuner's
+ *                            choice); 0: no cap; 1-8: each stencil launch
+ *                            requests enough (unused) LDS that at most this
+ *                            many of its blocks share a compute unit, fewer
+ *                            sites in flight per XCD (measured at 48^3 x 96,
+ *                            12 RHS: FP32 vectors 3.56 -> 3.30 ms with 3; the
+ *                            16-bit CG stencil gains nothing)
  *   "dslash_autotune_clear"  any value: forget the autotuner's choices
  *   "gemm_fp32_mfma"         -1: automatic; 0: never; 1: always: the projection
  *                            with FP32 eigenvectors (V^H B and V C) on the FP32
@@ -533,12 +540,14 @@ typedef struct hisq_tune_result {
     double us_default;     /* and of the shape in use before the call */
     int shapes_timed;
     int march;             /* time segments of the time-marching kernel (0: not used) */
-    int reserved[2];
+    int blocks_per_cu;     /* cap on blocks per compute unit (0: none) */
+    int reserved[1];
 } hisq_tune_result;
 
 /*
  * Autotuner of the half stencil: time every launch shape the kernel provides
- * (RHS per lane x lanes per site x block order x XCD remap) for this handle's
+ * (RHS per lane x lanes per site x block order x XCD remap, then a cap of 4,
+ * 3 or 2 blocks per compute unit on the fastest) for this handle's
  * volume, nrhs right-hand sides and precision prec (HISQ_FP64 or HISQ_FP32),
  * `reps` launches each (0 = 20) on scratch vectors, with HIP events on
  * `stream`; remember the fastest for (volume, nrhs, prec) for the rest of the

@@ -32,6 +32,7 @@ struct KnobGuard {
         (void)dslash_set_tuning("dslash_group_order", -1);
         (void)dslash_set_tuning("dslash_xcd_remap", -1);
         (void)dslash_set_tuning("dslash_march", -1);
+        (void)dslash_set_tuning("dslash_blocks_per_cu", -1);
     }
 };
 
@@ -86,7 +87,9 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
     HISQ_TRY(dslash_set_tuning("dslash_group_order", def.group_outer));
     HISQ_TRY(dslash_set_tuning("dslash_xcd_remap", def.xcd_remap));
     HISQ_TRY(dslash_set_tuning("dslash_march", def.march));
+    HISQ_TRY(dslash_set_tuning("dslash_blocks_per_cu", def.blocks_per_cu));
     HISQ_TRY(time_current(&us_def));
+    HISQ_TRY(dslash_set_tuning("dslash_blocks_per_cu", 0));
     const int kind = rb == 8 ? 0 : 1;
     const bool march_geom = (int64_t)g->geom.Xh * g->geom.Y * g->geom.Z % 256 == 0;
 
@@ -148,6 +151,26 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
             }
         }
     }
+    // then a cap on the blocks per compute unit for the best shape (fewer
+    // sites in flight per XCD can keep more of the neighbour gathers in L2)
+    if (best.march == 0) {
+        HISQ_TRY(dslash_set_tuning("dslash_rhs_per_thread", best.nr));
+        HISQ_TRY(dslash_set_tuning("dslash_lanes_per_site", best.lps));
+        HISQ_TRY(dslash_set_tuning("dslash_group_order", best.group_outer));
+        HISQ_TRY(dslash_set_tuning("dslash_xcd_remap", best.xcd_remap));
+        HISQ_TRY(dslash_set_tuning("dslash_march", 0));
+        for (int cap : {4, 3, 2}) {
+            HISQ_TRY(dslash_set_tuning("dslash_blocks_per_cu", cap));
+            double us = 0.0;
+            HISQ_TRY(time_current(&us));
+            ++timed;
+            if (us < us_best) {
+                us_best = us;
+                best.blocks_per_cu = cap;
+            }
+        }
+        HISQ_TRY(dslash_set_tuning("dslash_blocks_per_cu", -1));
+    }
     dslash_tuned_set(vh, nrhs, rb, best);
     if (result_host) {
         *result_host = hisq_tune_result{};
@@ -158,6 +181,7 @@ extern "C" hisq_status hisq_autotune_dslash(hisq_gauge g, int nrhs, hisq_prec pr
         result_host->us_best = us_best;
         result_host->us_default = us_def;
         result_host->shapes_timed = timed;
+        result_host->blocks_per_cu = best.blocks_per_cu;
         result_host->march = best.march;
     }
     return HISQ_OK;

@@ -11,6 +11,7 @@ struct DslashTuning {
     int64_t group_order = -1;
     int64_t xcd_remap = -1;
     int64_t march = -1;  // time-marching kernel: -1 automatic, 0 off, n > 0 n time segments
+    int64_t blocks_per_cu = -1;  // -1 automatic, 0 no cap, n > 0 at most n blocks per CU
 };
 DslashTuning g_tune;
 
@@ -104,16 +105,18 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
     } else {
         sh.nr = 3, sh.lps = 2;
     }
-    int order = 0;
+    int order = 0, cap = 0;
     // the autotuner's choice for this volume and batch, if any
     const auto it = g_tuned.find(TunedKey{vh, nrhs, q16_links ? 3 : (int)real_bytes});
     const bool tuned = it != g_tuned.end();
     if (tuned) {
         sh.nr = it->second.nr, sh.lps = it->second.lps;
         xcd = it->second.xcd_remap, order = it->second.group_outer;
+        cap = it->second.blocks_per_cu;
     }
     // explicit knobs override both
     if (g_tune.rhs_per_thread > 0 || g_tune.lanes_per_site > 0) {
+        cap = 0;  // a tuned cap belongs to the tuned shape
         sh.lps = g_tune.lanes_per_site > 0 ? (int)g_tune.lanes_per_site : 1;
         sh.nr = g_tune.rhs_per_thread > 0 ? (int)g_tune.rhs_per_thread : nr_for(nrhs, sh.lps);
     }
@@ -164,6 +167,7 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
     }
     if (sh.xcd_remap == kXcdChunkAuto)
         sh.xcd_remap = xcd_chunk_blocks(geom, (nrhs + sh.nr * sh.lps - 1) / (sh.nr * sh.lps));
+    sh.blocks_per_cu = g_tune.blocks_per_cu >= 0 ? (int)g_tune.blocks_per_cu : cap;
     return sh;
 }
 
@@ -195,6 +199,10 @@ hisq_status dslash_set_tuning(const std::string &key, int64_t v) {
     } else if (key == "dslash_march") {
         if (v < -1) return fail(HISQ_ERR_INVALID_ARG, "dslash_march must be -1, 0 or a segment count");
         g_tune.march = v;
+    } else if (key == "dslash_blocks_per_cu") {
+        if (v < -1 || v > dslash_impl::kMaxBlocksPerCu)
+            return fail(HISQ_ERR_INVALID_ARG, "dslash_blocks_per_cu must be in [-1, 8]");
+        g_tune.blocks_per_cu = v;
     } else if (key == "dslash_xcd_remap") {
         if (v < -1 || v > (1 << 20))
             return fail(HISQ_ERR_INVALID_ARG, "dslash_xcd_remap must be -1, 0, 1 or a chunk size");

@@ -31,6 +31,7 @@
 // Included by dslash.hip (FP64) and dslash_f32.hip (FP32) only.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <type_traits>
 
@@ -185,6 +186,7 @@ struct DslashShape {
     int xcd_remap;
     int group_outer;
     int march = 0;
+    int blocks_per_cu = 0;  // 0: no cap
 };
 
 // Launch shape of the half stencil (tuned or default) for nrhs RHS at half
@@ -196,9 +198,12 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
 // ngroups RHS groups per site block
 int xcd_chunk_blocks(const Geom &geom, int ngroups);
 
+
 namespace dslash_impl {
 
 constexpr int kSites = 256;  // output sites per block (and per partial sum)
+constexpr int kLdsPerCu = 160 * 1024;   // LDS of one compute unit
+constexpr int kMaxBlocksPerCu = 8;      // largest block cap of a launch shape
 
 // R: arithmetic; VS: stored complex of the vectors; LS: of the links.
 template <typename R, typename VS, typename LS>
@@ -219,6 +224,7 @@ struct DslashArgs {
     int out_parity;
     int xcd_remap;         // 0 off, 1 contiguous site ranges per XCD, n > 1 chunks
     int group_outer;       // 1: block index = group * nsb + site block
+    int blocks_per_cu;     // > 0: LDS requested so that at most this many blocks share a CU
     int nrhs;
     int ngroups;           // ceil(nrhs / (LPS * NR))
     int nsb;               // site blocks = ceil(Vh / kSites)
@@ -810,22 +816,44 @@ __global__ __launch_bounds__(kSites *LPS) void k_dslash(DslashArgs<R, VS, LS> a)
     }
 }
 
+// Dynamic LDS a launch of kernel f requests (and leaves unused) so that at
+// most `per_cu` of its blocks fit the 160 KiB of LDS of a compute unit; 0
+// when per_cu is 0 (no cap).
+inline size_t lds_cap_bytes(const void *f, int per_cu) {
+    if (per_cu <= 0) return 0;
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, f) != hipSuccess) return 0;
+    const size_t total = (size_t)kLdsPerCu / (size_t)per_cu / 512 * 512;
+    return total > attr.sharedSizeBytes ? total - attr.sharedSizeBytes : 0;
+}
+
+template <typename R, typename VS, typename LS, int NR, int LPS, bool AUX, bool AUX2, bool DOT,
+          bool NT>
+void launch_one(const DslashArgs<R, VS, LS> &args, int nblocks, int per_cu, hipStream_t s) {
+    auto *f = &k_dslash<R, VS, LS, NR, LPS, AUX, AUX2, DOT, NT>;
+    // per cap, the LDS request + 1 once known (0: not yet asked)
+    static std::atomic<int64_t> cache[kMaxBlocksPerCu + 1];
+    const int k = per_cu < 0 ? 0 : (per_cu > kMaxBlocksPerCu ? kMaxBlocksPerCu : per_cu);
+    int64_t v = cache[k].load(std::memory_order_relaxed);
+    if (v == 0) {
+        v = (int64_t)lds_cap_bytes(reinterpret_cast<const void *>(f), k) + 1;
+        cache[k].store(v, std::memory_order_relaxed);
+    }
+    hipLaunchKernelGGL(f, dim3(nblocks), dim3(kSites * LPS), (size_t)(v - 1), s, args);
+}
+
 template <typename R, typename VS, typename LS, int NR, int LPS, bool NT>
 void launch_variant(const DslashArgs<R, VS, LS> &args, int nblocks, bool aux, bool aux2, bool dot,
                     hipStream_t s) {
-    const dim3 grid(nblocks), block(kSites * LPS);
+    const int cap = args.blocks_per_cu;
     if (dot)
-        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, true, false, true, NT>), grid, block, 0, s,
-                           args);
+        launch_one<R, VS, LS, NR, LPS, true, false, true, NT>(args, nblocks, cap, s);
     else if (aux2)
-        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, true, true, false, NT>), grid, block, 0, s,
-                           args);
+        launch_one<R, VS, LS, NR, LPS, true, true, false, NT>(args, nblocks, cap, s);
     else if (aux)
-        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, true, false, false, NT>), grid, block, 0,
-                           s, args);
+        launch_one<R, VS, LS, NR, LPS, true, false, false, NT>(args, nblocks, cap, s);
     else
-        hipLaunchKernelGGL((k_dslash<R, VS, LS, NR, LPS, false, false, false, NT>), grid, block, 0,
-                           s, args);
+        launch_one<R, VS, LS, NR, LPS, false, false, false, NT>(args, nblocks, cap, s);
 }
 
 template <typename R, typename VS, typename LS, int NR, int LPS>
@@ -905,6 +933,7 @@ hisq_status launch_dslash_t(const Geom &geom, const LS *const fat[2], const LS *
     a.out_parity = p;
     a.xcd_remap = sh.xcd_remap;
     a.group_outer = sh.group_outer;
+    a.blocks_per_cu = sh.blocks_per_cu;
     a.nrhs = nrhs;
     a.ngroups = (nrhs + sh.lps * sh.nr - 1) / (sh.lps * sh.nr);
     a.nsb = (geom.vh + kSites - 1) / kSites;

@@ -100,7 +100,7 @@ class TuneResult(ctypes.Structure):
                 ("group_order", ctypes.c_int), ("xcd_remap", ctypes.c_int),
                 ("us_best", ctypes.c_double), ("us_default", ctypes.c_double),
                 ("shapes_timed", ctypes.c_int), ("march", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("blocks_per_cu", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 EIG_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,

@@ -253,6 +253,7 @@ def test_autotuner_picks_a_valid_shape_and_keeps_results(prec):
         assert r.shapes_timed > 10 and 0 < r.us_best <= r.us_default
         assert (r.rhs_per_thread, r.lanes_per_site) in \
             [(n, 1) for n in (1, 2, 3, 4, 6, 12)] + [(n, l) for l in (2, 4) for n in (1, 3, 6)]
+        assert r.blocks_per_cu in (0, 2, 3, 4)
         out = torch.empty_like(v)
         hisq.hisq_dslash_eo(g, 0, v, out)
         assert torch.equal(out, ref)
@@ -260,6 +261,45 @@ def test_autotuner_picks_a_valid_shape_and_keeps_results(prec):
             hisq.hisq_autotune_dslash(g, 12, hisq.HISQ_BF16)
     finally:
         hisq.hisq_set_tuning("dslash_autotune_clear", 1)
+        g.close()
+
+
+def test_block_cap_per_compute_unit_keeps_results_bitwise():
+    """"dslash_blocks_per_cu" only requests unused LDS: the half stencil in
+    FP64, FP32 and 16-bit storage with 12 RHS (several RHS groups) and a CG
+    solve are bitwise the same for every cap; values outside [-1, 8] are
+    rejected."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    dims = (8, 8, 8, 12)
+    pr = Problem(dims, 0.4, 5201, 5202)
+    g = pr.gauge()
+    v64 = dev(to_parity(sources(dims, 12, 920), dims, 1))
+    v32 = v64.to(torch.complex64)
+    b = dev(to_parity(sources(dims, 3, 921), dims, 0))
+    cases = ((v64, hisq.HISQ_FP64), (v32, hisq.HISQ_FP32), (v32, hisq.HISQ_HALF))
+    try:
+        refs = []
+        for v, prec in cases:
+            o = torch.empty_like(v)
+            hisq.hisq_dslash_eo(g, 0, v, o, prec=prec)
+            refs.append(o)
+        x0 = torch.zeros_like(b)
+        r0 = hisq.hisq_cg_solve(g, 0.2, b, x0, tol=1e-10)
+        for cap in (1, 2, 3, 8, 0):
+            hisq.hisq_set_tuning("dslash_blocks_per_cu", cap)
+            for (v, prec), ref in zip(cases, refs):
+                o = torch.empty_like(v)
+                hisq.hisq_dslash_eo(g, 0, v, o, prec=prec)
+                assert torch.equal(o, ref), (cap, prec)
+            x = torch.zeros_like(b)
+            r = hisq.hisq_cg_solve(g, 0.2, b, x, tol=1e-10)
+            assert r.iterations == r0.iterations and torch.equal(x, x0), cap
+        for bad in (-2, 9):
+            assert hisq.lib().hisq_set_tuning(b"dslash_blocks_per_cu", bad) == \
+                hisq.HISQ_ERR_INVALID_ARG
+    finally:
+        hisq.hisq_set_tuning("dslash_blocks_per_cu", -1)
         g.close()
 
 
