@@ -96,7 +96,7 @@ const char *hisq_last_error(void);
 
 /* ABI revision of this header; bumped on any incompatible change. */
 int hisq_abi_version(void);
-#define HISQ_ABI_VERSION 9
+#define HISQ_ABI_VERSION 10
 
 /* ------------------------------------------------------------------ gauge */
 

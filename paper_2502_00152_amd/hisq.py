@@ -37,7 +37,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "OOM", 4: "NOT_CONVERGED
 HISQ_FP64, HISQ_FP32, HISQ_BF16, HISQ_Q16, HISQ_HALF = 0, 1, 2, 3, 4
 HISQ_GAUGE_FOLD_PHASES = 1
 HISQ_GAUGE_ANTIPERIODIC_T = 2
-ABI_VERSION = 9
+ABI_VERSION = 10
 NOALLOC_SCRATCH_BYTES = 64 << 20  # HISQ_NOALLOC_SCRATCH_BYTES
 HISQ_NN_CHANNELS = 8
 HISQ_NN_PARAMS = 752
