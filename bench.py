@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S]
                     [--no-cpu-baseline] [--no-secondary] [--no-uneven]
                     [--no-dslash-scan] [--no-ru-variants] [--pmc-probe 48|16|32]
-                    [--gemm-probe]
+                    [--gemm-probe] [--eig-recipe]
 
 Headline workload (the learned-guess configuration, synthetic): one GPU's
 share of a large lattice, 48^3 x 96, random SU(3) fat and long links (eps 0.5,
@@ -799,6 +799,67 @@ def gemm_probe():
     print(json.dumps({"gemm_probe": out}), flush=True)
 
 
+def eig_recipe(n_ev=512, n_kr=640, block=6):
+    """The learned-guess lattice with its recipe's 512 eigenpairs, run on its
+    own (the eigensolve takes longer than a benchmark run): the block
+    eigensolve with FP32 output (one FP64 basis of n_kr + block vectors, about
+    190 GB with its work blocks, besides 65 GB of FP32 eigenvectors), then two
+    deflated, re-deflated mixed-precision solves of 12 sources with those
+    eigenvectors (deflation + CG timed).  Prints one JSON line."""
+    import torch
+    from paper_2502_00152_amd import hisq, inputs as I
+    cfg = I.workload(4)
+    two_m = cfg["two_m"]
+    g, W, N, _ = device_gauge(cfg)
+    del W, N
+    torch.cuda.empty_cache()
+    say(f"gauge ready, {torch.cuda.mem_get_info()[0] / 1e9:.1f} GB free")
+    ev = torch.empty((n_ev, 3, g.vh), dtype=torch.complex64, device="cuda")
+    last = [0.0]
+
+    def prog(r, j, mv, sec):
+        if sec - last[0] >= 30.0:
+            last[0] = sec
+            say(f"eigensolve restart {r} step {j} matvecs {mv} {sec:.0f} s")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, lam, es = hisq.hisq_eigensolve(g, two_m, n_ev, ev, n_kr=n_kr, tol=1e-10,
+                                      seed=cfg["seed_eig"], block=block, progress=prog)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    say(f"eigensolve {t_eig:.1f} s, {es.matvecs} matvecs, {es.restarts} restarts, "
+        f"max residual {es.max_residual:.2e}")
+    eps = lam - two_m * two_m
+    solves = []
+    for _ in range(2):
+        ee, eo = device_sources(g, 12, cfg["seed_src"][0], two_m)
+        y = torch.empty_like(ee)
+        hisq.hisq_prepare_source(g, two_m, ee, eo, y)
+        del ee, eo
+        x = torch.empty_like(y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hisq.hisq_deflate(g, ev, eps, two_m, y, x)
+        r = hisq.hisq_cg_solve(g, two_m, y, x, tol=cfg["tol"], sloppy_prec=hisq.HISQ_HALF,
+                               reliable_delta=0.1, evecs=ev, evals=eps, tol_restart=1e-3)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        solves.append({"seconds": dt, "solves_per_s": 12 / dt, "iterations": r.iterations,
+                       "max_true_residual": max(r.true_residual),
+                       "converged": all(r.converged)})
+        say(f"deflation + mixed CG of 12 sources: {dt:.2f} s ({12 / dt:.2f} solves/s), "
+            f"iterations {min(r.iterations)}-{max(r.iterations)}")
+        del y, x
+    g.close()
+    print(json.dumps({"workload": cfg["name"], "n_ev": n_ev, "n_kr": n_kr, "block": block,
+                      "eigensolve": {"seconds": t_eig, "matvecs": es.matvecs,
+                                     "restarts": es.restarts, "cheb_degree": es.cheb_degree,
+                                     "max_residual": es.max_residual,
+                                     "lambda_1": float(lam[0]), "lambda_last": float(lam[-1])},
+                      "solves": solves}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -811,7 +872,7 @@ def main():
                     help="Lanczos block size of the 48^3 x 96 eigensolve (0: one vector per step)")
     ap.add_argument("--pairs", type=int, default=48, help="training pairs for the learned guess")
     ap.add_argument("--n-ev", type=int, default=0,
-                    help="eigenpairs of the headline workload (0: its recipe's 64)")
+                    help="eigenpairs of the headline workload (0: the workload's 128)")
     ap.add_argument("--train-steps-per-batch", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
@@ -822,6 +883,9 @@ def main():
     ap.add_argument("--pmc-probe", choices=("48", "16", "32"))
     ap.add_argument("--gemm-probe", action="store_true",
                     help="time the deflation projection at 32^3 x 64 (for profiles) and exit")
+    ap.add_argument("--eig-recipe", action="store_true",
+                    help="512 eigenpairs at 48^3 x 96 and two deflated solves with them "
+                         "(about 12 minutes), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -837,6 +901,9 @@ def main():
         return
     if args.gemm_probe:
         gemm_probe()
+        return
+    if args.eig_recipe:
+        eig_recipe()
         return
     out = {}
     headline(args, out)
