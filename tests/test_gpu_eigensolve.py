@@ -49,11 +49,13 @@ def check_against(pr, two_m, lam, V, ref_w, ref_V=None):
     return np.array(res), lmax
 
 
-@pytest.mark.parametrize("block", [0, 4, 5])
+@pytest.mark.parametrize("block,n_kr", [(0, 0), (4, 0), (5, 0), (5, 47)])
 @pytest.mark.parametrize("dims,n_ev,two_m", [((4, 4, 4, 6), 16, 0.1), ((4, 6, 4, 8), 24, 0.0)])
-def test_eigensolve_small_vs_dense(dims, n_ev, two_m, block):
+def test_eigensolve_small_vs_dense(dims, n_ev, two_m, block, n_kr):
+    """n_kr = 47 with blocks of 5: the basis size is not a multiple of the
+    block, so each cycle stops at the last whole block below it."""
     pr = Problem(dims, 0.5, 3001, 3002)
-    lam, V, stats = gpu_eigs(pr, two_m, n_ev, block=block)
+    lam, V, stats = gpu_eigs(pr, two_m, n_ev, block=block, n_kr=n_kr)
     w, Vc = O.lowest_eigenpairs(pr.F, pr.L, two_m, n_ev + 1, method="dense")
     res, _ = check_against(pr, two_m, lam, V, w)
     lmax = stats.lambda_max
