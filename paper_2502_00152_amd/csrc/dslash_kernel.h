@@ -191,9 +191,10 @@ struct DslashShape {
 
 // Launch shape of the half stencil (tuned or default) for nrhs RHS at half
 // volume vh, real_bytes per stored vector real (8, 4 or 2); q16_links: FP32
-// vectors with 16-bit links.
+// vectors with 16-bit links (with real_bytes 2: the packed 16-bit vectors);
+// plain: a launch without an epilogue field.
 DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_links,
-                              const Geom &geom);
+                              const Geom &geom, bool plain = false);
 // XCD remap chunk (in launched blocks) of an eighth of a time slice for
 // ngroups RHS groups per site block
 int xcd_chunk_blocks(const Geom &geom, int ngroups);

@@ -243,7 +243,7 @@ hisq_status launch_dslash_h16(hisq_gauge_s *g, int out_parity, const void *in, v
                           reinterpret_cast<const q16s *>(g->fatn[1])};
     const q16s *lng[2] = {reinterpret_cast<const q16s *>(g->lngn[0]),
                           reinterpret_cast<const q16s *>(g->lngn[1])};
-    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, true, g->geom);
+    const DslashShape sh = dslash_pick_shape(nrhs, g->geom.vh, 2, true, g->geom, aux == nullptr);
     HISQ_TRY(dslash_check_shape(sh));
     ProfileScope prof(aux ? "dslash_h16_aux" : "dslash_h16", s);
     return dslash_impl::launch_dslash_t<float, h16p, q16s>(
