@@ -96,6 +96,29 @@ def test_dslash_fp32_24rhs_sampled_sites(wl):
     say(f"FP32 stencil worst error {worst / U32:.1f} u of |D||psi|")
 
 
+def test_half_stencil_12rhs_large_volume_shapes_bitwise(wl):
+    """At this volume the 16-bit stencil's launch without an epilogue takes all
+    12 RHS in one lane (one group, XCD chunks for one group) and M^H M's
+    second launch 6 per lane in two groups: both give the bits of the same
+    calls with 6 and 3 RHS per lane forced."""
+    import torch
+    from paper_2502_00152_amd import hisq
+    v = torch.empty((12, 3, wl.g.vh), dtype=torch.complex64, device="cuda")
+    hisq.hisq_convert_vectors(wl.eo[:12], v)
+    d0, m0 = torch.empty_like(v), torch.empty_like(v)
+    hisq.hisq_dslash_eo(wl.g, 0, v, d0, prec=hisq.HISQ_HALF)
+    hisq.hisq_mdagm(wl.g, wl.two_m, v, m0, prec=hisq.HISQ_HALF)
+    try:
+        for nr in (6, 3):
+            hisq.hisq_set_tuning("dslash_rhs_per_thread", nr)
+            d, m = torch.empty_like(v), torch.empty_like(v)
+            hisq.hisq_dslash_eo(wl.g, 0, v, d, prec=hisq.HISQ_HALF)
+            hisq.hisq_mdagm(wl.g, wl.two_m, v, m, prec=hisq.HISQ_HALF)
+            assert torch.equal(d, d0) and torch.equal(m, m0), nr
+    finally:
+        hisq.hisq_set_tuning("dslash_rhs_per_thread", 0)
+
+
 @pytest.mark.parametrize("mfma32", [0, 1])
 def test_deflate_fp32_256_vectors_24rhs_sampled(wl, mfma32):
     """Eq. (4) with 256 FP32 vectors x 24 RHS at full size: sampled entries of
