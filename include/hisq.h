@@ -494,13 +494,14 @@ hisq_status hisq_eigensolve(hisq_gauge g, double two_m, int n_ev,
  *                            slice and keeps their time neighbours in
  *                            registers (FP64, FP32 and 16-bit storage; never
  *                            BF16); bitwise the same results
- *   "dslash_blocks_per_cu"   -1: automatic (no cap, or the autotuner's
- *                            choice); 0: no cap; 1-8: each stencil launch
- *                            requests enough (unused) LDS that at most this
- *                            many of its blocks share a compute unit, fewer
- *                            sites in flight per XCD (measured at 48^3 x 96,
- *                            12 RHS: FP32 vectors 3.56 -> 3.30 ms with 3; the
- *                            16-bit CG stencil gains nothing)
+ *   "dslash_blocks_per_cu"   -1: automatic (3 for FP32 vectors with 12 or more
+ *                            RHS above 2^18 sites per parity, else no cap;
+ *                            or the autotuner's choice); 0: no cap; 1-8: each
+ *                            stencil launch requests enough (unused) LDS that
+ *                            at most this many of its blocks share a compute
+ *                            unit, fewer sites in flight per XCD (measured at
+ *                            48^3 x 96, 12 RHS: FP32 vectors 3.57 -> 3.34 ms
+ *                            with 3; the 16-bit CG stencil gains nothing)
  *   "dslash_autotune_clear"  any value: forget the autotuner's choices
  *   "gemm_fp32_mfma"         -1: automatic; 0: never; 1: always: the projection
  *                            with FP32 eigenvectors (V^H B and V C) on the FP32

@@ -111,7 +111,11 @@ DslashShape dslash_pick_shape(int nrhs, int vh, size_t real_bytes, bool q16_link
     } else {
         sh.nr = 3, sh.lps = 2;
     }
-    int order = 0, cap = 0;
+    int order = 0;
+    // FP32 vectors (FP32 or 16-bit links) with 12 or more RHS on large
+    // volumes: at most 3 blocks per CU (12 and 24 RHS: 3-5% faster at 32^3 x
+    // 64, 5-10% at 48^3 x 96; 6 RHS unchanged)
+    int cap = real_bytes == 4 && !small && nrhs >= 12 ? 3 : 0;
     // the autotuner's choice for this volume and batch, if any
     const auto it = g_tuned.find(TunedKey{vh, nrhs, q16_links ? 3 : (int)real_bytes});
     const bool tuned = it != g_tuned.end();
